@@ -1,0 +1,409 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics
+(brute force, closed forms, invariants, special cases), never against itself."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import Oracle, OracleParams
+from paper_2509_20012_amd import metrics
+from paper_2509_20012_amd import phantom as ph
+from tests.helpers import dense, from_dense
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+SHAPES = [(1, 1, 1.0), (7, 3, 0.5), (48, 12, 0.3), (64, 16, 0.2), (33, 5, 0.6)]
+
+
+def _x(C, seed, lo=0.2, hi=2.0):
+    return np.random.default_rng(seed).uniform(lo, hi, C)
+
+
+# --- products against dense brute force (Section 2.2: additive numerator and
+# denominator of Eq. 1, so d = D x and l = L x) ----------------------------------
+
+@pytest.mark.parametrize("R,C,dens", SHAPES)
+def test_forward_and_transposed_dense(R, C, dens):
+    p = ph.tiny_problem(R, C, dens, seed=R * 31 + C)
+    o = Oracle(p)
+    D, L = dense(p)
+    x = _x(C, 1)
+    d, l = o.forward(x)
+    np.testing.assert_allclose(d, D @ x, rtol=1e-14, atol=1e-15)
+    np.testing.assert_allclose(l, L @ x, rtol=1e-14, atol=1e-15)
+    u1 = np.random.default_rng(2).normal(size=R)
+    u2 = np.random.default_rng(3).normal(size=R)
+    t = o.transposed(u1, u2)
+    np.testing.assert_allclose(t, D.T @ u1 + L.T @ u2, rtol=1e-12, atol=1e-13)
+    rows = np.arange(R)[::2]
+    dr, lr = o.forward_rows(x, rows)
+    np.testing.assert_array_equal(dr, d[rows])
+    np.testing.assert_array_equal(lr, l[rows])
+
+
+def test_empty_rows_and_columns():
+    p = ph.tiny_problem(20, 6, 0.4, seed=5, empty_rows=[0, 7, 19], empty_cols=[2])
+    o = Oracle(p)
+    D, L = dense(p)
+    x = _x(6, 4)
+    d, l, letd, cdl = o.dose_let(x)
+    for i in (0, 7, 19):
+        assert d[i] == 0.0 and l[i] == 0.0 and letd[i] == 0.0
+    t = o.transposed(np.ones(20), np.ones(20))
+    assert t[2] == 0.0
+    np.testing.assert_allclose(t, D.sum(0) + L.sum(0), rtol=1e-13)
+
+
+def test_scipy_crosscheck():
+    sp = pytest.importorskip("scipy.sparse")
+    p = ph.tiny_problem(64, 16, 0.25, seed=9)
+    A = sp.csr_matrix((p.d_val.astype(np.float64), p.col_idx, p.row_ptr), shape=(64, 16))
+    x = _x(16, 5)
+    d, _ = Oracle(p).forward(x)
+    np.testing.assert_allclose(d, A @ x, rtol=1e-14)
+
+
+def test_linearity():
+    p = ph.tiny_problem(48, 12, 0.3, seed=11)
+    o = Oracle(p)
+    x1, x2 = _x(12, 1), _x(12, 2)
+    a, b = 0.75, -1.5
+    d12, l12 = o.forward(a * x1 + b * x2)
+    d1, l1 = o.forward(x1)
+    d2, l2 = o.forward(x2)
+    np.testing.assert_allclose(d12, a * d1 + b * d2, rtol=1e-13, atol=1e-13)
+    np.testing.assert_allclose(l12, a * l1 + b * l2, rtol=1e-13, atol=1e-13)
+
+
+def test_letd_convex_combination_bound():
+    """LETd_i is a dose-weighted mean of LET_ij = L_ij / D_ij over contributing
+    beamlets, so it lies between their min and max (Eq. 1)."""
+    p = ph.tiny_problem(64, 16, 0.3, seed=13)
+    o = Oracle(p)
+    x = _x(16, 6)
+    x[::3] = 0.0
+    d, l, letd, cdl = o.dose_let(x)
+    for i in range(p.n_rows):
+        sl = slice(p.row_ptr[i], p.row_ptr[i + 1])
+        cols = p.col_idx[sl]
+        act = x[cols] > 0
+        if not act.any():
+            assert letd[i] == 0.0
+            continue
+        let = (p.l_val[sl].astype(np.float64) / p.d_val[sl].astype(np.float64))[act]
+        assert let.min() * (1 - 1e-15) <= letd[i] <= let.max() * (1 + 1e-15)
+    np.testing.assert_array_equal(cdl, p.c * l)
+
+
+def test_constant_let_special_case():
+    """L = LET0 * D gives LETd = LET0 wherever dose > 0; a LETd row with bound T is
+    violated exactly when LET0 > T."""
+    p = ph.tiny_problem(40, 10, 0.3, seed=17, let_range=(3.0, 3.0))
+    o = Oracle(p)
+    d, l, letd, _ = o.dose_let(_x(10, 7))
+    np.testing.assert_allclose(letd[d > 0], 3.0, rtol=2e-7)  # FP32 storage of L = 3 D
+    for T, expect in ((2.5, True), (3.5, False)):
+        prob = p.problem_arrays()
+        prob = {k: v.copy() for k, v in prob.items()}
+        prob["kind"][:] = ph.LETD_HI
+        prob["letd_max"][:] = T
+        _, nv = Oracle(p, problem=prob).proximity(_x(10, 7))
+        assert (nv == p.n_rows) if expect else (nv == 0)
+
+
+# --- projections (Fig. 2) -----------------------------------------------------------
+
+def _single_row_problem(kind, bound, let=(1.0, 4.0), T=None):
+    """Three beamlets, two rows; only row 0 carries constraint `kind`."""
+    D = np.array([[0.5, 1.0, 0.25], [0.3, 0.0, 0.6]], np.float32)
+    L = D * np.array([[let[0], let[1], 2.0], [1.0, 1.0, 1.0]], np.float32)
+    prob = dict(kind=[kind, 0], dose_lo=[0, 0], dose_hi=[0, 0], cdl_lo=[0, 0], cdl_hi=[0, 0],
+                letd_max=[0, 0], w_feas=[1, 1])
+    key = {ph.DOSE_LO: "dose_lo", ph.DOSE_HI: "dose_hi", ph.CDL_LO: "cdl_lo",
+           ph.CDL_HI: "cdl_hi", ph.LETD_HI: "letd_max"}[kind]
+    prob[key] = [bound if T is None else T, 0]
+    return from_dense(D, L, **prob)
+
+
+@pytest.mark.parametrize("kind,bound,T", [
+    (ph.DOSE_HI, 2.0, None), (ph.DOSE_LO, 8.0, None),
+    (ph.CDL_HI, 0.2, None), (ph.CDL_LO, 0.9, None), (ph.LETD_HI, None, 2.0)])
+def test_projection_lands_on_hyperplane(kind, bound, T):
+    """With lambda = w = 1 a single violated half-space is projected onto exactly:
+    the new point satisfies <a, x+> = b and x+ - x is parallel to a.  This also pins
+    the sign of the lower-bound step (garbled in Fig. 2): it must move toward the
+    half-space."""
+    p = _single_row_problem(kind, bound, T=T)
+    o = Oracle(p)
+    D, L = dense(p)
+    c = p.c
+    a = {ph.DOSE_HI: D[0], ph.DOSE_LO: D[0], ph.CDL_HI: c * L[0], ph.CDL_LO: c * L[0],
+         ph.LETD_HI: L[0] - (T or 0.0) * D[0]}[kind]
+    b = 0.0 if kind == ph.LETD_HI else float(np.float32(bound))
+    x = np.array([3.0, 2.0, 4.0])
+    assert (a @ x > b) if kind in (ph.DOSE_HI, ph.CDL_HI, ph.LETD_HI) else (a @ x < b)
+    for norm in (1, 2):  # convex over violated (single row) and raw: same weight 1
+        xn, prox, nv = o.ams_simultaneous(x, lam=1.0, weight_scale=1.0, normalization=norm)
+        assert nv == 1 and np.all(xn > 0)
+        assert a @ xn == pytest.approx(b, rel=1e-14, abs=1e-14)
+        step = xn - x
+        cosang = abs(step @ a) / (np.linalg.norm(step) * np.linalg.norm(a))
+        assert cosang == pytest.approx(1.0, abs=1e-13)
+        xs = o.ams_sequential(x, [0, 1], [0, 1], lam=1.0, weight_scale=1.0)
+        np.testing.assert_allclose(xs, xn, rtol=1e-14, atol=1e-15)
+    # relaxation lambda moves lambda times as far
+    xh, _, _ = o.ams_simultaneous(x, lam=0.5, weight_scale=1.0, normalization=2)
+    np.testing.assert_allclose(xh - x, 0.5 * (xn - x), rtol=1e-12, atol=1e-15)
+
+
+def test_orthogonal_rows_simultaneous_equals_sequential():
+    """Rows with disjoint beamlet supports do not interact: with raw weights the
+    simultaneous and sequential sweeps coincide and every violated row lands on its
+    hyperplane."""
+    rng = np.random.default_rng(21)
+    R, per = 6, 3
+    C = R * per
+    D = np.zeros((R, C), np.float32)
+    for i in range(R):
+        D[i, i * per:(i + 1) * per] = rng.uniform(0.2, 1.0, per)
+    L = (D * 2.0).astype(np.float32)
+    x = rng.uniform(1.0, 2.0, C)
+    d0 = D.astype(np.float64) @ x
+    kind = [ph.DOSE_HI, ph.DOSE_LO, ph.DOSE_HI | ph.DOSE_LO, ph.CDL_HI, ph.CDL_LO, ph.DOSE_HI]
+    dose_hi = [0.8 * d0[0], 0, 1.1 * d0[2], 0, 0, 1.2 * d0[5]]
+    dose_lo = [0, 1.2 * d0[1], 0.5 * d0[2], 0, 0, 0]
+    cdl_hi = [0, 0, 0, 0.9 * ph.C_DL * 2 * d0[3], 0, 0]
+    cdl_lo = [0, 0, 0, 0, 1.1 * ph.C_DL * 2 * d0[4], 0]
+    p = from_dense(D, L, kind=kind, dose_hi=dose_hi, dose_lo=dose_lo, cdl_hi=cdl_hi,
+                   cdl_lo=cdl_lo, w_feas=np.ones(R))
+    o = Oracle(p)
+    xs = o.ams_sequential(x, range(R), range(R), lam=1.0, weight_scale=1.0)
+    xn, _, nv = o.ams_simultaneous(x, lam=1.0, weight_scale=1.0, normalization=2)
+    assert nv == 4
+    np.testing.assert_allclose(xn, xs, rtol=1e-14, atol=1e-15)
+    Dd, Ld = dense(p)
+    assert Dd[0] @ xn == pytest.approx(float(p.dose_hi[0]), rel=1e-14)
+    assert Dd[1] @ xn == pytest.approx(float(p.dose_lo[1]), rel=1e-14)
+    assert p.c * Ld[3] @ xn == pytest.approx(float(p.cdl_hi[3]), rel=1e-14)
+    assert p.c * Ld[4] @ xn == pytest.approx(float(p.cdl_lo[4]), rel=1e-14)
+    np.testing.assert_array_equal(xn[2 * per:3 * per], x[2 * per:3 * per])  # satisfied row
+
+
+def test_sequential_hand_worked_example():
+    """Fig. 2 on a 2 x 2 case worked by hand (tests/golden/ams_sequential_2x2.json)."""
+    with open(os.path.join(GOLDEN, "ams_sequential_2x2.json")) as f:
+        g = json.load(f)
+    p = from_dense(g["D"], g["L"], c=g["c"], **g["problem"])
+    o = Oracle(p)
+    xs = o.ams_sequential(g["x"], g["dose_order"], g["cdl_order"], lam=g["lambda"],
+                          weight_scale=1.0)
+    np.testing.assert_allclose(xs, g["expected_sequential"], rtol=1e-12)
+    xn, _, _ = o.ams_simultaneous(g["x"], lam=g["lambda"], weight_scale=1.0, normalization=2)
+    np.testing.assert_allclose(xn, g["expected_simultaneous_raw"], rtol=1e-12)
+
+
+def test_clamp_is_applied():
+    D = np.array([[1.0, 1.0]], np.float32)
+    p = from_dense(D, D, kind=[ph.DOSE_HI], dose_hi=[0.0], w_feas=[1.0])
+    xn, _, _ = Oracle(p).ams_simultaneous(np.array([2.0, 0.1]), normalization=2)
+    # unclamped projection onto d <= 0 would be [0.95, -0.95]
+    np.testing.assert_allclose(xn, [0.95, 0.0], rtol=1e-14)
+
+
+def test_feasible_point_is_fixed():
+    p = ph.tiny_problem(48, 12, 0.3, seed=23)
+    prob = {k: v.copy() for k, v in p.problem_arrays().items()}
+    prob["dose_lo"][:] = 0.0
+    prob["dose_hi"][:] = 1e6
+    prob["cdl_lo"][:] = 0.0
+    prob["cdl_hi"][:] = 1e6
+    prob["letd_max"][:] = 1e6
+    o = Oracle(p, problem=prob)
+    x = _x(12, 8)
+    for norm in (0, 1, 2):
+        xn, prox, nv = o.ams_simultaneous(x, normalization=norm)
+        assert nv == 0 and prox == 0.0
+        np.testing.assert_array_equal(xn, x)
+
+
+@pytest.mark.parametrize("lam", [0.5, 1.0, 1.9])
+def test_proximity_monotone_convex_weights(lam):
+    """Convex-weight simultaneous projection with lambda in (0, 2) is a projected
+    gradient step on the proximity function, which therefore never increases."""
+    p = ph.tiny_problem(64, 16, 0.3, seed=29)
+    o = Oracle(p)
+    x = p.x0.astype(np.float64)
+    prev, _ = o.proximity(x)
+    assert prev > 0
+    for _ in range(30):
+        x, prox_in, _ = o.ams_simultaneous(x, lam=lam, weight_scale=1.0, normalization=0)
+        cur, _ = o.proximity(x)
+        assert prox_in == pytest.approx(prev, rel=1e-12)
+        assert cur <= prev * (1 + 1e-12)
+        prev = cur
+
+
+def test_convergence_feasible_by_construction():
+    """Bounds [0.95, 1.05] * D x* around a non-negative x* make the set non-empty;
+    the sweeps drive the proximity to zero."""
+    rng = np.random.default_rng(31)
+    p = ph.tiny_problem(40, 10, 0.4, seed=31, kinds="dose")
+    D, _ = dense(p)
+    xs = rng.uniform(0.5, 1.5, 10)
+    ds = D @ xs
+    prob = {k: v.copy() for k, v in p.problem_arrays().items()}
+    prob["kind"][:] = ph.DOSE_LO | ph.DOSE_HI
+    prob["dose_lo"][:] = 0.95 * ds
+    prob["dose_hi"][:] = 1.05 * ds
+    o = Oracle(p, problem=prob)
+    x = np.full(10, 3.0)
+    p0, _ = o.proximity(x)
+    for _ in range(400):
+        x, _, _ = o.ams_simultaneous(x, lam=1.5, normalization=1)
+    p1, _ = o.proximity(x)
+    assert p1 < 1e-10 * p0
+
+
+# --- objective and superiorization (Eq. 2, Fig. 3) ----------------------------------
+
+def test_cost_and_gradient_dense():
+    p = ph.tiny_problem(48, 12, 0.3, seed=37)
+    o = Oracle(p)
+    D, L = dense(p)
+    x = _x(12, 9)
+    d, l = D @ x, L @ x
+    k = p.kind
+    ptv = (k & ph.OBJ_DOSE) > 0
+    oar = (k & ph.OBJ_CDL) > 0
+    w = p.w_obj.astype(np.float64)
+    chi = np.sum(w[ptv] * (p.dose_target[ptv] - d[ptv]) ** 2) + \
+        np.sum(w[oar] * (p.cdl_target[oar] - p.c * l[oar]) ** 2)
+    assert o.cost(x) == pytest.approx(chi, rel=1e-13)
+    # central finite differences of the brute-force cost
+    g = o.gradient(x)
+    h = 1e-6
+    for j in range(12):
+        e = np.zeros(12)
+        e[j] = h
+        fd = (o.cost(x + e) - o.cost(x - e)) / (2 * h)
+        assert g[j] == pytest.approx(fd, rel=1e-6, abs=1e-9)
+
+
+def test_quadratic_line_identity():
+    """chi^2(y - beta g) - chi^2(y) = -beta ||g||^2 + beta^2 Q for g = grad chi^2(y)."""
+    p = ph.tiny_problem(48, 12, 0.3, seed=41)
+    o = Oracle(p)
+    D, L = dense(p)
+    y = _x(12, 10)
+    g = o.gradient(y)
+    G = g @ g
+    w = p.w_obj.astype(np.float64)
+    ptv = (p.kind & ph.OBJ_DOSE) > 0
+    oar = (p.kind & ph.OBJ_CDL) > 0
+    Q = np.sum(w[ptv] * (D @ g)[ptv] ** 2) + np.sum(w[oar] * p.c ** 2 * (L @ g)[oar] ** 2)
+    for beta in (1e-3, 1e-2, 0.1):
+        lhs = o.cost(y - beta * g) - o.cost(y)
+        assert lhs == pytest.approx(-beta * G + beta * beta * Q, rel=1e-7, abs=1e-12)
+
+
+@pytest.mark.parametrize("seed", [43, 44, 45])
+@pytest.mark.parametrize("r", [1, 2])
+def test_literal_and_closed_form_pick_same_step(seed, r):
+    p = ph.tiny_problem(48, 12, 0.3, seed=seed)
+    o = Oracle(p)
+    x = p.x0.astype(np.float64)
+    k, s = 0, -1
+    for _ in range(5):
+        xa, ka, sa, ia = o.sa_iteration(x, k, s, OracleParams(reductions_n=r, line_search=0,
+                                                               alpha=0.9))
+        xb, kb, sb, ib = o.sa_iteration(x, k, s, OracleParams(reductions_n=r, line_search=1,
+                                                               alpha=0.9))
+        assert (ka, sa) == (kb, sb)
+        np.testing.assert_allclose(xa, xb, rtol=1e-9, atol=1e-12)
+        assert ia["n_accepted"] == ib["n_accepted"] == r
+        x, k, s = xb, kb, sb
+
+
+def test_perturbation_strictly_lowers_cost():
+    p = ph.tiny_problem(64, 16, 0.3, seed=47)
+    o = Oracle(p)
+    x = p.x0.astype(np.float64)
+    k, s = 0, -1
+    for _ in range(10):
+        x, k, s, info = o.sa_iteration(x, k, s, OracleParams(reductions_n=2))
+        assert info["n_accepted"] >= 1
+        assert info["cost_after_perturb"] < info["cost_before"]
+    assert k == 10 and s >= 10
+
+
+def test_zero_reductions_is_ams():
+    """reductions_n = 0 leaves only the feasibility-seeking step with weights
+    eta^k w (Fig. 3)."""
+    p = ph.tiny_problem(48, 12, 0.3, seed=53)
+    o = Oracle(p)
+    x = p.x0.astype(np.float64)
+    q = OracleParams(reductions_n=0, eta=0.9, normalization=0)
+    xa = x.copy()
+    k, s = 0, -1
+    for it in range(4):
+        xa, k, s, _ = o.sa_iteration(xa, k, s, q)
+        x, _, _ = o.ams_simultaneous(x, lam=q.lam, weight_scale=0.9 ** it, normalization=0)
+        np.testing.assert_array_equal(xa, x)
+    assert s == -1
+
+
+def test_power_of_two_scale_invariance():
+    """Scaling D, L, bounds and targets by 2^m and the objective weights by 2^-2m
+    leaves the iterates unchanged bit for bit (every operation is homogeneous and
+    power-of-two scaling is exact)."""
+    p = ph.tiny_problem(48, 12, 0.3, seed=59)
+    m = 3
+    s2 = 2.0 ** m
+    q = ph.tiny_problem(48, 12, 0.3, seed=59)
+    q.d_val = (p.d_val * s2).astype(np.float32)
+    q.l_val = (p.l_val * s2).astype(np.float32)
+    for k in ("dose_lo", "dose_hi", "cdl_lo", "cdl_hi", "dose_target", "cdl_target"):
+        setattr(q, k, (getattr(p, k) * s2).astype(np.float32))
+    q.w_obj = (p.w_obj / s2 ** 2).astype(np.float32)
+    o1, o2 = Oracle(p), Oracle(q)
+    x1 = x2 = p.x0.astype(np.float64)
+    k1 = k2 = 0
+    s1 = s2_ = -1
+    prm = OracleParams(reductions_n=1, alpha=0.9)
+    for _ in range(5):
+        x1, k1, s1, _ = o1.sa_iteration(x1, k1, s1, prm)
+        x2, k2, s2_, _ = o2.sa_iteration(x2, k2, s2_, prm)
+        np.testing.assert_array_equal(x1, x2)
+        assert s1 == s2_
+
+
+def test_column_permutation_equivariance():
+    p = ph.tiny_problem(48, 12, 0.3, seed=61)
+    perm = np.random.default_rng(61).permutation(12)
+    inv = np.argsort(perm)
+    D, L = dense(p)
+    q = from_dense(D[:, perm], L[:, perm], **{k: v for k, v in p.problem_arrays().items()})
+    o1, o2 = Oracle(p), Oracle(q)
+    prm = OracleParams(reductions_n=1, alpha=0.9)
+    x1 = p.x0.astype(np.float64)
+    x2 = x1[perm]
+    k1 = k2 = 0
+    s1 = s2 = -1
+    for _ in range(5):
+        x1, k1, s1, _ = o1.sa_iteration(x1, k1, s1, prm)
+        x2, k2, s2, _ = o2.sa_iteration(x2, k2, s2, prm)
+    assert s1 == s2
+    np.testing.assert_allclose(x2[inv], x1, rtol=1e-10, atol=1e-13)
+
+
+# --- evaluation helpers ----------------------------------------------------------
+
+def test_metrics_helpers():
+    v = np.arange(1, 101, dtype=np.float64)  # 1..100
+    assert metrics.d_percent(v, 0.95) == 5.0     # rank ceil(0.05 * 100) = 5
+    assert metrics.d_percent(v, 0.98) == 2.0
+    assert metrics.d_percent(np.array([3.0, 1.0, 2.0]), 0.95) == 1.0
+    assert metrics.d_percent(np.array([7.0]), 0.95) == 7.0
+    assert metrics.mean_letd(np.array([1.0, 0.0, 2.0]), np.array([2.0, 9.0, 4.0])) == 3.0
+    assert ph.percentile_nearest_rank(np.arange(1, 11), 0.7) == 7.0
