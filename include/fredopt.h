@@ -1,0 +1,236 @@
+/*
+ * fredopt.h - C ABI of the MI355X hot path of superiorized feasibility seeking for
+ * simultaneous proton dose and LETd plan optimization (Borys et al., arXiv
+ * 2509.20012, Section 2.4.3, Figs. 2-3, Eq. 2).
+ *
+ * Problem (Section 2.4, Fig. 2): R voxel rows, C pencil-beam columns, sparse
+ * influence matrices D (dose per unit fluence, Gy) and L (numerator of the
+ * dose-averaged LET of Eq. 1, Gy keV/um per unit fluence; Section 2.2 explains why
+ * numerator and denominator are stored separately, and the dose matrix serves as
+ * the denominator).  For a fluence x >= 0:
+ *     d = D x,   l = L x,   LETd_i = l_i / d_i (0 where d_i = 0),   cDL_i = c l_i
+ * with c = 0.04 um/keV (Section 2.4).  Each row carries a bit mask of half-space
+ * constraints (Fig. 2) and objective terms (Eq. 2):
+ *     FREDOPT_DOSE_LO   d_i >= dose_lo_i              normal a = D_i
+ *     FREDOPT_DOSE_HI   d_i <= dose_hi_i              normal a = D_i
+ *     FREDOPT_CDL_LO    c l_i >= cdl_lo_i             normal a = c L_i
+ *     FREDOPT_CDL_HI    c l_i <= cdl_hi_i             normal a = c L_i
+ *     FREDOPT_LETD_HI   LETd_i <= letd_max_i, linearised as l_i - T_i d_i <= 0,
+ *                       normal a = L_i - T_i D_i
+ *     FREDOPT_OBJ_DOSE  Eq. (2) PTV term   w_obj_i (dose_target_i - d_i)^2
+ *     FREDOPT_OBJ_CDL   Eq. (2) OAR term   w_obj_i (cdl_target_i - c l_i)^2
+ *
+ * Conventions for every call:
+ *  - Device pointers everywhere except fredopt_matrices with on_device = 0 and
+ *    the host structs (problem, params, state) themselves.  Every array of a
+ *    fredopt_problem is a device array of n_rows elements.
+ *  - The caller owns every buffer it passes.  The library keeps no caller pointer
+ *    after a call returns; it reads or writes the caller's arrays only during the
+ *    call (work is enqueued on `stream`; the call returns once the stream work that
+ *    touches caller buffers is enqueued, except where a call is documented as
+ *    synchronising).
+ *  - The device workspace is allocated by the caller (size from
+ *    fredopt_workspace_bytes) and must stay alive and untouched until
+ *    fredopt_free_plan.  The library does not allocate device memory, except a
+ *    temporary staging copy of host matrices during fredopt_load_matrices with
+ *    on_device = 0.
+ *  - `stream` is a hipStream_t (may be the null stream).
+ *  - Every call returns FREDOPT_OK or a negative status; on error nothing the
+ *    caller owns has been modified and fredopt_last_error() describes the cause.
+ *  - Calls on one plan must not overlap; calls on distinct plans are independent.
+ */
+#ifndef FREDOPT_H
+#define FREDOPT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FREDOPT_OK = 0,
+  FREDOPT_E_ARG = -1,        /* null pointer, parameter out of range            */
+  FREDOPT_E_SHAPE = -2,      /* inconsistent sizes or row pointers              */
+  FREDOPT_E_INDEX = -3,      /* column index out of range or not increasing     */
+  FREDOPT_E_NONFINITE = -4,  /* NaN/Inf or negative influence value, or a NaN/Inf
+                                produced during an iteration                     */
+  FREDOPT_E_WORKSPACE = -5,  /* workspace too small or misaligned               */
+  FREDOPT_E_DEVICE = -6,     /* HIP runtime error                               */
+  FREDOPT_E_STATE = -7,      /* invalid solver state (k < 0, s < -1)            */
+  FREDOPT_E_NOT_IMPLEMENTED = -8
+} fredopt_status;
+
+typedef enum { FREDOPT_F32 = 0, FREDOPT_F16 = 1, FREDOPT_BF16 = 2 } fredopt_dtype;
+
+#define FREDOPT_DOSE_LO 0x01u
+#define FREDOPT_DOSE_HI 0x02u
+#define FREDOPT_CDL_LO 0x04u
+#define FREDOPT_CDL_HI 0x08u
+#define FREDOPT_LETD_HI 0x10u
+#define FREDOPT_OBJ_DOSE 0x20u
+#define FREDOPT_OBJ_CDL 0x40u
+
+/* Normalisation of the simultaneous projection weights (the paper's Fig. 2 is
+ * sequential; its text says the projections run in parallel, Section 1):
+ * wt_i = weight_scale * w_i / W with W = sum of w over every enabled (row, kind)
+ * (CONVEX_ALL, Cimmino weights), over the violated ones (CONVEX_VIOLATED), or 1 (RAW). */
+#define FREDOPT_NORM_CONVEX_ALL 0
+#define FREDOPT_NORM_CONVEX_VIOLATED 1
+#define FREDOPT_NORM_RAW 2
+
+typedef struct fredopt_plan fredopt_plan; /* opaque; created by load, freed by free */
+
+/* Influence matrices in CSR with one sparsity pattern shared by D and L
+ * (Section 2.2: an influence matrix per quantity, per pencil beam, sparse).
+ *   row_ptr[n_rows + 1]: row_ptr[0] = 0, non-decreasing, row_ptr[n_rows] = nnz
+ *   col_idx[nnz]: in [0, n_cols), strictly increasing within a row
+ *   d_val[nnz], l_val[nnz]: finite and >= 0
+ * storage selects the device value format: FP32, or FP16 / BF16 with one FP32
+ * scale per column (scale_j = max over the column of max(D_ij, L_ij)); products
+ * always accumulate in FP32. */
+typedef struct {
+  int64_t n_rows, n_cols, nnz;
+  const int64_t *row_ptr;
+  const int32_t *col_idx;
+  const float *d_val;
+  const float *l_val;
+  int32_t storage;   /* fredopt_dtype */
+  int32_t on_device; /* 1: the four arrays are device pointers, 0: host pointers */
+} fredopt_matrices;
+
+/* Per-row bounds, priorities and objective data (Fig. 2, its caption, Eq. 2).
+ * All arrays are device arrays of n_rows elements; entries whose kind bit is not
+ * set are ignored.  w_feas is the AMS priority w_i (> 0), w_obj the Eq. (2) weight
+ * (>= 0). */
+typedef struct {
+  const uint16_t *kind;
+  const float *dose_lo, *dose_hi, *cdl_lo, *cdl_hi, *letd_max;
+  const float *w_feas, *w_obj, *dose_target, *cdl_target;
+  double c; /* um/keV, > 0; 0.04 in the paper (Section 2.4) */
+} fredopt_problem;
+
+/* Parameters of Figs. 2-3: relaxation lambda in (0, 2] (Fig. 2 caption), step base
+ * alpha in (0, 1) and weight decay eta in (0, 1] (text after Fig. 3; eta = 1 is
+ * accepted for testing), reductions_n >= 0 perturbations per outer iteration
+ * (0 = feasibility seeking only), iter_max outer iterations for fredopt_solve. */
+typedef struct {
+  double lambda, alpha, eta;
+  int32_t reductions_n;
+  int32_t iter_max;
+  int32_t normalization; /* FREDOPT_NORM_* */
+  int32_t reserved;      /* must be 0 */
+} fredopt_params;
+
+/* Solver state of Fig. 3: outer counter k (weights eta^k w) and the global step
+ * exponent s (beta = alpha^s, never reset).  A fresh solve starts from k = 0,
+ * s = -1.  The remaining fields are outputs of the last outer iteration. */
+typedef struct {
+  int64_t k, s;
+  int64_t n_violated;      /* violated constraints at the AMS input point       */
+  double beta;             /* last accepted step (0 if none)                    */
+  double cost;             /* Eq. (2) at the start of the last outer iteration  */
+  double cost_perturbed;   /* Eq. (2) at the perturbed point fed to AMS         */
+  double proximity;        /* 1/2 sum (w_i / W_all) v_i^2 / ||a_i||^2 at that point */
+  double grad_sq;          /* ||grad chi^2||^2 of the last perturbation         */
+  double q;                /* sum w (D g)^2 + sum w c^2 (L g)^2 of that direction */
+} fredopt_state;
+
+/* Bytes of device workspace a plan of this size needs (an upper bound valid for
+ * every sparsity pattern with these sizes).  Returns 0 for invalid sizes. */
+size_t fredopt_workspace_bytes(int64_t n_rows, int64_t n_cols, int64_t nnz, int32_t storage);
+
+/* Table 2 step (iii): validate the CSR, copy it to the workspace in the device
+ * layout (row-padded CSR with shared indices and planar D/L values, plus a CSC copy
+ * with rows ascending in every column for the transposed products), compute the
+ * per-row FP64 moments sum D^2, sum L^2, sum D L, and return a plan.  `workspace`
+ * must be 256-byte aligned device memory of at least
+ * fredopt_workspace_bytes(...) bytes.  Synchronises `stream`. */
+fredopt_status fredopt_load_matrices(const fredopt_matrices *m, void *workspace,
+                                     size_t workspace_bytes, void *stream,
+                                     fredopt_plan **out);
+
+/* Releases the host side of a plan (the caller then frees the workspace). */
+fredopt_status fredopt_free_plan(fredopt_plan *p);
+
+/* d = D x, LETd = l / d (0 where d = 0) and cDL = c l (Eq. 1, Section 2.4) for a
+ * device fluence x[n_cols].  Outputs are device arrays of n_rows floats; any of
+ * them may be NULL.  Asynchronous on `stream`. */
+fredopt_status fredopt_dose_let(fredopt_plan *p, const float *x, double c, float *dose,
+                                float *letd, float *cdl, void *stream);
+
+/* One simultaneous relaxed-projection sweep (the parallel form of Fig. 2) at the
+ * device fluence x_inout[n_cols], in place: every violated half-space contributes
+ * lambda * wt_i * v_i / ||a_i||^2 * a_i with wt_i = weight_scale * w_i / W, the
+ * contributions are summed, and x is clamped to >= 0.  *proximity_out (nullable)
+ * receives the proximity of the input point.  Synchronises `stream`. */
+fredopt_status fredopt_project_sweep(fredopt_plan *p, const fredopt_problem *pr,
+                                     const fredopt_params *q, double weight_scale,
+                                     float *x_inout, double *proximity_out, void *stream);
+
+/* One outer iteration k of Fig. 3 from state *st (in/out): reductions_n gradient
+ * perturbations of Eq. (2) with beta = alpha^s, s the smallest integer above the
+ * previous s for which the cost strictly decreases, then one sweep with weights
+ * eta^k w applied to the perturbed point; k += 1.  Synchronises `stream`. */
+fredopt_status fredopt_superiorize_step(fredopt_plan *p, const fredopt_problem *pr,
+                                        const fredopt_params *q, fredopt_state *st,
+                                        float *x_inout, void *stream);
+
+/* q->iter_max outer iterations of fredopt_superiorize_step, captured once as a
+ * HIP graph and replayed with all step decisions made on the device.  Resumable:
+ * continuing from the returned state reproduces an uninterrupted run bit for bit.
+ * Synchronises `stream`. */
+fredopt_status fredopt_solve(fredopt_plan *p, const fredopt_problem *pr,
+                             const fredopt_params *q, fredopt_state *st, float *x_inout,
+                             void *stream);
+
+/* Thread-local description of the last failing call on this thread. */
+const char *fredopt_last_error(void);
+
+/* ---- introspection and measurement ------------------------------------------ */
+
+typedef struct {
+  int64_t n_rows, n_cols, nnz;
+  int64_t csr_slots, csc_slots;  /* stored entries including row / column padding */
+  int64_t bytes_per_csr_slot, bytes_per_csc_slot;
+  int64_t fwd_items, tr_items, row_items;
+  int32_t storage, lanes_per_row, fwd_grid, tr_chunk;
+  int32_t lds_x; /* 1 if the forward kernels stage the vector in LDS */
+  int32_t reserved;
+} fredopt_plan_info;
+
+fredopt_status fredopt_get_plan_info(const fredopt_plan *p, fredopt_plan_info *info);
+
+/* Kernel identifiers of one outer iteration, in launch order. */
+#define FREDOPT_KERNEL_FWD_OBJ 0   /* d, l and Eq. (2) coefficients at x        */
+#define FREDOPT_KERNEL_TR_GRAD 1   /* g = grad chi^2 (transposed product)       */
+#define FREDOPT_KERNEL_FWD_DIR 2   /* D g, L g, Q and the step decision         */
+#define FREDOPT_KERNEL_ROWS 3      /* move d, l; constraint residuals           */
+#define FREDOPT_KERNEL_TR_PROJ 4   /* transposed projection, update, clamp      */
+#define FREDOPT_KERNEL_FWD_RESID 5 /* d, l and residuals (reductions_n = 0)     */
+#define FREDOPT_NUM_KERNELS 6
+
+/* Runs n_iters outer iterations (as fredopt_superiorize_step would) launching each
+ * kernel separately with HIP events around it on `stream`, and writes the mean
+ * duration in milliseconds of every kernel id to ms_out[FREDOPT_NUM_KERNELS]
+ * (0 for kernels not launched) and the launch count to count_out (nullable).
+ * Advances *st and x like the same number of steps.  Synchronises `stream`. */
+fredopt_status fredopt_profile_kernels(fredopt_plan *p, const fredopt_problem *pr,
+                                       const fredopt_params *q, fredopt_state *st,
+                                       float *x_inout, int32_t n_iters, void *stream,
+                                       double *ms_out, int64_t *count_out);
+
+/* Autotuner: times the candidate lanes-per-row widths of the forward kernel and
+ * chunk sizes of the transposed kernel on this plan (the plan's own matrices,
+ * fluence x) and keeps the fastest.  Synchronises `stream`. */
+fredopt_status fredopt_autotune(fredopt_plan *p, const float *x, void *stream);
+
+/* Sets the lanes-per-row width (4, 8, 16, 32 or 64) and transposed chunk size
+ * (nnz per work item, multiple of 1024) explicitly; 0 keeps the current value. */
+fredopt_status fredopt_set_tuning(fredopt_plan *p, int32_t lanes_per_row, int32_t tr_chunk);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FREDOPT_H */

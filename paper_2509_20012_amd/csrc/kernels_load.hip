@@ -1,0 +1,301 @@
+// Load-time kernels: the device side of Table 2 step (iii) of Borys et al.
+// (arXiv 2509.20012), loading the dose and LETd influence matrices.  They
+// validate the CSR input, build the row-padded CSR used by the forward kernels,
+// build the CSC copy (rows ascending inside every column, so the transposed
+// products are deterministic) with a row-block counting sort, quantise values for
+// 16-bit storage, and compute the per-row FP64 moments sum D^2, sum L^2, sum D L
+// that give the projection denominators of Fig. 2.
+#include "fredopt_device.h"
+#include "kernels.h"
+
+#include <math.h>
+
+namespace fo {
+
+namespace {
+
+constexpr int kRowsPerWg = kBlock / kWave;  // one wavefront per row
+
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
+  const uint32_t u = __float_as_uint(f);
+  const uint32_t r = u + 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(r >> 16);
+}
+
+__device__ __forceinline__ void store_value(int vtype, void* base, int64_t pos, float v,
+                                            float scale) {
+  if (vtype == kF32) {
+    static_cast<float*>(base)[pos] = v;
+  } else if (vtype == kF16) {
+    static_cast<_Float16*>(base)[pos] = (_Float16)(v / scale);
+  } else {
+    static_cast<uint16_t*>(base)[pos] = f32_to_bf16_rne(v / scale);
+  }
+}
+
+__device__ __forceinline__ double load_value(int vtype, const void* base, int64_t pos) {
+  if (vtype == kF32) return static_cast<const float*>(base)[pos];
+  if (vtype == kF16) return (double)(float)static_cast<const _Float16*>(base)[pos];
+  return (double)__uint_as_float((uint32_t)static_cast<const uint16_t*>(base)[pos] << 16);
+}
+
+__global__ __launch_bounds__(kBlock) void k_validate(int64_t R, int64_t C,
+                                                     const int64_t* __restrict__ row_ptr,
+                                                     const int32_t* __restrict__ col,
+                                                     const float* __restrict__ dv,
+                                                     const float* __restrict__ lv,
+                                                     uint32_t* flags) {
+  const int64_t row = (int64_t)blockIdx.x * kRowsPerWg + threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  if (row >= R) return;
+  const int64_t a = row_ptr[row], b = row_ptr[row + 1];
+  uint32_t f = 0;
+  for (int64_t k = a + lane; k < b; k += kWave) {
+    const int32_t c = col[k];
+    if (c < 0 || (int64_t)c >= C) f |= 1u;
+    if (k > a && !(col[k - 1] < c)) f |= 2u;
+    const float d = dv[k], l = lv[k];
+    if (!isfinite(d) || !isfinite(l) || d < 0.f || l < 0.f) f |= 4u;
+  }
+  if (f) atomicOr(flags, f);
+}
+
+__global__ __launch_bounds__(kBlock) void k_col_stats(int64_t nnz, const int32_t* __restrict__ col,
+                                                      const float* __restrict__ dv,
+                                                      const float* __restrict__ lv,
+                                                      uint32_t* col_count,
+                                                      uint32_t* col_max_bits) {
+  for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < nnz;
+       k += (int64_t)gridDim.x * kBlock) {
+    const int32_t c = col[k];
+    atomicAdd(&col_count[c], 1u);
+    if (col_max_bits) {
+      const float m = fmaxf(dv[k], lv[k]);  // both >= 0: bit patterns order like values
+      atomicMax(&col_max_bits[c], __float_as_uint(m));
+    }
+  }
+}
+
+__global__ void k_col_scale(int64_t C, const uint32_t* __restrict__ bits, float* scale) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= C) return;
+  const float m = __uint_as_float(bits[j]);
+  scale[j] = m > 0.f ? m : 1.f;
+}
+
+__global__ __launch_bounds__(kBlock) void k_pack_csr(int vtype, int64_t R,
+                                                     const int64_t* __restrict__ row_ptr,
+                                                     const int32_t* __restrict__ col,
+                                                     const float* __restrict__ dv,
+                                                     const float* __restrict__ lv,
+                                                     const float* __restrict__ scale,
+                                                     const int64_t* __restrict__ rp,
+                                                     int32_t* ci, void* pdv, void* plv) {
+  const int64_t row = (int64_t)blockIdx.x * kRowsPerWg + threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  if (row >= R) return;
+  const int64_t a = row_ptr[row], n = row_ptr[row + 1] - a;
+  const int64_t o = rp[row], np = rp[row + 1] - o;
+  for (int64_t t = lane; t < np; t += kWave) {
+    if (t < n) {
+      const int32_t c = col[a + t];
+      const float s = scale ? scale[c] : 1.f;
+      ci[o + t] = c;
+      store_value(vtype, pdv, o + t, dv[a + t], s);
+      store_value(vtype, plv, o + t, lv[a + t], s);
+    } else {  // padding slot: index 0, value 0
+      ci[o + t] = 0;
+      store_value(vtype, pdv, o + t, 0.f, 1.f);
+      store_value(vtype, plv, o + t, 0.f, 1.f);
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_block_count(int64_t R, int64_t C, int rows_per_block,
+                                                        const int64_t* __restrict__ row_ptr,
+                                                        const int32_t* __restrict__ col,
+                                                        uint32_t* bc) {
+  const int64_t row = (int64_t)blockIdx.x * kRowsPerWg + threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  if (row >= R) return;
+  const int64_t b = row / rows_per_block;
+  uint32_t* base = bc + b * C;
+  for (int64_t k = row_ptr[row] + lane; k < row_ptr[row + 1]; k += kWave)
+    atomicAdd(&base[col[k]], 1u);
+}
+
+// counts per (row block, column) -> first CSC slot of that block inside the column
+__global__ void k_block_offsets(int64_t C, int nb, const int64_t* __restrict__ cp, uint32_t* bc) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= C) return;
+  uint32_t run = (uint32_t)cp[j];
+  for (int b = 0; b < nb; ++b) {
+    const uint32_t t = bc[(int64_t)b * C + j];
+    bc[(int64_t)b * C + j] = run;
+    run += t;
+  }
+}
+
+// One workgroup per row block; its rows are visited in ascending order, the entries
+// of one row in parallel (a row's columns are distinct, so no two lanes share a
+// cursor), with a barrier between rows.  Inside every column the rows therefore come
+// out ascending, independent of scheduling.
+__global__ __launch_bounds__(kBlock) void k_fill_csc(int vtype, int64_t R, int64_t C,
+                                                     int rows_per_block,
+                                                     const int64_t* __restrict__ row_ptr,
+                                                     const int32_t* __restrict__ col,
+                                                     const float* __restrict__ dv,
+                                                     const float* __restrict__ lv,
+                                                     const float* __restrict__ scale,
+                                                     uint32_t* bc, int32_t* ri, void* cdv,
+                                                     void* clv) {
+  const int64_t b = blockIdx.x;
+  const int64_t r0 = b * rows_per_block;
+  int64_t r1 = r0 + rows_per_block;
+  if (r1 > R) r1 = R;
+  uint32_t* cur = bc + b * C;
+  for (int64_t row = r0; row < r1; ++row) {
+    for (int64_t k = row_ptr[row] + threadIdx.x; k < row_ptr[row + 1]; k += kBlock) {
+      const int32_t c = col[k];
+      const uint32_t pos = atomicAdd(&cur[c], 1u);
+      const float s = scale ? scale[c] : 1.f;
+      ri[pos] = (int32_t)row;
+      store_value(vtype, cdv, pos, dv[k], s);
+      store_value(vtype, clv, pos, lv[k], s);
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_moments(int vtype, int64_t R,
+                                                    const int64_t* __restrict__ rp,
+                                                    const void* __restrict__ pdv,
+                                                    const void* __restrict__ plv,
+                                                    const int32_t* __restrict__ ci,
+                                                    const float* __restrict__ scale,
+                                                    double* mom) {
+  const int64_t row = (int64_t)blockIdx.x * kRowsPerWg + threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  if (row >= R) return;
+  double sdd = 0.0, sll = 0.0, sdl = 0.0;
+  for (int64_t k = rp[row] + lane; k < rp[row + 1]; k += kWave) {
+    const double s = scale ? (double)scale[ci[k]] : 1.0;
+    const double d = load_value(vtype, pdv, k) * s;
+    const double l = load_value(vtype, plv, k) * s;
+    sdd += d * d;
+    sll += l * l;
+    sdl += d * l;
+  }
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    sdd += __shfl_xor(sdd, o);
+    sll += __shfl_xor(sll, o);
+    sdl += __shfl_xor(sdl, o);
+  }
+  if (lane == 0) {
+    mom[3 * row] = sdd;
+    mom[3 * row + 1] = sll;
+    mom[3 * row + 2] = sdl;
+  }
+}
+
+// flags: 1 non-finite bound/weight/target of an enabled kind, 2 lower > upper bound,
+// 4 non-positive AMS weight or negative objective weight, 8 unknown kind bits
+__global__ void k_check_problem(int64_t R, const uint16_t* __restrict__ kind,
+                                const float* __restrict__ dlo, const float* __restrict__ dhi,
+                                const float* __restrict__ clo, const float* __restrict__ chi,
+                                const float* __restrict__ tmax, const float* __restrict__ wf,
+                                const float* __restrict__ wo, const float* __restrict__ dt,
+                                const float* __restrict__ ct, uint32_t* flags) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < R;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    const unsigned k = kind[r];
+    uint32_t f = 0;
+    if (k & ~0x7Fu) f |= 8u;
+    if (k & kDoseLo && !isfinite(dlo[r])) f |= 1u;
+    if (k & kDoseHi && !isfinite(dhi[r])) f |= 1u;
+    if (k & kCdlLo && !isfinite(clo[r])) f |= 1u;
+    if (k & kCdlHi && !isfinite(chi[r])) f |= 1u;
+    if (k & kLetdHi && !isfinite(tmax[r])) f |= 1u;
+    if ((k & (kDoseLo | kDoseHi)) == (kDoseLo | kDoseHi) && dlo[r] > dhi[r]) f |= 2u;
+    if ((k & (kCdlLo | kCdlHi)) == (kCdlLo | kCdlHi) && clo[r] > chi[r]) f |= 2u;
+    if (k & kConstraintBits) {
+      const float w = wf[r];
+      if (!isfinite(w) || !(w > 0.f)) f |= 4u;
+    }
+    if (k & (kObjDose | kObjCdl)) {
+      const float w = wo[r];
+      if (!isfinite(w) || w < 0.f) f |= 4u;
+      if (k & kObjDose && !isfinite(dt[r])) f |= 1u;
+      if (k & kObjCdl && !isfinite(ct[r])) f |= 1u;
+    }
+    if (f) atomicOr(flags, f);
+  }
+}
+
+inline unsigned row_grid(int64_t R) { return (unsigned)((R + kRowsPerWg - 1) / kRowsPerWg); }
+
+}  // namespace
+
+void launch_validate(int64_t R, int64_t C, const int64_t* row_ptr, const int32_t* col,
+                     const float* dv, const float* lv, uint32_t* flags, hipStream_t s) {
+  if (R > 0) k_validate<<<row_grid(R), kBlock, 0, s>>>(R, C, row_ptr, col, dv, lv, flags);
+}
+
+void launch_col_stats(int64_t nnz, const int64_t* /*row_ptr*/, const int32_t* col,
+                      const float* dv, const float* lv, uint32_t* col_count,
+                      uint32_t* col_max_bits, hipStream_t s) {
+  if (nnz <= 0) return;
+  int64_t g = (nnz + kBlock - 1) / kBlock;
+  if (g > 65536) g = 65536;
+  k_col_stats<<<(unsigned)g, kBlock, 0, s>>>(nnz, col, dv, lv, col_count, col_max_bits);
+}
+
+void launch_col_scale(int64_t C, const uint32_t* bits, float* scale, hipStream_t s) {
+  if (C > 0) k_col_scale<<<(unsigned)((C + 255) / 256), 256, 0, s>>>(C, bits, scale);
+}
+
+void launch_pack_csr(int vtype, int64_t R, const int64_t* row_ptr, const int32_t* col,
+                     const float* dv, const float* lv, const float* scale, const int64_t* rp,
+                     int32_t* ci, void* pdv, void* plv, hipStream_t s) {
+  if (R > 0)
+    k_pack_csr<<<row_grid(R), kBlock, 0, s>>>(vtype, R, row_ptr, col, dv, lv, scale, rp, ci,
+                                               pdv, plv);
+}
+
+void launch_block_count(int64_t R, int64_t C, int rows_per_block, const int64_t* row_ptr,
+                        const int32_t* col, uint32_t* bc, hipStream_t s) {
+  if (R > 0)
+    k_block_count<<<row_grid(R), kBlock, 0, s>>>(R, C, rows_per_block, row_ptr, col, bc);
+}
+
+void launch_block_offsets(int64_t C, int nb, const int64_t* cp, uint32_t* bc, hipStream_t s) {
+  if (C > 0) k_block_offsets<<<(unsigned)((C + 255) / 256), 256, 0, s>>>(C, nb, cp, bc);
+}
+
+void launch_fill_csc(int vtype, int64_t R, int64_t C, int rows_per_block,
+                     const int64_t* row_ptr, const int32_t* col, const float* dv,
+                     const float* lv, const float* scale, uint32_t* bc, int32_t* ri,
+                     void* cdv, void* clv, hipStream_t s) {
+  if (R <= 0) return;
+  const unsigned nb = (unsigned)((R + rows_per_block - 1) / rows_per_block);
+  k_fill_csc<<<nb, kBlock, 0, s>>>(vtype, R, C, rows_per_block, row_ptr, col, dv, lv, scale, bc,
+                                    ri, cdv, clv);
+}
+
+void launch_moments(int vtype, int64_t R, const int64_t* rp, const void* pdv, const void* plv,
+                    const int32_t* ci, const float* scale, double* mom, hipStream_t s) {
+  if (R > 0) k_moments<<<row_grid(R), kBlock, 0, s>>>(vtype, R, rp, pdv, plv, ci, scale, mom);
+}
+
+void launch_check_problem(int64_t R, const uint16_t* kind, const float* dlo, const float* dhi,
+                          const float* clo, const float* chi, const float* tmax,
+                          const float* wf, const float* wo, const float* dt, const float* ct,
+                          uint32_t* flags, hipStream_t s) {
+  if (R <= 0) return;
+  int64_t g = (R + 255) / 256;
+  if (g > 16384) g = 16384;
+  k_check_problem<<<(unsigned)g, 256, 0, s>>>(R, kind, dlo, dhi, clo, chi, tmax, wf, wo, dt, ct,
+                                               flags);
+}
+
+}  // namespace fo

@@ -1,0 +1,323 @@
+"""Thin Python binding of the fredopt C ABI (include/fredopt.h).
+
+Argument marshalling only: every step of the optimizer runs in the HIP kernels of
+``libfredopt.so``.  PyTorch provides device memory (the workspace and the
+problem arrays) and the current HIP stream.  If the library is missing the import
+of a function fails loudly; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import dataclasses
+import os
+from typing import Dict, Optional, Sequence
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libfredopt.so")
+
+F32, F16, BF16 = 0, 1, 2
+STORAGE = {"f32": F32, "fp32": F32, "f16": F16, "fp16": F16, "bf16": BF16}
+NORM_CONVEX_ALL, NORM_CONVEX_VIOLATED, NORM_RAW = 0, 1, 2
+KERNEL_NAMES = ("fwd_obj", "tr_grad", "fwd_dir", "rows", "tr_proj", "fwd_resid")
+
+STATUS = {0: "OK", -1: "E_ARG", -2: "E_SHAPE", -3: "E_INDEX", -4: "E_NONFINITE",
+          -5: "E_WORKSPACE", -6: "E_DEVICE", -7: "E_STATE", -8: "E_NOT_IMPLEMENTED"}
+
+
+class FredoptError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+
+
+class Matrices(ct.Structure):
+    _fields_ = [("n_rows", ct.c_int64), ("n_cols", ct.c_int64), ("nnz", ct.c_int64),
+                ("row_ptr", ct.c_void_p), ("col_idx", ct.c_void_p),
+                ("d_val", ct.c_void_p), ("l_val", ct.c_void_p),
+                ("storage", ct.c_int32), ("on_device", ct.c_int32)]
+
+
+class Problem(ct.Structure):
+    _fields_ = [("kind", ct.c_void_p), ("dose_lo", ct.c_void_p), ("dose_hi", ct.c_void_p),
+                ("cdl_lo", ct.c_void_p), ("cdl_hi", ct.c_void_p), ("letd_max", ct.c_void_p),
+                ("w_feas", ct.c_void_p), ("w_obj", ct.c_void_p),
+                ("dose_target", ct.c_void_p), ("cdl_target", ct.c_void_p),
+                ("c", ct.c_double)]
+
+
+class Params(ct.Structure):
+    _fields_ = [("lambda_", ct.c_double), ("alpha", ct.c_double), ("eta", ct.c_double),
+                ("reductions_n", ct.c_int32), ("iter_max", ct.c_int32),
+                ("normalization", ct.c_int32), ("reserved", ct.c_int32)]
+
+
+class State(ct.Structure):
+    _fields_ = [("k", ct.c_int64), ("s", ct.c_int64), ("n_violated", ct.c_int64),
+                ("beta", ct.c_double), ("cost", ct.c_double), ("cost_perturbed", ct.c_double),
+                ("proximity", ct.c_double), ("grad_sq", ct.c_double), ("q", ct.c_double)]
+
+    def as_dict(self) -> Dict[str, float]:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class PlanInfo(ct.Structure):
+    _fields_ = [("n_rows", ct.c_int64), ("n_cols", ct.c_int64), ("nnz", ct.c_int64),
+                ("csr_slots", ct.c_int64), ("csc_slots", ct.c_int64),
+                ("bytes_per_csr_slot", ct.c_int64), ("bytes_per_csc_slot", ct.c_int64),
+                ("fwd_items", ct.c_int64), ("tr_items", ct.c_int64), ("row_items", ct.c_int64),
+                ("storage", ct.c_int32), ("lanes_per_row", ct.c_int32),
+                ("fwd_grid", ct.c_int32), ("tr_chunk", ct.c_int32), ("lds_x", ct.c_int32),
+                ("reserved", ct.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+EXPORTED = ("fredopt_workspace_bytes", "fredopt_load_matrices", "fredopt_free_plan",
+            "fredopt_dose_let", "fredopt_project_sweep", "fredopt_superiorize_step",
+            "fredopt_solve", "fredopt_last_error", "fredopt_get_plan_info",
+            "fredopt_profile_kernels", "fredopt_autotune", "fredopt_set_tuning")
+
+_lib = None
+
+
+def lib():
+    """The loaded HIP library.  Raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise FileNotFoundError(
+                f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                "(the optimizer has no CPU fallback)")
+        L = ct.CDLL(LIB_PATH)
+        P, PP = ct.c_void_p, ct.POINTER(ct.c_void_p)
+        L.fredopt_workspace_bytes.argtypes = [ct.c_int64, ct.c_int64, ct.c_int64, ct.c_int32]
+        L.fredopt_workspace_bytes.restype = ct.c_size_t
+        L.fredopt_load_matrices.argtypes = [ct.POINTER(Matrices), P, ct.c_size_t, P, PP]
+        L.fredopt_free_plan.argtypes = [P]
+        L.fredopt_dose_let.argtypes = [P, P, ct.c_double, P, P, P, P]
+        L.fredopt_project_sweep.argtypes = [P, ct.POINTER(Problem), ct.POINTER(Params),
+                                            ct.c_double, P, ct.POINTER(ct.c_double), P]
+        L.fredopt_superiorize_step.argtypes = [P, ct.POINTER(Problem), ct.POINTER(Params),
+                                               ct.POINTER(State), P, P]
+        L.fredopt_solve.argtypes = [P, ct.POINTER(Problem), ct.POINTER(Params),
+                                    ct.POINTER(State), P, P]
+        L.fredopt_last_error.restype = ct.c_char_p
+        L.fredopt_get_plan_info.argtypes = [P, ct.POINTER(PlanInfo)]
+        L.fredopt_profile_kernels.argtypes = [P, ct.POINTER(Problem), ct.POINTER(Params),
+                                              ct.POINTER(State), P, ct.c_int32, P,
+                                              ct.POINTER(ct.c_double), ct.POINTER(ct.c_int64)]
+        L.fredopt_autotune.argtypes = [P, P, P]
+        L.fredopt_set_tuning.argtypes = [P, ct.c_int32, ct.c_int32]
+        for name in EXPORTED:
+            if name not in ("fredopt_workspace_bytes", "fredopt_last_error"):
+                getattr(L, name).restype = ct.c_int
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().fredopt_last_error().decode()
+
+
+def _check(status: int):
+    if status != 0:
+        raise FredoptError(status, last_error())
+
+
+def _torch():
+    import torch  # noqa: WPS433  (device memory and streams only)
+    return torch
+
+
+def _stream(stream=None) -> int:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else int(t.data_ptr())
+
+
+def workspace_bytes(n_rows: int, n_cols: int, nnz: int, storage: int = F32) -> int:
+    return int(lib().fredopt_workspace_bytes(n_rows, n_cols, nnz, storage))
+
+
+@dataclasses.dataclass
+class SolverParams:
+    """Parameters of Figs. 2-3 (defaults documented in the design doc's readings)."""
+    lam: float = 1.0
+    alpha: float = 0.99
+    eta: float = 0.999
+    reductions_n: int = 1
+    iter_max: int = 100
+    normalization: int = NORM_CONVEX_ALL
+
+    def struct(self) -> Params:
+        return Params(lambda_=self.lam, alpha=self.alpha, eta=self.eta,
+                      reductions_n=self.reductions_n, iter_max=self.iter_max,
+                      normalization=self.normalization, reserved=0)
+
+
+class DeviceProblem:
+    """Per-row problem arrays resident on the device."""
+
+    def __init__(self, arrays: Dict[str, np.ndarray], c: float, device="cuda"):
+        torch = _torch()
+        self.c = float(c)
+        self.t = {}
+        for k in ("dose_lo", "dose_hi", "cdl_lo", "cdl_hi", "letd_max", "w_feas", "w_obj",
+                  "dose_target", "cdl_target"):
+            self.t[k] = torch.from_numpy(np.ascontiguousarray(arrays[k], np.float32)).to(device)
+        kind = np.ascontiguousarray(arrays["kind"], np.uint16).view(np.int16)
+        self.t["kind"] = torch.from_numpy(kind).to(device)
+
+    def struct(self) -> Problem:
+        return Problem(**{k: _ptr(v) for k, v in self.t.items()}, c=self.c)
+
+
+class Plan:
+    """A loaded pair of influence matrices (owns its device workspace)."""
+
+    def __init__(self, handle: ct.c_void_p, ws, n_rows: int, n_cols: int, nnz: int,
+                 storage: int, keep=()):
+        self._h = handle
+        self.ws = ws
+        self.n_rows, self.n_cols, self.nnz, self.storage = n_rows, n_cols, nnz, storage
+        self._keep = keep
+
+    @property
+    def handle(self):
+        return self._h
+
+    def free(self):
+        if self._h:
+            _check(lib().fredopt_free_plan(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            if self._h and _lib is not None:
+                _lib.fredopt_free_plan(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+    def info(self) -> Dict[str, int]:
+        inf = PlanInfo()
+        _check(lib().fredopt_get_plan_info(self._h, ct.byref(inf)))
+        return inf.as_dict()
+
+
+def load_matrices(row_ptr, col_idx, d_val, l_val, n_cols: int, storage: int = F32,
+                  device="cuda", stream=None, on_device: bool = True) -> Plan:
+    """Loads CSR influence matrices.  With on_device=True the arrays are copied to
+    the device with torch first (the library then reads device pointers); with
+    on_device=False host arrays are handed to the library, which stages them."""
+    torch = _torch()
+    row_ptr = np.ascontiguousarray(row_ptr, np.int64)
+    col_idx = np.ascontiguousarray(col_idx, np.int32)
+    d_val = np.ascontiguousarray(d_val, np.float32)
+    l_val = np.ascontiguousarray(l_val, np.float32)
+    R = row_ptr.size - 1
+    nnz = int(row_ptr[-1]) if R >= 0 and row_ptr.size else 0
+    nbytes = workspace_bytes(R, n_cols, nnz, storage)
+    if nbytes == 0:
+        raise FredoptError(-2, f"invalid sizes rows={R} cols={n_cols} nnz={nnz}")
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+    keep = ()
+    if on_device:
+        tens = [torch.from_numpy(a).to(device) for a in (row_ptr, col_idx, d_val, l_val)]
+        m = Matrices(R, n_cols, nnz, *[_ptr(t) for t in tens], storage, 1)
+        keep = tens
+    else:
+        m = Matrices(R, n_cols, nnz, row_ptr.ctypes.data, col_idx.ctypes.data,
+                     d_val.ctypes.data, l_val.ctypes.data, storage, 0)
+    h = ct.c_void_p()
+    _check(lib().fredopt_load_matrices(ct.byref(m), _ptr(ws), nbytes, _stream(stream),
+                                       ct.byref(h)))
+    del keep  # input arrays are no longer referenced after the load
+    return Plan(h, ws, R, n_cols, nnz, storage)
+
+
+def free_plan(plan: Plan):
+    plan.free()
+
+
+def dose_let(plan: Plan, x, c: float = 0.04, stream=None, want=("dose", "letd", "cdl")):
+    """(dose, LETd, cDL) device tensors for the device fluence x."""
+    torch = _torch()
+    outs = {k: (torch.empty(plan.n_rows, dtype=torch.float32, device=x.device)
+                if k in want else None) for k in ("dose", "letd", "cdl")}
+    _check(lib().fredopt_dose_let(plan.handle, _ptr(x), float(c), _ptr(outs["dose"]),
+                                  _ptr(outs["letd"]), _ptr(outs["cdl"]), _stream(stream)))
+    return outs["dose"], outs["letd"], outs["cdl"]
+
+
+def project_sweep(plan: Plan, problem: DeviceProblem, params: SolverParams, x,
+                  weight_scale: float = 1.0, stream=None) -> float:
+    """One simultaneous AMS sweep in place on x; returns the input proximity."""
+    prox = ct.c_double(0.0)
+    pr, q = problem.struct(), params.struct()
+    _check(lib().fredopt_project_sweep(plan.handle, ct.byref(pr), ct.byref(q),
+                                       float(weight_scale), _ptr(x), ct.byref(prox),
+                                       _stream(stream)))
+    return float(prox.value)
+
+
+def superiorize_step(plan: Plan, problem: DeviceProblem, params: SolverParams, state: State,
+                     x, stream=None) -> State:
+    pr, q = problem.struct(), params.struct()
+    _check(lib().fredopt_superiorize_step(plan.handle, ct.byref(pr), ct.byref(q),
+                                          ct.byref(state), _ptr(x), _stream(stream)))
+    return state
+
+
+def solve(plan: Plan, problem: DeviceProblem, params: SolverParams, state: State, x,
+          stream=None) -> State:
+    pr, q = problem.struct(), params.struct()
+    _check(lib().fredopt_solve(plan.handle, ct.byref(pr), ct.byref(q), ct.byref(state),
+                               _ptr(x), _stream(stream)))
+    return state
+
+
+def new_state(k: int = 0, s: int = -1) -> State:
+    st = State()
+    st.k, st.s = k, s
+    return st
+
+
+def profile_kernels(plan: Plan, problem: DeviceProblem, params: SolverParams, state: State,
+                    x, n_iters: int, stream=None):
+    ms = (ct.c_double * 6)()
+    cnt = (ct.c_int64 * 6)()
+    pr, q = problem.struct(), params.struct()
+    _check(lib().fredopt_profile_kernels(plan.handle, ct.byref(pr), ct.byref(q),
+                                         ct.byref(state), _ptr(x), int(n_iters),
+                                         _stream(stream), ms, cnt))
+    return {KERNEL_NAMES[i]: (float(ms[i]), int(cnt[i])) for i in range(6)}
+
+
+def autotune(plan: Plan, x, stream=None):
+    _check(lib().fredopt_autotune(plan.handle, _ptr(x), _stream(stream)))
+    return plan.info()
+
+
+def set_tuning(plan: Plan, lanes_per_row: int = 0, tr_chunk: int = 0):
+    _check(lib().fredopt_set_tuning(plan.handle, int(lanes_per_row), int(tr_chunk)))
+
+
+# ----------------------------------------------------------------------- phantoms
+
+def load_phantom(ph, storage: int = F32, device="cuda", on_device: bool = True):
+    """(Plan, DeviceProblem, x0 device tensor) for a ``phantom.Phantom``."""
+    torch = _torch()
+    plan = load_matrices(ph.row_ptr, ph.col_idx, ph.d_val, ph.l_val, ph.n_cols, storage,
+                         device=device, on_device=on_device)
+    prob = DeviceProblem(ph.problem_arrays(), ph.c, device=device)
+    x0 = torch.from_numpy(np.ascontiguousarray(ph.x0, np.float32)).to(device)
+    return plan, prob, x0

@@ -1,0 +1,86 @@
+"""C ABI checks that need no GPU: the library loads, exports every function that
+include/fredopt.h declares, sizes its workspace, and rejects bad arguments before
+touching the device."""
+import ctypes as ct
+import os
+import re
+
+import pytest
+
+from paper_2509_20012_amd import fredopt
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "fredopt.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fredopt_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_function():
+    L = fredopt.lib()
+    names = _declared()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(fredopt.EXPORTED)
+
+
+def test_workspace_bytes():
+    assert fredopt.workspace_bytes(0, 0, 0) == 0          # no columns
+    assert fredopt.workspace_bytes(-1, 4, 0) == 0
+    assert fredopt.workspace_bytes(10, 4, 5, storage=7) == 0
+    a = fredopt.workspace_bytes(1000, 100, 10_000)
+    b = fredopt.workspace_bytes(1000, 100, 20_000)
+    h = fredopt.workspace_bytes(1000, 100, 20_000, fredopt.F16)
+    assert 0 < a < b and h < b
+    # the matrices alone: two copies of 4-byte indices + two FP32 values per slot
+    assert b >= 2 * 12 * 20_000
+    assert b % 256 == 0
+
+
+def test_null_arguments_rejected_without_device():
+    L = fredopt.lib()
+    assert L.fredopt_load_matrices(None, None, 0, None, None) == -1
+    assert L.fredopt_free_plan(None) == -1
+    assert L.fredopt_dose_let(None, None, 0.04, None, None, None, None) == -1
+    q = fredopt.SolverParams().struct()
+    pr = fredopt.Problem()
+    st = fredopt.State()
+    assert L.fredopt_project_sweep(None, ct.byref(pr), ct.byref(q), 1.0, None, None, None) == -1
+    assert L.fredopt_superiorize_step(None, ct.byref(pr), ct.byref(q), ct.byref(st), None,
+                                      None) == -1
+    assert L.fredopt_solve(None, ct.byref(pr), ct.byref(q), ct.byref(st), None, None) == -1
+    assert L.fredopt_set_tuning(None, 0, 0) == -1
+    assert L.fredopt_autotune(None, None, None) == -1
+    assert L.fredopt_get_plan_info(None, None) == -1
+    assert "NULL" in fredopt.last_error() or "non-NULL" in fredopt.last_error()
+
+
+def test_load_rejects_bad_workspace_before_device_work():
+    import numpy as np
+    L = fredopt.lib()
+    rp = np.array([0, 1], np.int64)
+    ci = np.array([0], np.int32)
+    v = np.array([1.0], np.float32)
+    m = fredopt.Matrices(1, 1, 1, rp.ctypes.data, ci.ctypes.data, v.ctypes.data,
+                         v.ctypes.data, 0, 0)
+    h = ct.c_void_p()
+    assert L.fredopt_load_matrices(ct.byref(m), None, 1 << 20, None, ct.byref(h)) == -5
+    assert L.fredopt_load_matrices(ct.byref(m), ct.c_void_p(256), 16, None, ct.byref(h)) == -5
+    m.storage = 9
+    assert L.fredopt_load_matrices(ct.byref(m), ct.c_void_p(256), 1 << 20, None,
+                                   ct.byref(h)) == -2
+    assert not h.value
+
+
+@pytest.mark.parametrize("field,value", [("lam", 0.0), ("lam", 2.5), ("alpha", 1.0),
+                                         ("eta", 0.0), ("normalization", 5),
+                                         ("reductions_n", -1)])
+def test_param_ranges_documented(field, value):
+    """Parameter ranges from Fig. 2's caption and the text after Fig. 3 are the ones
+    the binding forwards; the library checks them (exercised on the GPU)."""
+    p = fredopt.SolverParams(**{field: value})
+    s = p.struct()
+    assert getattr(s, "lambda_" if field == "lam" else field) == value

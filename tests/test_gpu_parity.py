@@ -1,0 +1,274 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tiers (tolerances of the FP32 path):
+  T1  dose_let with identical inputs: max relative error <= 1e-5 over rows with
+      dose > 0, structurally empty rows exactly 0.
+  T2  one sweep / one outer iteration from the same state: ||x_gpu - x_ref|| /
+      ||x_ref|| <= 1e-5 and the same integer step exponent s.
+  T3  a full solve: PTV D95 and OAR mean LETd within 0.5 %.
+"""
+import numpy as np
+import pytest
+
+from oracle import Oracle, OracleParams
+from paper_2509_20012_amd import metrics
+from paper_2509_20012_amd import phantom as ph
+
+pytestmark = pytest.mark.gpu
+
+T1 = 1e-5
+T2 = 1e-5
+T3 = 5e-3
+
+
+@pytest.fixture(scope="module")
+def fo():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    from paper_2509_20012_amd import fredopt
+    fredopt.lib()  # raises if the library was not built
+    return fredopt
+
+
+@pytest.fixture(scope="module")
+def cfg0():
+    return ph.config0()
+
+
+def _np(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def _rel_rows(gpu, ref, mask=None):
+    ref = np.asarray(ref, np.float64)
+    m = (ref > 0) if mask is None else mask
+    if not m.any():
+        return 0.0
+    return float(np.max(np.abs(gpu[m] - ref[m]) / np.abs(ref[m])))
+
+
+def _params(fo, **kw):
+    return fo.SolverParams(**kw)
+
+
+def _oparams(p):
+    return OracleParams(lam=p.lam, alpha=p.alpha, eta=p.eta, reductions_n=p.reductions_n,
+                        normalization=p.normalization, line_search=1)
+
+
+TINY = [dict(R=1, C=1, density=1.0, seed=1), dict(R=7, C=3, density=0.5, seed=2),
+        dict(R=48, C=12, density=0.3, seed=3), dict(R=300, C=37, density=0.2, seed=4),
+        dict(R=1000, C=130, density=0.05, seed=5),
+        dict(R=64, C=16, density=0.3, seed=6, empty_rows=[0, 5, 63], empty_cols=[3, 15])]
+
+
+@pytest.mark.parametrize("case", TINY, ids=lambda c: f"R{c['R']}C{c['C']}s{c['seed']}")
+@pytest.mark.parametrize("on_device", [True, False])
+def test_dose_let_tiny(fo, case, on_device):
+    import torch
+    p = ph.tiny_problem(**case)
+    print(f"dose_let tiny {case} on_device={on_device}", flush=True)
+    plan, prob, _ = fo.load_phantom(p, on_device=on_device)
+    x = np.random.default_rng(case["seed"]).uniform(0.1, 2.0, p.n_cols).astype(np.float32)
+    xt = torch.from_numpy(x).cuda()
+    dose, letd, cdl = fo.dose_let(plan, xt, p.c)
+    torch.cuda.synchronize()
+    d_ref, l_ref, letd_ref, cdl_ref = Oracle(p).dose_let(x)
+    dg, lg, cg = _np(dose), _np(letd), _np(cdl)
+    assert _rel_rows(dg, d_ref) <= T1
+    assert _rel_rows(lg, letd_ref, d_ref > 0) <= T1
+    assert _rel_rows(cg, cdl_ref) <= T1
+    empty = np.diff(p.row_ptr) == 0
+    assert np.all(dg[empty] == 0.0) and np.all(lg[empty] == 0.0) and np.all(cg[empty] == 0.0)
+
+
+def test_dose_let_config0(fo, cfg0):
+    import torch
+    plan, prob, x0 = fo.load_phantom(cfg0)
+    x = np.random.default_rng(0).uniform(0.0, 2.0, cfg0.n_cols).astype(np.float32)
+    dose, letd, cdl = fo.dose_let(plan, torch.from_numpy(x).cuda(), cfg0.c)
+    torch.cuda.synchronize()
+    d_ref, l_ref, letd_ref, cdl_ref = Oracle(cfg0).dose_let(x)
+    assert _rel_rows(_np(dose), d_ref) <= T1
+    assert _rel_rows(_np(letd), letd_ref, d_ref > 0) <= T1
+    assert _rel_rows(_np(cdl), cdl_ref) <= T1
+    # LETd lies within the LET range of the contributing beamlets (0.5 .. 10 keV/um)
+    lg = _np(letd)[d_ref > 0]
+    assert lg.min() >= 0.5 * (1 - 1e-6) and lg.max() <= 10.0 * (1 + 1e-6)
+
+
+def test_dose_linearity_gpu(fo, cfg0):
+    import torch
+    plan, _, _ = fo.load_phantom(cfg0)
+    rng = np.random.default_rng(1)
+    x1 = rng.uniform(0, 1, cfg0.n_cols).astype(np.float32)
+    x2 = rng.uniform(0, 1, cfg0.n_cols).astype(np.float32)
+    d1 = _np(fo.dose_let(plan, torch.from_numpy(x1).cuda(), want=("dose",))[0])
+    d2 = _np(fo.dose_let(plan, torch.from_numpy(x2).cuda(), want=("dose",))[0])
+    d12 = _np(fo.dose_let(plan, torch.from_numpy(x1 + x2).cuda(), want=("dose",))[0])
+    m = d12 > 0
+    assert np.max(np.abs(d12[m] - d1[m] - d2[m]) / d12[m]) <= 1e-6 * 4
+
+
+@pytest.mark.parametrize("norm", [0, 1, 2])
+@pytest.mark.parametrize("seed", [11, 12])
+def test_project_sweep_tiny(fo, norm, seed):
+    import torch
+    p = ph.tiny_problem(200, 24, 0.2, seed=seed)
+    print(f"project_sweep tiny seed={seed} norm={norm}", flush=True)
+    plan, prob, _ = fo.load_phantom(p)
+    x = np.random.default_rng(seed).uniform(0.5, 1.5, p.n_cols).astype(np.float32)
+    xt = torch.from_numpy(x).cuda()
+    q = _params(fo, lam=1.3, normalization=norm)
+    prox = fo.project_sweep(plan, prob, q, xt, weight_scale=0.9)
+    xr, prox_ref, _ = Oracle(p).ams_simultaneous(x, lam=1.3, weight_scale=0.9, normalization=norm)
+    xg = _np(xt)
+    assert np.linalg.norm(xg - xr) <= T2 * max(np.linalg.norm(xr), 1e-30)
+    assert prox == pytest.approx(prox_ref, rel=1e-4)
+
+
+def test_project_sweep_config0(fo, cfg0):
+    import torch
+    plan, prob, x0 = fo.load_phantom(cfg0)
+    q = _params(fo)
+    o = Oracle(cfg0)
+    x = x0.clone()
+    xr = cfg0.x0.astype(np.float64)
+    for it in range(3):
+        prox = fo.project_sweep(plan, prob, q, x, weight_scale=0.999 ** it)
+        xr, prox_ref, nv = o.ams_simultaneous(xr, lam=1.0, weight_scale=0.999 ** it,
+                                              normalization=0)
+        assert prox == pytest.approx(prox_ref, rel=1e-4)
+    xg = _np(x)
+    assert np.linalg.norm(xg - xr) <= T2 * np.linalg.norm(xr)
+
+
+@pytest.mark.parametrize("r", [0, 1, 2])
+def test_superiorize_step_tiny(fo, r):
+    import torch
+    p = ph.tiny_problem(300, 30, 0.15, seed=21)
+    print(f"superiorize_step tiny r={r}", flush=True)
+    plan, prob, x0 = fo.load_phantom(p)
+    q = _params(fo, alpha=0.9, reductions_n=r)
+    st = fo.new_state()
+    o = Oracle(p)
+    x = x0.clone()
+    xr = p.x0.astype(np.float64)
+    k, s = 0, -1
+    for it in range(5):
+        fo.superiorize_step(plan, prob, q, st, x)
+        xr, k, s, info = o.sa_iteration(xr, k, s, _oparams(q))
+        assert (st.k, st.s) == (k, s), f"iteration {it}"
+        xg = _np(x)
+        assert np.linalg.norm(xg - xr) <= T2 * np.linalg.norm(xr), f"iteration {it}"
+        assert st.proximity == pytest.approx(info["proximity"], rel=1e-3, abs=1e-12)
+        if r:
+            assert st.cost_perturbed < st.cost
+
+
+def test_superiorize_step_config0(fo, cfg0):
+    plan, prob, x0 = fo.load_phantom(cfg0)
+    q = _params(fo)
+    st = fo.new_state()
+    o = Oracle(cfg0)
+    x = x0.clone()
+    xr = cfg0.x0.astype(np.float64)
+    k, s = 0, -1
+    for it in range(3):
+        fo.superiorize_step(plan, prob, q, st, x)
+        xr, k, s, info = o.sa_iteration(xr, k, s, _oparams(q))
+        assert (st.k, st.s) == (k, s)
+        xg = _np(x)
+        assert np.linalg.norm(xg - xr) <= T2 * np.linalg.norm(xr)
+        assert st.cost == pytest.approx(info["cost_before"], rel=1e-5)
+        assert st.grad_sq == pytest.approx(info["grad_sq"], rel=1e-4)
+
+
+def test_solve_config0_plan_quality(fo, cfg0):
+    """T3: 100 superiorized iterations on the 32^3 phantom."""
+    import torch
+    plan, prob, x0 = fo.load_phantom(cfg0)
+    q = _params(fo, iter_max=100)
+    st = fo.new_state()
+    x = x0.clone()
+    fo.solve(plan, prob, q, st, x)
+    xr, k, s, info = Oracle(cfg0).solve(cfg0.x0, 100, _oparams(q))
+    assert st.k == k == 100
+    print(f"gpu s={st.s} oracle s={s} cost={st.cost:.6g}/{info['cost_before']:.6g}", flush=True)
+    dose, letd, _ = fo.dose_let(plan, x, cfg0.c)
+    torch.cuda.synchronize()
+    d_ref, _, letd_ref, _ = Oracle(cfg0).dose_let(xr)
+    rg = metrics.plan_report(_np(dose), _np(letd), cfg0.roi)
+    rr = metrics.plan_report(d_ref, letd_ref, cfg0.roi)
+    print("gpu", rg, "\noracle", rr, flush=True)
+    assert rg["PTV_D95"] == pytest.approx(rr["PTV_D95"], rel=T3)
+    assert rg["OAR_cyl_mean_LETd"] == pytest.approx(rr["OAR_cyl_mean_LETd"], rel=T3)
+    xg = _np(x)
+    print("normwise x error", np.linalg.norm(xg - xr) / np.linalg.norm(xr), flush=True)
+
+
+def test_solve_deterministic_and_resumable(fo, cfg0):
+    plan, prob, x0 = fo.load_phantom(cfg0)
+    q = _params(fo, iter_max=20)
+    xa = x0.clone()
+    sa = fo.new_state()
+    fo.solve(plan, prob, q, sa, xa)
+    xb = x0.clone()
+    sb = fo.new_state()
+    fo.solve(plan, prob, q, sb, xb)
+    assert np.array_equal(_np(xa), _np(xb)) and (sa.k, sa.s) == (sb.k, sb.s)
+    xc = x0.clone()
+    sc = fo.new_state()
+    q10 = _params(fo, iter_max=10)
+    fo.solve(plan, prob, q10, sc, xc)
+    fo.solve(plan, prob, q10, sc, xc)
+    assert np.array_equal(_np(xa), _np(xc)) and (sa.k, sa.s) == (sc.k, sc.s)
+    # graph replay and direct launches agree bit for bit
+    xd = x0.clone()
+    sd = fo.new_state()
+    for _ in range(20):
+        fo.superiorize_step(plan, prob, q, sd, xd)
+    assert np.array_equal(_np(xa), _np(xd))
+
+
+def test_load_errors(fo):
+    import torch
+    p = ph.tiny_problem(10, 4, 0.5, seed=3)
+    bad_col = p.col_idx.copy()
+    bad_col[0] = 4
+    with pytest.raises(fo.FredoptError) as e:
+        fo.load_matrices(p.row_ptr, bad_col, p.d_val, p.l_val, p.n_cols)
+    assert e.value.name == "E_INDEX"
+    bad_d = p.d_val.copy()
+    bad_d[1] = -1.0
+    with pytest.raises(fo.FredoptError) as e:
+        fo.load_matrices(p.row_ptr, p.col_idx, bad_d, p.l_val, p.n_cols)
+    assert e.value.name == "E_NONFINITE"
+    bad_d[1] = np.nan
+    with pytest.raises(fo.FredoptError) as e:
+        fo.load_matrices(p.row_ptr, p.col_idx, bad_d, p.l_val, p.n_cols, on_device=False)
+    assert e.value.name == "E_NONFINITE"
+    bad_rp = p.row_ptr.copy()
+    bad_rp[3], bad_rp[4] = bad_rp[4], bad_rp[3] - 1
+    with pytest.raises(fo.FredoptError) as e:
+        fo.load_matrices(bad_rp, p.col_idx, p.d_val, p.l_val, p.n_cols)
+    assert e.value.name in ("E_SHAPE", "E_INDEX")
+    plan, prob, x0 = fo.load_phantom(p)
+    x_before = x0.clone()
+    with pytest.raises(fo.FredoptError) as e:
+        fo.project_sweep(plan, prob, fo.SolverParams(lam=2.5), x0)
+    assert e.value.name == "E_ARG"
+    arr = {k: v.copy() for k, v in p.problem_arrays().items()}
+    arr["kind"][:] = ph.DOSE_LO | ph.DOSE_HI
+    arr["dose_lo"][:] = 2.0
+    arr["dose_hi"][:] = 1.0
+    with pytest.raises(fo.FredoptError) as e:
+        fo.project_sweep(plan, fo.DeviceProblem(arr, p.c), fo.SolverParams(), x0)
+    assert e.value.name == "E_ARG"
+    st = fo.new_state(k=-1)
+    with pytest.raises(fo.FredoptError) as e:
+        fo.solve(plan, prob, fo.SolverParams(iter_max=2), st, x0)
+    assert e.value.name == "E_STATE"
+    torch.cuda.synchronize()
+    assert torch.equal(x0, x_before)
