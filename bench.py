@@ -1,0 +1,257 @@
+#!/usr/bin/env python3
+"""Throughput of the superiorized dose/LETd iteration on one MI355X.
+
+A step is one outer iteration of the superiorization algorithm (Fig. 3 of Borys et
+al., arXiv 2509.20012): the objective and its gradient (Eq. 2), the direction
+products and the device-side step decision, the perturbation, the constraint
+residuals and one simultaneous projection sweep (Fig. 2) with the x >= 0 clamp.
+The default workload is the clinical-scale phantom (160 x 160 x 120 grid at 2 mm,
+three fields of 80 x 50 spots = 12,000 beamlets, ~458k voxel rows, ~155M nonzeros
+in each of D and L), synthetic and seeded, resident in HBM before timing starts.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "superiorized iters/s + achieved HBM GB/s vs plain FP32; p50/p99 plan latency"
+HBM_PEAK_GBPS = 8000.0
+KERNEL_SYMBOLS = {  # fredopt kernel id -> device symbol in profiler output (vt: storage)
+    "fwd_obj": "fo::k_forward<{vt}, 1>", "fwd_dir": "fo::k_forward<{vt}, 2>",
+    "fwd_resid": "fo::k_forward<{vt}, 3>", "tr_grad": "fo::k_tr_chunks<{vt}, 0>",
+    "tr_proj": "fo::k_tr_chunks<{vt}, 1>", "rows": "fo::k_rows<1>", "col": "fo::k_tcol",
+    "finalize": "fo::k_finalize"}
+
+
+def log(msg: str):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2509_20012_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(kernel: str, R: int, C: int, nnz: int, vb: int, n_tr_items: int) -> int:
+    """Bytes a kernel launch must move: the unpadded matrix entries (shared index, D
+    and L values), the input vector once, per-row problem data and outputs.  Padding
+    and re-reads are not counted."""
+    b = 4 + 2 * vb
+    if kernel == "fwd_obj":     # x in; d, l, coef out; kind, w_obj, targets in
+        return nnz * b + 4 * C + R * (8 + 8 + 2 + 12)
+    if kernel == "fwd_dir":     # g in; Dg, Lg out; kind, w_obj in
+        return nnz * b + 4 * C + R * (8 + 2 + 4)
+    if kernel == "fwd_resid":   # x in; d, l, coef out; kind, bounds, weights, moments in
+        return nnz * b + 4 * C + R * (8 + 8 + 2 + 20 + 4 + 24 + 12)
+    if kernel in ("tr_grad", "tr_proj"):   # coefficient pair per row once; chunk sums
+        return nnz * b + 8 * R + n_tr_items * (32 + 4)
+    if kernel == "col":         # chunk sums in; x, g in and out
+        return n_tr_items * 4 + C * 16
+    if kernel == "rows":        # d, l, Dg, Lg in; d, l, coef out; problem data in
+        return R * (16 + 8 + 8 + 2 + 20 + 4 + 24 + 12)
+    if kernel == "finalize":
+        return 0
+    raise KeyError(kernel)
+
+
+def make_workload(name: str):
+    from paper_2509_20012_amd import phantom as ph
+    if name == "config1":
+        return ph.config1(progress=log)
+    if name == "config0":
+        return ph.config0()
+    if name.startswith("config1x"):
+        return ph.config1(scale=float(name[len("config1x"):]), progress=log)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(p, q, n_iters: int):
+    """The FP64 oracle, as it stands, on the host cores for n_iters outer iterations
+    (closed-form step search) of the same workload."""
+    from oracle import Oracle, OracleParams, num_threads
+    t0 = time.perf_counter()
+    o = Oracle(p)
+    t_load = time.perf_counter() - t0
+    prm = OracleParams(lam=q.lam, alpha=q.alpha, eta=q.eta, reductions_n=q.reductions_n,
+                       normalization=q.normalization, line_search=1)
+    x = p.x0.astype(np.float64)
+    k, s = 0, -1
+    t0 = time.perf_counter()
+    for _ in range(n_iters):
+        x, k, s, _ = o.sa_iteration(x, k, s, prm)
+    dt = time.perf_counter() - t0
+    return {"value": n_iters / dt, "unit": "iters/s", "cores": num_threads(), "kind": "oracle",
+            "sample": f"{n_iters} outer iterations (reductions_n={q.reductions_n}, closed-form "
+                      f"step search) of the same workload from x0; oracle load "
+                      f"(FP64 promotion + CSC) {t_load:.1f} s not timed",
+            "seconds": dt}, (x, k, s)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="config1")
+    ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
+    ap.add_argument("--reductions", type=int, default=1)
+    ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=3)
+    ap.add_argument("--profile-iters", type=int, default=5)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain device copy of known size (for PMC scaling)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(row sharding is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2509_20012_amd import fredopt
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a HIP device")
+    torch.cuda.set_device(0)
+    fredopt.lib()
+    log(f"generating workload {args.workload}")
+    t0 = time.perf_counter()
+    p = make_workload(args.workload)
+    log(f"workload {p.summary()} in {time.perf_counter() - t0:.1f} s")
+
+    storage = fredopt.STORAGE[args.storage]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan, prob, x0 = fredopt.load_phantom(p, storage=storage)
+    torch.cuda.synchronize()
+    t_load = time.perf_counter() - t0
+    log(f"loaded in {t_load:.2f} s: {plan.info()}")
+    if args.autotune:
+        info = fredopt.autotune(plan, x0)
+        log(f"autotuned: lanes {info['lanes_per_row']} chunk {info['tr_chunk']}")
+    info = plan.info()
+
+    q = fredopt.SolverParams(reductions_n=args.reductions, iter_max=args.warmup)
+    x = x0.clone()
+    st = fredopt.new_state()
+    if args.warmup:
+        fredopt.solve(plan, prob, q, st, x)
+    torch.cuda.synchronize()
+    log(f"warmup {args.warmup} iterations done (k={st.k}, s={st.s})")
+
+    q.iter_max = args.steps
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    fredopt.solve(plan, prob, q, st, x)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_total = ev0.elapsed_time(ev1)
+    ms_per_step = ms_total / args.steps
+    its = 1000.0 / ms_per_step
+    log(f"timed {args.steps} iterations: {ms_per_step:.4f} ms/iter ({its:.1f} it/s), "
+        f"wall {wall:.3f} s, state k={st.k} s={st.s} cost={st.cost:.6g} prox={st.proximity:.3g}")
+
+    # per-kernel durations with HIP events on the launch stream
+    xp = x.clone()
+    sp = fredopt.State()
+    sp.k, sp.s = st.k, st.s
+    prof = fredopt.profile_kernels(plan, prob, q, sp, xp, args.profile_iters)
+    R, C, nnz = p.n_rows, p.n_cols, p.nnz
+    vb = 4 if storage == fredopt.F32 else 2
+    per_kernel = {}
+    for name, (ms, cnt) in prof.items():
+        if cnt == 0:
+            continue
+        ab = algorithmic_bytes(name, R, C, nnz, vb, info["tr_items"])
+        per_kernel[name] = {"ms": ms, "launches_per_iter": cnt / args.profile_iters,
+                            "alg_bytes": ab, "gbps": ab / (ms * 1e-3) / 1e9 if ms > 0 else 0.0}
+    dom = max((k for k in per_kernel if per_kernel[k]["alg_bytes"] > 0),
+              key=lambda k: per_kernel[k]["ms"] * per_kernel[k]["launches_per_iter"])
+    b_iter = sum(v["alg_bytes"] * v["launches_per_iter"] for v in per_kernel.values())
+    log("kernels: " + ", ".join(f"{k} {v['ms']:.4f} ms {v['gbps']:.0f} GB/s"
+                                for k, v in per_kernel.items()))
+    log(f"plan: {info}")
+
+    traffic = None
+    src_hash = kernel_source_hash()
+    tpath = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if os.path.exists(tpath):
+        try:
+            with open(tpath) as fh:
+                tr = json.load(fh)
+            ent = tr.get(args.workload, {}).get(args.storage, {}).get(dom)
+            if ent and ent.get("kernel_source_hash") == src_hash:
+                traffic = ent["bytes_per_launch"]
+        except (OSError, ValueError, KeyError):
+            traffic = None
+
+    if args.copy_calibration:
+        n = 256 * 1024 * 1024
+        a = torch.empty(n, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 copies of {n} bytes")
+
+    roofline = {"bound": "hbm", "kernel": dom,
+                "symbol": KERNEL_SYMBOLS[dom].format(vt=storage),
+                "achieved": round(per_kernel[dom]["gbps"], 1), "peak": HBM_PEAK_GBPS,
+                "unit": "GB/s", "frac": round(per_kernel[dom]["gbps"] / HBM_PEAK_GBPS, 4),
+                "traffic": traffic,
+                "alg_bytes_per_launch": per_kernel[dom]["alg_bytes"],
+                "ms_per_launch": round(per_kernel[dom]["ms"], 5)}
+
+    result = {
+        "metric": METRIC, "value": round(its, 3), "unit": "iters/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if storage == fredopt.F32 else f"f32 (values stored {args.storage})",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {p.name}", "rows": R, "cols": C, "nnz": nnz,
+                   "storage": args.storage, "reductions_n": args.reductions,
+                   "normalization": "convex_all", "lanes_per_row": info["lanes_per_row"],
+                   "tr_chunk": info["tr_chunk"]},
+        "hbm_gbps_iteration": round(b_iter * its / 1e9, 1),
+        "hbm_frac_iteration": round(b_iter * its / 1e9 / HBM_PEAK_GBPS, 4),
+        "alg_bytes_per_iteration": b_iter,
+        "roofline": roofline,
+        "kernels": {k: {kk: (round(vv, 5) if isinstance(vv, float) else vv)
+                        for kk, vv in v.items()} for k, v in per_kernel.items()},
+        "load_seconds": round(t_load, 3),
+        "kernel_source_hash": src_hash,
+        "paper_context": "Table 2 stage (iv): 200 SA iterations in 2091 s / 1508 s "
+                         "(0.096 / 0.133 it/s) on an NVIDIA P100, private patient matrices",
+    }
+    if not args.no_cpu_baseline:
+        log(f"cpu baseline: oracle, {args.cpu_iters} iterations")
+        cb, _ = cpu_baseline(p, q, args.cpu_iters)
+        log(f"cpu baseline {cb['value']:.4f} it/s on {cb['cores']} threads ({cb['seconds']:.1f} s)")
+        cb.pop("seconds")
+        result["cpu_baseline"] = cb
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -36,7 +36,9 @@
  *    on_device = 0.
  *  - `stream` is a hipStream_t (may be the null stream).
  *  - Every call returns FREDOPT_OK or a negative status; on error nothing the
- *    caller owns has been modified and fredopt_last_error() describes the cause.
+ *    caller owns has been modified and fredopt_last_error() describes the cause,
+ *    except FREDOPT_E_NONFINITE raised by an iteration: x then holds the iterate
+ *    reached when the non-finite value was detected.
  *  - Calls on one plan must not overlap; calls on distinct plans are independent.
  */
 #ifndef FREDOPT_H
@@ -96,8 +98,13 @@ typedef struct {
   const int32_t *col_idx;
   const float *d_val;
   const float *l_val;
-  int32_t storage;   /* fredopt_dtype */
-  int32_t on_device; /* 1: the four arrays are device pointers, 0: host pointers */
+  int32_t storage;       /* fredopt_dtype */
+  int32_t on_device;     /* 1: the four arrays are device pointers, 0: host pointers */
+  int32_t lanes_per_row; /* forward layout: 0 automatic, or 1, 2, 4, 8, 16 lanes per row */
+  int32_t gradient_reserve_pct; /* workspace share, in % of the CSC, kept for the
+                                   objective-row copy used by the Eq. (2) gradient:
+                                   0 = default (25), < 0 = none (the gradient then
+                                   streams the full CSC), 1..100 */
 } fredopt_matrices;
 
 /* Per-row bounds, priorities and objective data (Fig. 2, its caption, Eq. 2).
@@ -137,16 +144,25 @@ typedef struct {
   double q;                /* sum w (D g)^2 + sum w c^2 (L g)^2 of that direction */
 } fredopt_state;
 
-/* Bytes of device workspace a plan of this size needs (an upper bound valid for
- * every sparsity pattern with these sizes).  Returns 0 for invalid sizes. */
+/* Bytes of device workspace a plan of this size needs: an upper bound valid for
+ * every sparsity pattern with these sizes and the automatic forward layout.
+ * Returns 0 for invalid sizes. */
 size_t fredopt_workspace_bytes(int64_t n_rows, int64_t n_cols, int64_t nnz, int32_t storage);
 
+/* The exact workspace for one pattern: row_ptr is a HOST array of n_rows + 1
+ * offsets; lanes_per_row and gradient_reserve_pct as in fredopt_matrices.  Returns 0
+ * for invalid input. */
+size_t fredopt_workspace_bytes_csr(int64_t n_rows, int64_t n_cols, const int64_t *row_ptr,
+                                   int32_t storage, int32_t lanes_per_row,
+                                   int32_t gradient_reserve_pct);
+
 /* Table 2 step (iii): validate the CSR, copy it to the workspace in the device
- * layout (row-padded CSR with shared indices and planar D/L values, plus a CSC copy
- * with rows ascending in every column for the transposed products), compute the
- * per-row FP64 moments sum D^2, sum L^2, sum D L, and return a plan.  `workspace`
- * must be 256-byte aligned device memory of at least
- * fredopt_workspace_bytes(...) bytes.  Synchronises `stream`. */
+ * layout (a sliced-ELL copy for the forward products: rows sorted by length inside
+ * windows of consecutive rows, lanes_per_row lanes per row, one shared index array
+ * and planar D / L values; a CSC copy with rows ascending in every column for the
+ * transposed products), compute the per-row FP64 moments sum D^2, sum L^2,
+ * sum D L, and return a plan.  `workspace` must be 256-byte aligned device memory
+ * of at least fredopt_workspace_bytes_csr(...) bytes.  Synchronises `stream`. */
 fredopt_status fredopt_load_matrices(const fredopt_matrices *m, void *workspace,
                                      size_t workspace_bytes, void *stream,
                                      fredopt_plan **out);
@@ -172,7 +188,9 @@ fredopt_status fredopt_project_sweep(fredopt_plan *p, const fredopt_problem *pr,
 /* One outer iteration k of Fig. 3 from state *st (in/out): reductions_n gradient
  * perturbations of Eq. (2) with beta = alpha^s, s the smallest integer above the
  * previous s for which the cost strictly decreases, then one sweep with weights
- * eta^k w applied to the perturbed point; k += 1.  Synchronises `stream`. */
+ * eta^k w applied to the perturbed point; k += 1.  The gradient only involves rows
+ * with objective terms; the plan keeps a copy of their CSC entries, rebuilt when the
+ * problem's kind array changes (address or contents).  Synchronises `stream`. */
 fredopt_status fredopt_superiorize_step(fredopt_plan *p, const fredopt_problem *pr,
                                         const fredopt_params *q, fredopt_state *st,
                                         float *x_inout, void *stream);
@@ -192,9 +210,10 @@ const char *fredopt_last_error(void);
 
 typedef struct {
   int64_t n_rows, n_cols, nnz;
-  int64_t csr_slots, csc_slots;  /* stored entries including row / column padding */
-  int64_t bytes_per_csr_slot, bytes_per_csc_slot;
-  int64_t fwd_items, tr_items, row_items;
+  int64_t sell_slots, csc_slots;  /* stored entries including padding               */
+  int64_t bytes_per_sell_slot, bytes_per_csc_slot;
+  int64_t n_slices, tr_items, row_items;
+  int64_t workspace_bytes;
   int32_t storage, lanes_per_row, fwd_grid, tr_chunk;
   int32_t lds_x; /* 1 if the forward kernels stage the vector in LDS */
   int32_t reserved;
@@ -202,14 +221,16 @@ typedef struct {
 
 fredopt_status fredopt_get_plan_info(const fredopt_plan *p, fredopt_plan_info *info);
 
-/* Kernel identifiers of one outer iteration, in launch order. */
-#define FREDOPT_KERNEL_FWD_OBJ 0   /* d, l and Eq. (2) coefficients at x        */
-#define FREDOPT_KERNEL_TR_GRAD 1   /* g = grad chi^2 (transposed product)       */
-#define FREDOPT_KERNEL_FWD_DIR 2   /* D g, L g, Q and the step decision         */
-#define FREDOPT_KERNEL_ROWS 3      /* move d, l; constraint residuals           */
-#define FREDOPT_KERNEL_TR_PROJ 4   /* transposed projection, update, clamp      */
-#define FREDOPT_KERNEL_FWD_RESID 5 /* d, l and residuals (reductions_n = 0)     */
-#define FREDOPT_NUM_KERNELS 6
+/* Kernel identifiers of one outer iteration. */
+#define FREDOPT_KERNEL_FWD_OBJ 0   /* d, l and Eq. (2) coefficients at x            */
+#define FREDOPT_KERNEL_TR_GRAD 1   /* gradient chunks of the transposed product     */
+#define FREDOPT_KERNEL_FWD_DIR 2   /* D g, L g and the Q partials                   */
+#define FREDOPT_KERNEL_ROWS 3      /* move d, l; constraint residuals               */
+#define FREDOPT_KERNEL_TR_PROJ 4   /* projection chunks of the transposed product   */
+#define FREDOPT_KERNEL_FWD_RESID 5 /* d, l and residuals (reductions_n = 0)         */
+#define FREDOPT_KERNEL_COL 6       /* per-column sums: gradient or update and clamp */
+#define FREDOPT_KERNEL_FINALIZE 7  /* plan scalars: step decision, weights          */
+#define FREDOPT_NUM_KERNELS 8
 
 /* Runs n_iters outer iterations (as fredopt_superiorize_step would) launching each
  * kernel separately with HIP events around it on `stream`, and writes the mean
@@ -221,14 +242,14 @@ fredopt_status fredopt_profile_kernels(fredopt_plan *p, const fredopt_problem *p
                                        float *x_inout, int32_t n_iters, void *stream,
                                        double *ms_out, int64_t *count_out);
 
-/* Autotuner: times the candidate lanes-per-row widths of the forward kernel and
- * chunk sizes of the transposed kernel on this plan (the plan's own matrices,
- * fluence x) and keeps the fastest.  Synchronises `stream`. */
+/* Autotuner: times the candidate workgroups-per-CU counts of the forward kernel and
+ * chunk sizes of the transposed kernel on this plan (its own matrices, fluence x)
+ * and keeps the fastest.  Synchronises `stream`. */
 fredopt_status fredopt_autotune(fredopt_plan *p, const float *x, void *stream);
 
-/* Sets the lanes-per-row width (4, 8, 16, 32 or 64) and transposed chunk size
- * (nnz per work item, multiple of 1024) explicitly; 0 keeps the current value. */
-fredopt_status fredopt_set_tuning(fredopt_plan *p, int32_t lanes_per_row, int32_t tr_chunk);
+/* Sets the forward workgroups per CU (1..8, capped by LDS) and the transposed chunk
+ * size (slots per work item, a multiple of 256); 0 keeps the current value. */
+fredopt_status fredopt_set_tuning(fredopt_plan *p, int32_t fwd_wgs_per_cu, int32_t tr_chunk);
 
 #ifdef __cplusplus
 }

@@ -7,10 +7,12 @@
 
 namespace fo {
 
-constexpr int kBlock = 256;            // threads per workgroup of every iteration kernel
 constexpr int kWave = 64;              // CDNA wavefront width
+constexpr int kFwdBlock = 512;         // forward kernel: 8 waves, one slice each
+constexpr int kFwdWaves = kFwdBlock / kWave;
+constexpr int kBlock = 256;            // other kernels
 constexpr int kNPart = 8;              // doubles per partial-sum slot
-constexpr int kPlanTickets = 4;        // plan-level ticket counters before column tickets
+constexpr int kCounters = 4;           // scheduling counters per batch
 constexpr double kDegenerateRel = 1e-12;
 constexpr double kBetaFloor = 1e-300;
 
@@ -25,8 +27,16 @@ enum ValueType : int { kF32 = 0, kF16 = 1, kBF16 = 2 };
 enum FwdMode : int { kFwdDoseLet = 0, kFwdObj = 1, kFwdDir = 2, kFwdResid = 3 };
 // rows-kernel epilogues
 enum RowMode : int { kRowsMoveObj = 0, kRowsMoveResid = 1 };
-// transposed-kernel epilogues
-enum TrMode : int { kTrGrad = 0, kTrGradMove = 1, kTrProj = 2, kTrProjMove = 3 };
+// column-finalise epilogues of the transposed product
+enum ColMode : int { kColGrad = 0, kColGradMove = 1, kColProj = 2, kColProjMove = 3 };
+// plan-level finalisation
+enum FinMode : int {
+  kFinDir0 = 0,        // first perturbation of an outer iteration: cost, reset, step
+  kFinDir = 1,         // later perturbations: step
+  kFinMoveObj = 2,     // cost at the perturbed point (between perturbations)
+  kFinResidRows = 3,   // residual pass done by the rows kernel
+  kFinResidFwd = 4     // residual pass done by the forward kernel
+};
 
 struct DevParams {
   double lambda, alpha, eta, c;
@@ -40,20 +50,37 @@ struct DevState {
   int32_t pstop, capped, nonfinite, pad;
 };
 
+// Forward layout (sliced ELL): a slice holds rpw = 64 / lpr rows, each row spread
+// over lpr lanes, each lane reading 4 consecutive entries of its row per step.  Entry
+// e of the row in slice position p sits at
+//   base[s] + ((e / 4) / lpr) * 256 + (p * lpr + (e / 4) % lpr) * 4 + e % 4
+// so one wave step reads 1 KiB contiguously per array.  Rows are sorted by length
+// (descending) inside windows of consecutive rows; srow maps slice positions back.
 struct DevPlan {
   int64_t R, C;
-  int32_t vtype, lanes;       // value storage, lanes per row in the forward kernel
-  int32_t n_fwd_items, n_row_items;
-  // CSR, rows padded to a multiple of 4 slots
-  const int64_t* rp;
-  const int32_t* ci;
-  const void* dv;
-  const void* lv;
-  // CSC, columns padded to a multiple of 4 slots, rows ascending in a column
-  const int64_t* cp;
+  int32_t vtype, lpr_log2;
+  int32_t n_slices, n_row_items;
+  int32_t n_col_blocks, n_groups;
+  // sliced-ELL copy for the forward products
+  const int64_t* sbase;       // [n_slices + 1]
+  const int32_t* swidth;      // [n_slices] steps
+  const int32_t* srow;        // [n_slices * rpw] original row, -1 for padding
+  const int32_t* sci;
+  const void* sdv;
+  const void* slv;
+  // CSC copy, columns padded to 4 slots, rows ascending in a column (projection)
   const int32_t* ri;
   const void* cdv;
   const void* clv;
+  const int32_t* col_tslot0;  // [C] first chunk partial of the column
+  const int32_t* col_nch;     // [C] chunks of the column
+  // CSC used for the Eq. (2) gradient: only rows with objective terms (their
+  // coefficients are the only non-zero ones), or the full CSC above
+  const int32_t* gri;
+  const void* gcdv;
+  const void* gclv;
+  const int32_t* gcol_tslot0;
+  const int32_t* gcol_nch;
   const float* cscale;        // per-column scale of 16-bit storage (null for FP32)
   const double* mom;          // [3R] sum D^2, sum L^2, sum D L per row
   // problem (device arrays of R)
@@ -71,17 +98,17 @@ struct DevPlan {
   float* out_letd;
   float* out_cdl;
   // reductions
-  double* fpart;              // [n_fwd_items * kNPart]
+  double* spart_a;            // [n_groups * kNPart] objective / residual passes
+  double* spart_b;            // [n_groups * kNPart] direction pass
   double* rpart;              // [n_row_items * kNPart]
-  float* tpart;               // [n_tr_items] chunk partials
-  double* colval;             // [C]
-  uint32_t* cnt;              // [kPlanTickets + C]
+  double* gpart;              // [n_col_blocks]
+  float* tpart;               // [sum of chunks]
   DevParams prm;
   DevState* st;
 };
 
-struct FwdItem {   // a range of rows of one plan
-  int32_t plan, slot, r0, r1;
+struct FwdGroup {  // up to kFwdWaves consecutive slices of one plan
+  int32_t plan, slice0, n, slot;  // slot: the group's partial-sum slot in its plan
 };
 
 struct RowItem {   // a range of rows of one plan (rows kernel)
@@ -89,10 +116,13 @@ struct RowItem {   // a range of rows of one plan (rows kernel)
 };
 
 struct TrItem {    // a chunk of one column of one plan
-  int32_t plan, col, chunk, nchunks;
+  int32_t plan, col;
+  int32_t tslot, pad;
   int64_t q0, q1;  // slot range in the CSC arrays
-  int32_t tslot0;  // tpart index of chunk 0 of this column
-  int32_t pad;
+};
+
+struct ColBlock {  // up to kBlock consecutive columns of one plan
+  int32_t plan, slot, c0, c1;
 };
 
 }  // namespace fo

@@ -6,12 +6,15 @@
 namespace fo {
 
 // iteration kernels (kernels_iter.hip)
-void launch_forward(int vtype, int mode, const DevPlan* plans, const FwdItem* items,
-                    int n_items, int grid, int lds_floats, hipStream_t s);
+void launch_forward(int vtype, int mode, const DevPlan* plans, const FwdGroup* groups,
+                    int n_groups, int grid, int lds_floats, uint32_t* ctr, hipStream_t s);
 void launch_rows(int mode, const DevPlan* plans, const RowItem* items, int n_items,
                  hipStream_t s);
-void launch_transposed(int vtype, int mode, const DevPlan* plans, const TrItem* items,
-                       int n_items, hipStream_t s);
+void launch_tr_chunks(int vtype, int tag, const DevPlan* plans, const TrItem* items,
+                      int n_items, hipStream_t s);
+void launch_tcol(int mode, const DevPlan* plans, const ColBlock* blocks, int n_blocks,
+                 hipStream_t s);
+void launch_finalize(int mode, const DevPlan* plans, int n_plans, hipStream_t s);
 hipError_t set_forward_lds_limit(int vtype, size_t bytes);
 
 // load kernels (kernels_load.hip)
@@ -19,13 +22,14 @@ hipError_t set_forward_lds_limit(int vtype, size_t bytes);
 //             4 non-finite or negative value
 void launch_validate(int64_t R, int64_t C, const int64_t* row_ptr, const int32_t* col,
                      const float* dv, const float* lv, uint32_t* flags, hipStream_t s);
-void launch_col_stats(int64_t R, const int64_t* row_ptr, const int32_t* col, const float* dv,
+void launch_col_stats(int64_t nnz, const int64_t* row_ptr, const int32_t* col, const float* dv,
                       const float* lv, uint32_t* col_count, uint32_t* col_max_bits,
                       hipStream_t s);
 void launch_col_scale(int64_t C, const uint32_t* col_max_bits, float* scale, hipStream_t s);
-void launch_pack_csr(int vtype, int64_t R, const int64_t* row_ptr, const int32_t* col,
-                     const float* dv, const float* lv, const float* scale, const int64_t* rp,
-                     int32_t* ci, void* pdv, void* plv, hipStream_t s);
+void launch_pack_sell(int vtype, int64_t R, int lpr_log2, const int64_t* row_ptr,
+                      const int32_t* col, const float* dv, const float* lv, const float* scale,
+                      const int32_t* rslice, const int64_t* sbase, int32_t* sci, void* sdv,
+                      void* slv, hipStream_t s);
 void launch_block_count(int64_t R, int64_t C, int rows_per_block, const int64_t* row_ptr,
                         const int32_t* col, uint32_t* bc, hipStream_t s);
 void launch_block_offsets(int64_t C, int nb, const int64_t* cp, uint32_t* bc, hipStream_t s);
@@ -33,8 +37,16 @@ void launch_fill_csc(int vtype, int64_t R, int64_t C, int rows_per_block,
                      const int64_t* row_ptr, const int32_t* col, const float* dv,
                      const float* lv, const float* scale, uint32_t* bc, int32_t* ri,
                      void* cdv, void* clv, hipStream_t s);
-void launch_moments(int vtype, int64_t R, const int64_t* rp, const void* pdv, const void* plv,
-                    const int32_t* ci, const float* scale, double* mom, hipStream_t s);
+void launch_moments(int vtype, int64_t R, const int64_t* row_ptr, const int32_t* col,
+                    const float* dv, const float* lv, const float* scale, double* mom,
+                    hipStream_t s);
+// count[j]: entries of column j (len[j] real entries from cp[j]) in rows with
+// objective terms.
+void launch_obj_count(int64_t C, const int64_t* cp, const uint32_t* len, const int32_t* ri,
+                      const uint16_t* kind, uint32_t* count, hipStream_t s);
+void launch_obj_fill(int vtype, int64_t C, const int64_t* cp, const uint32_t* len,
+                     const int32_t* ri, const void* cdv, const void* clv, const uint16_t* kind,
+                     const int64_t* ocp, int32_t* ori, void* ocdv, void* oclv, hipStream_t s);
 void launch_check_problem(int64_t R, const uint16_t* kind, const float* dlo, const float* dhi,
                           const float* clo, const float* chi, const float* tmax,
                           const float* wf, const float* wo, const float* dt, const float* ct,

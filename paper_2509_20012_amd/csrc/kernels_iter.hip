@@ -1,24 +1,23 @@
 // Iteration kernels of the superiorized dose / LETd feasibility-seeking loop
 // (Borys et al., arXiv 2509.20012, Figs. 2-3, Eq. 2) for gfx950.
 //
-//  k_forward     rows of D and L (CSR, rows padded to 4 slots, shared indices,
-//                planar values) times a vector staged in LDS; one group of G lanes
-//                per row, each lane streaming 4 slots per step with 16-byte loads,
-//                butterfly shuffles for the row sum.  Epilogues: dose/LETd/cDL
-//                (Eq. 1), Eq. (2) value and gradient coefficients, the direction
-//                products with Q and the step-size decision, or the constraint
-//                residuals of Fig. 2 folded into projection coefficients.
-//  k_rows        moves d and l along the accepted perturbation and evaluates the
-//                constraint residuals (or the next gradient coefficients).
-//  k_transposed  columns of D^T and L^T (CSC, rows ascending) against the per-row
-//                coefficient pair, chunked with fixed-order combination of chunk
-//                partials (no floating-point atomics, so results are bitwise
-//                reproducible); the epilogue writes the gradient, or applies the
-//                projection, the pending perturbation and the x >= 0 clamp.
-//
-// Every plan-level scalar (cost, ||g||^2, Q, proximity, weights) is reduced in
-// FP64: one partial slot per work item, then the last item of the plan (ticket
-// counter) sums the slots in index order.
+//  k_forward    d = D v and l = L v over a sliced-ELL copy (rows sorted by length
+//               inside windows, lpr lanes per row, 16-byte loads per lane and step,
+//               the vector staged in LDS), slices handed out to 512-thread groups by
+//               an atomic counter (scheduling only; every slice writes its own
+//               partial, so results do not depend on the schedule).  Epilogues:
+//               dose / LETd / cDL (Eq. 1), Eq. (2) value and gradient coefficients,
+//               the direction products with Q, or the Fig. 2 residuals folded into
+//               projection coefficients.
+//  k_rows       moves d and l along the accepted perturbation and evaluates the
+//               constraint residuals (or the next gradient coefficients).
+//  k_tr_chunks  D^T cD + L^T cL over the CSC copy, one wavefront per fixed-size chunk
+//               of a column; chunk partials only (no floating-point atomics).
+//  k_tcol       per column: chunk partials summed in chunk order, then the gradient
+//               store or the projection update with the pending perturbation and
+//               the x >= 0 clamp (Fig. 2, last loop).
+//  k_finalize   one workgroup per plan: sums the partial slots in index order (FP64)
+//               and makes the plan-level decisions (step size of Fig. 3, weights).
 //
 // Partial slot layout (kNPart doubles):
 //   objective pass  [0] chi^2                         [5] non-finite rows
@@ -62,10 +61,19 @@ struct VLoad<kBF16> {
 
 // ------------------------------------------------------------------ reductions --
 
-// Sum of v over the 256 threads in a fixed order (butterfly in each wave, then the
-// four wave sums in order).  Every thread receives the result.
-__device__ __forceinline__ double block_sum(double v, double* sh4) {
+__device__ __forceinline__ double wave_sum(double v) {
   for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+__device__ __forceinline__ float wave_sumf(float v) {
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// Sum over a 256-thread block in a fixed order; every thread gets the result.
+__device__ __forceinline__ double block_sum(double v, double* sh4) {
+  v = wave_sum(v);
   const int tid = threadIdx.x;
   __syncthreads();
   if ((tid & (kWave - 1)) == 0) sh4[tid / kWave] = v;
@@ -73,23 +81,6 @@ __device__ __forceinline__ double block_sum(double v, double* sh4) {
   const double r = (sh4[0] + sh4[1]) + (sh4[2] + sh4[3]);
   __syncthreads();
   return r;
-}
-
-// Sum of the plan's partial slots in a fixed order (thread-strided, then
-// block_sum); run by the whole workgroup that took the last ticket.
-__device__ __forceinline__ void sum_slots(const double* part, int n, double* out,
-                                          double* sh4) {
-  __threadfence();
-  double s[kNPart];
-#pragma unroll
-  for (int k = 0; k < kNPart; ++k) s[k] = 0.0;
-  for (int i = threadIdx.x; i < n; i += kBlock) {
-    const double* p = part + (int64_t)i * kNPart;
-#pragma unroll
-    for (int k = 0; k < kNPart; ++k) s[k] += __builtin_nontemporal_load(p + k);
-  }
-#pragma unroll
-  for (int k = 0; k < kNPart; ++k) out[k] = block_sum(s[k], sh4);
 }
 
 // ---------------------------------------------------------------- epilogues ----
@@ -198,7 +189,7 @@ __device__ __forceinline__ bool finite2(float a, float b) { return isfinite(a) &
 
 // Plan-level completion of a residual pass: proximity, weights, the projection
 // scale weight_scale / W, and the outer counter (Fig. 3: weights eta^k w).
-__device__ void finalize_residuals(const DevPlan* P, const double* s) {
+__device__ __noinline__ void finalize_residuals(const DevPlan* P, const double* s) {
   DevState* st = P->st;
   const double wall = s[0], wviol = s[1];
   st->w_all = wall;
@@ -221,10 +212,10 @@ __device__ void finalize_residuals(const DevPlan* P, const double* s) {
 // strictly lowers it iff beta Q < G.  s is the smallest integer above the previous
 // s with that property (the inner loop of Fig. 3 tries s+1, s+2, ...).  A search
 // that would need alpha^s < 1e-300 skips the perturbation and leaves s unchanged.
-__device__ void decide_step(const DevPlan* P, double Q) {
+__device__ __noinline__ void decide_step(const DevPlan* P, double G, double Q) {
   DevState* st = P->st;
+  st->G = G;
   st->Q = Q;
-  const double G = st->G;
   if (!isfinite(G) || !isfinite(Q)) st->nonfinite = 1;
   if (st->pstop || !(G > 0.0) || !isfinite(G) || !isfinite(Q)) {
     st->beta = 0.0;
@@ -261,164 +252,160 @@ __device__ void decide_step(const DevPlan* P, double Q) {
   st->beta = beta;
 }
 
-// Writes this work item's partials, takes a ticket, and returns (to every thread)
-// whether this item was the plan's last one.
-__device__ __forceinline__ bool publish_partials(double* slot, const double* s, uint32_t* ticket,
-                                                 int n_items, int* s_last) {
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int k = 0; k < kNPart; ++k) slot[k] = s[k];
-    __threadfence();
-    const unsigned t = atomicAdd(ticket, 1u);
-    *s_last = (t == (unsigned)n_items - 1) ? 1 : 0;
-  }
-  __syncthreads();
-  return *s_last != 0;
-}
-
 // -------------------------------------------------------------- forward pass ---
 
+template <int MODE>
+__device__ __forceinline__ constexpr unsigned fwd_slots() {
+  return MODE == kFwdResid ? 0x7Fu : 0x21u;
+}
+
 template <int VT, int MODE>
-__global__ __launch_bounds__(kBlock) void k_forward(const DevPlan* __restrict__ plans,
-                                                    const FwdItem* __restrict__ items,
-                                                    int n_items, int lds_floats) {
+__device__ __forceinline__ void forward_slice(const DevPlan* __restrict__ P, int s,
+                                              const float* __restrict__ xs, bool use_lds,
+                                              const float* __restrict__ vec, int lane,
+                                              double* wpart) {
+  const int lg2 = P->lpr_log2;
+  const int lpr = 1 << lg2;
+  const int rpw = kWave >> lg2;
+  const int pos = lane >> lg2;
+  const int64_t base = P->sbase[s] + 4 * lane;
+  const int W = P->swidth[s];
+  const int row = P->srow[(int64_t)s * rpw + pos];
+  const int32_t* __restrict__ ci = P->sci;
+  float ad = 0.f, al = 0.f;
+  if (use_lds) {
+#pragma unroll 4
+    for (int t = 0; t < W; ++t) {
+      const int64_t q = base + (int64_t)t * 256;
+      const int4 c4 = *reinterpret_cast<const int4*>(ci + q);
+      const float4 d4 = VLoad<VT>::q4(P->sdv, q);
+      const float4 l4 = VLoad<VT>::q4(P->slv, q);
+      const float x0 = xs[c4.x], x1 = xs[c4.y], x2 = xs[c4.z], x3 = xs[c4.w];
+      ad = fmaf(d4.x, x0, ad);
+      ad = fmaf(d4.y, x1, ad);
+      ad = fmaf(d4.z, x2, ad);
+      ad = fmaf(d4.w, x3, ad);
+      al = fmaf(l4.x, x0, al);
+      al = fmaf(l4.y, x1, al);
+      al = fmaf(l4.z, x2, al);
+      al = fmaf(l4.w, x3, al);
+    }
+  } else {
+    const float* __restrict__ cs = P->cscale;
+    for (int t = 0; t < W; ++t) {
+      const int64_t q = base + (int64_t)t * 256;
+      const int4 c4 = *reinterpret_cast<const int4*>(ci + q);
+      const float4 d4 = VLoad<VT>::q4(P->sdv, q);
+      const float4 l4 = VLoad<VT>::q4(P->slv, q);
+      const float x0 = cs ? vec[c4.x] * cs[c4.x] : vec[c4.x];
+      const float x1 = cs ? vec[c4.y] * cs[c4.y] : vec[c4.y];
+      const float x2 = cs ? vec[c4.z] * cs[c4.z] : vec[c4.z];
+      const float x3 = cs ? vec[c4.w] * cs[c4.w] : vec[c4.w];
+      ad = fmaf(d4.x, x0, ad);
+      ad = fmaf(d4.y, x1, ad);
+      ad = fmaf(d4.z, x2, ad);
+      ad = fmaf(d4.w, x3, ad);
+      al = fmaf(l4.x, x0, al);
+      al = fmaf(l4.y, x1, al);
+      al = fmaf(l4.z, x2, al);
+      al = fmaf(l4.w, x3, al);
+    }
+  }
+  for (int o = lpr >> 1; o > 0; o >>= 1) {
+    ad += __shfl_xor(ad, o);
+    al += __shfl_xor(al, o);
+  }
+  double acc[kNPart];
+#pragma unroll
+  for (int k = 0; k < kNPart; ++k) acc[k] = 0.0;
+  if ((lane & (lpr - 1)) == 0 && row >= 0) {
+    if constexpr (MODE == kFwdDoseLet) {
+      if (P->out_dose) P->out_dose[row] = ad;
+      if (P->out_letd) P->out_letd[row] = ad > 0.f ? al / ad : 0.f;
+      if (P->out_cdl) P->out_cdl[row] = (float)(P->prm.c * (double)al);
+    } else if constexpr (MODE == kFwdObj) {
+      P->d[row] = ad;
+      P->l[row] = al;
+      objective_row(P, row, ad, al, &acc[0]);
+      if (!finite2(ad, al)) acc[5] += 1.0;
+    } else if constexpr (MODE == kFwdDir) {
+      P->dg[row] = ad;
+      P->lg[row] = al;
+      const unsigned k = P->kind[row];
+      if (k & (kObjDose | kObjCdl)) {
+        const double wo = P->wo[row], c = P->prm.c;
+        if (k & kObjDose) acc[0] += wo * (double)ad * (double)ad;
+        if (k & kObjCdl) acc[0] += wo * c * c * (double)al * (double)al;
+      }
+      if (!finite2(ad, al)) acc[5] += 1.0;
+    } else {
+      P->d[row] = ad;
+      P->l[row] = al;
+      residual_row(P, row, ad, al, acc);
+      acc[6] += objective_value(P, row, ad, al);
+      if (!finite2(ad, al)) acc[5] += 1.0;
+    }
+  }
+  if constexpr (MODE != kFwdDoseLet) {
+    constexpr unsigned used = fwd_slots<MODE>();
+#pragma unroll
+    for (int k = 0; k < kNPart; ++k)
+      if (used & (1u << k)) acc[k] = wave_sum(acc[k]);
+    if (lane == 0) {
+#pragma unroll
+      for (int k = 0; k < kNPart; ++k) wpart[k] = acc[k];
+    }
+  }
+}
+
+template <int VT, int MODE>
+__global__ __launch_bounds__(kFwdBlock) void k_forward(const DevPlan* __restrict__ plans,
+                                                       const FwdGroup* __restrict__ groups,
+                                                       int n_groups, int lds_floats,
+                                                       uint32_t* ctr) {
   extern __shared__ float xs[];
-  __shared__ double gred[kBlock / 4][kNPart];
-  __shared__ double sh4[kBlock / kWave];
-  __shared__ int s_last;
-  const int tid = threadIdx.x;
+  __shared__ int s_g;
+  __shared__ double wpart[kFwdWaves][kNPart];
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   int cur = -1;
   bool use_lds = false;
-  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
-    const FwdItem w = items[it];
-    const DevPlan* __restrict__ P = plans + w.plan;
-    const float* __restrict__ vec = (MODE == kFwdDir) ? P->g : P->x;
-    const float* __restrict__ cs = P->cscale;
-    if (w.plan != cur) {
-      __syncthreads();
+  const float* vec = nullptr;
+  for (;;) {
+    if (tid == 0) s_g = (int)atomicAdd(&ctr[0], 1u);
+    __syncthreads();
+    const int gi = s_g;
+    if (gi >= n_groups) {
+      // the last workgroup to run out of work re-arms the counters for the next launch
+      if (tid == 0) {
+        const unsigned e = atomicAdd(&ctr[1], 1u);
+        if (e == gridDim.x - 1) {
+          atomicExch(&ctr[0], 0u);
+          atomicExch(&ctr[1], 0u);
+        }
+      }
+      break;
+    }
+    const FwdGroup G = groups[gi];
+    const DevPlan* __restrict__ P = plans + G.plan;
+    if (G.plan != cur) {
+      vec = (MODE == kFwdDir) ? P->g : P->x;
       use_lds = P->C <= (int64_t)lds_floats;
       if (use_lds) {
-        for (int64_t j = tid; j < P->C; j += kBlock) xs[j] = cs ? vec[j] * cs[j] : vec[j];
+        const float* cs = P->cscale;
+        for (int64_t j = tid; j < P->C; j += kFwdBlock) xs[j] = cs ? vec[j] * cs[j] : vec[j];
       }
       __syncthreads();
-      cur = w.plan;
+      cur = G.plan;
     }
-    const int G = P->lanes;
-    const int NG = kBlock / G;
-    const int gid = tid / G, gl = tid % G;
-    double acc[kNPart];
-#pragma unroll
-    for (int k = 0; k < kNPart; ++k) acc[k] = 0.0;
-    const int64_t* __restrict__ rp = P->rp;
-    const int32_t* __restrict__ ci = P->ci;
-    for (int r = w.r0 + gid; r < w.r1; r += NG) {
-      const int64_t q0 = rp[r], q1 = rp[r + 1];
-      float ad = 0.f, al = 0.f;
-      if (use_lds) {
-#pragma unroll 2
-        for (int64_t q = q0 + 4 * gl; q < q1; q += 4 * G) {
-          const int4 c4 = *reinterpret_cast<const int4*>(ci + q);
-          const float4 d4 = VLoad<VT>::q4(P->dv, q);
-          const float4 l4 = VLoad<VT>::q4(P->lv, q);
-          const float x0 = xs[c4.x], x1 = xs[c4.y], x2 = xs[c4.z], x3 = xs[c4.w];
-          ad = fmaf(d4.x, x0, ad);
-          ad = fmaf(d4.y, x1, ad);
-          ad = fmaf(d4.z, x2, ad);
-          ad = fmaf(d4.w, x3, ad);
-          al = fmaf(l4.x, x0, al);
-          al = fmaf(l4.y, x1, al);
-          al = fmaf(l4.z, x2, al);
-          al = fmaf(l4.w, x3, al);
-        }
-      } else {
-        for (int64_t q = q0 + 4 * gl; q < q1; q += 4 * G) {
-          const int4 c4 = *reinterpret_cast<const int4*>(ci + q);
-          const float4 d4 = VLoad<VT>::q4(P->dv, q);
-          const float4 l4 = VLoad<VT>::q4(P->lv, q);
-          const float x0 = cs ? vec[c4.x] * cs[c4.x] : vec[c4.x];
-          const float x1 = cs ? vec[c4.y] * cs[c4.y] : vec[c4.y];
-          const float x2 = cs ? vec[c4.z] * cs[c4.z] : vec[c4.z];
-          const float x3 = cs ? vec[c4.w] * cs[c4.w] : vec[c4.w];
-          ad = fmaf(d4.x, x0, ad);
-          ad = fmaf(d4.y, x1, ad);
-          ad = fmaf(d4.z, x2, ad);
-          ad = fmaf(d4.w, x3, ad);
-          al = fmaf(l4.x, x0, al);
-          al = fmaf(l4.y, x1, al);
-          al = fmaf(l4.z, x2, al);
-          al = fmaf(l4.w, x3, al);
-        }
-      }
-      for (int o = G >> 1; o > 0; o >>= 1) {
-        ad += __shfl_xor(ad, o);
-        al += __shfl_xor(al, o);
-      }
-      if (gl == 0) {
-        if constexpr (MODE == kFwdDoseLet) {
-          if (P->out_dose) P->out_dose[r] = ad;
-          if (P->out_letd) P->out_letd[r] = ad > 0.f ? al / ad : 0.f;
-          if (P->out_cdl) P->out_cdl[r] = (float)(P->prm.c * (double)al);
-        } else if constexpr (MODE == kFwdObj) {
-          P->d[r] = ad;
-          P->l[r] = al;
-          objective_row(P, r, ad, al, &acc[0]);
-          if (!finite2(ad, al)) acc[5] += 1.0;
-        } else if constexpr (MODE == kFwdDir) {
-          P->dg[r] = ad;
-          P->lg[r] = al;
-          const unsigned k = P->kind[r];
-          if (k & (kObjDose | kObjCdl)) {
-            const double wo = P->wo[r], c = P->prm.c;
-            if (k & kObjDose) acc[0] += wo * (double)ad * (double)ad;
-            if (k & kObjCdl) acc[0] += wo * c * c * (double)al * (double)al;
-          }
-          if (!finite2(ad, al)) acc[5] += 1.0;
-        } else {
-          P->d[r] = ad;
-          P->l[r] = al;
-          residual_row(P, r, ad, al, acc);
-          acc[6] += objective_value(P, r, ad, al);
-          if (!finite2(ad, al)) acc[5] += 1.0;
-        }
-      }
-    }
+    if (wave < G.n) forward_slice<VT, MODE>(P, G.slice0 + wave, xs, use_lds, vec, lane, wpart[wave]);
+    __syncthreads();
     if constexpr (MODE != kFwdDoseLet) {
-      if (gl == 0) {
-#pragma unroll
-        for (int k = 0; k < kNPart; ++k) gred[gid][k] = acc[k];
+      // the group's partial: its slices' partials in wave order
+      if (tid < kNPart) {
+        double v = 0.0;
+        for (int w = 0; w < G.n; ++w) v += wpart[w][tid];
+        (MODE == kFwdDir ? P->spart_b : P->spart_a)[(int64_t)G.slot * kNPart + tid] = v;
       }
-      __syncthreads();
-      double s[kNPart];
-#pragma unroll
-      for (int k = 0; k < kNPart; ++k) s[k] = 0.0;
-      if (tid == 0) {
-        for (int g2 = 0; g2 < NG; ++g2)
-#pragma unroll
-          for (int k = 0; k < kNPart; ++k) s[k] += gred[g2][k];
-      }
-      if (publish_partials(P->fpart + (int64_t)w.slot * kNPart, s, &P->cnt[0],
-                           P->n_fwd_items, &s_last)) {
-        double tot[kNPart];
-        sum_slots(P->fpart, P->n_fwd_items, tot, sh4);
-        if (tid == 0) {
-          DevState* st = P->st;
-          if constexpr (MODE == kFwdObj) {
-            st->cost = tot[0];
-            st->cost_y = tot[0];
-            st->pstop = 0;
-            st->capped = 0;
-            st->beta = 0.0;
-            if (tot[5] > 0.0) st->nonfinite = 1;
-          } else if constexpr (MODE == kFwdDir) {
-            if (tot[5] > 0.0) st->nonfinite = 1;
-            decide_step(P, tot[0]);
-          } else {
-            finalize_residuals(P, tot);
-          }
-          P->cnt[0] = 0u;
-        }
-      }
-      __syncthreads();
     }
   }
 }
@@ -429,7 +416,6 @@ template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_rows(const DevPlan* __restrict__ plans,
                                                  const RowItem* __restrict__ items) {
   __shared__ double sh4[kBlock / kWave];
-  __shared__ int s_last;
   const RowItem w = items[blockIdx.x];
   const DevPlan* __restrict__ P = plans + w.plan;
   const int tid = threadIdx.x;
@@ -451,63 +437,44 @@ __global__ __launch_bounds__(kBlock) void k_rows(const DevPlan* __restrict__ pla
     }
     if (!finite2(d, l)) acc[5] += 1.0;
   }
+  constexpr unsigned used = MODE == kRowsMoveObj ? 0x21u : 0x7Fu;
   double s[kNPart];
 #pragma unroll
-  for (int k = 0; k < kNPart; ++k) s[k] = block_sum(acc[k], sh4);
-  if (publish_partials(P->rpart + (int64_t)w.slot * kNPart, s, &P->cnt[1], P->n_row_items,
-                       &s_last)) {
-    double tot[kNPart];
-    sum_slots(P->rpart, P->n_row_items, tot, sh4);
-    if (tid == 0) {
-      DevState* st = P->st;
-      if constexpr (MODE == kRowsMoveObj) {
-        st->cost_y = tot[0];
-        if (tot[5] > 0.0) st->nonfinite = 1;
-      } else {
-        finalize_residuals(P, tot);
-      }
-      P->cnt[1] = 0u;
-    }
+  for (int k = 0; k < kNPart; ++k) s[k] = (used & (1u << k)) ? block_sum(acc[k], sh4) : 0.0;
+  if (tid == 0) {
+    double* dst = P->rpart + (int64_t)w.slot * kNPart;
+#pragma unroll
+    for (int k = 0; k < kNPart; ++k) dst[k] = s[k];
   }
 }
 
 // ------------------------------------------------------------ transposed pass --
 
-template <int MODE>
-__device__ __forceinline__ void column_epilogue(const DevPlan* P, int col, float t) {
-  if (P->cscale) t *= P->cscale[col];
-  if constexpr (MODE == kTrGrad || MODE == kTrGradMove) {
-    if constexpr (MODE == kTrGradMove) {
-      const double b = P->st->beta;
-      P->x[col] = (float)((double)P->x[col] - b * (double)P->g[col]);
-    }
-    P->g[col] = t;
-    P->colval[col] = (double)t * (double)t;
-  } else {
-    double y = P->x[col];
-    if constexpr (MODE == kTrProjMove) y -= P->st->beta * (double)P->g[col];
-    const double xn = y - P->st->scale * (double)t;
-    P->x[col] = xn > 0.0 ? (float)xn : 0.f;
-  }
-}
-
-template <int VT, int MODE>
-__global__ __launch_bounds__(kBlock) void k_transposed(const DevPlan* __restrict__ plans,
-                                                       const TrItem* __restrict__ items) {
-  __shared__ float wsum[kBlock / kWave];
-  __shared__ double sh4[kBlock / kWave];
-  __shared__ int s_fin, s_last;
-  const TrItem w = items[blockIdx.x];
+// Work items are laid out so that consecutive logical blocks cover consecutive
+// columns; the hardware hands block b to XCD b % 8, so block b runs logical block
+// (b % 8) * nb8 + b / 8 and each XCD's L2 sees a contiguous column range.
+// TAG only separates the gradient (0) and projection (1) launches in profiles.
+template <int VT, int TAG>
+__global__ __launch_bounds__(kBlock) void k_tr_chunks(const DevPlan* __restrict__ plans,
+                                                      const TrItem* __restrict__ items,
+                                                      int n_items, int nb8) {
+  const int b = blockIdx.x;
+  const int lb = (b & 7) * nb8 + (b >> 3);
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int it = lb * (kBlock / kWave) + wave;
+  if (it >= n_items) return;
+  const TrItem w = items[it];
   const DevPlan* __restrict__ P = plans + w.plan;
-  const int tid = threadIdx.x;
-  const int32_t* __restrict__ ri = P->ri;
+  const int32_t* __restrict__ ri = TAG == 0 ? P->gri : P->ri;
+  const void* __restrict__ cdv = TAG == 0 ? P->gcdv : P->cdv;
+  const void* __restrict__ clv = TAG == 0 ? P->gclv : P->clv;
   const float2* __restrict__ cf = P->coef;
   float acc = 0.f;
-#pragma unroll 2
-  for (int64_t q = w.q0 + 4 * tid; q < w.q1; q += 4 * kBlock) {
+#pragma unroll 4
+  for (int64_t q = w.q0 + 4 * lane; q < w.q1; q += 4 * kWave) {
     const int4 r4 = *reinterpret_cast<const int4*>(ri + q);
-    const float4 d4 = VLoad<VT>::q4(P->cdv, q);
-    const float4 l4 = VLoad<VT>::q4(P->clv, q);
+    const float4 d4 = VLoad<VT>::q4(cdv, q);
+    const float4 l4 = VLoad<VT>::q4(clv, q);
     const float2 c0 = cf[r4.x], c1 = cf[r4.y], c2 = cf[r4.z], c3 = cf[r4.w];
     acc = fmaf(d4.x, c0.x, acc);
     acc = fmaf(l4.x, c0.y, acc);
@@ -518,83 +485,137 @@ __global__ __launch_bounds__(kBlock) void k_transposed(const DevPlan* __restrict
     acc = fmaf(d4.w, c3.x, acc);
     acc = fmaf(l4.w, c3.y, acc);
   }
-  for (int o = kWave / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-  if ((tid & (kWave - 1)) == 0) wsum[tid / kWave] = acc;
-  __syncthreads();
-  if (tid == 0) {
-    float t = (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
-    int fin = 1;
-    if (w.nchunks > 1) {
-      P->tpart[w.tslot0 + w.chunk] = t;
-      __threadfence();
-      const unsigned tk = atomicAdd(&P->cnt[kPlanTickets + w.col], 1u);
-      fin = (tk == (unsigned)w.nchunks - 1) ? 1 : 0;
-      if (fin) {
-        __threadfence();
-        t = 0.f;
-        for (int c = 0; c < w.nchunks; ++c) t += __builtin_nontemporal_load(P->tpart + w.tslot0 + c);
-        P->cnt[kPlanTickets + w.col] = 0u;
+  acc = wave_sumf(acc);
+  if (lane == 0) P->tpart[w.tslot] = acc;
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_tcol(const DevPlan* __restrict__ plans,
+                                                 const ColBlock* __restrict__ blocks) {
+  __shared__ double sh4[kBlock / kWave];
+  const ColBlock cb = blocks[blockIdx.x];
+  const DevPlan* __restrict__ P = plans + cb.plan;
+  const int j = cb.c0 + threadIdx.x;
+  double cv = 0.0;
+  if (j < cb.c1) {
+    constexpr bool grad = MODE == kColGrad || MODE == kColGradMove;
+    const int ts = grad ? P->gcol_tslot0[j] : P->col_tslot0[j];
+    const int n = grad ? P->gcol_nch[j] : P->col_nch[j];
+    float t = 0.f;
+    for (int c = 0; c < n; ++c) t += P->tpart[ts + c];
+    if (P->cscale) t *= P->cscale[j];
+    if constexpr (MODE == kColGrad || MODE == kColGradMove) {
+      if constexpr (MODE == kColGradMove) {
+        const double b = P->st->beta;
+        P->x[j] = (float)((double)P->x[j] - b * (double)P->g[j]);
       }
+      P->g[j] = t;
+      cv = (double)t * (double)t;
+    } else {
+      double y = P->x[j];
+      if constexpr (MODE == kColProjMove) y -= P->st->beta * (double)P->g[j];
+      const double xn = y - P->st->scale * (double)t;
+      P->x[j] = xn > 0.0 ? (float)xn : 0.f;
     }
-    if (fin) column_epilogue<MODE>(P, w.col, t);
-    s_fin = fin;
   }
-  if constexpr (MODE == kTrGrad || MODE == kTrGradMove) {
-    __syncthreads();
-    if (s_fin) {
-      // plan-level ||g||^2: the finaliser of the plan's last column sums colval
-      if (tid == 0) {
-        __threadfence();
-        const unsigned tk = atomicAdd(&P->cnt[2], 1u);
-        s_last = (tk == (unsigned)P->C - 1) ? 1 : 0;
+  if constexpr (MODE == kColGrad || MODE == kColGradMove) {
+    const double s = block_sum(cv, sh4);
+    if (threadIdx.x == 0) P->gpart[cb.slot] = s;
+  }
+}
+
+// ------------------------------------------------------------ finalisation ----
+
+__device__ __forceinline__ void sum_slots(const double* part, int n, double* out,
+                                          unsigned used, double* sh4) {
+  double s[kNPart];
+#pragma unroll
+  for (int k = 0; k < kNPart; ++k) s[k] = 0.0;
+  for (int i = threadIdx.x; i < n; i += kBlock) {
+    const double* p = part + (int64_t)i * kNPart;
+#pragma unroll
+    for (int k = 0; k < kNPart; ++k)
+      if (used & (1u << k)) s[k] += p[k];
+  }
+#pragma unroll
+  for (int k = 0; k < kNPart; ++k) out[k] = (used & (1u << k)) ? block_sum(s[k], sh4) : 0.0;
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_finalize(const DevPlan* __restrict__ plans) {
+  __shared__ double sh4[kBlock / kWave];
+  const DevPlan* __restrict__ P = plans + blockIdx.x;
+  double a[kNPart];
+  if constexpr (MODE == kFinDir0 || MODE == kFinDir) {
+    double b[kNPart];
+    sum_slots(P->spart_b, P->n_groups, b, 0x21u, sh4);
+    double g = 0.0;
+    for (int i = threadIdx.x; i < P->n_col_blocks; i += kBlock) g += P->gpart[i];
+    const double G = block_sum(g, sh4);
+    if constexpr (MODE == kFinDir0) sum_slots(P->spart_a, P->n_groups, a, 0x21u, sh4);
+    if (threadIdx.x == 0) {
+      DevState* st = P->st;
+      if constexpr (MODE == kFinDir0) {
+        st->cost = a[0];
+        st->cost_y = a[0];
+        st->pstop = 0;
+        st->capped = 0;
+        st->beta = 0.0;
+        if (a[5] > 0.0) st->nonfinite = 1;
       }
-      __syncthreads();
-      if (s_last) {
-        __threadfence();
-        double s = 0.0;
-        for (int64_t j = tid; j < P->C; j += kBlock) s += __builtin_nontemporal_load(P->colval + j);
-        const double G = block_sum(s, sh4);
-        if (tid == 0) {
-          DevState* st = P->st;
-          st->G = G;
-          if (!isfinite(G)) st->nonfinite = 1;
-          P->cnt[2] = 0u;
-        }
-      }
+      if (b[5] > 0.0) st->nonfinite = 1;
+      decide_step(P, G, b[0]);
     }
+  } else if constexpr (MODE == kFinMoveObj) {
+    sum_slots(P->rpart, P->n_row_items, a, 0x21u, sh4);
+    if (threadIdx.x == 0) {
+      P->st->cost_y = a[0];
+      if (a[5] > 0.0) P->st->nonfinite = 1;
+    }
+  } else if constexpr (MODE == kFinResidRows) {
+    sum_slots(P->rpart, P->n_row_items, a, 0x7Fu, sh4);
+    if (threadIdx.x == 0) finalize_residuals(P, a);
+  } else {
+    sum_slots(P->spart_a, P->n_groups, a, 0x7Fu, sh4);
+    if (threadIdx.x == 0) finalize_residuals(P, a);
   }
 }
 
 // ---------------------------------------------------------------- launchers ----
 
 template <int VT>
-static void launch_forward_vt(int mode, const DevPlan* plans, const FwdItem* items,
-                              int n_items, int grid, int lds_floats, hipStream_t s) {
+static void launch_forward_vt(int mode, const DevPlan* plans, const FwdGroup* groups,
+                              int n_groups, int grid, int lds_floats, uint32_t* ctr,
+                              hipStream_t s) {
   const size_t lds = (size_t)lds_floats * sizeof(float);
   switch (mode) {
     case kFwdDoseLet:
-      k_forward<VT, kFwdDoseLet><<<grid, kBlock, lds, s>>>(plans, items, n_items, lds_floats);
+      k_forward<VT, kFwdDoseLet><<<grid, kFwdBlock, lds, s>>>(plans, groups, n_groups,
+                                                               lds_floats, ctr);
       break;
     case kFwdObj:
-      k_forward<VT, kFwdObj><<<grid, kBlock, lds, s>>>(plans, items, n_items, lds_floats);
+      k_forward<VT, kFwdObj><<<grid, kFwdBlock, lds, s>>>(plans, groups, n_groups, lds_floats,
+                                                           ctr);
       break;
     case kFwdDir:
-      k_forward<VT, kFwdDir><<<grid, kBlock, lds, s>>>(plans, items, n_items, lds_floats);
+      k_forward<VT, kFwdDir><<<grid, kFwdBlock, lds, s>>>(plans, groups, n_groups, lds_floats,
+                                                           ctr);
       break;
     default:
-      k_forward<VT, kFwdResid><<<grid, kBlock, lds, s>>>(plans, items, n_items, lds_floats);
+      k_forward<VT, kFwdResid><<<grid, kFwdBlock, lds, s>>>(plans, groups, n_groups,
+                                                             lds_floats, ctr);
       break;
   }
 }
 
-void launch_forward(int vtype, int mode, const DevPlan* plans, const FwdItem* items,
-                    int n_items, int grid, int lds_floats, hipStream_t s) {
+void launch_forward(int vtype, int mode, const DevPlan* plans, const FwdGroup* groups,
+                    int n_groups, int grid, int lds_floats, uint32_t* ctr, hipStream_t s) {
   if (vtype == kF16)
-    launch_forward_vt<kF16>(mode, plans, items, n_items, grid, lds_floats, s);
+    launch_forward_vt<kF16>(mode, plans, groups, n_groups, grid, lds_floats, ctr, s);
   else if (vtype == kBF16)
-    launch_forward_vt<kBF16>(mode, plans, items, n_items, grid, lds_floats, s);
+    launch_forward_vt<kBF16>(mode, plans, groups, n_groups, grid, lds_floats, ctr, s);
   else
-    launch_forward_vt<kF32>(mode, plans, items, n_items, grid, lds_floats, s);
+    launch_forward_vt<kF32>(mode, plans, groups, n_groups, grid, lds_floats, ctr, s);
 }
 
 void launch_rows(int mode, const DevPlan* plans, const RowItem* items, int n_items,
@@ -605,25 +626,47 @@ void launch_rows(int mode, const DevPlan* plans, const RowItem* items, int n_ite
     k_rows<kRowsMoveResid><<<n_items, kBlock, 0, s>>>(plans, items);
 }
 
-template <int VT>
-static void launch_tr_vt(int mode, const DevPlan* plans, const TrItem* items, int n_items,
-                         hipStream_t s) {
+template <int TAG>
+static void launch_tr_tag(int vtype, const DevPlan* plans, const TrItem* items, int n_items,
+                          int grid, int nb8, hipStream_t s) {
+  if (vtype == kF16)
+    k_tr_chunks<kF16, TAG><<<grid, kBlock, 0, s>>>(plans, items, n_items, nb8);
+  else if (vtype == kBF16)
+    k_tr_chunks<kBF16, TAG><<<grid, kBlock, 0, s>>>(plans, items, n_items, nb8);
+  else
+    k_tr_chunks<kF32, TAG><<<grid, kBlock, 0, s>>>(plans, items, n_items, nb8);
+}
+
+void launch_tr_chunks(int vtype, int tag, const DevPlan* plans, const TrItem* items,
+                      int n_items, hipStream_t s) {
+  const int per = kBlock / kWave;
+  const int nblocks = (n_items + per - 1) / per;
+  const int nb8 = (nblocks + 7) / 8;
+  const int grid = nb8 * 8;
+  if (tag == 0)
+    launch_tr_tag<0>(vtype, plans, items, n_items, grid, nb8, s);
+  else
+    launch_tr_tag<1>(vtype, plans, items, n_items, grid, nb8, s);
+}
+
+void launch_tcol(int mode, const DevPlan* plans, const ColBlock* blocks, int n_blocks,
+                 hipStream_t s) {
   switch (mode) {
-    case kTrGrad: k_transposed<VT, kTrGrad><<<n_items, kBlock, 0, s>>>(plans, items); break;
-    case kTrGradMove: k_transposed<VT, kTrGradMove><<<n_items, kBlock, 0, s>>>(plans, items); break;
-    case kTrProj: k_transposed<VT, kTrProj><<<n_items, kBlock, 0, s>>>(plans, items); break;
-    default: k_transposed<VT, kTrProjMove><<<n_items, kBlock, 0, s>>>(plans, items); break;
+    case kColGrad: k_tcol<kColGrad><<<n_blocks, kBlock, 0, s>>>(plans, blocks); break;
+    case kColGradMove: k_tcol<kColGradMove><<<n_blocks, kBlock, 0, s>>>(plans, blocks); break;
+    case kColProj: k_tcol<kColProj><<<n_blocks, kBlock, 0, s>>>(plans, blocks); break;
+    default: k_tcol<kColProjMove><<<n_blocks, kBlock, 0, s>>>(plans, blocks); break;
   }
 }
 
-void launch_transposed(int vtype, int mode, const DevPlan* plans, const TrItem* items,
-                       int n_items, hipStream_t s) {
-  if (vtype == kF16)
-    launch_tr_vt<kF16>(mode, plans, items, n_items, s);
-  else if (vtype == kBF16)
-    launch_tr_vt<kBF16>(mode, plans, items, n_items, s);
-  else
-    launch_tr_vt<kF32>(mode, plans, items, n_items, s);
+void launch_finalize(int mode, const DevPlan* plans, int n_plans, hipStream_t s) {
+  switch (mode) {
+    case kFinDir0: k_finalize<kFinDir0><<<n_plans, kBlock, 0, s>>>(plans); break;
+    case kFinDir: k_finalize<kFinDir><<<n_plans, kBlock, 0, s>>>(plans); break;
+    case kFinMoveObj: k_finalize<kFinMoveObj><<<n_plans, kBlock, 0, s>>>(plans); break;
+    case kFinResidRows: k_finalize<kFinResidRows><<<n_plans, kBlock, 0, s>>>(plans); break;
+    default: k_finalize<kFinResidFwd><<<n_plans, kBlock, 0, s>>>(plans); break;
+  }
 }
 
 hipError_t set_forward_lds_limit(int vtype, size_t bytes) {

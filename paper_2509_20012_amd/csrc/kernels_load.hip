@@ -1,6 +1,6 @@
 // Load-time kernels: the device side of Table 2 step (iii) of Borys et al.
 // (arXiv 2509.20012), loading the dose and LETd influence matrices.  They
-// validate the CSR input, build the row-padded CSR used by the forward kernels,
+// validate the CSR input, build the sliced-ELL copy used by the forward kernels,
 // build the CSC copy (rows ascending inside every column, so the transposed
 // products are deterministic) with a row-block counting sort, quantise values for
 // 16-bit storage, and compute the per-row FP64 moments sum D^2, sum L^2, sum D L
@@ -33,10 +33,10 @@ __device__ __forceinline__ void store_value(int vtype, void* base, int64_t pos, 
   }
 }
 
-__device__ __forceinline__ double load_value(int vtype, const void* base, int64_t pos) {
-  if (vtype == kF32) return static_cast<const float*>(base)[pos];
-  if (vtype == kF16) return (double)(float)static_cast<const _Float16*>(base)[pos];
-  return (double)__uint_as_float((uint32_t)static_cast<const uint16_t*>(base)[pos] << 16);
+// The value a 16-bit slot holds for input v with column scale sc, as a double.
+__device__ __forceinline__ double stored_value(int vtype, float v, float sc) {
+  if (vtype == kF16) return (double)(float)(_Float16)(v / sc);
+  return (double)__uint_as_float((uint32_t)f32_to_bf16_rne(v / sc) << 16);
 }
 
 __global__ __launch_bounds__(kBlock) void k_validate(int64_t R, int64_t C,
@@ -83,31 +83,38 @@ __global__ void k_col_scale(int64_t C, const uint32_t* __restrict__ bits, float*
   scale[j] = m > 0.f ? m : 1.f;
 }
 
-__global__ __launch_bounds__(kBlock) void k_pack_csr(int vtype, int64_t R,
-                                                     const int64_t* __restrict__ row_ptr,
-                                                     const int32_t* __restrict__ col,
-                                                     const float* __restrict__ dv,
-                                                     const float* __restrict__ lv,
-                                                     const float* __restrict__ scale,
-                                                     const int64_t* __restrict__ rp,
-                                                     int32_t* ci, void* pdv, void* plv) {
+// Sliced-ELL packing: every row is written by one wavefront into its slice position
+// sp = slice * rpw + position (chosen on the host after the length sort).  Slots that
+// no entry reaches keep the zero fill (index 0, value 0).
+__global__ __launch_bounds__(kBlock) void k_pack_sell(int vtype, int64_t R, int lpr_log2,
+                                                      const int64_t* __restrict__ row_ptr,
+                                                      const int32_t* __restrict__ col,
+                                                      const float* __restrict__ dv,
+                                                      const float* __restrict__ lv,
+                                                      const float* __restrict__ scale,
+                                                      const int32_t* __restrict__ rslice,
+                                                      const int64_t* __restrict__ sbase,
+                                                      int32_t* sci, void* sdv, void* slv) {
   const int64_t row = (int64_t)blockIdx.x * kRowsPerWg + threadIdx.x / kWave;
   const int lane = threadIdx.x % kWave;
   if (row >= R) return;
+  const int rpw_log2 = 6 - lpr_log2;
+  const int sp = rslice[row];
+  const int64_t s = sp >> rpw_log2;
+  const int p = sp & ((1 << rpw_log2) - 1);
+  const int lpr = 1 << lpr_log2;
+  const int64_t base = sbase[s];
   const int64_t a = row_ptr[row], n = row_ptr[row + 1] - a;
-  const int64_t o = rp[row], np = rp[row + 1] - o;
-  for (int64_t t = lane; t < np; t += kWave) {
-    if (t < n) {
-      const int32_t c = col[a + t];
-      const float s = scale ? scale[c] : 1.f;
-      ci[o + t] = c;
-      store_value(vtype, pdv, o + t, dv[a + t], s);
-      store_value(vtype, plv, o + t, lv[a + t], s);
-    } else {  // padding slot: index 0, value 0
-      ci[o + t] = 0;
-      store_value(vtype, pdv, o + t, 0.f, 1.f);
-      store_value(vtype, plv, o + t, 0.f, 1.f);
-    }
+  for (int64_t e = lane; e < n; e += kWave) {
+    const int64_t quad = e >> 2;
+    const int64_t t = quad >> lpr_log2;
+    const int64_t j = quad & (lpr - 1);
+    const int64_t slot = base + t * 256 + ((int64_t)p * lpr + j) * 4 + (e & 3);
+    const int32_t c = col[a + e];
+    const float sc = scale ? scale[c] : 1.f;
+    sci[slot] = c;
+    store_value(vtype, sdv, slot, dv[a + e], sc);
+    store_value(vtype, slv, slot, lv[a + e], sc);
   }
 }
 
@@ -167,21 +174,26 @@ __global__ __launch_bounds__(kBlock) void k_fill_csc(int vtype, int64_t R, int64
   }
 }
 
+// Per-row FP64 moments sum D^2, sum L^2, sum D L of the values the kernels multiply
+// (for 16-bit storage: the quantised value times the column scale).
 __global__ __launch_bounds__(kBlock) void k_moments(int vtype, int64_t R,
-                                                    const int64_t* __restrict__ rp,
-                                                    const void* __restrict__ pdv,
-                                                    const void* __restrict__ plv,
-                                                    const int32_t* __restrict__ ci,
+                                                    const int64_t* __restrict__ row_ptr,
+                                                    const int32_t* __restrict__ col,
+                                                    const float* __restrict__ dv,
+                                                    const float* __restrict__ lv,
                                                     const float* __restrict__ scale,
                                                     double* mom) {
   const int64_t row = (int64_t)blockIdx.x * kRowsPerWg + threadIdx.x / kWave;
   const int lane = threadIdx.x % kWave;
   if (row >= R) return;
   double sdd = 0.0, sll = 0.0, sdl = 0.0;
-  for (int64_t k = rp[row] + lane; k < rp[row + 1]; k += kWave) {
-    const double s = scale ? (double)scale[ci[k]] : 1.0;
-    const double d = load_value(vtype, pdv, k) * s;
-    const double l = load_value(vtype, plv, k) * s;
+  for (int64_t k = row_ptr[row] + lane; k < row_ptr[row + 1]; k += kWave) {
+    double d = dv[k], l = lv[k];
+    if (vtype != kF32) {
+      const float sc = scale[col[k]];
+      d = stored_value(vtype, dv[k], sc) * (double)sc;
+      l = stored_value(vtype, lv[k], sc) * (double)sc;
+    }
     sdd += d * d;
     sll += l * l;
     sdl += d * l;
@@ -198,8 +210,18 @@ __global__ __launch_bounds__(kBlock) void k_moments(int vtype, int64_t R,
   }
 }
 
-// flags: 1 non-finite bound/weight/target of an enabled kind, 2 lower > upper bound,
-// 4 non-positive AMS weight or negative objective weight, 8 unknown kind bits
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  // SplitMix64 finaliser (Steele, Lea, Flood 2014)
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// flags[0]: 1 non-finite bound/weight/target of an enabled kind, 2 lower > upper bound,
+// 4 non-positive AMS weight or negative objective weight, 8 unknown kind bits.
+// flags[2..3]: order-independent 64-bit fingerprint of the kind array (a sum of
+// hashes of (row, kind) pairs), so per-problem preprocessing can be reused.
 __global__ void k_check_problem(int64_t R, const uint16_t* __restrict__ kind,
                                 const float* __restrict__ dlo, const float* __restrict__ dhi,
                                 const float* __restrict__ clo, const float* __restrict__ chi,
@@ -229,6 +251,61 @@ __global__ void k_check_problem(int64_t R, const uint16_t* __restrict__ kind,
       if (k & kObjCdl && !isfinite(ct[r])) f |= 1u;
     }
     if (f) atomicOr(flags, f);
+    atomicAdd(reinterpret_cast<unsigned long long*>(flags + 2),
+              (unsigned long long)mix64(((uint64_t)r << 16) | k));
+  }
+}
+
+// Entries of column j whose row carries an objective term.
+__global__ __launch_bounds__(kBlock) void k_obj_count(int64_t C, const int64_t* __restrict__ cp,
+                                                      const uint32_t* __restrict__ len,
+                                                      const int32_t* __restrict__ ri,
+                                                      const uint16_t* __restrict__ kind,
+                                                      uint32_t* count) {
+  const int64_t j = (int64_t)blockIdx.x * kRowsPerWg + threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  if (j >= C) return;
+  uint32_t n = 0;
+  // only the real entries of the column (padding slots hold row 0)
+  for (int64_t k = cp[j] + lane; k < cp[j] + (int64_t)len[j]; k += kWave)
+    n += (kind[ri[k]] & (kObjDose | kObjCdl)) ? 1u : 0u;
+  for (int o = kWave / 2; o > 0; o >>= 1) n += __shfl_xor(n, o);
+  if (lane == 0) count[j] = n;
+}
+
+// Order-preserving compaction of the objective-row entries of every column into
+// the gradient CSC (one wavefront per column, ballot prefix sums per 64 entries).
+__global__ __launch_bounds__(kBlock) void k_obj_fill(int vtype, int64_t C,
+                                                     const int64_t* __restrict__ cp,
+                                                     const uint32_t* __restrict__ len,
+                                                     const int32_t* __restrict__ ri,
+                                                     const void* __restrict__ cdv,
+                                                     const void* __restrict__ clv,
+                                                     const uint16_t* __restrict__ kind,
+                                                     const int64_t* __restrict__ ocp,
+                                                     int32_t* ori, void* ocdv, void* oclv) {
+  const int64_t j = (int64_t)blockIdx.x * kRowsPerWg + threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  if (j >= C) return;
+  const int64_t a = cp[j], b = cp[j] + (int64_t)len[j];
+  int64_t out = ocp[j];
+  for (int64_t k0 = a; k0 < b; k0 += kWave) {
+    const int64_t k = k0 + lane;
+    const bool take = k < b && (kind[ri[k]] & (kObjDose | kObjCdl));
+    const uint64_t m = __ballot(take);
+    const int before = __popcll(m & ((1ull << lane) - 1ull));
+    if (take) {
+      const int64_t o = out + before;
+      ori[o] = ri[k];
+      if (vtype == kF32) {
+        static_cast<float*>(ocdv)[o] = static_cast<const float*>(cdv)[k];
+        static_cast<float*>(oclv)[o] = static_cast<const float*>(clv)[k];
+      } else {
+        static_cast<uint16_t*>(ocdv)[o] = static_cast<const uint16_t*>(cdv)[k];
+        static_cast<uint16_t*>(oclv)[o] = static_cast<const uint16_t*>(clv)[k];
+      }
+    }
+    out += __popcll(m);
   }
 }
 
@@ -254,12 +331,13 @@ void launch_col_scale(int64_t C, const uint32_t* bits, float* scale, hipStream_t
   if (C > 0) k_col_scale<<<(unsigned)((C + 255) / 256), 256, 0, s>>>(C, bits, scale);
 }
 
-void launch_pack_csr(int vtype, int64_t R, const int64_t* row_ptr, const int32_t* col,
-                     const float* dv, const float* lv, const float* scale, const int64_t* rp,
-                     int32_t* ci, void* pdv, void* plv, hipStream_t s) {
+void launch_pack_sell(int vtype, int64_t R, int lpr_log2, const int64_t* row_ptr,
+                      const int32_t* col, const float* dv, const float* lv, const float* scale,
+                      const int32_t* rslice, const int64_t* sbase, int32_t* sci, void* sdv,
+                      void* slv, hipStream_t s) {
   if (R > 0)
-    k_pack_csr<<<row_grid(R), kBlock, 0, s>>>(vtype, R, row_ptr, col, dv, lv, scale, rp, ci,
-                                               pdv, plv);
+    k_pack_sell<<<row_grid(R), kBlock, 0, s>>>(vtype, R, lpr_log2, row_ptr, col, dv, lv, scale,
+                                                rslice, sbase, sci, sdv, slv);
 }
 
 void launch_block_count(int64_t R, int64_t C, int rows_per_block, const int64_t* row_ptr,
@@ -282,9 +360,23 @@ void launch_fill_csc(int vtype, int64_t R, int64_t C, int rows_per_block,
                                     ri, cdv, clv);
 }
 
-void launch_moments(int vtype, int64_t R, const int64_t* rp, const void* pdv, const void* plv,
-                    const int32_t* ci, const float* scale, double* mom, hipStream_t s) {
-  if (R > 0) k_moments<<<row_grid(R), kBlock, 0, s>>>(vtype, R, rp, pdv, plv, ci, scale, mom);
+void launch_moments(int vtype, int64_t R, const int64_t* row_ptr, const int32_t* col,
+                    const float* dv, const float* lv, const float* scale, double* mom,
+                    hipStream_t s) {
+  if (R > 0) k_moments<<<row_grid(R), kBlock, 0, s>>>(vtype, R, row_ptr, col, dv, lv, scale, mom);
+}
+
+void launch_obj_count(int64_t C, const int64_t* cp, const uint32_t* len, const int32_t* ri,
+                      const uint16_t* kind, uint32_t* count, hipStream_t s) {
+  if (C > 0) k_obj_count<<<row_grid(C), kBlock, 0, s>>>(C, cp, len, ri, kind, count);
+}
+
+void launch_obj_fill(int vtype, int64_t C, const int64_t* cp, const uint32_t* len,
+                     const int32_t* ri, const void* cdv, const void* clv, const uint16_t* kind,
+                     const int64_t* ocp, int32_t* ori, void* ocdv, void* oclv, hipStream_t s) {
+  if (C > 0)
+    k_obj_fill<<<row_grid(C), kBlock, 0, s>>>(vtype, C, cp, len, ri, cdv, clv, kind, ocp, ori,
+                                               ocdv, oclv);
 }
 
 void launch_check_problem(int64_t R, const uint16_t* kind, const float* dlo, const float* dhi,

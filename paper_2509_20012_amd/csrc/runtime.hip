@@ -13,6 +13,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <numeric>
 #include <string>
 #include <vector>
 
@@ -40,11 +41,9 @@ fredopt_status fail(fredopt_status s, const char* fmt, ...) {
   } while (0)
 
 constexpr size_t kAlign = 256;
-constexpr int64_t kFwdItemMinSlots = 1024;
-constexpr int64_t kFwdItemMaxSlots = 65536;
-constexpr int64_t kFwdItemMaxRows = 4096;
+constexpr int64_t kSortWindow = 8192;     // rows sorted by length inside such windows
 constexpr int64_t kRowItemRows = 2048;
-constexpr int64_t kTrChunkMin = 1024;
+constexpr int64_t kTrChunkMin = 256;
 constexpr int64_t kTrChunkDefault = 4096;
 constexpr int64_t kBlockCountCap = int64_t(1) << 24;
 
@@ -52,28 +51,109 @@ inline size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
 int value_bytes(int storage) { return storage == FREDOPT_F32 ? 4 : 2; }
 
+int auto_lpr_log2(int64_t R, int64_t nnz) {
+  const double avg = R > 0 ? (double)nnz / (double)R : 0.0;
+  int lg = 0;
+  while (lg < 4 && (double)(1 << (lg + 1)) <= avg / 64.0) ++lg;
+  return lg;
+}
+
+bool lpr_log2_of(int32_t lanes, int64_t R, int64_t nnz, int* out) {
+  if (lanes == 0) {
+    *out = auto_lpr_log2(R, nnz);
+    return true;
+  }
+  for (int lg = 0; lg <= 4; ++lg)
+    if (lanes == (1 << lg)) {
+      *out = lg;
+      return true;
+    }
+  return false;
+}
+
+// Sliced-ELL geometry of one pattern.
+struct Sell {
+  int lpr_log2 = 0;
+  int64_t n_slices = 0, slots = 0;
+  std::vector<int64_t> base;   // n_slices + 1
+  std::vector<int32_t> width;  // n_slices
+  std::vector<int32_t> srow;   // n_slices * rpw
+  std::vector<int32_t> rslice; // R
+};
+
+// Rows sorted by length (descending, stable) inside windows of kSortWindow rows,
+// cut into slices of rpw rows; each slice is as wide as its longest row.
+void build_sell(const int64_t* rp, int64_t R, int lpr_log2, bool full, Sell* S) {
+  const int rpw = kWave >> lpr_log2;
+  const int64_t lpr4 = 4LL << lpr_log2;
+  S->lpr_log2 = lpr_log2;
+  S->n_slices = 0;
+  S->slots = 0;
+  if (full) {
+    S->base.assign(1, 0);
+    S->width.clear();
+    S->srow.clear();
+    S->rslice.assign(R, -1);
+  }
+  std::vector<int64_t> idx;
+  for (int64_t w0 = 0; w0 < R; w0 += kSortWindow) {
+    const int64_t w1 = std::min(R, w0 + kSortWindow);
+    idx.resize(w1 - w0);
+    std::iota(idx.begin(), idx.end(), w0);
+    std::stable_sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) {
+      return rp[a + 1] - rp[a] > rp[b + 1] - rp[b];
+    });
+    for (size_t s0 = 0; s0 < idx.size(); s0 += rpw) {
+      const int64_t len = rp[idx[s0] + 1] - rp[idx[s0]];  // longest row of the slice
+      const int64_t steps = (len + lpr4 - 1) / lpr4;
+      if (full) {
+        for (int p = 0; p < rpw; ++p) {
+          const size_t k = s0 + p;
+          const int32_t row = k < idx.size() ? (int32_t)idx[k] : -1;
+          S->srow.push_back(row);
+          if (row >= 0) S->rslice[row] = (int32_t)(S->n_slices * rpw + p);
+        }
+        S->width.push_back((int32_t)steps);
+        S->base.push_back(S->base.back() + steps * 256);
+      }
+      S->slots += steps * 256;
+      S->n_slices += 1;
+    }
+  }
+}
+
 struct Layout {
-  size_t table, state, cnt, rp, cp, ci, dv, lv, ri, cdv, clv, cscale, mom;
-  size_t d, l, dg, lg, coef, g, colval, fpart, rpart, tpart;
-  size_t fwd_items, row_items, tr_items, bc, colcount, colmax, flags, total;
-  int64_t csr_slots, csc_slots, max_fwd, max_rows, max_tr;
+  size_t table, state, ctr, sbase, swidth, srow, sci, sdv, slv, cp, ri, cdv, clv;
+  size_t col_tslot0, col_nch, cscale, mom, d, l, dg, lg, coef, g;
+  size_t gri, gcdv, gclv, gcol_tslot0, gcol_nch, ocp, ocount, gtr_items;
+  size_t spart_a, spart_b, rpart, gpart, tpart, groups, row_items, tr_items, col_blocks;
+  size_t bc, colcount, colmax, flags, rslice, total;
+  int64_t sell_slots, n_slices, csc_slots, obj_slots, max_rows, max_tr, n_groups, n_col_blocks;
   int64_t rows_per_block, nb;
 };
 
-// Upper-bound layout for every pattern with these sizes (row / column padding to a
-// multiple of 4 slots adds at most 3 slots per row / column).
-bool make_layout(int64_t R, int64_t C, int64_t nnz, int storage, Layout* L) {
+constexpr int kDefaultGradientReservePct = 25;
+
+int reserve_pct_of(int32_t v) { return v == 0 ? kDefaultGradientReservePct : (v < 0 ? 0 : std::min(v, 100)); }
+
+// Layout for given SELL sizes; CSC and work lists use pattern-free bounds.
+bool make_layout(int64_t R, int64_t C, int64_t nnz, int storage, int lpr_log2,
+                 int64_t sell_slots, int64_t n_slices, int reserve_pct, Layout* L) {
   if (R < 0 || C < 1 || nnz < 0 || R >= (int64_t(1) << 31) || C >= (int64_t(1) << 31))
     return false;
   if (storage < FREDOPT_F32 || storage > FREDOPT_BF16) return false;
-  const int64_t csr = nnz + 3 * R, csc = nnz + 3 * C;
+  const int64_t csc = nnz + 3 * C;
   if (csc >= (int64_t(1) << 32) - 4) return false;
+  const int rpw = kWave >> lpr_log2;
   const int vb = value_bytes(storage);
-  L->csr_slots = csr;
+  L->sell_slots = sell_slots;
+  L->n_slices = n_slices;
   L->csc_slots = csc;
-  L->max_fwd = csr / kFwdItemMinSlots + R / kFwdItemMaxRows + 2;
+  L->obj_slots = ((csc * reserve_pct) / 100 + 3) & ~int64_t(3);
   L->max_rows = R / kRowItemRows + 2;
   L->max_tr = C + csc / kTrChunkMin + 2;
+  L->n_groups = (n_slices + kFwdWaves - 1) / kFwdWaves + 1;
+  L->n_col_blocks = (C + kBlock - 1) / kBlock;
   int64_t rpb = 1024;
   if (R > 0 && R * C / rpb > kBlockCountCap) rpb = (R * C + kBlockCountCap - 1) / kBlockCountCap;
   L->rows_per_block = rpb;
@@ -84,46 +164,74 @@ bool make_layout(int64_t R, int64_t C, int64_t nnz, int storage, Layout* L) {
     o = align_up(o + bytes);
     return at;
   };
+  const size_t Rm = (size_t)std::max<int64_t>(R, 1);
   L->table = take(sizeof(DevPlan));
   L->state = take(sizeof(DevState));
-  L->cnt = take(sizeof(uint32_t) * (kPlanTickets + C));
-  L->rp = take(sizeof(int64_t) * (R + 1));
+  L->ctr = take(sizeof(uint32_t) * kCounters);
+  L->sbase = take(sizeof(int64_t) * (n_slices + 1));
+  L->swidth = take(sizeof(int32_t) * (n_slices + 1));
+  L->srow = take(sizeof(int32_t) * (n_slices * rpw + 1));
+  L->sci = take(sizeof(int32_t) * sell_slots);
+  L->sdv = take((size_t)vb * sell_slots);
+  L->slv = take((size_t)vb * sell_slots);
   L->cp = take(sizeof(int64_t) * (C + 1));
-  L->ci = take(sizeof(int32_t) * csr);
-  L->dv = take((size_t)vb * csr);
-  L->lv = take((size_t)vb * csr);
   L->ri = take(sizeof(int32_t) * csc);
   L->cdv = take((size_t)vb * csc);
   L->clv = take((size_t)vb * csc);
+  L->col_tslot0 = take(sizeof(int32_t) * C);
+  L->col_nch = take(sizeof(int32_t) * C);
+  L->gri = take(sizeof(int32_t) * L->obj_slots);
+  L->gcdv = take((size_t)vb * L->obj_slots);
+  L->gclv = take((size_t)vb * L->obj_slots);
+  L->gcol_tslot0 = take(sizeof(int32_t) * C);
+  L->gcol_nch = take(sizeof(int32_t) * C);
+  L->ocp = take(sizeof(int64_t) * (C + 1));
+  L->ocount = take(sizeof(uint32_t) * C);
+  L->gtr_items = take(sizeof(TrItem) * L->max_tr);
   L->cscale = take(sizeof(float) * C);
-  L->mom = take(sizeof(double) * 3 * (R > 0 ? R : 1));
-  L->d = take(sizeof(float) * R);
-  L->l = take(sizeof(float) * R);
-  L->dg = take(sizeof(float) * R);
-  L->lg = take(sizeof(float) * R);
-  L->coef = take(sizeof(float2) * R);
+  L->mom = take(sizeof(double) * 3 * Rm);
+  L->d = take(sizeof(float) * Rm);
+  L->l = take(sizeof(float) * Rm);
+  L->dg = take(sizeof(float) * Rm);
+  L->lg = take(sizeof(float) * Rm);
+  L->coef = take(sizeof(float2) * Rm);
   L->g = take(sizeof(float) * C);
-  L->colval = take(sizeof(double) * C);
-  L->fpart = take(sizeof(double) * kNPart * L->max_fwd);
+  L->spart_a = take(sizeof(double) * kNPart * L->n_groups);
+  L->spart_b = take(sizeof(double) * kNPart * L->n_groups);
   L->rpart = take(sizeof(double) * kNPart * L->max_rows);
+  L->gpart = take(sizeof(double) * L->n_col_blocks);
   L->tpart = take(sizeof(float) * L->max_tr);
-  L->fwd_items = take(sizeof(FwdItem) * L->max_fwd);
+  L->groups = take(sizeof(FwdGroup) * L->n_groups);
   L->row_items = take(sizeof(RowItem) * L->max_rows);
   L->tr_items = take(sizeof(TrItem) * L->max_tr);
+  L->col_blocks = take(sizeof(ColBlock) * L->n_col_blocks);
   L->bc = take(sizeof(uint32_t) * L->nb * C);
   L->colcount = take(sizeof(uint32_t) * C);
   L->colmax = take(sizeof(uint32_t) * C);
   L->flags = take(sizeof(uint32_t) * 4);
+  L->rslice = take(sizeof(int32_t) * Rm);
   L->total = o;
   return true;
 }
 
+// Pattern-free bound of the SELL size (rows sorted by length inside a window: the
+// slice widths telescope, so a window wastes at most rpw * n_cols slots plus the
+// per-slice rounding).
+bool bound_layout(int64_t R, int64_t C, int64_t nnz, int storage, int lpr_log2, int reserve_pct,
+                  Layout* L) {
+  if (R < 0 || C < 1 || nnz < 0) return false;
+  const int64_t rpw = kWave >> lpr_log2;
+  const int64_t nwin = (R + kSortWindow - 1) / kSortWindow;
+  const int64_t n_slices = R / rpw + nwin + 1;
+  const int64_t sell = nnz + nwin * rpw * C + n_slices * rpw * ((4LL << lpr_log2) - 1);
+  return make_layout(R, C, nnz, storage, lpr_log2, sell, n_slices, reserve_pct, L);
+}
+
 struct DeviceGuard {
   int prev = -1;
-  bool ok = true;
   explicit DeviceGuard(int dev) {
     if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-    if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+    if (prev != dev) (void)hipSetDevice(dev);
   }
   ~DeviceGuard() {
     int cur = -1;
@@ -137,20 +245,31 @@ struct fredopt_plan {
   int64_t R = 0, C = 0, nnz = 0;
   int storage = 0, device = 0;
   char* ws = nullptr;
+  size_t ws_bytes = 0;
   Layout L{};
-  std::vector<int64_t> rp, cp;
-  int lanes = 64, tr_chunk = (int)kTrChunkDefault, fwd_grid = 0, lds_floats = 0;
-  int n_cu = 256, grid_mult = 3;
-  size_t lds_cap = 65536;
-  std::vector<FwdItem> fwd;
+  Sell sell;
+  std::vector<int64_t> cp;
+  int tr_chunk = (int)kTrChunkDefault;
+  int n_cu = 256, wgs_per_cu = 2, max_wgs_per_cu = 2, lds_floats = 0;
+  std::vector<FwdGroup> groups;
   std::vector<RowItem> rows;
-  std::vector<TrItem> tr;
+  std::vector<TrItem> tr, gtr;
+  std::vector<int32_t> col_ts0, col_nch, gcol_ts0, gcol_nch;
+  std::vector<uint32_t> col_len;      // real (unpadded) column lengths
+  bool grad_valid = false;            // gradient CSC matches (grad_kind, grad_fp)
+  bool grad_sub = false;              // gradient uses the objective-row CSC
+  const uint16_t* grad_kind = nullptr;
+  uint64_t grad_fp = 0, last_fp = 0;
+  std::vector<ColBlock> cblocks;
   DevPlan hp{};
   DevPlan* d_table = nullptr;
   DevState* d_state = nullptr;
-  FwdItem* d_fwd = nullptr;
+  uint32_t* d_ctr = nullptr;
+  FwdGroup* d_groups = nullptr;
   RowItem* d_rows = nullptr;
   TrItem* d_tr = nullptr;
+  TrItem* d_gtr = nullptr;
+  ColBlock* d_cblocks = nullptr;
   hipStream_t cap = nullptr;
   hipGraphExec_t graph = nullptr;
   int graph_r = -1;
@@ -163,19 +282,12 @@ T* at(fredopt_plan* p, size_t off) {
   return reinterpret_cast<T*>(p->ws + off);
 }
 
-void build_fwd_items(fredopt_plan* p) {
-  p->fwd.clear();
-  const int64_t slots = p->rp[p->R];
-  int64_t target = slots / (8 * (int64_t)std::max(1, p->fwd_grid));
-  target = std::min(std::max(target, kFwdItemMinSlots), kFwdItemMaxSlots);
-  int64_t r0 = 0;
-  while (r0 < p->R) {
-    int64_t r1 = r0;
-    while (r1 < p->R && r1 - r0 < kFwdItemMaxRows && p->rp[r1] - p->rp[r0] < target) ++r1;
-    p->fwd.push_back(FwdItem{0, (int32_t)p->fwd.size(), (int32_t)r0, (int32_t)r1});
-    r0 = r1;
-  }
-  if (p->fwd.empty()) p->fwd.push_back(FwdItem{0, 0, 0, 0});
+void build_groups(fredopt_plan* p) {
+  p->groups.clear();
+  for (int64_t s0 = 0; s0 < p->sell.n_slices; s0 += kFwdWaves)
+    p->groups.push_back(FwdGroup{0, (int32_t)s0,
+                                 (int32_t)std::min<int64_t>(kFwdWaves, p->sell.n_slices - s0),
+                                 (int32_t)p->groups.size()});
 }
 
 void build_row_items(fredopt_plan* p) {
@@ -186,55 +298,55 @@ void build_row_items(fredopt_plan* p) {
   if (p->rows.empty()) p->rows.push_back(RowItem{0, 0, 0, 0});
 }
 
-// Columns split into chunks of about tr_chunk slots (boundaries on 4-slot quads),
-// then ordered longest first so the hardware dispatcher balances the grid.
-void build_tr_items(fredopt_plan* p) {
-  p->tr.clear();
+// Columns cut into chunks of about `chunk` slots (on 4-slot boundaries), kept in
+// column order so that consecutive blocks cover neighbouring beamlets.  Columns
+// with no entries get no chunk (their sum is 0).
+void chunk_columns(const std::vector<int64_t>& cp, int64_t C, int64_t chunk,
+                   std::vector<TrItem>* items, std::vector<int32_t>* ts0,
+                   std::vector<int32_t>* nch) {
+  items->clear();
+  ts0->assign(C, 0);
+  nch->assign(C, 0);
   int32_t tslot = 0;
-  const int64_t ch = p->tr_chunk;
-  for (int64_t j = 0; j < p->C; ++j) {
-    const int64_t a = p->cp[j], b = p->cp[j + 1];
+  for (int64_t j = 0; j < C; ++j) {
+    const int64_t a = cp[j], b = cp[j + 1];
     const int64_t quads = (b - a) / 4;
-    const int64_t n = std::max<int64_t>(1, (b - a + ch - 1) / ch);
+    const int64_t n = (b - a + chunk - 1) / chunk;
+    (*ts0)[j] = tslot;
+    (*nch)[j] = (int32_t)n;
     for (int64_t c = 0; c < n; ++c) {
       TrItem t{};
       t.plan = 0;
       t.col = (int32_t)j;
-      t.chunk = (int32_t)c;
-      t.nchunks = (int32_t)n;
+      t.tslot = tslot + (int32_t)c;
       t.q0 = a + 4 * (c * quads / n);
       t.q1 = a + 4 * ((c + 1) * quads / n);
-      t.tslot0 = tslot;
-      p->tr.push_back(t);
+      items->push_back(t);
     }
     tslot += (int32_t)n;
   }
-  std::stable_sort(p->tr.begin(), p->tr.end(), [](const TrItem& x, const TrItem& y) {
-    return (x.q1 - x.q0) > (y.q1 - y.q0);
-  });
 }
 
-int pick_lanes(const fredopt_plan* p) {
-  if (p->R == 0) return 64;
-  const double aq = (double)p->rp[p->R] / 4.0 / (double)p->R;
-  int g = 4;
-  while (g < 64 && g < aq / 2.0) g *= 2;
-  return g;
+void build_tr_items(fredopt_plan* p) {
+  chunk_columns(p->cp, p->C, p->tr_chunk, &p->tr, &p->col_ts0, &p->col_nch);
+  p->cblocks.clear();
+  for (int64_t c0 = 0; c0 < p->C; c0 += kBlock)
+    p->cblocks.push_back(ColBlock{0, (int32_t)p->cblocks.size(), (int32_t)c0,
+                                  (int32_t)std::min<int64_t>(p->C, c0 + kBlock)});
+  p->grad_valid = false;
 }
 
-fredopt_status upload_items(fredopt_plan* p, hipStream_t s) {
-  if ((int64_t)p->fwd.size() > p->L.max_fwd || (int64_t)p->rows.size() > p->L.max_rows ||
-      (int64_t)p->tr.size() > p->L.max_tr)
-    return fail(FREDOPT_E_WORKSPACE, "work lists exceed the workspace bound");
-  HIPCHK(hipMemcpyAsync(p->d_fwd, p->fwd.data(), sizeof(FwdItem) * p->fwd.size(),
+fredopt_status upload_tr(fredopt_plan* p, hipStream_t s) {
+  if ((int64_t)p->tr.size() > p->L.max_tr) return fail(FREDOPT_E_WORKSPACE, "chunk list too long");
+  if (!p->tr.empty())
+    HIPCHK(hipMemcpyAsync(p->d_tr, p->tr.data(), sizeof(TrItem) * p->tr.size(),
+                          hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(at<int32_t>(p, p->L.col_tslot0), p->col_ts0.data(),
+                        sizeof(int32_t) * p->C, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(at<int32_t>(p, p->L.col_nch), p->col_nch.data(), sizeof(int32_t) * p->C,
                         hipMemcpyHostToDevice, s));
-  HIPCHK(hipMemcpyAsync(p->d_rows, p->rows.data(), sizeof(RowItem) * p->rows.size(),
+  HIPCHK(hipMemcpyAsync(p->d_cblocks, p->cblocks.data(), sizeof(ColBlock) * p->cblocks.size(),
                         hipMemcpyHostToDevice, s));
-  HIPCHK(hipMemcpyAsync(p->d_tr, p->tr.data(), sizeof(TrItem) * p->tr.size(),
-                        hipMemcpyHostToDevice, s));
-  p->hp.lanes = p->lanes;
-  p->hp.n_fwd_items = (int32_t)p->fwd.size();
-  p->hp.n_row_items = (int32_t)p->rows.size();
   return FREDOPT_OK;
 }
 
@@ -302,18 +414,80 @@ fredopt_status upload_table(fredopt_plan* p, hipStream_t s) {
 
 fredopt_status run_problem_check(fredopt_plan* p, const fredopt_problem* pr, hipStream_t s) {
   uint32_t* flags = at<uint32_t>(p, p->L.flags);
-  HIPCHK(hipMemsetAsync(flags, 0, sizeof(uint32_t), s));
+  HIPCHK(hipMemsetAsync(flags, 0, sizeof(uint32_t) * 4, s));
   launch_check_problem(p->R, pr->kind, pr->dose_lo, pr->dose_hi, pr->cdl_lo, pr->cdl_hi,
                        pr->letd_max, pr->w_feas, pr->w_obj, pr->dose_target, pr->cdl_target,
                        flags, s);
   HIPCHK(hipGetLastError());
-  uint32_t f = 0;
-  HIPCHK(hipMemcpyAsync(&f, flags, sizeof f, hipMemcpyDeviceToHost, s));
+  uint32_t fl[4] = {0, 0, 0, 0};
+  HIPCHK(hipMemcpyAsync(fl, flags, sizeof fl, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  const uint32_t f = fl[0];
+  p->last_fp = (uint64_t)fl[2] | ((uint64_t)fl[3] << 32);
   if (f & 8u) return fail(FREDOPT_E_ARG, "problem: unknown kind bits");
   if (f & 1u) return fail(FREDOPT_E_NONFINITE, "problem: non-finite bound, target or weight");
   if (f & 2u) return fail(FREDOPT_E_ARG, "problem: lower bound above upper bound");
   if (f & 4u) return fail(FREDOPT_E_ARG, "problem: AMS weight <= 0 or objective weight < 0");
+  return FREDOPT_OK;
+}
+
+// Gradient CSC for this problem: the entries of rows with objective terms (Eq. 2
+// has no other non-zero coefficients), compacted column by column in row order.
+// Rebuilt only when the kind array (address or fingerprint) changes; falls back to
+// the full CSC when it does not fit the reserved space.
+fredopt_status prepare_gradient(fredopt_plan* p, const fredopt_problem* pr, hipStream_t s) {
+  if (p->grad_valid && p->grad_kind == pr->kind && p->grad_fp == p->last_fp) return FREDOPT_OK;
+  DevPlan& h = p->hp;
+  const Layout& L = p->L;
+  uint32_t* ocount = at<uint32_t>(p, L.ocount);
+  const int64_t* d_cp = at<int64_t>(p, L.cp);
+  launch_obj_count(p->C, d_cp, at<uint32_t>(p, L.colcount), h.ri, pr->kind, ocount, s);
+  HIPCHK(hipGetLastError());
+  std::vector<uint32_t> cnt(p->C);
+  HIPCHK(hipMemcpyAsync(cnt.data(), ocount, sizeof(uint32_t) * p->C, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  std::vector<int64_t> ocp(p->C + 1, 0);
+  for (int64_t j = 0; j < p->C; ++j) ocp[j + 1] = ocp[j] + (((int64_t)cnt[j] + 3) & ~int64_t(3));
+  if (ocp[p->C] <= L.obj_slots) {
+    const int vb = value_bytes(p->storage);
+    HIPCHK(hipMemcpyAsync(at<int64_t>(p, L.ocp), ocp.data(), sizeof(int64_t) * (p->C + 1),
+                          hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemsetAsync(p->ws + L.gri, 0, sizeof(int32_t) * ocp[p->C], s));
+    HIPCHK(hipMemsetAsync(p->ws + L.gcdv, 0, (size_t)vb * ocp[p->C], s));
+    HIPCHK(hipMemsetAsync(p->ws + L.gclv, 0, (size_t)vb * ocp[p->C], s));
+    launch_obj_fill(p->storage, p->C, d_cp, at<uint32_t>(p, L.colcount), h.ri, h.cdv, h.clv,
+                    pr->kind, at<int64_t>(p, L.ocp), at<int32_t>(p, L.gri), p->ws + L.gcdv,
+                    p->ws + L.gclv, s);
+    HIPCHK(hipGetLastError());
+    chunk_columns(ocp, p->C, p->tr_chunk, &p->gtr, &p->gcol_ts0, &p->gcol_nch);
+    h.gri = at<int32_t>(p, L.gri);
+    h.gcdv = p->ws + L.gcdv;
+    h.gclv = p->ws + L.gclv;
+    p->grad_sub = true;
+  } else {
+    p->gtr = p->tr;
+    p->gcol_ts0 = p->col_ts0;
+    p->gcol_nch = p->col_nch;
+    h.gri = h.ri;
+    h.gcdv = h.cdv;
+    h.gclv = h.clv;
+    p->grad_sub = false;
+  }
+  if ((int64_t)p->gtr.size() > L.max_tr) return fail(FREDOPT_E_WORKSPACE, "gradient chunks");
+  if (!p->gtr.empty())
+    HIPCHK(hipMemcpyAsync(p->d_gtr, p->gtr.data(), sizeof(TrItem) * p->gtr.size(),
+                          hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(at<int32_t>(p, L.gcol_tslot0), p->gcol_ts0.data(), sizeof(int32_t) * p->C,
+                        hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(at<int32_t>(p, L.gcol_nch), p->gcol_nch.data(), sizeof(int32_t) * p->C,
+                        hipMemcpyHostToDevice, s));
+  h.gcol_tslot0 = at<int32_t>(p, L.gcol_tslot0);
+  h.gcol_nch = at<int32_t>(p, L.gcol_nch);
+  HIPCHK(hipStreamSynchronize(s));
+  p->grad_valid = true;
+  p->grad_kind = pr->kind;
+  p->grad_fp = p->last_fp;
+  drop_graph(p);
   return FREDOPT_OK;
 }
 
@@ -343,38 +517,65 @@ void export_state(const DevState& d, fredopt_state* st) {
   st->q = d.Q;
 }
 
+enum Kind { kKindFwd, kKindRows, kKindChunks, kKindCol, kKindFin };
+
 struct Launch {
-  int id;       // FREDOPT_KERNEL_*
-  int kind;     // 0 forward, 1 rows, 2 transposed
+  int id;    // FREDOPT_KERNEL_*
+  int kind;  // Kind
   int mode;
 };
 
+// One outer iteration of Fig. 3 (reductions_n = r perturbations, then the sweep).
 std::vector<Launch> iteration_sequence(int r) {
   std::vector<Launch> seq;
   if (r == 0) {
-    seq.push_back({FREDOPT_KERNEL_FWD_RESID, 0, kFwdResid});
-    seq.push_back({FREDOPT_KERNEL_TR_PROJ, 2, kTrProj});
+    seq.push_back({FREDOPT_KERNEL_FWD_RESID, kKindFwd, kFwdResid});
+    seq.push_back({FREDOPT_KERNEL_FINALIZE, kKindFin, kFinResidFwd});
+    seq.push_back({FREDOPT_KERNEL_TR_PROJ, kKindChunks, 1});
+    seq.push_back({FREDOPT_KERNEL_COL, kKindCol, kColProj});
     return seq;
   }
-  seq.push_back({FREDOPT_KERNEL_FWD_OBJ, 0, kFwdObj});
+  seq.push_back({FREDOPT_KERNEL_FWD_OBJ, kKindFwd, kFwdObj});
   for (int t = 0; t < r; ++t) {
-    seq.push_back({FREDOPT_KERNEL_TR_GRAD, 2, t == 0 ? kTrGrad : kTrGradMove});
-    seq.push_back({FREDOPT_KERNEL_FWD_DIR, 0, kFwdDir});
-    seq.push_back({FREDOPT_KERNEL_ROWS, 1, t + 1 < r ? kRowsMoveObj : kRowsMoveResid});
+    const bool last = t + 1 == r;
+    seq.push_back({FREDOPT_KERNEL_TR_GRAD, kKindChunks, 0});
+    seq.push_back({FREDOPT_KERNEL_COL, kKindCol, t == 0 ? kColGrad : kColGradMove});
+    seq.push_back({FREDOPT_KERNEL_FWD_DIR, kKindFwd, kFwdDir});
+    seq.push_back({FREDOPT_KERNEL_FINALIZE, kKindFin, t == 0 ? kFinDir0 : kFinDir});
+    seq.push_back({FREDOPT_KERNEL_ROWS, kKindRows, last ? kRowsMoveResid : kRowsMoveObj});
+    seq.push_back({FREDOPT_KERNEL_FINALIZE, kKindFin, last ? kFinResidRows : kFinMoveObj});
   }
-  seq.push_back({FREDOPT_KERNEL_TR_PROJ, 2, kTrProjMove});
+  seq.push_back({FREDOPT_KERNEL_TR_PROJ, kKindChunks, 1});
+  seq.push_back({FREDOPT_KERNEL_COL, kKindCol, kColProjMove});
   return seq;
 }
 
 void enqueue(fredopt_plan* p, const Launch& l, hipStream_t s) {
-  if (l.kind == 0) {
-    const int grid = std::min<int>((int)p->fwd.size(), p->fwd_grid);
-    launch_forward(p->storage, l.mode, p->d_table, p->d_fwd, (int)p->fwd.size(), grid,
-                   p->lds_floats, s);
-  } else if (l.kind == 1) {
-    launch_rows(l.mode, p->d_table, p->d_rows, (int)p->rows.size(), s);
-  } else {
-    launch_transposed(p->storage, l.mode, p->d_table, p->d_tr, (int)p->tr.size(), s);
+  switch (l.kind) {
+    case kKindFwd: {
+      const int grid = (int)std::min<int64_t>((int64_t)p->groups.size(),
+                                              (int64_t)p->n_cu * p->wgs_per_cu);
+      launch_forward(p->storage, l.mode, p->d_table, p->d_groups, (int)p->groups.size(),
+                     std::max(grid, 1), p->lds_floats, p->d_ctr, s);
+      break;
+    }
+    case kKindRows:
+      launch_rows(l.mode, p->d_table, p->d_rows, (int)p->rows.size(), s);
+      break;
+    case kKindChunks:
+      if (l.mode == 0) {
+        if (!p->gtr.empty())
+          launch_tr_chunks(p->storage, 0, p->d_table, p->d_gtr, (int)p->gtr.size(), s);
+      } else if (!p->tr.empty()) {
+        launch_tr_chunks(p->storage, 1, p->d_table, p->d_tr, (int)p->tr.size(), s);
+      }
+      break;
+    case kKindCol:
+      launch_tcol(l.mode, p->d_table, p->d_cblocks, (int)p->cblocks.size(), s);
+      break;
+    default:
+      launch_finalize(l.mode, p->d_table, 1, s);
+      break;
   }
 }
 
@@ -419,21 +620,29 @@ fredopt_status device_limits(fredopt_plan* p) {
       smem_sm <= 0)
     smem_sm = smem_block;
   p->n_cu = ncu > 0 ? ncu : 256;
-  p->lds_cap = (size_t)std::max(smem_block, 0);
-  const size_t static_lds = 4096 + 64;  // reduction scratch of k_forward
+  const size_t static_lds = 64;
   const size_t need = (size_t)p->C * sizeof(float);
-  if (need + static_lds <= p->lds_cap) {
+  if (need + static_lds <= (size_t)std::max(smem_block, 0)) {
     p->lds_floats = (int)p->C;
-    if (need > 0) HIPCHK(set_forward_lds_limit(p->storage, need));
-    const size_t per_wg = need + static_lds;
-    const int fit = (int)std::max<size_t>(1, (size_t)std::max(smem_sm, 1) / per_wg);
-    p->grid_mult = std::min(4, std::max(1, fit));
+    HIPCHK(set_forward_lds_limit(p->storage, need));
+    const int fit = (int)std::max<size_t>(1, (size_t)std::max(smem_sm, 1) / (need + static_lds));
+    p->max_wgs_per_cu = std::min(4, fit);  // 4 x 512 threads = 32 waves per CU
   } else {
     p->lds_floats = 0;
-    p->grid_mult = 4;
+    p->max_wgs_per_cu = 4;
   }
-  p->fwd_grid = p->n_cu * p->grid_mult;
+  p->wgs_per_cu = p->max_wgs_per_cu;
   return FREDOPT_OK;
+}
+
+size_t exact_bytes(int64_t R, int64_t C, const int64_t* rp, int storage, int lpr_log2,
+                   int reserve_pct) {
+  Sell S;
+  build_sell(rp, R, lpr_log2, false, &S);
+  Layout L;
+  if (!make_layout(R, C, rp[R], storage, lpr_log2, S.slots, S.n_slices, reserve_pct, &L))
+    return 0;
+  return L.total;
 }
 
 }  // namespace
@@ -446,8 +655,22 @@ const char* fredopt_last_error(void) { return g_err.c_str(); }
 
 size_t fredopt_workspace_bytes(int64_t n_rows, int64_t n_cols, int64_t nnz, int32_t storage) {
   Layout L;
-  if (!make_layout(n_rows, n_cols, nnz, storage, &L)) return 0;
+  if (!bound_layout(n_rows, n_cols, nnz, storage, auto_lpr_log2(n_rows, nnz),
+                    kDefaultGradientReservePct, &L))
+    return 0;
   return L.total;
+}
+
+size_t fredopt_workspace_bytes_csr(int64_t n_rows, int64_t n_cols, const int64_t* row_ptr,
+                                   int32_t storage, int32_t lanes_per_row,
+                                   int32_t gradient_reserve_pct) {
+  if (!row_ptr || n_rows < 0 || n_cols < 1) return 0;
+  int lg = 0;
+  if (!lpr_log2_of(lanes_per_row, n_rows, row_ptr[n_rows], &lg)) return 0;
+  for (int64_t i = 0; i < n_rows; ++i)
+    if (row_ptr[i + 1] < row_ptr[i]) return 0;
+  if (row_ptr[0] != 0) return 0;
+  return exact_bytes(n_rows, n_cols, row_ptr, storage, lg, reserve_pct_of(gradient_reserve_pct));
 }
 
 fredopt_status fredopt_load_matrices(const fredopt_matrices* m, void* workspace,
@@ -455,19 +678,20 @@ fredopt_status fredopt_load_matrices(const fredopt_matrices* m, void* workspace,
   if (!m || !out) return fail(FREDOPT_E_ARG, "matrices and out must be non-NULL");
   *out = nullptr;
   const int64_t R = m->n_rows, C = m->n_cols, nnz = m->nnz;
-  Layout L;
-  if (!make_layout(R, C, nnz, m->storage, &L))
-    return fail(FREDOPT_E_SHAPE, "invalid sizes or storage (rows %lld cols %lld nnz %lld)",
+  int lg = 0;
+  Layout Lb;
+  const int pct = reserve_pct_of(m->gradient_reserve_pct);
+  if (!lpr_log2_of(m->lanes_per_row, R, nnz, &lg) ||
+      !bound_layout(R, C, nnz, m->storage, lg, pct, &Lb))
+    return fail(FREDOPT_E_SHAPE, "invalid sizes, storage or layout (rows %lld cols %lld nnz %lld)",
                 (long long)R, (long long)C, (long long)nnz);
   if (!m->row_ptr || (nnz > 0 && (!m->col_idx || !m->d_val || !m->l_val)))
     return fail(FREDOPT_E_ARG, "matrix array is NULL");
   if (!workspace || (reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0)
     return fail(FREDOPT_E_WORKSPACE, "workspace must be non-NULL and 256-byte aligned");
-  if (workspace_bytes < L.total)
-    return fail(FREDOPT_E_WORKSPACE, "workspace too small: %zu < %zu", workspace_bytes, L.total);
   hipStream_t s = static_cast<hipStream_t>(stream);
 
-  // host copy of the row pointers: validation, padding, work lists
+  // host copy of the row pointers: validation, slicing, work lists
   std::vector<int64_t> h_rp(R + 1);
   if (m->on_device) {
     HIPCHK(hipMemcpyAsync(h_rp.data(), m->row_ptr, sizeof(int64_t) * (R + 1),
@@ -476,7 +700,8 @@ fredopt_status fredopt_load_matrices(const fredopt_matrices* m, void* workspace,
   } else {
     std::memcpy(h_rp.data(), m->row_ptr, sizeof(int64_t) * (R + 1));
   }
-  if (h_rp[0] != 0 || h_rp[R] != nnz) return fail(FREDOPT_E_SHAPE, "row_ptr[0] != 0 or row_ptr[n] != nnz");
+  if (h_rp[0] != 0 || h_rp[R] != nnz)
+    return fail(FREDOPT_E_SHAPE, "row_ptr[0] != 0 or row_ptr[n] != nnz");
   for (int64_t i = 0; i < R; ++i)
     if (h_rp[i + 1] < h_rp[i]) return fail(FREDOPT_E_SHAPE, "row_ptr decreases at row %lld", (long long)i);
   for (int64_t i = 0; i < R; ++i)
@@ -489,7 +714,18 @@ fredopt_status fredopt_load_matrices(const fredopt_matrices* m, void* workspace,
   p->nnz = nnz;
   p->storage = m->storage;
   p->ws = static_cast<char*>(workspace);
-  p->L = L;
+  p->ws_bytes = workspace_bytes;
+  build_sell(h_rp.data(), R, lg, true, &p->sell);
+  if (!make_layout(R, C, nnz, m->storage, lg, p->sell.slots, p->sell.n_slices, pct, &p->L)) {
+    delete p;
+    return fail(FREDOPT_E_SHAPE, "layout failed");
+  }
+  const Layout& L = p->L;
+  if (workspace_bytes < L.total) {
+    const size_t need = L.total;
+    delete p;
+    return fail(FREDOPT_E_WORKSPACE, "workspace too small: %zu < %zu", workspace_bytes, need);
+  }
   fredopt_status st = device_limits(p);
   if (st != FREDOPT_OK) {
     delete p;
@@ -511,10 +747,10 @@ fredopt_status fredopt_load_matrices(const fredopt_matrices* m, void* workspace,
     }
     return code;
   };
-#define LCHK(expr)                                                                         \
-  do {                                                                                     \
-    hipError_t e_ = (expr);                                                                \
-    if (e_ != hipSuccess)                                                                  \
+#define LCHK(expr)                                                                           \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
       return cleanup(fail(FREDOPT_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_))); \
   } while (0)
   if (!m->on_device) {
@@ -547,9 +783,10 @@ fredopt_status fredopt_load_matrices(const fredopt_matrices* m, void* workspace,
   uint32_t* colmax = reinterpret_cast<uint32_t*>(ws + L.colmax);
   float* cscale = reinterpret_cast<float*>(ws + L.cscale);
   const bool q16 = m->storage != FREDOPT_F32;
+  const int vb = value_bytes(m->storage);
 
   LCHK(hipMemsetAsync(ws + L.flags, 0, sizeof(uint32_t) * 4, s));
-  LCHK(hipMemsetAsync(ws + L.cnt, 0, sizeof(uint32_t) * (kPlanTickets + C), s));
+  LCHK(hipMemsetAsync(ws + L.ctr, 0, sizeof(uint32_t) * kCounters, s));
   LCHK(hipMemsetAsync(ws + L.colcount, 0, sizeof(uint32_t) * C, s));
   LCHK(hipMemsetAsync(ws + L.colmax, 0, sizeof(uint32_t) * C, s));
   LCHK(hipMemsetAsync(ws + L.state, 0, sizeof(DevState), s));
@@ -568,27 +805,37 @@ fredopt_status fredopt_load_matrices(const fredopt_matrices* m, void* workspace,
   std::vector<uint32_t> h_cc(C);
   LCHK(hipMemcpyAsync(h_cc.data(), colcount, sizeof(uint32_t) * C, hipMemcpyDeviceToHost, s));
   LCHK(hipStreamSynchronize(s));
-
-  // padded row / column pointers
-  p->rp.assign(R + 1, 0);
-  for (int64_t i = 0; i < R; ++i) p->rp[i + 1] = p->rp[i] + ((h_rp[i + 1] - h_rp[i] + 3) & ~int64_t(3));
   p->cp.assign(C + 1, 0);
   for (int64_t j = 0; j < C; ++j) p->cp[j + 1] = p->cp[j] + (((int64_t)h_cc[j] + 3) & ~int64_t(3));
-  if (p->rp[R] > L.csr_slots || p->cp[C] > L.csc_slots)
-    return cleanup(fail(FREDOPT_E_WORKSPACE, "padded matrix exceeds the workspace bound"));
+  if (p->cp[C] > L.csc_slots)
+    return cleanup(fail(FREDOPT_E_WORKSPACE, "padded CSC exceeds the workspace bound"));
 
-  int64_t* d_rp = reinterpret_cast<int64_t*>(ws + L.rp);
-  int64_t* d_cp = reinterpret_cast<int64_t*>(ws + L.cp);
-  LCHK(hipMemcpyAsync(d_rp, p->rp.data(), sizeof(int64_t) * (R + 1), hipMemcpyHostToDevice, s));
-  LCHK(hipMemcpyAsync(d_cp, p->cp.data(), sizeof(int64_t) * (C + 1), hipMemcpyHostToDevice, s));
-
-  const int vb = value_bytes(m->storage);
+  // sliced-ELL copy
+  const Sell& S = p->sell;
+  int64_t* d_sbase = reinterpret_cast<int64_t*>(ws + L.sbase);
+  int32_t* d_rslice = reinterpret_cast<int32_t*>(ws + L.rslice);
+  int32_t* sci = reinterpret_cast<int32_t*>(ws + L.sci);
+  LCHK(hipMemcpyAsync(d_sbase, S.base.data(), sizeof(int64_t) * (S.n_slices + 1),
+                      hipMemcpyHostToDevice, s));
+  if (S.n_slices > 0) {
+    LCHK(hipMemcpyAsync(ws + L.swidth, S.width.data(), sizeof(int32_t) * S.n_slices,
+                        hipMemcpyHostToDevice, s));
+    LCHK(hipMemcpyAsync(ws + L.srow, S.srow.data(), sizeof(int32_t) * S.srow.size(),
+                        hipMemcpyHostToDevice, s));
+  }
+  if (R > 0)
+    LCHK(hipMemcpyAsync(d_rslice, S.rslice.data(), sizeof(int32_t) * R, hipMemcpyHostToDevice, s));
+  LCHK(hipMemsetAsync(sci, 0, sizeof(int32_t) * S.slots, s));
+  LCHK(hipMemsetAsync(ws + L.sdv, 0, (size_t)vb * S.slots, s));
+  LCHK(hipMemsetAsync(ws + L.slv, 0, (size_t)vb * S.slots, s));
   const float* scale = q16 ? cscale : nullptr;
-  int32_t* ci = reinterpret_cast<int32_t*>(ws + L.ci);
-  int32_t* ri = reinterpret_cast<int32_t*>(ws + L.ri);
-  launch_pack_csr(m->storage, R, in_rp, in_col, in_dv, in_lv, scale, d_rp, ci, ws + L.dv,
-                  ws + L.lv, s);
+  launch_pack_sell(m->storage, R, S.lpr_log2, in_rp, in_col, in_dv, in_lv, scale, d_rslice,
+                   d_sbase, sci, ws + L.sdv, ws + L.slv, s);
+
   // CSC: zero (padding slots keep row 0, value 0), per-block counts, offsets, fill
+  int64_t* d_cp = reinterpret_cast<int64_t*>(ws + L.cp);
+  int32_t* ri = reinterpret_cast<int32_t*>(ws + L.ri);
+  LCHK(hipMemcpyAsync(d_cp, p->cp.data(), sizeof(int64_t) * (C + 1), hipMemcpyHostToDevice, s));
   LCHK(hipMemsetAsync(ri, 0, sizeof(int32_t) * p->cp[C], s));
   LCHK(hipMemsetAsync(ws + L.cdv, 0, (size_t)vb * p->cp[C], s));
   LCHK(hipMemsetAsync(ws + L.clv, 0, (size_t)vb * p->cp[C], s));
@@ -598,29 +845,48 @@ fredopt_status fredopt_load_matrices(const fredopt_matrices* m, void* workspace,
   launch_block_offsets(C, (int)L.nb, d_cp, bc, s);
   launch_fill_csc(m->storage, R, C, (int)L.rows_per_block, in_rp, in_col, in_dv, in_lv, scale, bc,
                   ri, ws + L.cdv, ws + L.clv, s);
-  launch_moments(m->storage, R, d_rp, ws + L.dv, ws + L.lv, ci, scale,
+  launch_moments(m->storage, R, in_rp, in_col, in_dv, in_lv, scale,
                  reinterpret_cast<double*>(ws + L.mom), s);
   LCHK(hipGetLastError());
 
-  // plan descriptor
+  // plan descriptor and work lists
   p->d_table = reinterpret_cast<DevPlan*>(ws + L.table);
   p->d_state = reinterpret_cast<DevState*>(ws + L.state);
-  p->d_fwd = reinterpret_cast<FwdItem*>(ws + L.fwd_items);
+  p->d_ctr = reinterpret_cast<uint32_t*>(ws + L.ctr);
+  p->d_groups = reinterpret_cast<FwdGroup*>(ws + L.groups);
   p->d_rows = reinterpret_cast<RowItem*>(ws + L.row_items);
   p->d_tr = reinterpret_cast<TrItem*>(ws + L.tr_items);
+  p->d_gtr = reinterpret_cast<TrItem*>(ws + L.gtr_items);
+  p->d_cblocks = reinterpret_cast<ColBlock*>(ws + L.col_blocks);
+  build_groups(p);
+  build_row_items(p);
+  build_tr_items(p);
   DevPlan& h = p->hp;
   std::memset(&h, 0, sizeof h);
   h.R = R;
   h.C = C;
   h.vtype = m->storage;
-  h.rp = d_rp;
-  h.ci = ci;
-  h.dv = ws + L.dv;
-  h.lv = ws + L.lv;
-  h.cp = d_cp;
+  h.lpr_log2 = S.lpr_log2;
+  h.n_slices = (int32_t)S.n_slices;
+  h.n_row_items = (int32_t)p->rows.size();
+  h.n_col_blocks = (int32_t)p->cblocks.size();
+  h.n_groups = (int32_t)p->groups.size();
+  h.sbase = d_sbase;
+  h.swidth = reinterpret_cast<const int32_t*>(ws + L.swidth);
+  h.srow = reinterpret_cast<const int32_t*>(ws + L.srow);
+  h.sci = sci;
+  h.sdv = ws + L.sdv;
+  h.slv = ws + L.slv;
   h.ri = ri;
   h.cdv = ws + L.cdv;
   h.clv = ws + L.clv;
+  h.col_tslot0 = reinterpret_cast<const int32_t*>(ws + L.col_tslot0);
+  h.col_nch = reinterpret_cast<const int32_t*>(ws + L.col_nch);
+  h.gri = ri;  // until a problem is prepared
+  h.gcdv = h.cdv;
+  h.gclv = h.clv;
+  h.gcol_tslot0 = h.col_tslot0;
+  h.gcol_nch = h.col_nch;
   h.cscale = scale;
   h.mom = reinterpret_cast<const double*>(ws + L.mom);
   h.d = reinterpret_cast<float*>(ws + L.d);
@@ -629,21 +895,26 @@ fredopt_status fredopt_load_matrices(const fredopt_matrices* m, void* workspace,
   h.lg = reinterpret_cast<float*>(ws + L.lg);
   h.coef = reinterpret_cast<float2*>(ws + L.coef);
   h.g = reinterpret_cast<float*>(ws + L.g);
-  h.fpart = reinterpret_cast<double*>(ws + L.fpart);
+  h.spart_a = reinterpret_cast<double*>(ws + L.spart_a);
+  h.spart_b = reinterpret_cast<double*>(ws + L.spart_b);
   h.rpart = reinterpret_cast<double*>(ws + L.rpart);
+  h.gpart = reinterpret_cast<double*>(ws + L.gpart);
   h.tpart = reinterpret_cast<float*>(ws + L.tpart);
-  h.colval = reinterpret_cast<double*>(ws + L.colval);
-  h.cnt = reinterpret_cast<uint32_t*>(ws + L.cnt);
   h.st = p->d_state;
   h.prm.ws_fixed = -1.0;
-  p->lanes = pick_lanes(p);
-  build_fwd_items(p);
-  build_row_items(p);
-  build_tr_items(p);
-  st = upload_items(p, s);
+  if ((int64_t)p->groups.size() > L.n_groups || (int64_t)p->rows.size() > L.max_rows)
+    return cleanup(fail(FREDOPT_E_WORKSPACE, "work lists exceed the workspace bound"));
+  if (!p->groups.empty())
+    LCHK(hipMemcpyAsync(p->d_groups, p->groups.data(), sizeof(FwdGroup) * p->groups.size(),
+                        hipMemcpyHostToDevice, s));
+  LCHK(hipMemcpyAsync(p->d_rows, p->rows.data(), sizeof(RowItem) * p->rows.size(),
+                      hipMemcpyHostToDevice, s));
+  st = upload_tr(p, s);
   if (st != FREDOPT_OK) return cleanup(st);
   LCHK(hipMemsetAsync(h.g, 0, sizeof(float) * C, s));
-  LCHK(hipMemsetAsync(h.coef, 0, sizeof(float2) * (R > 0 ? R : 1), s));
+  LCHK(hipMemsetAsync(h.coef, 0, sizeof(float2) * std::max<int64_t>(R, 1), s));
+  LCHK(hipMemsetAsync(h.spart_a, 0, sizeof(double) * kNPart * L.n_groups, s));
+  LCHK(hipMemsetAsync(h.spart_b, 0, sizeof(double) * kNPart * L.n_groups, s));
   st = upload_table(p, s);
   if (st != FREDOPT_OK) return cleanup(st);
   LCHK(hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking));
@@ -670,16 +941,18 @@ fredopt_status fredopt_get_plan_info(const fredopt_plan* p, fredopt_plan_info* i
   info->n_rows = p->R;
   info->n_cols = p->C;
   info->nnz = p->nnz;
-  info->csr_slots = p->rp.empty() ? 0 : p->rp[p->R];
+  info->sell_slots = p->sell.slots;
   info->csc_slots = p->cp.empty() ? 0 : p->cp[p->C];
-  info->bytes_per_csr_slot = 4 + 2 * value_bytes(p->storage);
+  info->bytes_per_sell_slot = 4 + 2 * value_bytes(p->storage);
   info->bytes_per_csc_slot = 4 + 2 * value_bytes(p->storage);
-  info->fwd_items = (int64_t)p->fwd.size();
+  info->n_slices = p->sell.n_slices;
   info->tr_items = (int64_t)p->tr.size();
   info->row_items = (int64_t)p->rows.size();
+  info->workspace_bytes = (int64_t)p->L.total;
   info->storage = p->storage;
-  info->lanes_per_row = p->lanes;
-  info->fwd_grid = std::min<int>((int)p->fwd.size(), p->fwd_grid);
+  info->lanes_per_row = 1 << p->sell.lpr_log2;
+  info->fwd_grid = (int32_t)std::min<int64_t>((int64_t)p->groups.size(),
+                                              (int64_t)p->n_cu * p->wgs_per_cu);
   info->tr_chunk = p->tr_chunk;
   info->lds_x = p->lds_floats > 0 ? 1 : 0;
   return FREDOPT_OK;
@@ -700,7 +973,7 @@ fredopt_status fredopt_dose_let(fredopt_plan* p, const float* x, double c, float
   fredopt_status st = upload_table(p, s);
   h.out_dose = h.out_letd = h.out_cdl = nullptr;
   if (st != FREDOPT_OK) return st;
-  if (dose || letd || cdl) enqueue(p, Launch{0, 0, kFwdDoseLet}, s);
+  if (dose || letd || cdl) enqueue(p, Launch{0, kKindFwd, kFwdDoseLet}, s);
   HIPCHK(hipGetLastError());
   return FREDOPT_OK;
 }
@@ -722,9 +995,7 @@ fredopt_status fredopt_project_sweep(fredopt_plan* p, const fredopt_problem* pr,
   fredopt_state zero{};
   zero.s = -1;
   if ((st = upload_state(p, &zero, s)) != FREDOPT_OK) return st;
-  enqueue(p, Launch{FREDOPT_KERNEL_FWD_RESID, 0, kFwdResid}, s);
-  enqueue(p, Launch{FREDOPT_KERNEL_TR_PROJ, 2, kTrProj}, s);
-  HIPCHK(hipGetLastError());
+  if ((st = enqueue_iteration(p, 0, s)) != FREDOPT_OK) return st;
   DevState d;
   if ((st = download_state(p, &d, s)) != FREDOPT_OK) return st;
   if (proximity_out) *proximity_out = d.proximity;
@@ -743,10 +1014,11 @@ static fredopt_status step_common(fredopt_plan* p, const fredopt_problem* pr,
   DeviceGuard guard(p->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
   if ((st = run_problem_check(p, pr, s)) != FREDOPT_OK) return st;
+  const int r = q->reductions_n;
+  if (r > 0 && (st = prepare_gradient(p, pr, s)) != FREDOPT_OK) return st;
   set_problem(p, pr, q, -1.0, x);
   if ((st = upload_table(p, s)) != FREDOPT_OK) return st;
   if ((st = upload_state(p, stt, s)) != FREDOPT_OK) return st;
-  const int r = q->reductions_n;
   if (use_graph && iters > 0) {
     if ((st = ensure_graph(p, r)) != FREDOPT_OK) return st;
     for (int i = 0; i < iters; ++i) HIPCHK(hipGraphLaunch(p->graph, s));
@@ -785,6 +1057,7 @@ fredopt_status fredopt_profile_kernels(fredopt_plan* p, const fredopt_problem* p
   DeviceGuard guard(p->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
   if ((st = run_problem_check(p, pr, s)) != FREDOPT_OK) return st;
+  if (q->reductions_n > 0 && (st = prepare_gradient(p, pr, s)) != FREDOPT_OK) return st;
   set_problem(p, pr, q, -1.0, x);
   if ((st = upload_table(p, s)) != FREDOPT_OK) return st;
   if ((st = upload_state(p, stt, s)) != FREDOPT_OK) return st;
@@ -825,22 +1098,21 @@ fredopt_status fredopt_profile_kernels(fredopt_plan* p, const fredopt_problem* p
   return FREDOPT_OK;
 }
 
-fredopt_status fredopt_set_tuning(fredopt_plan* p, int32_t lanes_per_row, int32_t tr_chunk) {
+fredopt_status fredopt_set_tuning(fredopt_plan* p, int32_t fwd_wgs_per_cu, int32_t tr_chunk) {
   if (!p) return fail(FREDOPT_E_ARG, "plan is NULL");
-  if (lanes_per_row != 0 && lanes_per_row != 4 && lanes_per_row != 8 && lanes_per_row != 16 &&
-      lanes_per_row != 32 && lanes_per_row != 64)
-    return fail(FREDOPT_E_ARG, "lanes_per_row must be 4, 8, 16, 32 or 64");
-  if (tr_chunk != 0 && (tr_chunk < kTrChunkMin || tr_chunk % 1024 != 0))
-    return fail(FREDOPT_E_ARG, "tr_chunk must be a multiple of 1024");
+  if (fwd_wgs_per_cu < 0 || fwd_wgs_per_cu > 8)
+    return fail(FREDOPT_E_ARG, "fwd_wgs_per_cu must lie in [0, 8]");
+  if (tr_chunk != 0 && (tr_chunk < kTrChunkMin || tr_chunk % 256 != 0))
+    return fail(FREDOPT_E_ARG, "tr_chunk must be a multiple of 256");
   DeviceGuard guard(p->device);
-  if (lanes_per_row) p->lanes = lanes_per_row;
-  if (tr_chunk) p->tr_chunk = tr_chunk;
-  build_tr_items(p);
+  if (fwd_wgs_per_cu) p->wgs_per_cu = std::min(fwd_wgs_per_cu, p->max_wgs_per_cu);
+  if (tr_chunk) {
+    p->tr_chunk = tr_chunk;
+    build_tr_items(p);
+    fredopt_status st = upload_tr(p, nullptr);
+    if (st != FREDOPT_OK) return st;
+  }
   drop_graph(p);
-  fredopt_status st = upload_items(p, nullptr);
-  if (st != FREDOPT_OK) return st;
-  st = upload_table(p, nullptr);
-  if (st != FREDOPT_OK) return st;
   HIPCHK(hipStreamSynchronize(nullptr));
   return FREDOPT_OK;
 }
@@ -862,49 +1134,44 @@ fredopt_status fredopt_autotune(fredopt_plan* p, const float* x, void* stream) {
     (void)hipEventElapsedTime(&ms, e0, e1);
     return ms / reps;
   };
-  DevPlan saved = p->hp;
-  // forward width: dose / LETd outputs into the plan's own d and l buffers
+  const DevPlan saved = p->hp;
+  // forward: dose / LETd outputs into the plan's own d and l buffers
   p->hp.x = const_cast<float*>(x);
   p->hp.prm.c = 0.04;
   p->hp.out_dose = p->hp.d;
   p->hp.out_letd = p->hp.l;
   p->hp.out_cdl = nullptr;
-  fredopt_status st = FREDOPT_OK;
-  int best_lanes = p->lanes;
+  fredopt_status st = upload_table(p, s);
+  int best_w = p->wgs_per_cu;
   double best = 1e30;
-  for (int g : {4, 8, 16, 32, 64}) {
-    p->lanes = g;
-    p->hp.lanes = g;
-    if ((st = upload_table(p, s)) != FREDOPT_OK) break;
-    const double t = timeit(Launch{0, 0, kFwdDoseLet}, 5);
+  for (int w = 1; st == FREDOPT_OK && w <= p->max_wgs_per_cu; ++w) {
+    p->wgs_per_cu = w;
+    const double t = timeit(Launch{0, kKindFwd, kFwdDoseLet}, 5);
     if (t < best) {
       best = t;
-      best_lanes = g;
+      best_w = w;
     }
   }
-  p->lanes = best_lanes;
-  p->hp.lanes = best_lanes;
-  // transposed chunk: gradient mode on zero coefficients
-  HIPCHK(hipMemsetAsync(p->hp.coef, 0, sizeof(float2) * (p->R > 0 ? p->R : 1), s));
+  p->wgs_per_cu = best_w;
+  // transposed chunks (coefficients zero: the timing does not depend on them)
+  HIPCHK(hipMemsetAsync(p->hp.coef, 0, sizeof(float2) * std::max<int64_t>(p->R, 1), s));
   int best_chunk = p->tr_chunk;
   best = 1e30;
-  if (st == FREDOPT_OK && (st = upload_table(p, s)) == FREDOPT_OK) {
-    for (int ch : {1024, 2048, 4096, 8192, 16384}) {
-      p->tr_chunk = ch;
-      build_tr_items(p);
-      if ((st = upload_items(p, s)) != FREDOPT_OK) break;
-      const double t = timeit(Launch{0, 2, kTrGrad}, 5);
-      if (t < best) {
-        best = t;
-        best_chunk = ch;
-      }
+  for (int ch : {1024, 2048, 4096, 8192, 16384}) {
+    if (st != FREDOPT_OK) break;
+    p->tr_chunk = ch;
+    build_tr_items(p);
+    if ((st = upload_tr(p, s)) != FREDOPT_OK) break;
+    const double t = timeit(Launch{0, kKindChunks, 1}, 5);
+    if (t < best) {
+      best = t;
+      best_chunk = ch;
     }
   }
   p->tr_chunk = best_chunk;
   build_tr_items(p);
-  saved.lanes = p->lanes;
   p->hp = saved;
-  if (st == FREDOPT_OK) st = upload_items(p, s);
+  if (st == FREDOPT_OK) st = upload_tr(p, s);
   if (st == FREDOPT_OK) st = upload_table(p, s);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

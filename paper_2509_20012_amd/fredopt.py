@@ -20,7 +20,8 @@ LIB_PATH = os.path.join(_PKG, "libfredopt.so")
 F32, F16, BF16 = 0, 1, 2
 STORAGE = {"f32": F32, "fp32": F32, "f16": F16, "fp16": F16, "bf16": BF16}
 NORM_CONVEX_ALL, NORM_CONVEX_VIOLATED, NORM_RAW = 0, 1, 2
-KERNEL_NAMES = ("fwd_obj", "tr_grad", "fwd_dir", "rows", "tr_proj", "fwd_resid")
+KERNEL_NAMES = ("fwd_obj", "tr_grad", "fwd_dir", "rows", "tr_proj", "fwd_resid", "col",
+                "finalize")
 
 STATUS = {0: "OK", -1: "E_ARG", -2: "E_SHAPE", -3: "E_INDEX", -4: "E_NONFINITE",
           -5: "E_WORKSPACE", -6: "E_DEVICE", -7: "E_STATE", -8: "E_NOT_IMPLEMENTED"}
@@ -37,7 +38,8 @@ class Matrices(ct.Structure):
     _fields_ = [("n_rows", ct.c_int64), ("n_cols", ct.c_int64), ("nnz", ct.c_int64),
                 ("row_ptr", ct.c_void_p), ("col_idx", ct.c_void_p),
                 ("d_val", ct.c_void_p), ("l_val", ct.c_void_p),
-                ("storage", ct.c_int32), ("on_device", ct.c_int32)]
+                ("storage", ct.c_int32), ("on_device", ct.c_int32),
+                ("lanes_per_row", ct.c_int32), ("gradient_reserve_pct", ct.c_int32)]
 
 
 class Problem(ct.Structure):
@@ -65,9 +67,10 @@ class State(ct.Structure):
 
 class PlanInfo(ct.Structure):
     _fields_ = [("n_rows", ct.c_int64), ("n_cols", ct.c_int64), ("nnz", ct.c_int64),
-                ("csr_slots", ct.c_int64), ("csc_slots", ct.c_int64),
-                ("bytes_per_csr_slot", ct.c_int64), ("bytes_per_csc_slot", ct.c_int64),
-                ("fwd_items", ct.c_int64), ("tr_items", ct.c_int64), ("row_items", ct.c_int64),
+                ("sell_slots", ct.c_int64), ("csc_slots", ct.c_int64),
+                ("bytes_per_sell_slot", ct.c_int64), ("bytes_per_csc_slot", ct.c_int64),
+                ("n_slices", ct.c_int64), ("tr_items", ct.c_int64), ("row_items", ct.c_int64),
+                ("workspace_bytes", ct.c_int64),
                 ("storage", ct.c_int32), ("lanes_per_row", ct.c_int32),
                 ("fwd_grid", ct.c_int32), ("tr_chunk", ct.c_int32), ("lds_x", ct.c_int32),
                 ("reserved", ct.c_int32)]
@@ -76,7 +79,8 @@ class PlanInfo(ct.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
-EXPORTED = ("fredopt_workspace_bytes", "fredopt_load_matrices", "fredopt_free_plan",
+EXPORTED = ("fredopt_workspace_bytes", "fredopt_workspace_bytes_csr",
+            "fredopt_load_matrices", "fredopt_free_plan",
             "fredopt_dose_let", "fredopt_project_sweep", "fredopt_superiorize_step",
             "fredopt_solve", "fredopt_last_error", "fredopt_get_plan_info",
             "fredopt_profile_kernels", "fredopt_autotune", "fredopt_set_tuning")
@@ -96,6 +100,9 @@ def lib():
         P, PP = ct.c_void_p, ct.POINTER(ct.c_void_p)
         L.fredopt_workspace_bytes.argtypes = [ct.c_int64, ct.c_int64, ct.c_int64, ct.c_int32]
         L.fredopt_workspace_bytes.restype = ct.c_size_t
+        L.fredopt_workspace_bytes_csr.argtypes = [ct.c_int64, ct.c_int64, P, ct.c_int32,
+                                                  ct.c_int32, ct.c_int32]
+        L.fredopt_workspace_bytes_csr.restype = ct.c_size_t
         L.fredopt_load_matrices.argtypes = [ct.POINTER(Matrices), P, ct.c_size_t, P, PP]
         L.fredopt_free_plan.argtypes = [P]
         L.fredopt_dose_let.argtypes = [P, P, ct.c_double, P, P, P, P]
@@ -113,7 +120,8 @@ def lib():
         L.fredopt_autotune.argtypes = [P, P, P]
         L.fredopt_set_tuning.argtypes = [P, ct.c_int32, ct.c_int32]
         for name in EXPORTED:
-            if name not in ("fredopt_workspace_bytes", "fredopt_last_error"):
+            if name not in ("fredopt_workspace_bytes", "fredopt_workspace_bytes_csr",
+                            "fredopt_last_error"):
                 getattr(L, name).restype = ct.c_int
         _lib = L
     return _lib
@@ -144,12 +152,23 @@ def _ptr(t) -> Optional[int]:
 
 
 def workspace_bytes(n_rows: int, n_cols: int, nnz: int, storage: int = F32) -> int:
+    """Pattern-free upper bound of the workspace."""
     return int(lib().fredopt_workspace_bytes(n_rows, n_cols, nnz, storage))
+
+
+def workspace_bytes_csr(row_ptr, n_cols: int, storage: int = F32, lanes_per_row: int = 0,
+                        gradient_reserve_pct: int = 0) -> int:
+    """Exact workspace for one sparsity pattern (host row pointers)."""
+    rp = np.ascontiguousarray(row_ptr, np.int64)
+    return int(lib().fredopt_workspace_bytes_csr(rp.size - 1, n_cols, rp.ctypes.data, storage,
+                                                 lanes_per_row, gradient_reserve_pct))
 
 
 @dataclasses.dataclass
 class SolverParams:
-    """Parameters of Figs. 2-3 (defaults documented in the design doc's readings)."""
+    """Parameters of Figs. 2-3.  The paper gives no values; these defaults are the
+    library's (relaxation 1, alpha 0.99, eta 0.999, one perturbation per iteration,
+    convex weights over all constraints)."""
     lam: float = 1.0
     alpha: float = 0.99
     eta: float = 0.999
@@ -214,7 +233,8 @@ class Plan:
 
 
 def load_matrices(row_ptr, col_idx, d_val, l_val, n_cols: int, storage: int = F32,
-                  device="cuda", stream=None, on_device: bool = True) -> Plan:
+                  device="cuda", stream=None, on_device: bool = True,
+                  lanes_per_row: int = 0, gradient_reserve_pct: int = 0) -> Plan:
     """Loads CSR influence matrices.  With on_device=True the arrays are copied to
     the device with torch first (the library then reads device pointers); with
     on_device=False host arrays are handed to the library, which stages them."""
@@ -224,19 +244,21 @@ def load_matrices(row_ptr, col_idx, d_val, l_val, n_cols: int, storage: int = F3
     d_val = np.ascontiguousarray(d_val, np.float32)
     l_val = np.ascontiguousarray(l_val, np.float32)
     R = row_ptr.size - 1
-    nnz = int(row_ptr[-1]) if R >= 0 and row_ptr.size else 0
-    nbytes = workspace_bytes(R, n_cols, nnz, storage)
+    nnz = int(row_ptr[-1]) if row_ptr.size else 0
+    nbytes = workspace_bytes_csr(row_ptr, n_cols, storage, lanes_per_row, gradient_reserve_pct)
     if nbytes == 0:
-        raise FredoptError(-2, f"invalid sizes rows={R} cols={n_cols} nnz={nnz}")
+        nbytes = 256  # invalid sizes: let the library report the error
     ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
     keep = ()
     if on_device:
         tens = [torch.from_numpy(a).to(device) for a in (row_ptr, col_idx, d_val, l_val)]
-        m = Matrices(R, n_cols, nnz, *[_ptr(t) for t in tens], storage, 1)
+        m = Matrices(R, n_cols, nnz, *[_ptr(t) for t in tens], storage, 1, lanes_per_row,
+                     gradient_reserve_pct)
         keep = tens
     else:
         m = Matrices(R, n_cols, nnz, row_ptr.ctypes.data, col_idx.ctypes.data,
-                     d_val.ctypes.data, l_val.ctypes.data, storage, 0)
+                     d_val.ctypes.data, l_val.ctypes.data, storage, 0, lanes_per_row,
+                     gradient_reserve_pct)
     h = ct.c_void_p()
     _check(lib().fredopt_load_matrices(ct.byref(m), _ptr(ws), nbytes, _stream(stream),
                                        ct.byref(h)))
@@ -293,13 +315,14 @@ def new_state(k: int = 0, s: int = -1) -> State:
 
 def profile_kernels(plan: Plan, problem: DeviceProblem, params: SolverParams, state: State,
                     x, n_iters: int, stream=None):
-    ms = (ct.c_double * 6)()
-    cnt = (ct.c_int64 * 6)()
+    nk = len(KERNEL_NAMES)
+    ms = (ct.c_double * nk)()
+    cnt = (ct.c_int64 * nk)()
     pr, q = problem.struct(), params.struct()
     _check(lib().fredopt_profile_kernels(plan.handle, ct.byref(pr), ct.byref(q),
                                          ct.byref(state), _ptr(x), int(n_iters),
                                          _stream(stream), ms, cnt))
-    return {KERNEL_NAMES[i]: (float(ms[i]), int(cnt[i])) for i in range(6)}
+    return {KERNEL_NAMES[i]: (float(ms[i]), int(cnt[i])) for i in range(nk)}
 
 
 def autotune(plan: Plan, x, stream=None):
@@ -307,17 +330,19 @@ def autotune(plan: Plan, x, stream=None):
     return plan.info()
 
 
-def set_tuning(plan: Plan, lanes_per_row: int = 0, tr_chunk: int = 0):
-    _check(lib().fredopt_set_tuning(plan.handle, int(lanes_per_row), int(tr_chunk)))
+def set_tuning(plan: Plan, fwd_wgs_per_cu: int = 0, tr_chunk: int = 0):
+    _check(lib().fredopt_set_tuning(plan.handle, int(fwd_wgs_per_cu), int(tr_chunk)))
 
 
 # ----------------------------------------------------------------------- phantoms
 
-def load_phantom(ph, storage: int = F32, device="cuda", on_device: bool = True):
+def load_phantom(ph, storage: int = F32, device="cuda", on_device: bool = True,
+                 lanes_per_row: int = 0, gradient_reserve_pct: int = 0):
     """(Plan, DeviceProblem, x0 device tensor) for a ``phantom.Phantom``."""
     torch = _torch()
     plan = load_matrices(ph.row_ptr, ph.col_idx, ph.d_val, ph.l_val, ph.n_cols, storage,
-                         device=device, on_device=on_device)
+                         device=device, on_device=on_device, lanes_per_row=lanes_per_row,
+                         gradient_reserve_pct=gradient_reserve_pct)
     prob = DeviceProblem(ph.problem_arrays(), ph.c, device=device)
     x0 = torch.from_numpy(np.ascontiguousarray(ph.x0, np.float32)).to(device)
     return plan, prob, x0

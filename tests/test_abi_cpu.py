@@ -27,6 +27,21 @@ def test_library_exports_every_declared_function():
     assert set(names) == set(fredopt.EXPORTED)
 
 
+def test_workspace_bytes_exact_within_bound():
+    import numpy as np
+    from paper_2509_20012_amd import phantom as ph
+    for args in ((48, 12, 0.3, 1), (300, 37, 0.2, 2), (1000, 130, 0.05, 3)):
+        p = ph.tiny_problem(*args[:3], seed=args[3])
+        exact = fredopt.workspace_bytes_csr(p.row_ptr, p.n_cols)
+        bound = fredopt.workspace_bytes(p.n_rows, p.n_cols, p.nnz)
+        assert 0 < exact <= bound
+        for lpr in (1, 2, 4, 8, 16):
+            assert fredopt.workspace_bytes_csr(p.row_ptr, p.n_cols, lanes_per_row=lpr) > 0
+        assert fredopt.workspace_bytes_csr(p.row_ptr, p.n_cols, lanes_per_row=3) == 0
+    bad = np.array([0, 3, 2], np.int64)
+    assert fredopt.workspace_bytes_csr(bad, 4) == 0
+
+
 def test_workspace_bytes():
     assert fredopt.workspace_bytes(0, 0, 0) == 0          # no columns
     assert fredopt.workspace_bytes(-1, 4, 0) == 0
@@ -53,6 +68,7 @@ def test_null_arguments_rejected_without_device():
                                       None) == -1
     assert L.fredopt_solve(None, ct.byref(pr), ct.byref(q), ct.byref(st), None, None) == -1
     assert L.fredopt_set_tuning(None, 0, 0) == -1
+    assert L.fredopt_profile_kernels(None, None, None, None, None, 1, None, None, None) == -1
     assert L.fredopt_autotune(None, None, None) == -1
     assert L.fredopt_get_plan_info(None, None) == -1
     assert "NULL" in fredopt.last_error() or "non-NULL" in fredopt.last_error()
@@ -65,7 +81,7 @@ def test_load_rejects_bad_workspace_before_device_work():
     ci = np.array([0], np.int32)
     v = np.array([1.0], np.float32)
     m = fredopt.Matrices(1, 1, 1, rp.ctypes.data, ci.ctypes.data, v.ctypes.data,
-                         v.ctypes.data, 0, 0)
+                         v.ctypes.data, 0, 0, 0, 0)
     h = ct.c_void_p()
     assert L.fredopt_load_matrices(ct.byref(m), None, 1 << 20, None, ct.byref(h)) == -5
     assert L.fredopt_load_matrices(ct.byref(m), ct.c_void_p(256), 16, None, ct.byref(h)) == -5

@@ -83,6 +83,23 @@ def test_dose_let_tiny(fo, case, on_device):
     assert np.all(dg[empty] == 0.0) and np.all(lg[empty] == 0.0) and np.all(cg[empty] == 0.0)
 
 
+@pytest.mark.parametrize("lpr", [1, 2, 4, 8, 16])
+def test_dose_let_every_layout_width(fo, lpr):
+    """Every lanes-per-row width of the sliced-ELL layout gives T1 results, on rows
+    of very uneven length (ragged slices and windows)."""
+    import torch
+    p = ph.tiny_problem(2500, 300, 0.08, seed=40 + lpr, empty_rows=[0, 17, 2499])
+    plan, _, _ = fo.load_phantom(p, lanes_per_row=lpr)
+    assert plan.info()["lanes_per_row"] == lpr
+    x = np.random.default_rng(lpr).uniform(0.0, 2.0, p.n_cols).astype(np.float32)
+    dose, letd, _ = fo.dose_let(plan, torch.from_numpy(x).cuda(), p.c)
+    torch.cuda.synchronize()
+    d_ref, _, letd_ref, _ = Oracle(p).dose_let(x)
+    assert _rel_rows(_np(dose), d_ref) <= T1
+    assert _rel_rows(_np(letd), letd_ref, d_ref > 0) <= T1
+    assert np.all(_np(dose)[np.diff(p.row_ptr) == 0] == 0.0)
+
+
 def test_dose_let_config0(fo, cfg0):
     import torch
     plan, prob, x0 = fo.load_phantom(cfg0)
@@ -144,12 +161,13 @@ def test_project_sweep_config0(fo, cfg0):
     assert np.linalg.norm(xg - xr) <= T2 * np.linalg.norm(xr)
 
 
+@pytest.mark.parametrize("lpr", [1, 4])
 @pytest.mark.parametrize("r", [0, 1, 2])
-def test_superiorize_step_tiny(fo, r):
+def test_superiorize_step_tiny(fo, r, lpr):
     import torch
     p = ph.tiny_problem(300, 30, 0.15, seed=21)
-    print(f"superiorize_step tiny r={r}", flush=True)
-    plan, prob, x0 = fo.load_phantom(p)
+    print(f"superiorize_step tiny r={r} lpr={lpr}", flush=True)
+    plan, prob, x0 = fo.load_phantom(p, lanes_per_row=lpr)
     q = _params(fo, alpha=0.9, reductions_n=r)
     st = fo.new_state()
     o = Oracle(p)
@@ -272,3 +290,43 @@ def test_load_errors(fo):
     assert e.value.name == "E_STATE"
     torch.cuda.synchronize()
     assert torch.equal(x0, x_before)
+
+
+@pytest.mark.parametrize("reserve", [-1, 0, 100])
+def test_gradient_copy_and_fallback(fo, reserve):
+    """The objective-row CSC used by the gradient (default reserve), the full CSC
+    (no reserve) and a reserve of the whole CSC give the oracle's iterates."""
+    p = ph.tiny_problem(600, 50, 0.1, seed=77)
+    plan, prob, x0 = fo.load_phantom(p, gradient_reserve_pct=reserve)
+    q = _params(fo, alpha=0.9, reductions_n=2)
+    st = fo.new_state()
+    x = x0.clone()
+    o = Oracle(p)
+    xr, k, s = p.x0.astype(np.float64), 0, -1
+    for it in range(4):
+        fo.superiorize_step(plan, prob, q, st, x)
+        xr, k, s, info = o.sa_iteration(xr, k, s, _oparams(q))
+        assert (st.k, st.s) == (k, s)
+        assert st.grad_sq == pytest.approx(info["grad_sq"], rel=1e-4)
+        assert np.linalg.norm(_np(x) - xr) <= T2 * np.linalg.norm(xr)
+
+
+def test_gradient_copy_follows_kind_changes(fo):
+    """Changing the kind array in place (same device address) is detected."""
+    import torch
+    p = ph.tiny_problem(400, 40, 0.12, seed=78)
+    plan, prob, x0 = fo.load_phantom(p)
+    q = _params(fo, alpha=0.9, iter_max=3)
+    st = fo.new_state()
+    x = x0.clone()
+    fo.solve(plan, prob, q, st, x)
+    # drop the objective terms of every other row, in place
+    arr = {k: v.copy() for k, v in p.problem_arrays().items()}
+    arr["kind"][::2] &= ~np.uint16(ph.OBJ_DOSE | ph.OBJ_CDL)
+    prob.t["kind"].copy_(torch.from_numpy(arr["kind"].view(np.int16)).cuda())
+    st2 = fo.new_state()
+    x2 = x0.clone()
+    fo.solve(plan, prob, q, st2, x2)
+    xr, k, s, _ = Oracle(p, problem=arr).solve(p.x0, 3, _oparams(q))
+    assert (st2.k, st2.s) == (k, s)
+    assert np.linalg.norm(_np(x2) - xr) <= T2 * np.linalg.norm(xr)
