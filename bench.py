@@ -48,18 +48,25 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def algorithmic_bytes(kernel: str, R: int, C: int, nnz: int, vb: int, n_tr_items: int) -> int:
+def algorithmic_bytes(kernel: str, R: int, C: int, nnz: int, vb: int, n_tr_items: int,
+                      grad_entries: int, n_obj_rows: int, obj_entries: int) -> int:
     """Bytes a kernel launch must move: the unpadded matrix entries (shared index, D
     and L values), the input vector once, per-row problem data and outputs.  Padding
     and re-reads are not counted."""
     b = 4 + 2 * vb
+    if kernel == "fwd_obj" and obj_entries:   # objective rows only
+        return obj_entries * b + 4 * C + n_obj_rows * (8 + 8 + 2 + 12)
+    if kernel == "fwd_dir" and obj_entries:   # objective rows only; Q
+        return obj_entries * b + 4 * C + n_obj_rows * (2 + 4)
     if kernel == "fwd_obj":     # x in; d, l, coef out; kind, w_obj, targets in
         return nnz * b + 4 * C + R * (8 + 8 + 2 + 12)
     if kernel == "fwd_dir":     # g in; Dg, Lg out; kind, w_obj in
         return nnz * b + 4 * C + R * (8 + 2 + 4)
     if kernel == "fwd_resid":   # x in; d, l, coef out; kind, bounds, weights, moments in
         return nnz * b + 4 * C + R * (8 + 8 + 2 + 20 + 4 + 24 + 12)
-    if kernel in ("tr_grad", "tr_proj"):   # coefficient pair per row once; chunk sums
+    if kernel == "tr_grad":     # entries of rows with objective terms only
+        return grad_entries * b + 8 * n_obj_rows + C * (32 + 4)
+    if kernel == "tr_proj":     # coefficient pair per row once; chunk sums
         return nnz * b + 8 * R + n_tr_items * (32 + 4)
     if kernel == "col":         # chunk sums in; x, g in and out
         return n_tr_items * 4 + C * 16
@@ -170,20 +177,25 @@ def main():
     ms_per_step = ms_total / args.steps
     its = 1000.0 / ms_per_step
     log(f"timed {args.steps} iterations: {ms_per_step:.4f} ms/iter ({its:.1f} it/s), "
-        f"wall {wall:.3f} s, state k={st.k} s={st.s} cost={st.cost:.6g} prox={st.proximity:.3g}")
+        f"wall {wall:.3f} s, state k={st.k} s={st.s} cost={st.cost:.6g} prox={st.proximity:.3g} "
+        f"violated={st.n_violated}")
 
     # per-kernel durations with HIP events on the launch stream
     xp = x.clone()
     sp = fredopt.State()
     sp.k, sp.s = st.k, st.s
     prof = fredopt.profile_kernels(plan, prob, q, sp, xp, args.profile_iters)
+    info = plan.info()
+    from paper_2509_20012_amd import phantom as ph_mod
+    n_obj_rows = int(np.count_nonzero(p.kind & (ph_mod.OBJ_DOSE | ph_mod.OBJ_CDL)))
     R, C, nnz = p.n_rows, p.n_cols, p.nnz
     vb = 4 if storage == fredopt.F32 else 2
     per_kernel = {}
     for name, (ms, cnt) in prof.items():
         if cnt == 0:
             continue
-        ab = algorithmic_bytes(name, R, C, nnz, vb, info["tr_items"])
+        ab = algorithmic_bytes(name, R, C, nnz, vb, info["tr_items"], info["grad_entries"],
+                               n_obj_rows, info["obj_entries"])
         per_kernel[name] = {"ms": ms, "launches_per_iter": cnt / args.profile_iters,
                             "alg_bytes": ab, "gbps": ab / (ms * 1e-3) / 1e9 if ms > 0 else 0.0}
     dom = max((k for k in per_kernel if per_kernel[k]["alg_bytes"] > 0),

@@ -214,9 +214,13 @@ typedef struct {
   int64_t bytes_per_sell_slot, bytes_per_csc_slot;
   int64_t n_slices, tr_items, row_items;
   int64_t workspace_bytes;
+  int64_t grad_entries;     /* entries the gradient pass streams (after a problem was
+                               prepared: objective rows only, or nnz), else 0     */
+  int64_t obj_entries;      /* entries of the objective-row forward view (0 if unused) */
   int32_t storage, lanes_per_row, fwd_grid, tr_chunk;
-  int32_t lds_x; /* 1 if the forward kernels stage the vector in LDS */
-  int32_t reserved;
+  int32_t lds_x;    /* 1 if the forward kernels stage the vector in LDS */
+  int32_t schedule; /* 1: objective-row view in use (one all-row forward product per
+                       outer iteration), 0: two all-row forward products */
 } fredopt_plan_info;
 
 fredopt_status fredopt_get_plan_info(const fredopt_plan *p, fredopt_plan_info *info);

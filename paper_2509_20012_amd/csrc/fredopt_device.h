@@ -5,7 +5,29 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// Pointers read from a plan descriptor are generic; casting them to the global
+// address space lets the compiler use global (not flat) loads, which do not share a
+// wait counter with LDS traffic.
+#define FO_GLOBAL __attribute__((address_space(1)))
+
 namespace fo {
+
+template <typename T>
+__device__ __forceinline__ const FO_GLOBAL T* gconst(const T* p) {
+  return (const FO_GLOBAL T*)p;
+}
+template <typename T>
+__device__ __forceinline__ FO_GLOBAL T* gmut(T* p) {
+  return (FO_GLOBAL T*)p;
+}
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// native vector types (HIP's float4 & co. are classes and cannot live in a
+// non-generic address space)
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef float v2f __attribute__((ext_vector_type(2)));
+typedef unsigned v2u __attribute__((ext_vector_type(2)));
 
 constexpr int kWave = 64;              // CDNA wavefront width
 constexpr int kFwdBlock = 512;         // forward kernel: 8 waves, one slice each
@@ -28,7 +50,17 @@ enum FwdMode : int { kFwdDoseLet = 0, kFwdObj = 1, kFwdDir = 2, kFwdResid = 3 };
 // rows-kernel epilogues
 enum RowMode : int { kRowsMoveObj = 0, kRowsMoveResid = 1 };
 // column-finalise epilogues of the transposed product
-enum ColMode : int { kColGrad = 0, kColGradMove = 1, kColProj = 2, kColProjMove = 3 };
+enum ColMode : int {
+  kColGrad = 0,      // g = sum
+  kColGradMove = 1,  // x -= beta g (pending move), then g = sum
+  kColProj = 2,      // x = max(0, x - scale sum)
+  kColProjMove = 3,  // x = max(0, x - beta g - scale sum)
+  kColProjY = 4,     // x = y = max(0, y - scale sum)
+  kColYMove = 5,     // y -= beta g (no sum)
+  kColYCopy = 6      // y = x (no sum)
+};
+// which vector a forward pass multiplies
+enum VecSel : int { kVecX = 0, kVecY = 1, kVecG = 2 };
 // plan-level finalisation
 enum FinMode : int {
   kFinDir0 = 0,        // first perturbation of an outer iteration: cost, reset, step
@@ -56,18 +88,22 @@ struct DevState {
 //   base[s] + ((e / 4) / lpr) * 256 + (p * lpr + (e / 4) % lpr) * 4 + e % 4
 // so one wave step reads 1 KiB contiguously per array.  Rows are sorted by length
 // (descending) inside windows of consecutive rows; srow maps slice positions back.
-struct DevPlan {
-  int64_t R, C;
-  int32_t vtype, lpr_log2;
-  int32_t n_slices, n_row_items;
-  int32_t n_col_blocks, n_groups;
-  // sliced-ELL copy for the forward products
+struct SellView {
   const int64_t* sbase;       // [n_slices + 1]
   const int32_t* swidth;      // [n_slices] steps
   const int32_t* srow;        // [n_slices * rpw] original row, -1 for padding
   const int32_t* sci;
   const void* sdv;
   const void* slv;
+  int32_t n_slices, n_groups;
+};
+
+struct DevPlan {
+  int64_t R, C;
+  int32_t vtype, lpr_log2;
+  int32_t n_row_items, n_col_blocks;
+  SellView sell;              // every row
+  SellView osell;             // rows with objective terms (per problem), for Eq. (2)
   // CSC copy, columns padded to 4 slots, rows ascending in a column (projection)
   const int32_t* ri;
   const void* cdv;
@@ -88,6 +124,7 @@ struct DevPlan {
   const float *dlo, *dhi, *clo, *chi, *tmax, *wf, *wo, *dt, *ct;
   // vectors
   float* x;                   // fluence (caller's array during a call)
+  float* y;                   // perturbed point fed to the feasibility step
   float* d;
   float* l;
   float* dg;
@@ -98,8 +135,8 @@ struct DevPlan {
   float* out_letd;
   float* out_cdl;
   // reductions
-  double* spart_a;            // [n_groups * kNPart] objective / residual passes
-  double* spart_b;            // [n_groups * kNPart] direction pass
+  double* spart_a;            // [groups * kNPart] objective / residual passes
+  double* spart_b;            // [groups * kNPart] direction pass
   double* rpart;              // [n_row_items * kNPart]
   double* gpart;              // [n_col_blocks]
   float* tpart;               // [sum of chunks]

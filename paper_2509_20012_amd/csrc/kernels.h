@@ -6,15 +6,17 @@
 namespace fo {
 
 // iteration kernels (kernels_iter.hip)
-void launch_forward(int vtype, int mode, const DevPlan* plans, const FwdGroup* groups,
-                    int n_groups, int grid, int lds_floats, uint32_t* ctr, hipStream_t s);
+// sub: 0 all-row view, 1 objective-row view; vsel: VecSel
+void launch_forward(int vtype, int mode, int sub, const DevPlan* plans, const FwdGroup* groups,
+                    int n_groups, int grid, int lds_floats, uint32_t* ctr, int vsel,
+                    hipStream_t s);
 void launch_rows(int mode, const DevPlan* plans, const RowItem* items, int n_items,
                  hipStream_t s);
 void launch_tr_chunks(int vtype, int tag, const DevPlan* plans, const TrItem* items,
                       int n_items, hipStream_t s);
 void launch_tcol(int mode, const DevPlan* plans, const ColBlock* blocks, int n_blocks,
                  hipStream_t s);
-void launch_finalize(int mode, const DevPlan* plans, int n_plans, hipStream_t s);
+void launch_finalize(int mode, int sub, const DevPlan* plans, int n_plans, hipStream_t s);
 hipError_t set_forward_lds_limit(int vtype, size_t bytes);
 
 // load kernels (kernels_load.hip)
@@ -47,6 +49,14 @@ void launch_obj_count(int64_t C, const int64_t* cp, const uint32_t* len, const i
 void launch_obj_fill(int vtype, int64_t C, const int64_t* cp, const uint32_t* len,
                      const int32_t* ri, const void* cdv, const void* clv, const uint16_t* kind,
                      const int64_t* ocp, int32_t* ori, void* ocdv, void* oclv, hipStream_t s);
+// copies the objective rows' entries from the all-row sliced-ELL view into the
+// objective-row view: row obj_row[i] sits at slice position src_pos[i] of the full
+// view and dst_pos[i] of the objective view and has len[i] entries
+void launch_pack_sub(int vtype, int lpr_log2, int64_t n, const int32_t* src_pos,
+                     const int32_t* dst_pos, const int32_t* len, const int64_t* src_base,
+                     const int32_t* src_ci, const void* src_dv, const void* src_lv,
+                     const int64_t* dst_base, int32_t* dst_ci, void* dst_dv, void* dst_lv,
+                     hipStream_t s);
 void launch_check_problem(int64_t R, const uint16_t* kind, const float* dlo, const float* dhi,
                           const float* clo, const float* chi, const float* tmax,
                           const float* wf, const float* wo, const float* dt, const float* ct,

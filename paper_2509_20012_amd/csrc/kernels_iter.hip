@@ -31,33 +31,40 @@
 
 namespace fo {
 
+// Four consecutive stored values starting at element e of a global array, as floats.
 template <int VT>
 struct VLoad;
 
 template <>
 struct VLoad<kF32> {
-  static __device__ __forceinline__ float4 q4(const void* p, int64_t q) {
-    return *reinterpret_cast<const float4*>(static_cast<const float*>(p) + q);
+  static __device__ __forceinline__ v4f q4(const FO_GLOBAL void* p, uint32_t e) {
+    return *((const FO_GLOBAL v4f*)((const FO_GLOBAL float*)p + e));
   }
 };
 
 template <>
 struct VLoad<kF16> {
   typedef _Float16 h4 __attribute__((ext_vector_type(4)));
-  static __device__ __forceinline__ float4 q4(const void* p, int64_t q) {
-    const h4 h = *reinterpret_cast<const h4*>(static_cast<const _Float16*>(p) + q);
-    return make_float4((float)h.x, (float)h.y, (float)h.z, (float)h.w);
+  static __device__ __forceinline__ v4f q4(const FO_GLOBAL void* p, uint32_t e) {
+    const h4 h = *((const FO_GLOBAL h4*)((const FO_GLOBAL _Float16*)p + e));
+    return v4f{(float)h.x, (float)h.y, (float)h.z, (float)h.w};
   }
 };
 
 template <>
 struct VLoad<kBF16> {
-  static __device__ __forceinline__ float4 q4(const void* p, int64_t q) {
-    const uint2 u = *reinterpret_cast<const uint2*>(static_cast<const uint16_t*>(p) + q);
-    return make_float4(__uint_as_float(u.x << 16), __uint_as_float(u.x & 0xffff0000u),
-                       __uint_as_float(u.y << 16), __uint_as_float(u.y & 0xffff0000u));
+  static __device__ __forceinline__ v4f q4(const FO_GLOBAL void* p, uint32_t e) {
+    const v2u u = *((const FO_GLOBAL v2u*)((const FO_GLOBAL uint16_t*)p + e));
+    return v4f{__uint_as_float(u.x << 16), __uint_as_float(u.x & 0xffff0000u),
+               __uint_as_float(u.y << 16), __uint_as_float(u.y & 0xffff0000u)};
   }
 };
+
+template <int VT>
+__device__ __forceinline__ const FO_GLOBAL void* value_ptr(const void* base, int64_t e) {
+  const int vb = VT == kF32 ? 4 : 2;
+  return (const FO_GLOBAL char*)(base) + e * vb;
+}
 
 // ------------------------------------------------------------------ reductions --
 
@@ -89,35 +96,35 @@ __device__ __forceinline__ double block_sum(double v, double* sh4) {
 // coefficients (-2 w (Dhat - d), -2 c w (cDLhat - c l)) of the row.
 __device__ __forceinline__ void objective_row(const DevPlan* P, int r, float d, float l,
                                               double* chi) {
-  const unsigned k = P->kind[r];
+  const unsigned k = gconst(P->kind)[r];
   double uD = 0.0, uL = 0.0;
   if (k & (kObjDose | kObjCdl)) {
-    const double w = P->wo[r], c = P->prm.c;
+    const double w = gconst(P->wo)[r], c = P->prm.c;
     if (k & kObjDose) {
-      const double e = (double)P->dt[r] - (double)d;
+      const double e = (double)gconst(P->dt)[r] - (double)d;
       *chi += w * e * e;
       uD = -2.0 * w * e;
     }
     if (k & kObjCdl) {
-      const double f = (double)P->ct[r] - c * (double)l;
+      const double f = (double)gconst(P->ct)[r] - c * (double)l;
       *chi += w * f * f;
       uL = -2.0 * c * w * f;
     }
   }
-  P->coef[r] = make_float2((float)uD, (float)uL);
+  ((FO_GLOBAL v2f*)(P->coef))[r] = v2f{(float)uD, (float)uL};
 }
 
 __device__ __forceinline__ double objective_value(const DevPlan* P, int r, float d, float l) {
-  const unsigned k = P->kind[r];
+  const unsigned k = gconst(P->kind)[r];
   double s = 0.0;
   if (k & (kObjDose | kObjCdl)) {
-    const double w = P->wo[r], c = P->prm.c;
+    const double w = gconst(P->wo)[r], c = P->prm.c;
     if (k & kObjDose) {
-      const double e = (double)P->dt[r] - (double)d;
+      const double e = (double)gconst(P->dt)[r] - (double)d;
       s += w * e * e;
     }
     if (k & kObjCdl) {
-      const double f = (double)P->ct[r] - c * (double)l;
+      const double f = (double)gconst(P->ct)[r] - c * (double)l;
       s += w * f * f;
     }
   }
@@ -131,12 +138,12 @@ __device__ __forceinline__ double objective_value(const DevPlan* P, int r, float
 // T^2 sum D^2.  Accumulates slots [0]..[4] of the residual layout.
 __device__ __forceinline__ void residual_row(const DevPlan* P, int r, float d, float l,
                                              double* acc) {
-  const unsigned k = P->kind[r];
+  const unsigned k = gconst(P->kind)[r];
   double kD = 0.0, kL = 0.0;
   if (k & kConstraintBits) {
-    const double w = P->wf[r], lam = P->prm.lambda, c = P->prm.c;
+    const double w = gconst(P->wf)[r], lam = P->prm.lambda, c = P->prm.c;
     const double dd = d, ll = l;
-    const double* m = P->mom + 3 * (int64_t)r;
+    const FO_GLOBAL double* m = gconst(P->mom) + 3 * (int64_t)r;
     const double sdd = m[0], sll = m[1], sdl = m[2];
     auto take = [&](double v, double n2, double scale, int which, double T) {
       if (!(n2 > kDegenerateRel * scale)) {
@@ -158,31 +165,31 @@ __device__ __forceinline__ void residual_row(const DevPlan* P, int r, float d, f
     };
     if (k & kDoseHi) {
       acc[0] += w;
-      const double b = P->dhi[r];
+      const double b = gconst(P->dhi)[r];
       if (dd > b) take(dd - b, sdd, sdd, 0, 0.0);
     }
     if (k & kDoseLo) {
       acc[0] += w;
-      const double b = P->dlo[r];
+      const double b = gconst(P->dlo)[r];
       if (dd < b) take(dd - b, sdd, sdd, 0, 0.0);
     }
     if (k & kCdlHi) {
       acc[0] += w;
-      const double b = P->chi[r], ax = c * ll;
+      const double b = gconst(P->chi)[r], ax = c * ll;
       if (ax > b) take(ax - b, c * c * sll, c * c * sll, 1, 0.0);
     }
     if (k & kCdlLo) {
       acc[0] += w;
-      const double b = P->clo[r], ax = c * ll;
+      const double b = gconst(P->clo)[r], ax = c * ll;
       if (ax < b) take(ax - b, c * c * sll, c * c * sll, 1, 0.0);
     }
     if (k & kLetdHi) {
       acc[0] += w;
-      const double T = P->tmax[r], ax = ll - T * dd;
+      const double T = gconst(P->tmax)[r], ax = ll - T * dd;
       if (ax > 0.0) take(ax, sll - 2.0 * T * sdl + T * T * sdd, sll + T * T * sdd, 2, T);
     }
   }
-  P->coef[r] = make_float2((float)kD, (float)kL);
+  ((FO_GLOBAL v2f*)(P->coef))[r] = v2f{(float)kD, (float)kL};
 }
 
 __device__ __forceinline__ bool finite2(float a, float b) { return isfinite(a) && isfinite(b); }
@@ -259,27 +266,33 @@ __device__ __forceinline__ constexpr unsigned fwd_slots() {
   return MODE == kFwdResid ? 0x7Fu : 0x21u;
 }
 
-template <int VT, int MODE>
+// One slice of a sliced-ELL view: d = D v, l = L v for its rows, then the epilogue
+// of MODE.  SUB selects the objective-row view, whose direction pass only needs Q.
+template <int VT, int MODE, int SUB>
 __device__ __forceinline__ void forward_slice(const DevPlan* __restrict__ P, int s,
                                               const float* __restrict__ xs, bool use_lds,
                                               const float* __restrict__ vec, int lane,
                                               double* wpart) {
+  const SellView& V = SUB ? P->osell : P->sell;
   const int lg2 = P->lpr_log2;
   const int lpr = 1 << lg2;
   const int rpw = kWave >> lg2;
   const int pos = lane >> lg2;
-  const int64_t base = P->sbase[s] + 4 * lane;
-  const int W = P->swidth[s];
-  const int row = P->srow[(int64_t)s * rpw + pos];
-  const int32_t* __restrict__ ci = P->sci;
+  const int64_t sb = gconst(V.sbase)[s];
+  const int W = uniform(gconst(V.swidth)[s]);
+  const int row = gconst(V.srow)[(int64_t)s * rpw + pos];
+  // slice-relative element offsets fit 32 bits; the slice bases are wave-uniform
+  const FO_GLOBAL int32_t* ci = gconst(V.sci) + sb;
+  const FO_GLOBAL void* dv = value_ptr<VT>(V.sdv, sb);
+  const FO_GLOBAL void* lv = value_ptr<VT>(V.slv, sb);
   float ad = 0.f, al = 0.f;
   if (use_lds) {
 #pragma unroll 4
     for (int t = 0; t < W; ++t) {
-      const int64_t q = base + (int64_t)t * 256;
-      const int4 c4 = *reinterpret_cast<const int4*>(ci + q);
-      const float4 d4 = VLoad<VT>::q4(P->sdv, q);
-      const float4 l4 = VLoad<VT>::q4(P->slv, q);
+      const uint32_t e = (uint32_t)t * 256u + 4u * (uint32_t)lane;
+      const v4i c4 = *((const FO_GLOBAL v4i*)(ci + e));
+      const v4f d4 = VLoad<VT>::q4(dv, e);
+      const v4f l4 = VLoad<VT>::q4(lv, e);
       const float x0 = xs[c4.x], x1 = xs[c4.y], x2 = xs[c4.z], x3 = xs[c4.w];
       ad = fmaf(d4.x, x0, ad);
       ad = fmaf(d4.y, x1, ad);
@@ -291,16 +304,18 @@ __device__ __forceinline__ void forward_slice(const DevPlan* __restrict__ P, int
       al = fmaf(l4.w, x3, al);
     }
   } else {
-    const float* __restrict__ cs = P->cscale;
+    const FO_GLOBAL float* cs = gconst(P->cscale);
+    const FO_GLOBAL float* gv = gconst(vec);
+    const bool scaled = P->cscale != nullptr;
     for (int t = 0; t < W; ++t) {
-      const int64_t q = base + (int64_t)t * 256;
-      const int4 c4 = *reinterpret_cast<const int4*>(ci + q);
-      const float4 d4 = VLoad<VT>::q4(P->sdv, q);
-      const float4 l4 = VLoad<VT>::q4(P->slv, q);
-      const float x0 = cs ? vec[c4.x] * cs[c4.x] : vec[c4.x];
-      const float x1 = cs ? vec[c4.y] * cs[c4.y] : vec[c4.y];
-      const float x2 = cs ? vec[c4.z] * cs[c4.z] : vec[c4.z];
-      const float x3 = cs ? vec[c4.w] * cs[c4.w] : vec[c4.w];
+      const uint32_t e = (uint32_t)t * 256u + 4u * (uint32_t)lane;
+      const v4i c4 = *((const FO_GLOBAL v4i*)(ci + e));
+      const v4f d4 = VLoad<VT>::q4(dv, e);
+      const v4f l4 = VLoad<VT>::q4(lv, e);
+      const float x0 = scaled ? gv[c4.x] * cs[c4.x] : gv[c4.x];
+      const float x1 = scaled ? gv[c4.y] * cs[c4.y] : gv[c4.y];
+      const float x2 = scaled ? gv[c4.z] * cs[c4.z] : gv[c4.z];
+      const float x3 = scaled ? gv[c4.w] * cs[c4.w] : gv[c4.w];
       ad = fmaf(d4.x, x0, ad);
       ad = fmaf(d4.y, x1, ad);
       ad = fmaf(d4.z, x2, ad);
@@ -320,27 +335,29 @@ __device__ __forceinline__ void forward_slice(const DevPlan* __restrict__ P, int
   for (int k = 0; k < kNPart; ++k) acc[k] = 0.0;
   if ((lane & (lpr - 1)) == 0 && row >= 0) {
     if constexpr (MODE == kFwdDoseLet) {
-      if (P->out_dose) P->out_dose[row] = ad;
-      if (P->out_letd) P->out_letd[row] = ad > 0.f ? al / ad : 0.f;
-      if (P->out_cdl) P->out_cdl[row] = (float)(P->prm.c * (double)al);
+      if (P->out_dose) gmut(P->out_dose)[row] = ad;
+      if (P->out_letd) gmut(P->out_letd)[row] = ad > 0.f ? al / ad : 0.f;
+      if (P->out_cdl) gmut(P->out_cdl)[row] = (float)(P->prm.c * (double)al);
     } else if constexpr (MODE == kFwdObj) {
-      P->d[row] = ad;
-      P->l[row] = al;
+      gmut(P->d)[row] = ad;
+      gmut(P->l)[row] = al;
       objective_row(P, row, ad, al, &acc[0]);
       if (!finite2(ad, al)) acc[5] += 1.0;
     } else if constexpr (MODE == kFwdDir) {
-      P->dg[row] = ad;
-      P->lg[row] = al;
-      const unsigned k = P->kind[row];
+      if constexpr (!SUB) {
+        gmut(P->dg)[row] = ad;
+        gmut(P->lg)[row] = al;
+      }
+      const unsigned k = gconst(P->kind)[row];
       if (k & (kObjDose | kObjCdl)) {
-        const double wo = P->wo[row], c = P->prm.c;
+        const double wo = gconst(P->wo)[row], c = P->prm.c;
         if (k & kObjDose) acc[0] += wo * (double)ad * (double)ad;
         if (k & kObjCdl) acc[0] += wo * c * c * (double)al * (double)al;
       }
       if (!finite2(ad, al)) acc[5] += 1.0;
     } else {
-      P->d[row] = ad;
-      P->l[row] = al;
+      gmut(P->d)[row] = ad;
+      gmut(P->l)[row] = al;
       residual_row(P, row, ad, al, acc);
       acc[6] += objective_value(P, row, ad, al);
       if (!finite2(ad, al)) acc[5] += 1.0;
@@ -358,11 +375,11 @@ __device__ __forceinline__ void forward_slice(const DevPlan* __restrict__ P, int
   }
 }
 
-template <int VT, int MODE>
+template <int VT, int MODE, int SUB>
 __global__ __launch_bounds__(kFwdBlock) void k_forward(const DevPlan* __restrict__ plans,
                                                        const FwdGroup* __restrict__ groups,
                                                        int n_groups, int lds_floats,
-                                                       uint32_t* ctr) {
+                                                       uint32_t* ctr, int vsel) {
   extern __shared__ float xs[];
   __shared__ int s_g;
   __shared__ double wpart[kFwdWaves][kNPart];
@@ -388,23 +405,29 @@ __global__ __launch_bounds__(kFwdBlock) void k_forward(const DevPlan* __restrict
     const FwdGroup G = groups[gi];
     const DevPlan* __restrict__ P = plans + G.plan;
     if (G.plan != cur) {
-      vec = (MODE == kFwdDir) ? P->g : P->x;
+      vec = vsel == kVecG ? P->g : (vsel == kVecY ? P->y : P->x);
       use_lds = P->C <= (int64_t)lds_floats;
       if (use_lds) {
-        const float* cs = P->cscale;
-        for (int64_t j = tid; j < P->C; j += kFwdBlock) xs[j] = cs ? vec[j] * cs[j] : vec[j];
+        const FO_GLOBAL float* gv = gconst(vec);
+        const FO_GLOBAL float* cs = gconst(P->cscale);
+        const int C = (int)P->C;
+        if (P->cscale)
+          for (int j = tid; j < C; j += kFwdBlock) xs[j] = gv[j] * cs[j];
+        else
+          for (int j = tid; j < C; j += kFwdBlock) xs[j] = gv[j];
       }
       __syncthreads();
       cur = G.plan;
     }
-    if (wave < G.n) forward_slice<VT, MODE>(P, G.slice0 + wave, xs, use_lds, vec, lane, wpart[wave]);
+    if (wave < G.n)
+      forward_slice<VT, MODE, SUB>(P, G.slice0 + wave, xs, use_lds, vec, lane, wpart[wave]);
     __syncthreads();
     if constexpr (MODE != kFwdDoseLet) {
       // the group's partial: its slices' partials in wave order
       if (tid < kNPart) {
         double v = 0.0;
         for (int w = 0; w < G.n; ++w) v += wpart[w][tid];
-        (MODE == kFwdDir ? P->spart_b : P->spart_a)[(int64_t)G.slot * kNPart + tid] = v;
+        gmut(MODE == kFwdDir ? P->spart_b : P->spart_a)[(int64_t)G.slot * kNPart + tid] = v;
       }
     }
   }
@@ -425,10 +448,10 @@ __global__ __launch_bounds__(kBlock) void k_rows(const DevPlan* __restrict__ pla
   for (int k = 0; k < kNPart; ++k) acc[k] = 0.0;
   for (int r = w.r0 + tid; r < w.r1; r += kBlock) {
     // the accepted perturbation y = x - beta g moves d and l by -beta (D g, L g)
-    const float d = (float)((double)P->d[r] - beta * (double)P->dg[r]);
-    const float l = (float)((double)P->l[r] - beta * (double)P->lg[r]);
-    P->d[r] = d;
-    P->l[r] = l;
+    const float d = (float)((double)gmut(P->d)[r] - beta * (double)gmut(P->dg)[r]);
+    const float l = (float)((double)gmut(P->l)[r] - beta * (double)gmut(P->lg)[r]);
+    gmut(P->d)[r] = d;
+    gmut(P->l)[r] = l;
     if constexpr (MODE == kRowsMoveObj) {
       objective_row(P, r, d, l, &acc[0]);
     } else {
@@ -442,7 +465,7 @@ __global__ __launch_bounds__(kBlock) void k_rows(const DevPlan* __restrict__ pla
 #pragma unroll
   for (int k = 0; k < kNPart; ++k) s[k] = (used & (1u << k)) ? block_sum(acc[k], sh4) : 0.0;
   if (tid == 0) {
-    double* dst = P->rpart + (int64_t)w.slot * kNPart;
+    FO_GLOBAL double* dst = gmut(P->rpart) + (int64_t)w.slot * kNPart;
 #pragma unroll
     for (int k = 0; k < kNPart; ++k) dst[k] = s[k];
   }
@@ -463,19 +486,22 @@ __global__ __launch_bounds__(kBlock) void k_tr_chunks(const DevPlan* __restrict_
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const int it = lb * (kBlock / kWave) + wave;
   if (it >= n_items) return;
-  const TrItem w = items[it];
+  const TrItem w = items[uniform(it)];
   const DevPlan* __restrict__ P = plans + w.plan;
-  const int32_t* __restrict__ ri = TAG == 0 ? P->gri : P->ri;
-  const void* __restrict__ cdv = TAG == 0 ? P->gcdv : P->cdv;
-  const void* __restrict__ clv = TAG == 0 ? P->gclv : P->clv;
-  const float2* __restrict__ cf = P->coef;
+  // chunk-relative element offsets fit 32 bits; the chunk base is wave-uniform
+  const FO_GLOBAL int32_t* ri = gconst(TAG == 0 ? P->gri : P->ri) + w.q0;
+  const FO_GLOBAL void* cdv = value_ptr<VT>(TAG == 0 ? P->gcdv : P->cdv, w.q0);
+  const FO_GLOBAL void* clv = value_ptr<VT>(TAG == 0 ? P->gclv : P->clv, w.q0);
+  const FO_GLOBAL v2f* cf = (const FO_GLOBAL v2f*)(P->coef);
+  const uint32_t n = (uint32_t)(w.q1 - w.q0);
   float acc = 0.f;
 #pragma unroll 4
-  for (int64_t q = w.q0 + 4 * lane; q < w.q1; q += 4 * kWave) {
-    const int4 r4 = *reinterpret_cast<const int4*>(ri + q);
-    const float4 d4 = VLoad<VT>::q4(cdv, q);
-    const float4 l4 = VLoad<VT>::q4(clv, q);
-    const float2 c0 = cf[r4.x], c1 = cf[r4.y], c2 = cf[r4.z], c3 = cf[r4.w];
+  for (uint32_t e = 4u * (uint32_t)lane; e < n; e += 4u * kWave) {
+    const v4i r4 = *((const FO_GLOBAL v4i*)(ri + e));
+    const v4f d4 = VLoad<VT>::q4(cdv, e);
+    const v4f l4 = VLoad<VT>::q4(clv, e);
+    const v2f c0 = cf[(uint32_t)r4.x], c1 = cf[(uint32_t)r4.y];
+    const v2f c2 = cf[(uint32_t)r4.z], c3 = cf[(uint32_t)r4.w];
     acc = fmaf(d4.x, c0.x, acc);
     acc = fmaf(l4.x, c0.y, acc);
     acc = fmaf(d4.y, c1.x, acc);
@@ -486,7 +512,7 @@ __global__ __launch_bounds__(kBlock) void k_tr_chunks(const DevPlan* __restrict_
     acc = fmaf(l4.w, c3.y, acc);
   }
   acc = wave_sumf(acc);
-  if (lane == 0) P->tpart[w.tslot] = acc;
+  if (lane == 0) gmut(P->tpart)[w.tslot] = acc;
 }
 
 template <int MODE>
@@ -496,43 +522,53 @@ __global__ __launch_bounds__(kBlock) void k_tcol(const DevPlan* __restrict__ pla
   const ColBlock cb = blocks[blockIdx.x];
   const DevPlan* __restrict__ P = plans + cb.plan;
   const int j = cb.c0 + threadIdx.x;
+  constexpr bool grad = MODE == kColGrad || MODE == kColGradMove;
   double cv = 0.0;
   if (j < cb.c1) {
-    constexpr bool grad = MODE == kColGrad || MODE == kColGradMove;
-    const int ts = grad ? P->gcol_tslot0[j] : P->col_tslot0[j];
-    const int n = grad ? P->gcol_nch[j] : P->col_nch[j];
-    float t = 0.f;
-    for (int c = 0; c < n; ++c) t += P->tpart[ts + c];
-    if (P->cscale) t *= P->cscale[j];
-    if constexpr (MODE == kColGrad || MODE == kColGradMove) {
-      if constexpr (MODE == kColGradMove) {
-        const double b = P->st->beta;
-        P->x[j] = (float)((double)P->x[j] - b * (double)P->g[j]);
-      }
-      P->g[j] = t;
-      cv = (double)t * (double)t;
+    if constexpr (MODE == kColYCopy) {
+      gmut(P->y)[j] = gconst(P->x)[j];
+    } else if constexpr (MODE == kColYMove) {
+      const double b = P->st->beta;
+      gmut(P->y)[j] = (float)((double)gconst(P->y)[j] - b * (double)gconst(P->g)[j]);
     } else {
-      double y = P->x[j];
-      if constexpr (MODE == kColProjMove) y -= P->st->beta * (double)P->g[j];
-      const double xn = y - P->st->scale * (double)t;
-      P->x[j] = xn > 0.0 ? (float)xn : 0.f;
+      const int ts = grad ? gconst(P->gcol_tslot0)[j] : gconst(P->col_tslot0)[j];
+      const int n = grad ? gconst(P->gcol_nch)[j] : gconst(P->col_nch)[j];
+      float t = 0.f;
+      for (int c = 0; c < n; ++c) t += gconst(P->tpart)[ts + c];
+      if (P->cscale) t *= gconst(P->cscale)[j];
+      if constexpr (grad) {
+        if constexpr (MODE == kColGradMove) {
+          const double b = P->st->beta;
+          gmut(P->x)[j] = (float)((double)gconst(P->x)[j] - b * (double)gconst(P->g)[j]);
+        }
+        gmut(P->g)[j] = t;
+        cv = (double)t * (double)t;
+      } else {
+        double y = MODE == kColProjY ? gconst(P->y)[j] : gconst(P->x)[j];
+        if constexpr (MODE == kColProjMove) y -= P->st->beta * (double)gconst(P->g)[j];
+        const double xn = y - P->st->scale * (double)t;
+        const float xf = xn > 0.0 ? (float)xn : 0.f;
+        gmut(P->x)[j] = xf;
+        if constexpr (MODE == kColProjY) gmut(P->y)[j] = xf;
+      }
     }
   }
-  if constexpr (MODE == kColGrad || MODE == kColGradMove) {
+  if constexpr (grad) {
     const double s = block_sum(cv, sh4);
-    if (threadIdx.x == 0) P->gpart[cb.slot] = s;
+    if (threadIdx.x == 0) gmut(P->gpart)[cb.slot] = s;
   }
 }
 
 // ------------------------------------------------------------ finalisation ----
 
-__device__ __forceinline__ void sum_slots(const double* part, int n, double* out,
+__device__ __forceinline__ void sum_slots(const double* part_, int n, double* out,
                                           unsigned used, double* sh4) {
+  const FO_GLOBAL double* part = gconst(part_);
   double s[kNPart];
 #pragma unroll
   for (int k = 0; k < kNPart; ++k) s[k] = 0.0;
   for (int i = threadIdx.x; i < n; i += kBlock) {
-    const double* p = part + (int64_t)i * kNPart;
+    const FO_GLOBAL double* p = part + (int64_t)i * kNPart;
 #pragma unroll
     for (int k = 0; k < kNPart; ++k)
       if (used & (1u << k)) s[k] += p[k];
@@ -541,18 +577,20 @@ __device__ __forceinline__ void sum_slots(const double* part, int n, double* out
   for (int k = 0; k < kNPart; ++k) out[k] = (used & (1u << k)) ? block_sum(s[k], sh4) : 0.0;
 }
 
-template <int MODE>
+// SUB: the objective and direction partials come from the objective-row view.
+template <int MODE, int SUB>
 __global__ __launch_bounds__(kBlock) void k_finalize(const DevPlan* __restrict__ plans) {
   __shared__ double sh4[kBlock / kWave];
   const DevPlan* __restrict__ P = plans + blockIdx.x;
+  const int ng = SUB ? P->osell.n_groups : P->sell.n_groups;
   double a[kNPart];
   if constexpr (MODE == kFinDir0 || MODE == kFinDir) {
     double b[kNPart];
-    sum_slots(P->spart_b, P->n_groups, b, 0x21u, sh4);
+    sum_slots(P->spart_b, ng, b, 0x21u, sh4);
     double g = 0.0;
-    for (int i = threadIdx.x; i < P->n_col_blocks; i += kBlock) g += P->gpart[i];
+    for (int i = threadIdx.x; i < P->n_col_blocks; i += kBlock) g += gconst(P->gpart)[i];
     const double G = block_sum(g, sh4);
-    if constexpr (MODE == kFinDir0) sum_slots(P->spart_a, P->n_groups, a, 0x21u, sh4);
+    if constexpr (MODE == kFinDir0) sum_slots(P->spart_a, ng, a, 0x21u, sh4);
     if (threadIdx.x == 0) {
       DevState* st = P->st;
       if constexpr (MODE == kFinDir0) {
@@ -576,46 +614,51 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const DevPlan* __restrict__
     sum_slots(P->rpart, P->n_row_items, a, 0x7Fu, sh4);
     if (threadIdx.x == 0) finalize_residuals(P, a);
   } else {
-    sum_slots(P->spart_a, P->n_groups, a, 0x7Fu, sh4);
+    sum_slots(P->spart_a, P->sell.n_groups, a, 0x7Fu, sh4);
     if (threadIdx.x == 0) finalize_residuals(P, a);
   }
 }
 
 // ---------------------------------------------------------------- launchers ----
 
-template <int VT>
-static void launch_forward_vt(int mode, const DevPlan* plans, const FwdGroup* groups,
-                              int n_groups, int grid, int lds_floats, uint32_t* ctr,
+template <int VT, int SUB>
+static void launch_forward_vs(int mode, const DevPlan* plans, const FwdGroup* groups,
+                              int n_groups, int grid, int lds_floats, uint32_t* ctr, int vsel,
                               hipStream_t s) {
   const size_t lds = (size_t)lds_floats * sizeof(float);
   switch (mode) {
     case kFwdDoseLet:
-      k_forward<VT, kFwdDoseLet><<<grid, kFwdBlock, lds, s>>>(plans, groups, n_groups,
-                                                               lds_floats, ctr);
+      k_forward<VT, kFwdDoseLet, SUB><<<grid, kFwdBlock, lds, s>>>(plans, groups, n_groups,
+                                                                    lds_floats, ctr, vsel);
       break;
     case kFwdObj:
-      k_forward<VT, kFwdObj><<<grid, kFwdBlock, lds, s>>>(plans, groups, n_groups, lds_floats,
-                                                           ctr);
+      k_forward<VT, kFwdObj, SUB><<<grid, kFwdBlock, lds, s>>>(plans, groups, n_groups,
+                                                                lds_floats, ctr, vsel);
       break;
     case kFwdDir:
-      k_forward<VT, kFwdDir><<<grid, kFwdBlock, lds, s>>>(plans, groups, n_groups, lds_floats,
-                                                           ctr);
+      k_forward<VT, kFwdDir, SUB><<<grid, kFwdBlock, lds, s>>>(plans, groups, n_groups,
+                                                                lds_floats, ctr, vsel);
       break;
     default:
-      k_forward<VT, kFwdResid><<<grid, kFwdBlock, lds, s>>>(plans, groups, n_groups,
-                                                             lds_floats, ctr);
+      k_forward<VT, kFwdResid, SUB><<<grid, kFwdBlock, lds, s>>>(plans, groups, n_groups,
+                                                                  lds_floats, ctr, vsel);
       break;
   }
 }
 
-void launch_forward(int vtype, int mode, const DevPlan* plans, const FwdGroup* groups,
-                    int n_groups, int grid, int lds_floats, uint32_t* ctr, hipStream_t s) {
-  if (vtype == kF16)
-    launch_forward_vt<kF16>(mode, plans, groups, n_groups, grid, lds_floats, ctr, s);
-  else if (vtype == kBF16)
-    launch_forward_vt<kBF16>(mode, plans, groups, n_groups, grid, lds_floats, ctr, s);
-  else
-    launch_forward_vt<kF32>(mode, plans, groups, n_groups, grid, lds_floats, ctr, s);
+void launch_forward(int vtype, int mode, int sub, const DevPlan* plans, const FwdGroup* groups,
+                    int n_groups, int grid, int lds_floats, uint32_t* ctr, int vsel,
+                    hipStream_t s) {
+  if (vtype == kF16) {
+    if (sub) launch_forward_vs<kF16, 1>(mode, plans, groups, n_groups, grid, lds_floats, ctr, vsel, s);
+    else launch_forward_vs<kF16, 0>(mode, plans, groups, n_groups, grid, lds_floats, ctr, vsel, s);
+  } else if (vtype == kBF16) {
+    if (sub) launch_forward_vs<kBF16, 1>(mode, plans, groups, n_groups, grid, lds_floats, ctr, vsel, s);
+    else launch_forward_vs<kBF16, 0>(mode, plans, groups, n_groups, grid, lds_floats, ctr, vsel, s);
+  } else {
+    if (sub) launch_forward_vs<kF32, 1>(mode, plans, groups, n_groups, grid, lds_floats, ctr, vsel, s);
+    else launch_forward_vs<kF32, 0>(mode, plans, groups, n_groups, grid, lds_floats, ctr, vsel, s);
+  }
 }
 
 void launch_rows(int mode, const DevPlan* plans, const RowItem* items, int n_items,
@@ -655,43 +698,51 @@ void launch_tcol(int mode, const DevPlan* plans, const ColBlock* blocks, int n_b
     case kColGrad: k_tcol<kColGrad><<<n_blocks, kBlock, 0, s>>>(plans, blocks); break;
     case kColGradMove: k_tcol<kColGradMove><<<n_blocks, kBlock, 0, s>>>(plans, blocks); break;
     case kColProj: k_tcol<kColProj><<<n_blocks, kBlock, 0, s>>>(plans, blocks); break;
-    default: k_tcol<kColProjMove><<<n_blocks, kBlock, 0, s>>>(plans, blocks); break;
+    case kColProjMove: k_tcol<kColProjMove><<<n_blocks, kBlock, 0, s>>>(plans, blocks); break;
+    case kColProjY: k_tcol<kColProjY><<<n_blocks, kBlock, 0, s>>>(plans, blocks); break;
+    case kColYMove: k_tcol<kColYMove><<<n_blocks, kBlock, 0, s>>>(plans, blocks); break;
+    default: k_tcol<kColYCopy><<<n_blocks, kBlock, 0, s>>>(plans, blocks); break;
   }
 }
 
-void launch_finalize(int mode, const DevPlan* plans, int n_plans, hipStream_t s) {
+void launch_finalize(int mode, int sub, const DevPlan* plans, int n_plans, hipStream_t s) {
   switch (mode) {
-    case kFinDir0: k_finalize<kFinDir0><<<n_plans, kBlock, 0, s>>>(plans); break;
-    case kFinDir: k_finalize<kFinDir><<<n_plans, kBlock, 0, s>>>(plans); break;
-    case kFinMoveObj: k_finalize<kFinMoveObj><<<n_plans, kBlock, 0, s>>>(plans); break;
-    case kFinResidRows: k_finalize<kFinResidRows><<<n_plans, kBlock, 0, s>>>(plans); break;
-    default: k_finalize<kFinResidFwd><<<n_plans, kBlock, 0, s>>>(plans); break;
+    case kFinDir0:
+      if (sub) k_finalize<kFinDir0, 1><<<n_plans, kBlock, 0, s>>>(plans);
+      else k_finalize<kFinDir0, 0><<<n_plans, kBlock, 0, s>>>(plans);
+      break;
+    case kFinDir:
+      if (sub) k_finalize<kFinDir, 1><<<n_plans, kBlock, 0, s>>>(plans);
+      else k_finalize<kFinDir, 0><<<n_plans, kBlock, 0, s>>>(plans);
+      break;
+    case kFinMoveObj: k_finalize<kFinMoveObj, 0><<<n_plans, kBlock, 0, s>>>(plans); break;
+    case kFinResidRows: k_finalize<kFinResidRows, 0><<<n_plans, kBlock, 0, s>>>(plans); break;
+    default: k_finalize<kFinResidFwd, 0><<<n_plans, kBlock, 0, s>>>(plans); break;
   }
 }
 
-hipError_t set_forward_lds_limit(int vtype, size_t bytes) {
+template <int VT>
+static hipError_t set_lds_vt(size_t bytes) {
   hipError_t e = hipSuccess;
   auto set = [&](const void* f) {
     hipError_t r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (r != hipSuccess) e = r;
   };
-  if (vtype == kF16) {
-    set((const void*)k_forward<kF16, kFwdDoseLet>);
-    set((const void*)k_forward<kF16, kFwdObj>);
-    set((const void*)k_forward<kF16, kFwdDir>);
-    set((const void*)k_forward<kF16, kFwdResid>);
-  } else if (vtype == kBF16) {
-    set((const void*)k_forward<kBF16, kFwdDoseLet>);
-    set((const void*)k_forward<kBF16, kFwdObj>);
-    set((const void*)k_forward<kBF16, kFwdDir>);
-    set((const void*)k_forward<kBF16, kFwdResid>);
-  } else {
-    set((const void*)k_forward<kF32, kFwdDoseLet>);
-    set((const void*)k_forward<kF32, kFwdObj>);
-    set((const void*)k_forward<kF32, kFwdDir>);
-    set((const void*)k_forward<kF32, kFwdResid>);
-  }
+  set((const void*)k_forward<VT, kFwdDoseLet, 0>);
+  set((const void*)k_forward<VT, kFwdObj, 0>);
+  set((const void*)k_forward<VT, kFwdDir, 0>);
+  set((const void*)k_forward<VT, kFwdResid, 0>);
+  set((const void*)k_forward<VT, kFwdDoseLet, 1>);
+  set((const void*)k_forward<VT, kFwdObj, 1>);
+  set((const void*)k_forward<VT, kFwdDir, 1>);
+  set((const void*)k_forward<VT, kFwdResid, 1>);
   return e;
+}
+
+hipError_t set_forward_lds_limit(int vtype, size_t bytes) {
+  if (vtype == kF16) return set_lds_vt<kF16>(bytes);
+  if (vtype == kBF16) return set_lds_vt<kBF16>(bytes);
+  return set_lds_vt<kF32>(bytes);
 }
 
 }  // namespace fo

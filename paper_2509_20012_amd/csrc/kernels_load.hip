@@ -309,6 +309,43 @@ __global__ __launch_bounds__(kBlock) void k_obj_fill(int vtype, int64_t C,
   }
 }
 
+// Objective-row view: every listed row is copied by one wavefront from its slice
+// position in the all-row view to its position in the objective-row view (values
+// as stored).  Unreached slots keep the zero fill.
+__global__ __launch_bounds__(kBlock) void k_pack_sub(int vtype, int lpr_log2, int64_t n,
+                                                     const int32_t* __restrict__ src_pos,
+                                                     const int32_t* __restrict__ dst_pos,
+                                                     const int32_t* __restrict__ len,
+                                                     const int64_t* __restrict__ src_base,
+                                                     const int32_t* __restrict__ src_ci,
+                                                     const void* __restrict__ src_dv,
+                                                     const void* __restrict__ src_lv,
+                                                     const int64_t* __restrict__ dst_base,
+                                                     int32_t* dst_ci, void* dst_dv,
+                                                     void* dst_lv) {
+  const int64_t i = (int64_t)blockIdx.x * kRowsPerWg + threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  if (i >= n) return;
+  const int rpw_log2 = 6 - lpr_log2;
+  const int lpr = 1 << lpr_log2;
+  const int sp = src_pos[i], dp = dst_pos[i];
+  const int64_t sb = src_base[sp >> rpw_log2], db = dst_base[dp >> rpw_log2];
+  const int64_t spp = sp & ((1 << rpw_log2) - 1), dpp = dp & ((1 << rpw_log2) - 1);
+  for (int64_t e = lane; e < len[i]; e += kWave) {
+    const int64_t quad = e >> 2, t = quad >> lpr_log2, j = quad & (lpr - 1);
+    const int64_t os = sb + t * 256 + (spp * lpr + j) * 4 + (e & 3);
+    const int64_t od = db + t * 256 + (dpp * lpr + j) * 4 + (e & 3);
+    dst_ci[od] = src_ci[os];
+    if (vtype == kF32) {
+      static_cast<float*>(dst_dv)[od] = static_cast<const float*>(src_dv)[os];
+      static_cast<float*>(dst_lv)[od] = static_cast<const float*>(src_lv)[os];
+    } else {
+      static_cast<uint16_t*>(dst_dv)[od] = static_cast<const uint16_t*>(src_dv)[os];
+      static_cast<uint16_t*>(dst_lv)[od] = static_cast<const uint16_t*>(src_lv)[os];
+    }
+  }
+}
+
 inline unsigned row_grid(int64_t R) { return (unsigned)((R + kRowsPerWg - 1) / kRowsPerWg); }
 
 }  // namespace
@@ -377,6 +414,17 @@ void launch_obj_fill(int vtype, int64_t C, const int64_t* cp, const uint32_t* le
   if (C > 0)
     k_obj_fill<<<row_grid(C), kBlock, 0, s>>>(vtype, C, cp, len, ri, cdv, clv, kind, ocp, ori,
                                                ocdv, oclv);
+}
+
+void launch_pack_sub(int vtype, int lpr_log2, int64_t n, const int32_t* src_pos,
+                     const int32_t* dst_pos, const int32_t* len, const int64_t* src_base,
+                     const int32_t* src_ci, const void* src_dv, const void* src_lv,
+                     const int64_t* dst_base, int32_t* dst_ci, void* dst_dv, void* dst_lv,
+                     hipStream_t s) {
+  if (n > 0)
+    k_pack_sub<<<row_grid(n), kBlock, 0, s>>>(vtype, lpr_log2, n, src_pos, dst_pos, len, src_base,
+                                               src_ci, src_dv, src_lv, dst_base, dst_ci, dst_dv,
+                                               dst_lv);
 }
 
 void launch_check_problem(int64_t R, const uint16_t* kind, const float* dlo, const float* dhi,

@@ -81,9 +81,12 @@ struct Sell {
   std::vector<int32_t> rslice; // R
 };
 
-// Rows sorted by length (descending, stable) inside windows of kSortWindow rows,
-// cut into slices of rpw rows; each slice is as wide as its longest row.
-void build_sell(const int64_t* rp, int64_t R, int lpr_log2, bool full, Sell* S) {
+// Listed rows (row_id(i), length len(i), i = 0..n-1) sorted by length (descending,
+// stable) inside windows of kSortWindow consecutive list positions, cut into slices
+// of rpw rows; each slice is as wide as its longest row.  With full set, the slice
+// tables are kept and pos[i] receives list entry i's slice position.
+template <typename RowId, typename Len>
+void build_sell_list(int64_t n, RowId row_id, Len len, int lpr_log2, bool full, Sell* S) {
   const int rpw = kWave >> lpr_log2;
   const int64_t lpr4 = 4LL << lpr_log2;
   S->lpr_log2 = lpr_log2;
@@ -93,25 +96,21 @@ void build_sell(const int64_t* rp, int64_t R, int lpr_log2, bool full, Sell* S) 
     S->base.assign(1, 0);
     S->width.clear();
     S->srow.clear();
-    S->rslice.assign(R, -1);
+    S->rslice.assign(n, -1);
   }
   std::vector<int64_t> idx;
-  for (int64_t w0 = 0; w0 < R; w0 += kSortWindow) {
-    const int64_t w1 = std::min(R, w0 + kSortWindow);
+  for (int64_t w0 = 0; w0 < n; w0 += kSortWindow) {
+    const int64_t w1 = std::min(n, w0 + kSortWindow);
     idx.resize(w1 - w0);
     std::iota(idx.begin(), idx.end(), w0);
-    std::stable_sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) {
-      return rp[a + 1] - rp[a] > rp[b + 1] - rp[b];
-    });
+    std::stable_sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) { return len(a) > len(b); });
     for (size_t s0 = 0; s0 < idx.size(); s0 += rpw) {
-      const int64_t len = rp[idx[s0] + 1] - rp[idx[s0]];  // longest row of the slice
-      const int64_t steps = (len + lpr4 - 1) / lpr4;
+      const int64_t steps = (len(idx[s0]) + lpr4 - 1) / lpr4;  // longest row of the slice
       if (full) {
         for (int p = 0; p < rpw; ++p) {
           const size_t k = s0 + p;
-          const int32_t row = k < idx.size() ? (int32_t)idx[k] : -1;
-          S->srow.push_back(row);
-          if (row >= 0) S->rslice[row] = (int32_t)(S->n_slices * rpw + p);
+          S->srow.push_back(k < idx.size() ? (int32_t)row_id(idx[k]) : -1);
+          if (k < idx.size()) S->rslice[idx[k]] = (int32_t)(S->n_slices * rpw + p);
         }
         S->width.push_back((int32_t)steps);
         S->base.push_back(S->base.back() + steps * 256);
@@ -122,13 +121,20 @@ void build_sell(const int64_t* rp, int64_t R, int lpr_log2, bool full, Sell* S) 
   }
 }
 
+void build_sell(const int64_t* rp, int64_t R, int lpr_log2, bool full, Sell* S) {
+  build_sell_list(R, [](int64_t i) { return i; },
+                  [rp](int64_t i) { return rp[i + 1] - rp[i]; }, lpr_log2, full, S);
+}
+
 struct Layout {
   size_t table, state, ctr, sbase, swidth, srow, sci, sdv, slv, cp, ri, cdv, clv;
   size_t col_tslot0, col_nch, cscale, mom, d, l, dg, lg, coef, g;
   size_t gri, gcdv, gclv, gcol_tslot0, gcol_nch, ocp, ocount, gtr_items;
+  size_t y, osbase, oswidth, osrow, osci, osdv, oslv, ogroups, pk_src, pk_dst, pk_len;
   size_t spart_a, spart_b, rpart, gpart, tpart, groups, row_items, tr_items, col_blocks;
   size_t bc, colcount, colmax, flags, rslice, total;
   int64_t sell_slots, n_slices, csc_slots, obj_slots, max_rows, max_tr, n_groups, n_col_blocks;
+  int64_t obj_sell_slots, max_obj_slices, max_obj_groups;
   int64_t rows_per_block, nb;
 };
 
@@ -150,6 +156,9 @@ bool make_layout(int64_t R, int64_t C, int64_t nnz, int storage, int lpr_log2,
   L->n_slices = n_slices;
   L->csc_slots = csc;
   L->obj_slots = ((csc * reserve_pct) / 100 + 3) & ~int64_t(3);
+  L->obj_sell_slots = reserve_pct > 0 ? (((sell_slots * reserve_pct) / 100 + 255) & ~int64_t(255)) : 0;
+  L->max_obj_slices = reserve_pct > 0 ? R / rpw + R / kSortWindow + 2 : 0;
+  L->max_obj_groups = (L->max_obj_slices + kFwdWaves - 1) / kFwdWaves + 1;
   L->max_rows = R / kRowItemRows + 2;
   L->max_tr = C + csc / kTrChunkMin + 2;
   L->n_groups = (n_slices + kFwdWaves - 1) / kFwdWaves + 1;
@@ -188,6 +197,17 @@ bool make_layout(int64_t R, int64_t C, int64_t nnz, int storage, int lpr_log2,
   L->ocp = take(sizeof(int64_t) * (C + 1));
   L->ocount = take(sizeof(uint32_t) * C);
   L->gtr_items = take(sizeof(TrItem) * L->max_tr);
+  L->y = take(sizeof(float) * C);
+  L->osbase = take(sizeof(int64_t) * (L->max_obj_slices + 1));
+  L->oswidth = take(sizeof(int32_t) * (L->max_obj_slices + 1));
+  L->osrow = take(sizeof(int32_t) * (L->max_obj_slices * rpw + 1));
+  L->osci = take(sizeof(int32_t) * L->obj_sell_slots);
+  L->osdv = take((size_t)vb * L->obj_sell_slots);
+  L->oslv = take((size_t)vb * L->obj_sell_slots);
+  L->ogroups = take(sizeof(FwdGroup) * L->max_obj_groups);
+  L->pk_src = take(sizeof(int32_t) * (reserve_pct > 0 ? Rm : 1));
+  L->pk_dst = take(sizeof(int32_t) * (reserve_pct > 0 ? Rm : 1));
+  L->pk_len = take(sizeof(int32_t) * (reserve_pct > 0 ? Rm : 1));
   L->cscale = take(sizeof(float) * C);
   L->mom = take(sizeof(double) * 3 * Rm);
   L->d = take(sizeof(float) * Rm);
@@ -196,8 +216,8 @@ bool make_layout(int64_t R, int64_t C, int64_t nnz, int storage, int lpr_log2,
   L->lg = take(sizeof(float) * Rm);
   L->coef = take(sizeof(float2) * Rm);
   L->g = take(sizeof(float) * C);
-  L->spart_a = take(sizeof(double) * kNPart * L->n_groups);
-  L->spart_b = take(sizeof(double) * kNPart * L->n_groups);
+  L->spart_a = take(sizeof(double) * kNPart * std::max(L->n_groups, L->max_obj_groups));
+  L->spart_b = take(sizeof(double) * kNPart * std::max(L->n_groups, L->max_obj_groups));
   L->rpart = take(sizeof(double) * kNPart * L->max_rows);
   L->gpart = take(sizeof(double) * L->n_col_blocks);
   L->tpart = take(sizeof(float) * L->max_tr);
@@ -255,17 +275,22 @@ struct fredopt_plan {
   std::vector<RowItem> rows;
   std::vector<TrItem> tr, gtr;
   std::vector<int32_t> col_ts0, col_nch, gcol_ts0, gcol_nch;
-  std::vector<uint32_t> col_len;      // real (unpadded) column lengths
+  std::vector<int32_t> row_len;       // real row lengths
+  Sell osell;                         // objective-row view (host tables)
+  std::vector<FwdGroup> ogroups;
+  bool sched_obj = false;             // iterations use the objective-row view
   bool grad_valid = false;            // gradient CSC matches (grad_kind, grad_fp)
   bool grad_sub = false;              // gradient uses the objective-row CSC
   const uint16_t* grad_kind = nullptr;
   uint64_t grad_fp = 0, last_fp = 0;
+  int64_t grad_entries = 0;
   std::vector<ColBlock> cblocks;
   DevPlan hp{};
   DevPlan* d_table = nullptr;
   DevState* d_state = nullptr;
   uint32_t* d_ctr = nullptr;
   FwdGroup* d_groups = nullptr;
+  FwdGroup* d_ogroups = nullptr;
   RowItem* d_rows = nullptr;
   TrItem* d_tr = nullptr;
   TrItem* d_gtr = nullptr;
@@ -282,12 +307,12 @@ T* at(fredopt_plan* p, size_t off) {
   return reinterpret_cast<T*>(p->ws + off);
 }
 
-void build_groups(fredopt_plan* p) {
-  p->groups.clear();
-  for (int64_t s0 = 0; s0 < p->sell.n_slices; s0 += kFwdWaves)
-    p->groups.push_back(FwdGroup{0, (int32_t)s0,
-                                 (int32_t)std::min<int64_t>(kFwdWaves, p->sell.n_slices - s0),
-                                 (int32_t)p->groups.size()});
+void build_groups(int64_t n_slices, std::vector<FwdGroup>* groups) {
+  groups->clear();
+  for (int64_t s0 = 0; s0 < n_slices; s0 += kFwdWaves)
+    groups->push_back(FwdGroup{0, (int32_t)s0,
+                               (int32_t)std::min<int64_t>(kFwdWaves, n_slices - s0),
+                               (int32_t)groups->size()});
 }
 
 void build_row_items(fredopt_plan* p) {
@@ -436,7 +461,6 @@ fredopt_status run_problem_check(fredopt_plan* p, const fredopt_problem* pr, hip
 // Rebuilt only when the kind array (address or fingerprint) changes; falls back to
 // the full CSC when it does not fit the reserved space.
 fredopt_status prepare_gradient(fredopt_plan* p, const fredopt_problem* pr, hipStream_t s) {
-  if (p->grad_valid && p->grad_kind == pr->kind && p->grad_fp == p->last_fp) return FREDOPT_OK;
   DevPlan& h = p->hp;
   const Layout& L = p->L;
   uint32_t* ocount = at<uint32_t>(p, L.ocount);
@@ -447,7 +471,11 @@ fredopt_status prepare_gradient(fredopt_plan* p, const fredopt_problem* pr, hipS
   HIPCHK(hipMemcpyAsync(cnt.data(), ocount, sizeof(uint32_t) * p->C, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   std::vector<int64_t> ocp(p->C + 1, 0);
-  for (int64_t j = 0; j < p->C; ++j) ocp[j + 1] = ocp[j] + (((int64_t)cnt[j] + 3) & ~int64_t(3));
+  int64_t real = 0;
+  for (int64_t j = 0; j < p->C; ++j) {
+    ocp[j + 1] = ocp[j] + (((int64_t)cnt[j] + 3) & ~int64_t(3));
+    real += cnt[j];
+  }
   if (ocp[p->C] <= L.obj_slots) {
     const int vb = value_bytes(p->storage);
     HIPCHK(hipMemcpyAsync(at<int64_t>(p, L.ocp), ocp.data(), sizeof(int64_t) * (p->C + 1),
@@ -464,6 +492,7 @@ fredopt_status prepare_gradient(fredopt_plan* p, const fredopt_problem* pr, hipS
     h.gcdv = p->ws + L.gcdv;
     h.gclv = p->ws + L.gclv;
     p->grad_sub = true;
+    p->grad_entries = real;
   } else {
     p->gtr = p->tr;
     p->gcol_ts0 = p->col_ts0;
@@ -472,6 +501,7 @@ fredopt_status prepare_gradient(fredopt_plan* p, const fredopt_problem* pr, hipS
     h.gcdv = h.cdv;
     h.gclv = h.clv;
     p->grad_sub = false;
+    p->grad_entries = p->nnz;
   }
   if ((int64_t)p->gtr.size() > L.max_tr) return fail(FREDOPT_E_WORKSPACE, "gradient chunks");
   if (!p->gtr.empty())
@@ -489,6 +519,86 @@ fredopt_status prepare_gradient(fredopt_plan* p, const fredopt_problem* pr, hipS
   p->grad_fp = p->last_fp;
   drop_graph(p);
   return FREDOPT_OK;
+}
+
+// Objective-row sliced-ELL view for this problem: the rows with objective terms,
+// copied from the all-row view.  With it an outer iteration needs the all-row
+// forward product only once (at the perturbed point); without room for it the
+// iteration keeps the two all-row forward products.
+fredopt_status prepare_objective_view(fredopt_plan* p, const fredopt_problem* pr, hipStream_t s) {
+  DevPlan& h = p->hp;
+  const Layout& L = p->L;
+  p->sched_obj = false;
+  h.osell = h.sell;
+  drop_graph(p);
+  if (L.obj_sell_slots == 0) return FREDOPT_OK;
+  std::vector<uint16_t> kind(p->R);
+  if (p->R > 0) {
+    HIPCHK(hipMemcpyAsync(kind.data(), pr->kind, sizeof(uint16_t) * p->R, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  std::vector<int32_t> rows;
+  for (int64_t i = 0; i < p->R; ++i)
+    if (kind[i] & (FREDOPT_OBJ_DOSE | FREDOPT_OBJ_CDL)) rows.push_back((int32_t)i);
+  const int64_t n = (int64_t)rows.size();
+  Sell& O = p->osell;
+  build_sell_list(n, [&](int64_t i) { return (int64_t)rows[i]; },
+                  [&](int64_t i) { return (int64_t)p->row_len[rows[i]]; }, p->sell.lpr_log2, true,
+                  &O);
+  if (O.slots > L.obj_sell_slots || O.n_slices > L.max_obj_slices) return FREDOPT_OK;
+  build_groups(O.n_slices, &p->ogroups);
+  if ((int64_t)p->ogroups.size() > L.max_obj_groups) return FREDOPT_OK;
+  std::vector<int32_t> src(n), len(n);
+  for (int64_t i = 0; i < n; ++i) {
+    src[i] = p->sell.rslice[rows[i]];
+    len[i] = p->row_len[rows[i]];
+  }
+  const int vb = value_bytes(p->storage);
+  HIPCHK(hipMemcpyAsync(p->ws + L.osbase, O.base.data(), sizeof(int64_t) * (O.n_slices + 1),
+                        hipMemcpyHostToDevice, s));
+  if (O.n_slices > 0) {
+    HIPCHK(hipMemcpyAsync(p->ws + L.oswidth, O.width.data(), sizeof(int32_t) * O.n_slices,
+                          hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(p->ws + L.osrow, O.srow.data(), sizeof(int32_t) * O.srow.size(),
+                          hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(p->d_ogroups, p->ogroups.data(), sizeof(FwdGroup) * p->ogroups.size(),
+                          hipMemcpyHostToDevice, s));
+  }
+  if (n > 0) {
+    HIPCHK(hipMemcpyAsync(p->ws + L.pk_src, src.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(p->ws + L.pk_dst, O.rslice.data(), sizeof(int32_t) * n,
+                          hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(p->ws + L.pk_len, len.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
+  }
+  HIPCHK(hipMemsetAsync(p->ws + L.osci, 0, sizeof(int32_t) * O.slots, s));
+  HIPCHK(hipMemsetAsync(p->ws + L.osdv, 0, (size_t)vb * O.slots, s));
+  HIPCHK(hipMemsetAsync(p->ws + L.oslv, 0, (size_t)vb * O.slots, s));
+  launch_pack_sub(p->storage, p->sell.lpr_log2, n, at<int32_t>(p, L.pk_src),
+                  at<int32_t>(p, L.pk_dst), at<int32_t>(p, L.pk_len), h.sell.sbase, h.sell.sci,
+                  h.sell.sdv, h.sell.slv, at<int64_t>(p, L.osbase), at<int32_t>(p, L.osci),
+                  p->ws + L.osdv, p->ws + L.oslv, s);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  h.osell.sbase = at<int64_t>(p, L.osbase);
+  h.osell.swidth = at<int32_t>(p, L.oswidth);
+  h.osell.srow = at<int32_t>(p, L.osrow);
+  h.osell.sci = at<int32_t>(p, L.osci);
+  h.osell.sdv = p->ws + L.osdv;
+  h.osell.slv = p->ws + L.oslv;
+  h.osell.n_slices = (int32_t)O.n_slices;
+  h.osell.n_groups = (int32_t)p->ogroups.size();
+  p->sched_obj = true;
+  drop_graph(p);
+  return FREDOPT_OK;
+}
+
+// Per-problem preprocessing (gradient CSC and objective-row view), reused while the
+// kind array keeps its address and fingerprint.
+fredopt_status prepare_problem(fredopt_plan* p, const fredopt_problem* pr, hipStream_t s) {
+  if (p->grad_valid && p->grad_kind == pr->kind && p->grad_fp == p->last_fp) return FREDOPT_OK;
+  fredopt_status st = prepare_gradient(p, pr, s);
+  if (st != FREDOPT_OK) return st;
+  return prepare_objective_view(p, pr, s);
 }
 
 fredopt_status upload_state(fredopt_plan* p, const fredopt_state* st, hipStream_t s) {
@@ -520,28 +630,51 @@ void export_state(const DevState& d, fredopt_state* st) {
 enum Kind { kKindFwd, kKindRows, kKindChunks, kKindCol, kKindFin };
 
 struct Launch {
-  int id;    // FREDOPT_KERNEL_*
-  int kind;  // Kind
+  int id;        // FREDOPT_KERNEL_*
+  int kind;      // Kind
   int mode;
+  int sub = 0;   // forward / finalize: objective-row view
+  int vsel = kVecX;
 };
 
 // One outer iteration of Fig. 3 (reductions_n = r perturbations, then the sweep).
-std::vector<Launch> iteration_sequence(int r) {
+// With the objective-row view (obj): Eq. (2), its gradient and the direction
+// products touch only rows with objective terms; the all-row forward product is
+// taken once, at the perturbed point y, and feeds the constraint residuals.
+// Without it: the all-row forward products at x and along g, d and l moved by the
+// accepted step.  The caller sets y = x before the first iteration; the
+// projection writes x and y.
+std::vector<Launch> iteration_sequence(int r, bool obj) {
   std::vector<Launch> seq;
   if (r == 0) {
-    seq.push_back({FREDOPT_KERNEL_FWD_RESID, kKindFwd, kFwdResid});
+    seq.push_back({FREDOPT_KERNEL_FWD_RESID, kKindFwd, kFwdResid, 0, kVecX});
     seq.push_back({FREDOPT_KERNEL_FINALIZE, kKindFin, kFinResidFwd});
     seq.push_back({FREDOPT_KERNEL_TR_PROJ, kKindChunks, 1});
     seq.push_back({FREDOPT_KERNEL_COL, kKindCol, kColProj});
     return seq;
   }
-  seq.push_back({FREDOPT_KERNEL_FWD_OBJ, kKindFwd, kFwdObj});
+  if (obj) {
+    for (int t = 0; t < r; ++t) {
+      seq.push_back({FREDOPT_KERNEL_FWD_OBJ, kKindFwd, kFwdObj, 1, kVecY});
+      seq.push_back({FREDOPT_KERNEL_TR_GRAD, kKindChunks, 0});
+      seq.push_back({FREDOPT_KERNEL_COL, kKindCol, kColGrad});
+      seq.push_back({FREDOPT_KERNEL_FWD_DIR, kKindFwd, kFwdDir, 1, kVecG});
+      seq.push_back({FREDOPT_KERNEL_FINALIZE, kKindFin, t == 0 ? kFinDir0 : kFinDir, 1});
+      seq.push_back({FREDOPT_KERNEL_COL, kKindCol, kColYMove});
+    }
+    seq.push_back({FREDOPT_KERNEL_FWD_RESID, kKindFwd, kFwdResid, 0, kVecY});
+    seq.push_back({FREDOPT_KERNEL_FINALIZE, kKindFin, kFinResidFwd});
+    seq.push_back({FREDOPT_KERNEL_TR_PROJ, kKindChunks, 1});
+    seq.push_back({FREDOPT_KERNEL_COL, kKindCol, kColProjY});
+    return seq;
+  }
+  seq.push_back({FREDOPT_KERNEL_FWD_OBJ, kKindFwd, kFwdObj, 0, kVecX});
   for (int t = 0; t < r; ++t) {
     const bool last = t + 1 == r;
     seq.push_back({FREDOPT_KERNEL_TR_GRAD, kKindChunks, 0});
     seq.push_back({FREDOPT_KERNEL_COL, kKindCol, t == 0 ? kColGrad : kColGradMove});
-    seq.push_back({FREDOPT_KERNEL_FWD_DIR, kKindFwd, kFwdDir});
-    seq.push_back({FREDOPT_KERNEL_FINALIZE, kKindFin, t == 0 ? kFinDir0 : kFinDir});
+    seq.push_back({FREDOPT_KERNEL_FWD_DIR, kKindFwd, kFwdDir, 0, kVecG});
+    seq.push_back({FREDOPT_KERNEL_FINALIZE, kKindFin, t == 0 ? kFinDir0 : kFinDir, 0});
     seq.push_back({FREDOPT_KERNEL_ROWS, kKindRows, last ? kRowsMoveResid : kRowsMoveObj});
     seq.push_back({FREDOPT_KERNEL_FINALIZE, kKindFin, last ? kFinResidRows : kFinMoveObj});
   }
@@ -553,10 +686,10 @@ std::vector<Launch> iteration_sequence(int r) {
 void enqueue(fredopt_plan* p, const Launch& l, hipStream_t s) {
   switch (l.kind) {
     case kKindFwd: {
-      const int grid = (int)std::min<int64_t>((int64_t)p->groups.size(),
-                                              (int64_t)p->n_cu * p->wgs_per_cu);
-      launch_forward(p->storage, l.mode, p->d_table, p->d_groups, (int)p->groups.size(),
-                     std::max(grid, 1), p->lds_floats, p->d_ctr, s);
+      const std::vector<FwdGroup>& G = l.sub ? p->ogroups : p->groups;
+      const int grid = (int)std::min<int64_t>((int64_t)G.size(), (int64_t)p->n_cu * p->wgs_per_cu);
+      launch_forward(p->storage, l.mode, l.sub, p->d_table, l.sub ? p->d_ogroups : p->d_groups,
+                     (int)G.size(), std::max(grid, 1), p->lds_floats, p->d_ctr, l.vsel, s);
       break;
     }
     case kKindRows:
@@ -574,13 +707,13 @@ void enqueue(fredopt_plan* p, const Launch& l, hipStream_t s) {
       launch_tcol(l.mode, p->d_table, p->d_cblocks, (int)p->cblocks.size(), s);
       break;
     default:
-      launch_finalize(l.mode, p->d_table, 1, s);
+      launch_finalize(l.mode, l.sub, p->d_table, 1, s);
       break;
   }
 }
 
 fredopt_status enqueue_iteration(fredopt_plan* p, int r, hipStream_t s) {
-  for (const Launch& l : iteration_sequence(r)) enqueue(p, l, s);
+  for (const Launch& l : iteration_sequence(r, p->sched_obj)) enqueue(p, l, s);
   HIPCHK(hipGetLastError());
   return FREDOPT_OK;
 }
@@ -590,7 +723,7 @@ fredopt_status ensure_graph(fredopt_plan* p, int r) {
   drop_graph(p);
   hipGraph_t g = nullptr;
   HIPCHK(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
-  for (const Launch& l : iteration_sequence(r)) enqueue(p, l, p->cap);
+  for (const Launch& l : iteration_sequence(r, p->sched_obj)) enqueue(p, l, p->cap);
   const hipError_t le = hipGetLastError();
   const hipError_t ce = hipStreamEndCapture(p->cap, &g);
   if (le != hipSuccess || ce != hipSuccess) {
@@ -716,6 +849,8 @@ fredopt_status fredopt_load_matrices(const fredopt_matrices* m, void* workspace,
   p->ws = static_cast<char*>(workspace);
   p->ws_bytes = workspace_bytes;
   build_sell(h_rp.data(), R, lg, true, &p->sell);
+  p->row_len.resize(R);
+  for (int64_t i = 0; i < R; ++i) p->row_len[i] = (int32_t)(h_rp[i + 1] - h_rp[i]);
   if (!make_layout(R, C, nnz, m->storage, lg, p->sell.slots, p->sell.n_slices, pct, &p->L)) {
     delete p;
     return fail(FREDOPT_E_SHAPE, "layout failed");
@@ -854,11 +989,12 @@ fredopt_status fredopt_load_matrices(const fredopt_matrices* m, void* workspace,
   p->d_state = reinterpret_cast<DevState*>(ws + L.state);
   p->d_ctr = reinterpret_cast<uint32_t*>(ws + L.ctr);
   p->d_groups = reinterpret_cast<FwdGroup*>(ws + L.groups);
+  p->d_ogroups = reinterpret_cast<FwdGroup*>(ws + L.ogroups);
   p->d_rows = reinterpret_cast<RowItem*>(ws + L.row_items);
   p->d_tr = reinterpret_cast<TrItem*>(ws + L.tr_items);
   p->d_gtr = reinterpret_cast<TrItem*>(ws + L.gtr_items);
   p->d_cblocks = reinterpret_cast<ColBlock*>(ws + L.col_blocks);
-  build_groups(p);
+  build_groups(S.n_slices, &p->groups);
   build_row_items(p);
   build_tr_items(p);
   DevPlan& h = p->hp;
@@ -867,16 +1003,18 @@ fredopt_status fredopt_load_matrices(const fredopt_matrices* m, void* workspace,
   h.C = C;
   h.vtype = m->storage;
   h.lpr_log2 = S.lpr_log2;
-  h.n_slices = (int32_t)S.n_slices;
   h.n_row_items = (int32_t)p->rows.size();
   h.n_col_blocks = (int32_t)p->cblocks.size();
-  h.n_groups = (int32_t)p->groups.size();
-  h.sbase = d_sbase;
-  h.swidth = reinterpret_cast<const int32_t*>(ws + L.swidth);
-  h.srow = reinterpret_cast<const int32_t*>(ws + L.srow);
-  h.sci = sci;
-  h.sdv = ws + L.sdv;
-  h.slv = ws + L.slv;
+  h.sell.n_slices = (int32_t)S.n_slices;
+  h.sell.n_groups = (int32_t)p->groups.size();
+  h.sell.sbase = d_sbase;
+  h.sell.swidth = reinterpret_cast<const int32_t*>(ws + L.swidth);
+  h.sell.srow = reinterpret_cast<const int32_t*>(ws + L.srow);
+  h.sell.sci = sci;
+  h.sell.sdv = ws + L.sdv;
+  h.sell.slv = ws + L.slv;
+  h.osell = h.sell;
+  h.y = reinterpret_cast<float*>(ws + L.y);
   h.ri = ri;
   h.cdv = ws + L.cdv;
   h.clv = ws + L.clv;
@@ -949,6 +1087,13 @@ fredopt_status fredopt_get_plan_info(const fredopt_plan* p, fredopt_plan_info* i
   info->tr_items = (int64_t)p->tr.size();
   info->row_items = (int64_t)p->rows.size();
   info->workspace_bytes = (int64_t)p->L.total;
+  info->grad_entries = p->grad_valid ? p->grad_entries : 0;
+  int64_t oe = 0;
+  if (p->grad_valid && p->sched_obj)
+    for (int32_t row : p->osell.srow)
+      if (row >= 0) oe += p->row_len[row];
+  info->obj_entries = oe;
+  info->schedule = p->sched_obj ? 1 : 0;
   info->storage = p->storage;
   info->lanes_per_row = 1 << p->sell.lpr_log2;
   info->fwd_grid = (int32_t)std::min<int64_t>((int64_t)p->groups.size(),
@@ -973,7 +1118,7 @@ fredopt_status fredopt_dose_let(fredopt_plan* p, const float* x, double c, float
   fredopt_status st = upload_table(p, s);
   h.out_dose = h.out_letd = h.out_cdl = nullptr;
   if (st != FREDOPT_OK) return st;
-  if (dose || letd || cdl) enqueue(p, Launch{0, kKindFwd, kFwdDoseLet}, s);
+  if (dose || letd || cdl) enqueue(p, Launch{0, kKindFwd, kFwdDoseLet, 0, kVecX}, s);
   HIPCHK(hipGetLastError());
   return FREDOPT_OK;
 }
@@ -1015,10 +1160,11 @@ static fredopt_status step_common(fredopt_plan* p, const fredopt_problem* pr,
   hipStream_t s = static_cast<hipStream_t>(stream);
   if ((st = run_problem_check(p, pr, s)) != FREDOPT_OK) return st;
   const int r = q->reductions_n;
-  if (r > 0 && (st = prepare_gradient(p, pr, s)) != FREDOPT_OK) return st;
+  if (r > 0 && (st = prepare_problem(p, pr, s)) != FREDOPT_OK) return st;
   set_problem(p, pr, q, -1.0, x);
   if ((st = upload_table(p, s)) != FREDOPT_OK) return st;
   if ((st = upload_state(p, stt, s)) != FREDOPT_OK) return st;
+  if (iters > 0) enqueue(p, Launch{FREDOPT_KERNEL_COL, kKindCol, kColYCopy}, s);
   if (use_graph && iters > 0) {
     if ((st = ensure_graph(p, r)) != FREDOPT_OK) return st;
     for (int i = 0; i < iters; ++i) HIPCHK(hipGraphLaunch(p->graph, s));
@@ -1057,11 +1203,12 @@ fredopt_status fredopt_profile_kernels(fredopt_plan* p, const fredopt_problem* p
   DeviceGuard guard(p->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
   if ((st = run_problem_check(p, pr, s)) != FREDOPT_OK) return st;
-  if (q->reductions_n > 0 && (st = prepare_gradient(p, pr, s)) != FREDOPT_OK) return st;
+  if (q->reductions_n > 0 && (st = prepare_problem(p, pr, s)) != FREDOPT_OK) return st;
   set_problem(p, pr, q, -1.0, x);
   if ((st = upload_table(p, s)) != FREDOPT_OK) return st;
   if ((st = upload_state(p, stt, s)) != FREDOPT_OK) return st;
-  const std::vector<Launch> seq = iteration_sequence(q->reductions_n);
+  enqueue(p, Launch{FREDOPT_KERNEL_COL, kKindCol, kColYCopy}, s);
+  const std::vector<Launch> seq = iteration_sequence(q->reductions_n, p->sched_obj);
   const size_t n = seq.size() * (size_t)n_iters;
   std::vector<hipEvent_t> ev(2 * n, nullptr);
   for (auto& e : ev) HIPCHK(hipEventCreate(&e));
@@ -1146,7 +1293,7 @@ fredopt_status fredopt_autotune(fredopt_plan* p, const float* x, void* stream) {
   double best = 1e30;
   for (int w = 1; st == FREDOPT_OK && w <= p->max_wgs_per_cu; ++w) {
     p->wgs_per_cu = w;
-    const double t = timeit(Launch{0, kKindFwd, kFwdDoseLet}, 5);
+    const double t = timeit(Launch{0, kKindFwd, kFwdDoseLet, 0, kVecX}, 5);
     if (t < best) {
       best = t;
       best_w = w;

@@ -70,10 +70,11 @@ class PlanInfo(ct.Structure):
                 ("sell_slots", ct.c_int64), ("csc_slots", ct.c_int64),
                 ("bytes_per_sell_slot", ct.c_int64), ("bytes_per_csc_slot", ct.c_int64),
                 ("n_slices", ct.c_int64), ("tr_items", ct.c_int64), ("row_items", ct.c_int64),
-                ("workspace_bytes", ct.c_int64),
+                ("workspace_bytes", ct.c_int64), ("grad_entries", ct.c_int64),
+                ("obj_entries", ct.c_int64),
                 ("storage", ct.c_int32), ("lanes_per_row", ct.c_int32),
                 ("fwd_grid", ct.c_int32), ("tr_chunk", ct.c_int32), ("lds_x", ct.c_int32),
-                ("reserved", ct.c_int32)]
+                ("schedule", ct.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -161,13 +161,17 @@ def test_project_sweep_config0(fo, cfg0):
     assert np.linalg.norm(xg - xr) <= T2 * np.linalg.norm(xr)
 
 
+@pytest.mark.parametrize("reserve", [0, 100])
 @pytest.mark.parametrize("lpr", [1, 4])
 @pytest.mark.parametrize("r", [0, 1, 2])
-def test_superiorize_step_tiny(fo, r, lpr):
+def test_superiorize_step_tiny(fo, r, lpr, reserve):
+    """Both iteration schedules (objective-row view with a 100 % reserve, two
+    all-row forward products with the default reserve on this 2/3-objective
+    problem) against the oracle."""
     import torch
     p = ph.tiny_problem(300, 30, 0.15, seed=21)
-    print(f"superiorize_step tiny r={r} lpr={lpr}", flush=True)
-    plan, prob, x0 = fo.load_phantom(p, lanes_per_row=lpr)
+    print(f"superiorize_step tiny r={r} lpr={lpr} reserve={reserve}", flush=True)
+    plan, prob, x0 = fo.load_phantom(p, lanes_per_row=lpr, gradient_reserve_pct=reserve)
     q = _params(fo, alpha=0.9, reductions_n=r)
     st = fo.new_state()
     o = Oracle(p)
@@ -305,6 +309,9 @@ def test_gradient_copy_and_fallback(fo, reserve):
     xr, k, s = p.x0.astype(np.float64), 0, -1
     for it in range(4):
         fo.superiorize_step(plan, prob, q, st, x)
+        info = plan.info()
+        # two thirds of the rows carry objective terms: the 100 % reserve holds them
+        assert info["schedule"] == (1 if reserve == 100 else 0)
         xr, k, s, info = o.sa_iteration(xr, k, s, _oparams(q))
         assert (st.k, st.s) == (k, s)
         assert st.grad_sq == pytest.approx(info["grad_sq"], rel=1e-4)
