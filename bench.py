@@ -29,10 +29,11 @@ sys.path.insert(0, ROOT)
 METRIC = "superiorized iters/s + achieved HBM GB/s vs plain FP32; p50/p99 plan latency"
 HBM_PEAK_GBPS = 8000.0
 KERNEL_SYMBOLS = {  # fredopt kernel id -> device symbol in profiler output (vt: storage)
-    "fwd_obj": "fo::k_forward<{vt}, 1>", "fwd_dir": "fo::k_forward<{vt}, 2>",
-    "fwd_resid": "fo::k_forward<{vt}, 3>", "tr_grad": "fo::k_tr_chunks<{vt}, 0>",
+    "fwd_obj": "fo::k_forward<{vt}, 1, {sub}>", "fwd_dir": "fo::k_forward<{vt}, 2, {sub}>",
+    "fwd_resid": "fo::k_forward<{vt}, 3, 0>", "tr_grad": "fo::k_tr_chunks<{vt}, 0>",
     "tr_proj": "fo::k_tr_chunks<{vt}, 1>", "rows": "fo::k_rows<1>", "col": "fo::k_tcol",
-    "finalize": "fo::k_finalize"}
+    "finalize": "fo::k_finalize", "active_list": "fo::k_active_list",
+    "scatter": "fo::k_scatter<{vt}>"}
 
 
 def log(msg: str):
@@ -72,8 +73,8 @@ def algorithmic_bytes(kernel: str, R: int, C: int, nnz: int, vb: int, n_tr_items
         return n_tr_items * 4 + C * 16
     if kernel == "rows":        # d, l, Dg, Lg in; d, l, coef out; problem data in
         return R * (16 + 8 + 8 + 2 + 20 + 4 + 24 + 12)
-    if kernel == "finalize":
-        return 0
+    if kernel in ("finalize", "active_list", "scatter"):
+        return 0  # scalars; the active-row work depends on the iterate (not priced)
     raise KeyError(kernel)
 
 
@@ -228,7 +229,7 @@ def main():
         log(f"copy calibration: 3 copies of {n} bytes")
 
     roofline = {"bound": "hbm", "kernel": dom,
-                "symbol": KERNEL_SYMBOLS[dom].format(vt=storage),
+                "symbol": KERNEL_SYMBOLS[dom].format(vt=storage, sub=info["schedule"]),
                 "achieved": round(per_kernel[dom]["gbps"], 1), "peak": HBM_PEAK_GBPS,
                 "unit": "GB/s", "frac": round(per_kernel[dom]["gbps"] / HBM_PEAK_GBPS, 4),
                 "traffic": traffic,

@@ -221,6 +221,8 @@ typedef struct {
   int32_t lds_x;    /* 1 if the forward kernels stage the vector in LDS */
   int32_t schedule; /* 1: objective-row view in use (one all-row forward product per
                        outer iteration), 0: two all-row forward products */
+  int32_t scatter_wgs;      /* workgroups of the active-row projection (0: off)  */
+  int64_t scatter_max_rows; /* largest active-row count that takes that path     */
 } fredopt_plan_info;
 
 fredopt_status fredopt_get_plan_info(const fredopt_plan *p, fredopt_plan_info *info);
@@ -234,7 +236,9 @@ fredopt_status fredopt_get_plan_info(const fredopt_plan *p, fredopt_plan_info *i
 #define FREDOPT_KERNEL_FWD_RESID 5 /* d, l and residuals (reductions_n = 0)         */
 #define FREDOPT_KERNEL_COL 6       /* per-column sums: gradient or update and clamp */
 #define FREDOPT_KERNEL_FINALIZE 7  /* plan scalars: step decision, weights          */
-#define FREDOPT_NUM_KERNELS 8
+#define FREDOPT_KERNEL_ACTIVE_LIST 8 /* list of rows with a projection coefficient  */
+#define FREDOPT_KERNEL_SCATTER 9   /* transposed product over those rows only       */
+#define FREDOPT_NUM_KERNELS 10
 
 /* Runs n_iters outer iterations (as fredopt_superiorize_step would) launching each
  * kernel separately with HIP events around it on `stream`, and writes the mean
@@ -254,6 +258,19 @@ fredopt_status fredopt_autotune(fredopt_plan *p, const float *x, void *stream);
 /* Sets the forward workgroups per CU (1..8, capped by LDS) and the transposed chunk
  * size (slots per work item, a multiple of 256); 0 keeps the current value. */
 fredopt_status fredopt_set_tuning(fredopt_plan *p, int32_t fwd_wgs_per_cu, int32_t tr_chunk);
+
+/* The projection of Fig. 2 needs D^T and L^T applied to the rows' coefficients, which
+ * are zero for every satisfied constraint.  When at most max_active_rows rows have a
+ * non-zero coefficient, the plan applies the transposes to those rows only (read
+ * through the forward layout, summed in 64-bit fixed point, order independent);
+ * otherwise it streams the column-major copy.  The choice is made on the device at
+ * every sweep.  Both paths give the same result up to FP32 rounding of the sums.
+ * n_workgroups: 0 default (one per compute unit), -1 disables the active-row path,
+ * 1..256 sets the count.  max_active_rows: -1 default (a quarter of the rows).
+ * Needs 8 * n_cols bytes of LDS per workgroup (FREDOPT_E_NOT_IMPLEMENTED if the
+ * columns do not fit). */
+fredopt_status fredopt_set_scatter(fredopt_plan *p, int32_t n_workgroups,
+                                   int64_t max_active_rows);
 
 #ifdef __cplusplus
 }

@@ -33,7 +33,8 @@ constexpr int kWave = 64;              // CDNA wavefront width
 constexpr int kFwdBlock = 512;         // forward kernel: 8 waves, one slice each
 constexpr int kFwdWaves = kFwdBlock / kWave;
 constexpr int kBlock = 256;            // other kernels
-constexpr int kNPart = 8;              // doubles per partial-sum slot
+constexpr int kScatterBlock = 1024;    // active-row scatter: 16 waves, one row each
+constexpr int kNPart = 16;             // doubles per partial-sum slot
 constexpr int kCounters = 4;           // scheduling counters per batch
 constexpr double kDegenerateRel = 1e-12;
 constexpr double kBetaFloor = 1e-300;
@@ -80,6 +81,17 @@ struct DevState {
   int64_t k, s, n_violated, n_degenerate;
   double beta, cost, cost_y, proximity, G, Q, w_all, w_viol, scale, ws;
   int32_t pstop, capped, nonfinite, pad;
+  int32_t n_active;           // rows with a non-zero projection coefficient
+  int32_t proj_scatter;       // 1: the projection uses the active-row scatter
+  double fx_scale;            // fixed-point scale of the active-row scatter
+};
+
+// A row with a non-zero projection coefficient, as the scatter reads it.
+struct ActRow {
+  int64_t sb;                 // base slot of the row's slice
+  int32_t nq, p;              // quads of the slice (width * lpr); slice position
+  float cd, cl;               // projection coefficients (dose part, LET part)
+  int32_t pad[2];
 };
 
 // Forward layout (sliced ELL): a slice holds rpw = 64 / lpr rows, each row spread
@@ -119,6 +131,7 @@ struct DevPlan {
   const int32_t* gcol_nch;
   const float* cscale;        // per-column scale of 16-bit storage (null for FP32)
   const double* mom;          // [3R] sum D^2, sum L^2, sum D L per row
+  const float* rsum;          // [2R] sum of the stored D and L values of a row
   // problem (device arrays of R)
   const uint16_t* kind;
   const float *dlo, *dhi, *clo, *chi, *tmax, *wf, *wo, *dt, *ct;
@@ -140,6 +153,11 @@ struct DevPlan {
   double* rpart;              // [n_row_items * kNPart]
   double* gpart;              // [n_col_blocks]
   float* tpart;               // [sum of chunks]
+  // projection restricted to rows with non-zero coefficients
+  int32_t* goff;              // [groups] first list position of each group's rows
+  ActRow* alist;              // [R] the active rows in slice order
+  int64_t* spart;             // [n_scatter * C] per-workgroup fixed-point sums
+  int32_t n_scatter, scatter_max_rows;  // workgroups; largest list that uses it
   DevParams prm;
   DevState* st;
 };

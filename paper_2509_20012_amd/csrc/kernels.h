@@ -18,6 +18,10 @@ void launch_tcol(int mode, const DevPlan* plans, const ColBlock* blocks, int n_b
                  hipStream_t s);
 void launch_finalize(int mode, int sub, const DevPlan* plans, int n_plans, hipStream_t s);
 hipError_t set_forward_lds_limit(int vtype, size_t bytes);
+void launch_active_list(const DevPlan* plans, const FwdGroup* groups, int n_groups,
+                        hipStream_t s);
+void launch_scatter(int vtype, const DevPlan* plans, int n_scatter, int C, hipStream_t s);
+hipError_t set_scatter_lds_limit(size_t bytes);
 
 // load kernels (kernels_load.hip)
 // flags bits: 1 column index out of range, 2 columns not strictly increasing,
@@ -39,9 +43,10 @@ void launch_fill_csc(int vtype, int64_t R, int64_t C, int rows_per_block,
                      const int64_t* row_ptr, const int32_t* col, const float* dv,
                      const float* lv, const float* scale, uint32_t* bc, int32_t* ri,
                      void* cdv, void* clv, hipStream_t s);
+// mom: sum D^2, sum L^2, sum D L per row; rsum: sum of the stored D and L values
 void launch_moments(int vtype, int64_t R, const int64_t* row_ptr, const int32_t* col,
                     const float* dv, const float* lv, const float* scale, double* mom,
-                    hipStream_t s);
+                    float* rsum, hipStream_t s);
 // count[j]: entries of column j (len[j] real entries from cp[j]) in rows with
 // objective terms.
 void launch_obj_count(int64_t C, const int64_t* cp, const uint32_t* len, const int32_t* ri,

@@ -24,6 +24,8 @@
 //   direction pass  [0] Q                             [5] non-finite rows
 //   residual pass   [0] sum w (enabled) [1] sum w (violated) [2] sum w v^2/||a||^2
 //                   [3] violated  [4] degenerate  [5] non-finite  [6] chi^2
+//                   [7] rows with a non-zero projection coefficient
+//                   [8] sum over those rows of |cD| sum D + |cL| sum L (stored units)
 #include "fredopt_device.h"
 #include "kernels.h"
 
@@ -189,7 +191,13 @@ __device__ __forceinline__ void residual_row(const DevPlan* P, int r, float d, f
       if (ax > 0.0) take(ax, sll - 2.0 * T * sdl + T * T * sdd, sll + T * T * sdd, 2, T);
     }
   }
-  ((FO_GLOBAL v2f*)(P->coef))[r] = v2f{(float)kD, (float)kL};
+  const float fD = (float)kD, fL = (float)kL;
+  ((FO_GLOBAL v2f*)(P->coef))[r] = v2f{fD, fL};
+  if (fD != 0.f || fL != 0.f) {
+    const v2f rs = ((const FO_GLOBAL v2f*)(P->rsum))[r];
+    acc[7] += 1.0;
+    acc[8] += fabs((double)fD) * (double)rs.x + fabs((double)fL) * (double)rs.y;
+  }
 }
 
 __device__ __forceinline__ bool finite2(float a, float b) { return isfinite(a) && isfinite(b); }
@@ -263,7 +271,7 @@ __device__ __noinline__ void decide_step(const DevPlan* P, double G, double Q) {
 
 template <int MODE>
 __device__ __forceinline__ constexpr unsigned fwd_slots() {
-  return MODE == kFwdResid ? 0x7Fu : 0x21u;
+  return MODE == kFwdResid ? 0x1FFu : 0x21u;
 }
 
 // One slice of a sliced-ELL view: d = D v, l = L v for its rows, then the epilogue
@@ -460,7 +468,7 @@ __global__ __launch_bounds__(kBlock) void k_rows(const DevPlan* __restrict__ pla
     }
     if (!finite2(d, l)) acc[5] += 1.0;
   }
-  constexpr unsigned used = MODE == kRowsMoveObj ? 0x21u : 0x7Fu;
+  constexpr unsigned used = MODE == kRowsMoveObj ? 0x21u : 0x1FFu;
   double s[kNPart];
 #pragma unroll
   for (int k = 0; k < kNPart; ++k) s[k] = (used & (1u << k)) ? block_sum(acc[k], sh4) : 0.0;
@@ -488,6 +496,7 @@ __global__ __launch_bounds__(kBlock) void k_tr_chunks(const DevPlan* __restrict_
   if (it >= n_items) return;
   const TrItem w = items[uniform(it)];
   const DevPlan* __restrict__ P = plans + w.plan;
+  if (TAG == 1 && P->st->proj_scatter) return;
   // chunk-relative element offsets fit 32 bits; the chunk base is wave-uniform
   const FO_GLOBAL int32_t* ri = gconst(TAG == 0 ? P->gri : P->ri) + w.q0;
   const FO_GLOBAL void* cdv = value_ptr<VT>(TAG == 0 ? P->gcdv : P->cdv, w.q0);
@@ -515,6 +524,97 @@ __global__ __launch_bounds__(kBlock) void k_tr_chunks(const DevPlan* __restrict_
   if (lane == 0) gmut(P->tpart)[w.tslot] = acc;
 }
 
+// ---------------------------------------------- projection over active rows ----
+
+// The rows with a non-zero projection coefficient, group by group in slice order
+// (list offsets from the residual finalisation), with what the scatter needs.
+__global__ __launch_bounds__(kFwdBlock) void k_active_list(const DevPlan* __restrict__ plans,
+                                                           const FwdGroup* __restrict__ groups,
+                                                           int n_groups) {
+  __shared__ int wsum[kFwdWaves];
+  const FwdGroup G = groups[blockIdx.x];
+  const DevPlan* __restrict__ P = plans + G.plan;
+  if (!P->st->proj_scatter) return;
+  const int rpw_log2 = 6 - P->lpr_log2;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+  const int n = G.n << rpw_log2;
+  const int sp = (G.slice0 << rpw_log2) + tid;
+  bool act = false;
+  v2f c = v2f{0.f, 0.f};
+  if (tid < n) {
+    const int row = gconst(P->sell.srow)[sp];
+    if (row >= 0) {
+      c = ((const FO_GLOBAL v2f*)(P->coef))[row];
+      act = c.x != 0.f || c.y != 0.f;
+    }
+  }
+  const uint64_t m = __ballot(act);
+  if (lane == 0) wsum[wave] = __popcll(m);
+  __syncthreads();
+  int before = 0;
+  for (int w = 0; w < wave; ++w) before += wsum[w];
+  before += __popcll(m & ((1ull << lane) - 1ull));
+  if (act) {
+    const int s = sp >> rpw_log2;
+    const int64_t sb = gconst(P->sell.sbase)[s];
+    // ActRow as two 16-byte stores
+    FO_GLOBAL v4i* dst = (FO_GLOBAL v4i*)(P->alist + gconst(P->goff)[G.slot] + before);
+    dst[0] = v4i{(int)(uint32_t)sb, (int)(sb >> 32), gconst(P->sell.swidth)[s] << P->lpr_log2,
+                 sp & ((1 << rpw_log2) - 1)};
+    dst[1] = v4i{__float_as_int(c.x), __float_as_int(c.y), 0, 0};
+  }
+}
+
+__device__ __forceinline__ void fx_add(unsigned long long* acc, int col, double v, double fs) {
+  if (v != 0.0) atomicAdd(&acc[col], (unsigned long long)__double2ll_rn(v * fs));
+}
+
+// D^T cD + L^T cL over the active rows only.  Contributions are rounded to 64-bit
+// fixed point (scale 2^61 / bound from the residual pass) and added with integer LDS
+// atomics: integer sums do not depend on the order of the additions, so the waves of
+// a workgroup take rows concurrently and the result is still reproducible bit for
+// bit.  Workgroup w takes a contiguous share of the list; the column kernel adds
+// the shares.
+template <int VT>
+__global__ __launch_bounds__(kScatterBlock) void k_scatter(const DevPlan* __restrict__ plans) {
+  extern __shared__ unsigned long long facc[];
+  const DevPlan* __restrict__ P = plans;
+  if (!P->st->proj_scatter) return;
+  const int C = (int)P->C;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+  for (int j = tid; j < C; j += kScatterBlock) facc[j] = 0ull;
+  __syncthreads();
+  const int64_t A = P->st->n_active, NW = P->n_scatter;
+  const int i0 = (int)(blockIdx.x * A / NW), i1 = (int)((blockIdx.x + 1) * A / NW);
+  const int lg2 = P->lpr_log2, lpr = 1 << lg2;
+  const double fs = P->st->fx_scale;
+  const ActRow* list = P->alist;
+  for (int i = i0 + wave; i < i1; i += kScatterBlock / kWave) {
+    const v4i a0 = ((const FO_GLOBAL v4i*)(list + i))[0];
+    const v4i a1 = ((const FO_GLOBAL v4i*)(list + i))[1];
+    const int64_t sb = (int64_t)(((uint64_t)(uint32_t)uniform(a0.y) << 32) | (uint32_t)uniform(a0.x));
+    const int nq = uniform(a0.z), p = uniform(a0.w);
+    const double cd = __int_as_float(uniform(a1.x)), cl = __int_as_float(uniform(a1.y));
+    const FO_GLOBAL int32_t* ci = gconst(P->sell.sci) + sb;
+    const FO_GLOBAL void* dv = value_ptr<VT>(P->sell.sdv, sb);
+    const FO_GLOBAL void* lv = value_ptr<VT>(P->sell.slv, sb);
+    for (int q = lane; q < nq; q += kWave) {
+      const uint32_t e = (uint32_t)(q >> lg2) * 256u + (uint32_t)(p * lpr + (q & (lpr - 1))) * 4u;
+      const v4i c4 = *((const FO_GLOBAL v4i*)(ci + e));
+      const v4f d4 = VLoad<VT>::q4(dv, e);
+      const v4f l4 = VLoad<VT>::q4(lv, e);
+      // padding slots hold the value 0 and add nothing
+      fx_add(facc, c4.x, cd * d4.x + cl * l4.x, fs);
+      fx_add(facc, c4.y, cd * d4.y + cl * l4.y, fs);
+      fx_add(facc, c4.z, cd * d4.z + cl * l4.z, fs);
+      fx_add(facc, c4.w, cd * d4.w + cl * l4.w, fs);
+    }
+  }
+  __syncthreads();
+  FO_GLOBAL int64_t* out = gmut(P->spart) + (int64_t)blockIdx.x * C;
+  for (int j = tid; j < C; j += kScatterBlock) out[j] = (int64_t)facc[j];
+}
+
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_tcol(const DevPlan* __restrict__ plans,
                                                  const ColBlock* __restrict__ blocks) {
@@ -531,10 +631,19 @@ __global__ __launch_bounds__(kBlock) void k_tcol(const DevPlan* __restrict__ pla
       const double b = P->st->beta;
       gmut(P->y)[j] = (float)((double)gconst(P->y)[j] - b * (double)gconst(P->g)[j]);
     } else {
-      const int ts = grad ? gconst(P->gcol_tslot0)[j] : gconst(P->col_tslot0)[j];
-      const int n = grad ? gconst(P->gcol_nch)[j] : gconst(P->col_nch)[j];
       float t = 0.f;
-      for (int c = 0; c < n; ++c) t += gconst(P->tpart)[ts + c];
+      if (!grad && P->st->proj_scatter) {
+        // fixed-point shares of the active-row scatter (exact integer sum)
+        const FO_GLOBAL int64_t* sp = gconst(P->spart) + j;
+        int64_t S = 0;
+#pragma unroll 8
+        for (int w = 0; w < P->n_scatter; ++w) S += sp[(int64_t)w * P->C];
+        t = (float)((double)S / P->st->fx_scale);
+      } else {
+        const int ts = grad ? gconst(P->gcol_tslot0)[j] : gconst(P->col_tslot0)[j];
+        const int n = grad ? gconst(P->gcol_nch)[j] : gconst(P->col_nch)[j];
+        for (int c = 0; c < n; ++c) t += gconst(P->tpart)[ts + c];
+      }
       if (P->cscale) t *= gconst(P->cscale)[j];
       if constexpr (grad) {
         if constexpr (MODE == kColGradMove) {
@@ -611,11 +720,46 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const DevPlan* __restrict__
       if (a[5] > 0.0) P->st->nonfinite = 1;
     }
   } else if constexpr (MODE == kFinResidRows) {
-    sum_slots(P->rpart, P->n_row_items, a, 0x7Fu, sh4);
-    if (threadIdx.x == 0) finalize_residuals(P, a);
+    sum_slots(P->rpart, P->n_row_items, a, 0x1FFu, sh4);
+    if (threadIdx.x == 0) {
+      finalize_residuals(P, a);
+      P->st->n_active = (int)a[7];
+      P->st->proj_scatter = 0;
+    }
   } else {
-    sum_slots(P->spart_a, P->sell.n_groups, a, 0x7Fu, sh4);
-    if (threadIdx.x == 0) finalize_residuals(P, a);
+    sum_slots(P->spart_a, P->sell.n_groups, a, 0x1FFu, sh4);
+    const int A = (int)a[7];
+    // contributions are rounded to multiples of 1 / fx_scale; with every column
+    // total bounded by a[8], 2^61 / a[8] keeps all sums far inside int64
+    const double B = a[8];
+    const bool scatter = P->n_scatter > 0 && A <= P->scatter_max_rows && B < 1e300;
+    if (scatter) {
+      // exclusive scan of the groups' active-row counts (list offsets), in group order
+      __shared__ int sc[kBlock];
+      int carry = 0;
+      const FO_GLOBAL double* part = gconst(P->spart_a);
+      for (int g0 = 0; g0 < P->sell.n_groups; g0 += kBlock) {
+        const int g = g0 + threadIdx.x;
+        const int v = g < P->sell.n_groups ? (int)part[(int64_t)g * kNPart + 7] : 0;
+        sc[threadIdx.x] = v;
+        __syncthreads();
+        for (int o = 1; o < kBlock; o <<= 1) {
+          const int add = threadIdx.x >= o ? sc[threadIdx.x - o] : 0;
+          __syncthreads();
+          sc[threadIdx.x] += add;
+          __syncthreads();
+        }
+        if (g < P->sell.n_groups) gmut(P->goff)[g] = carry + sc[threadIdx.x] - v;
+        carry += sc[kBlock - 1];
+        __syncthreads();
+      }
+    }
+    if (threadIdx.x == 0) {
+      finalize_residuals(P, a);
+      P->st->n_active = A;
+      P->st->proj_scatter = scatter ? 1 : 0;
+      P->st->fx_scale = B > 0.0 ? 0x1p61 / B : 1.0;
+    }
   }
 }
 
@@ -690,6 +834,33 @@ void launch_tr_chunks(int vtype, int tag, const DevPlan* plans, const TrItem* it
     launch_tr_tag<0>(vtype, plans, items, n_items, grid, nb8, s);
   else
     launch_tr_tag<1>(vtype, plans, items, n_items, grid, nb8, s);
+}
+
+void launch_active_list(const DevPlan* plans, const FwdGroup* groups, int n_groups,
+                        hipStream_t s) {
+  if (n_groups > 0) k_active_list<<<n_groups, kFwdBlock, 0, s>>>(plans, groups, n_groups);
+}
+
+void launch_scatter(int vtype, const DevPlan* plans, int n_scatter, int C, hipStream_t s) {
+  if (n_scatter <= 0) return;
+  const size_t lds = (size_t)C * sizeof(unsigned long long);
+  if (vtype == kF16)
+    k_scatter<kF16><<<n_scatter, kScatterBlock, lds, s>>>(plans);
+  else if (vtype == kBF16)
+    k_scatter<kBF16><<<n_scatter, kScatterBlock, lds, s>>>(plans);
+  else
+    k_scatter<kF32><<<n_scatter, kScatterBlock, lds, s>>>(plans);
+}
+
+hipError_t set_scatter_lds_limit(size_t bytes) {
+  hipError_t e = hipSuccess;
+  for (const void* f : {(const void*)k_scatter<kF32>, (const void*)k_scatter<kF16>,
+                        (const void*)k_scatter<kBF16>}) {
+    const hipError_t r =
+        hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (r != hipSuccess) e = r;
+  }
+  return e;
 }
 
 void launch_tcol(int mode, const DevPlan* plans, const ColBlock* blocks, int n_blocks,

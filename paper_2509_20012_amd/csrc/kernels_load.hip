@@ -175,24 +175,31 @@ __global__ __launch_bounds__(kBlock) void k_fill_csc(int vtype, int64_t R, int64
 }
 
 // Per-row FP64 moments sum D^2, sum L^2, sum D L of the values the kernels multiply
-// (for 16-bit storage: the quantised value times the column scale).
+// (for 16-bit storage: the quantised value times the column scale), and the row sums
+// of the stored values (rounded up: they bound the active-row scatter's sums).
 __global__ __launch_bounds__(kBlock) void k_moments(int vtype, int64_t R,
                                                     const int64_t* __restrict__ row_ptr,
                                                     const int32_t* __restrict__ col,
                                                     const float* __restrict__ dv,
                                                     const float* __restrict__ lv,
                                                     const float* __restrict__ scale,
-                                                    double* mom) {
+                                                    double* mom, float* rsum) {
   const int64_t row = (int64_t)blockIdx.x * kRowsPerWg + threadIdx.x / kWave;
   const int lane = threadIdx.x % kWave;
   if (row >= R) return;
-  double sdd = 0.0, sll = 0.0, sdl = 0.0;
+  double sdd = 0.0, sll = 0.0, sdl = 0.0, sd = 0.0, sl = 0.0;
   for (int64_t k = row_ptr[row] + lane; k < row_ptr[row + 1]; k += kWave) {
     double d = dv[k], l = lv[k];
     if (vtype != kF32) {
       const float sc = scale[col[k]];
-      d = stored_value(vtype, dv[k], sc) * (double)sc;
-      l = stored_value(vtype, lv[k], sc) * (double)sc;
+      const double qd = stored_value(vtype, dv[k], sc), ql = stored_value(vtype, lv[k], sc);
+      sd += qd;
+      sl += ql;
+      d = qd * (double)sc;
+      l = ql * (double)sc;
+    } else {
+      sd += d;
+      sl += l;
     }
     sdd += d * d;
     sll += l * l;
@@ -202,11 +209,15 @@ __global__ __launch_bounds__(kBlock) void k_moments(int vtype, int64_t R,
     sdd += __shfl_xor(sdd, o);
     sll += __shfl_xor(sll, o);
     sdl += __shfl_xor(sdl, o);
+    sd += __shfl_xor(sd, o);
+    sl += __shfl_xor(sl, o);
   }
   if (lane == 0) {
     mom[3 * row] = sdd;
     mom[3 * row + 1] = sll;
     mom[3 * row + 2] = sdl;
+    rsum[2 * row] = __double2float_ru(sd);
+    rsum[2 * row + 1] = __double2float_ru(sl);
   }
 }
 
@@ -399,8 +410,9 @@ void launch_fill_csc(int vtype, int64_t R, int64_t C, int rows_per_block,
 
 void launch_moments(int vtype, int64_t R, const int64_t* row_ptr, const int32_t* col,
                     const float* dv, const float* lv, const float* scale, double* mom,
-                    hipStream_t s) {
-  if (R > 0) k_moments<<<row_grid(R), kBlock, 0, s>>>(vtype, R, row_ptr, col, dv, lv, scale, mom);
+                    float* rsum, hipStream_t s) {
+  if (R > 0)
+    k_moments<<<row_grid(R), kBlock, 0, s>>>(vtype, R, row_ptr, col, dv, lv, scale, mom, rsum);
 }
 
 void launch_obj_count(int64_t C, const int64_t* cp, const uint32_t* len, const int32_t* ri,

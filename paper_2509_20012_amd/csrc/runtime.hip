@@ -46,8 +46,12 @@ constexpr int64_t kRowItemRows = 2048;
 constexpr int64_t kTrChunkMin = 256;
 constexpr int64_t kTrChunkDefault = 4096;
 constexpr int64_t kBlockCountCap = int64_t(1) << 24;
+constexpr int64_t kScatterMaxWGs = 256;   // workgroups of the active-row scatter (max)
+constexpr size_t kScatterLdsMax = 159744; // its LDS accumulator: C 64-bit sums
 
 inline size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
+
+inline bool scatter_fits(int64_t C) { return (size_t)C * sizeof(int64_t) <= kScatterLdsMax; }
 
 int value_bytes(int storage) { return storage == FREDOPT_F32 ? 4 : 2; }
 
@@ -132,7 +136,7 @@ struct Layout {
   size_t gri, gcdv, gclv, gcol_tslot0, gcol_nch, ocp, ocount, gtr_items;
   size_t y, osbase, oswidth, osrow, osci, osdv, oslv, ogroups, pk_src, pk_dst, pk_len;
   size_t spart_a, spart_b, rpart, gpart, tpart, groups, row_items, tr_items, col_blocks;
-  size_t bc, colcount, colmax, flags, rslice, total;
+  size_t bc, colcount, colmax, flags, rslice, rsum, goff, alist, spart, total;
   int64_t sell_slots, n_slices, csc_slots, obj_slots, max_rows, max_tr, n_groups, n_col_blocks;
   int64_t obj_sell_slots, max_obj_slices, max_obj_groups;
   int64_t rows_per_block, nb;
@@ -230,6 +234,10 @@ bool make_layout(int64_t R, int64_t C, int64_t nnz, int storage, int lpr_log2,
   L->colmax = take(sizeof(uint32_t) * C);
   L->flags = take(sizeof(uint32_t) * 4);
   L->rslice = take(sizeof(int32_t) * Rm);
+  L->rsum = take(sizeof(float) * 2 * Rm);
+  L->goff = take(sizeof(int32_t) * L->n_groups);
+  L->alist = take(sizeof(ActRow) * Rm);
+  L->spart = take(scatter_fits(C) ? sizeof(int64_t) * kScatterMaxWGs * C : sizeof(int64_t));
   L->total = o;
   return true;
 }
@@ -271,6 +279,9 @@ struct fredopt_plan {
   std::vector<int64_t> cp;
   int tr_chunk = (int)kTrChunkDefault;
   int n_cu = 256, wgs_per_cu = 2, max_wgs_per_cu = 2, lds_floats = 0;
+  size_t smem_block = 0;              // LDS bytes a workgroup may use
+  int n_scatter = 0;                  // active-row scatter workgroups (0: off)
+  int64_t scatter_max_rows = 0;       // largest active-row count that uses it
   std::vector<FwdGroup> groups;
   std::vector<RowItem> rows;
   std::vector<TrItem> tr, gtr;
@@ -627,7 +638,7 @@ void export_state(const DevState& d, fredopt_state* st) {
   st->q = d.Q;
 }
 
-enum Kind { kKindFwd, kKindRows, kKindChunks, kKindCol, kKindFin };
+enum Kind { kKindFwd, kKindRows, kKindChunks, kKindCol, kKindFin, kKindList, kKindScatter };
 
 struct Launch {
   int id;        // FREDOPT_KERNEL_*
@@ -649,6 +660,8 @@ std::vector<Launch> iteration_sequence(int r, bool obj) {
   if (r == 0) {
     seq.push_back({FREDOPT_KERNEL_FWD_RESID, kKindFwd, kFwdResid, 0, kVecX});
     seq.push_back({FREDOPT_KERNEL_FINALIZE, kKindFin, kFinResidFwd});
+    seq.push_back({FREDOPT_KERNEL_ACTIVE_LIST, kKindList, 0});
+    seq.push_back({FREDOPT_KERNEL_SCATTER, kKindScatter, 0});
     seq.push_back({FREDOPT_KERNEL_TR_PROJ, kKindChunks, 1});
     seq.push_back({FREDOPT_KERNEL_COL, kKindCol, kColProj});
     return seq;
@@ -664,6 +677,8 @@ std::vector<Launch> iteration_sequence(int r, bool obj) {
     }
     seq.push_back({FREDOPT_KERNEL_FWD_RESID, kKindFwd, kFwdResid, 0, kVecY});
     seq.push_back({FREDOPT_KERNEL_FINALIZE, kKindFin, kFinResidFwd});
+    seq.push_back({FREDOPT_KERNEL_ACTIVE_LIST, kKindList, 0});
+    seq.push_back({FREDOPT_KERNEL_SCATTER, kKindScatter, 0});
     seq.push_back({FREDOPT_KERNEL_TR_PROJ, kKindChunks, 1});
     seq.push_back({FREDOPT_KERNEL_COL, kKindCol, kColProjY});
     return seq;
@@ -705,6 +720,12 @@ void enqueue(fredopt_plan* p, const Launch& l, hipStream_t s) {
       break;
     case kKindCol:
       launch_tcol(l.mode, p->d_table, p->d_cblocks, (int)p->cblocks.size(), s);
+      break;
+    case kKindList:
+      if (p->n_scatter > 0) launch_active_list(p->d_table, p->d_groups, (int)p->groups.size(), s);
+      break;
+    case kKindScatter:
+      if (p->n_scatter > 0) launch_scatter(p->storage, p->d_table, p->n_scatter, (int)p->C, s);
       break;
     default:
       launch_finalize(l.mode, l.sub, p->d_table, 1, s);
@@ -753,6 +774,7 @@ fredopt_status device_limits(fredopt_plan* p) {
       smem_sm <= 0)
     smem_sm = smem_block;
   p->n_cu = ncu > 0 ? ncu : 256;
+  p->smem_block = (size_t)std::max(smem_block, 0);
   const size_t static_lds = 64;
   const size_t need = (size_t)p->C * sizeof(float);
   if (need + static_lds <= (size_t)std::max(smem_block, 0)) {
@@ -763,6 +785,15 @@ fredopt_status device_limits(fredopt_plan* p) {
   } else {
     p->lds_floats = 0;
     p->max_wgs_per_cu = 4;
+  }
+  const size_t sneed = (size_t)p->C * sizeof(int64_t);
+  if (scatter_fits(p->C) && sneed + static_lds <= (size_t)std::max(smem_block, 0)) {
+    HIPCHK(set_scatter_lds_limit(sneed));
+    p->n_scatter = (int)std::min<int64_t>(p->n_cu, kScatterMaxWGs);
+    p->scatter_max_rows = p->R / 4;
+  } else {
+    p->n_scatter = 0;
+    p->scatter_max_rows = 0;
   }
   p->wgs_per_cu = p->max_wgs_per_cu;
   return FREDOPT_OK;
@@ -981,7 +1012,7 @@ fredopt_status fredopt_load_matrices(const fredopt_matrices* m, void* workspace,
   launch_fill_csc(m->storage, R, C, (int)L.rows_per_block, in_rp, in_col, in_dv, in_lv, scale, bc,
                   ri, ws + L.cdv, ws + L.clv, s);
   launch_moments(m->storage, R, in_rp, in_col, in_dv, in_lv, scale,
-                 reinterpret_cast<double*>(ws + L.mom), s);
+                 reinterpret_cast<double*>(ws + L.mom), reinterpret_cast<float*>(ws + L.rsum), s);
   LCHK(hipGetLastError());
 
   // plan descriptor and work lists
@@ -1038,6 +1069,12 @@ fredopt_status fredopt_load_matrices(const fredopt_matrices* m, void* workspace,
   h.rpart = reinterpret_cast<double*>(ws + L.rpart);
   h.gpart = reinterpret_cast<double*>(ws + L.gpart);
   h.tpart = reinterpret_cast<float*>(ws + L.tpart);
+  h.rsum = reinterpret_cast<const float*>(ws + L.rsum);
+  h.goff = reinterpret_cast<int32_t*>(ws + L.goff);
+  h.alist = reinterpret_cast<ActRow*>(ws + L.alist);
+  h.spart = reinterpret_cast<int64_t*>(ws + L.spart);
+  h.n_scatter = p->n_scatter;
+  h.scatter_max_rows = (int32_t)std::min<int64_t>(p->scatter_max_rows, INT32_MAX);
   h.st = p->d_state;
   h.prm.ws_fixed = -1.0;
   if ((int64_t)p->groups.size() > L.n_groups || (int64_t)p->rows.size() > L.max_rows)
@@ -1100,6 +1137,8 @@ fredopt_status fredopt_get_plan_info(const fredopt_plan* p, fredopt_plan_info* i
                                               (int64_t)p->n_cu * p->wgs_per_cu);
   info->tr_chunk = p->tr_chunk;
   info->lds_x = p->lds_floats > 0 ? 1 : 0;
+  info->scatter_wgs = p->n_scatter;
+  info->scatter_max_rows = p->scatter_max_rows;
   return FREDOPT_OK;
 }
 
@@ -1259,6 +1298,33 @@ fredopt_status fredopt_set_tuning(fredopt_plan* p, int32_t fwd_wgs_per_cu, int32
     fredopt_status st = upload_tr(p, nullptr);
     if (st != FREDOPT_OK) return st;
   }
+  drop_graph(p);
+  HIPCHK(hipStreamSynchronize(nullptr));
+  return FREDOPT_OK;
+}
+
+fredopt_status fredopt_set_scatter(fredopt_plan* p, int32_t n_workgroups,
+                                   int64_t max_active_rows) {
+  if (!p) return fail(FREDOPT_E_ARG, "plan is NULL");
+  if (n_workgroups < -1 || n_workgroups > kScatterMaxWGs)
+    return fail(FREDOPT_E_ARG, "n_workgroups must lie in [-1, %d]", (int)kScatterMaxWGs);
+  if (max_active_rows < -1) return fail(FREDOPT_E_ARG, "max_active_rows must be >= -1");
+  DeviceGuard guard(p->device);
+  const bool avail = scatter_fits(p->C) && p->hp.spart != nullptr &&
+                     (size_t)p->C * sizeof(int64_t) + 64 <= p->smem_block;
+  if (n_workgroups > 0 && !avail)
+    return fail(FREDOPT_E_NOT_IMPLEMENTED, "the active-row scatter needs 8 C bytes of LDS");
+  if (n_workgroups == -1)
+    p->n_scatter = 0;
+  else if (n_workgroups > 0)
+    p->n_scatter = n_workgroups;
+  else
+    p->n_scatter = avail ? (int)std::min<int64_t>(p->n_cu, kScatterMaxWGs) : 0;
+  p->scatter_max_rows = max_active_rows >= 0 ? max_active_rows : p->R / 4;
+  p->hp.n_scatter = p->n_scatter;
+  p->hp.scatter_max_rows = (int32_t)std::min<int64_t>(p->scatter_max_rows, INT32_MAX);
+  fredopt_status st = upload_table(p, nullptr);
+  if (st != FREDOPT_OK) return st;
   drop_graph(p);
   HIPCHK(hipStreamSynchronize(nullptr));
   return FREDOPT_OK;

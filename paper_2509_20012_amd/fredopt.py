@@ -21,7 +21,7 @@ F32, F16, BF16 = 0, 1, 2
 STORAGE = {"f32": F32, "fp32": F32, "f16": F16, "fp16": F16, "bf16": BF16}
 NORM_CONVEX_ALL, NORM_CONVEX_VIOLATED, NORM_RAW = 0, 1, 2
 KERNEL_NAMES = ("fwd_obj", "tr_grad", "fwd_dir", "rows", "tr_proj", "fwd_resid", "col",
-                "finalize")
+                "finalize", "active_list", "scatter")
 
 STATUS = {0: "OK", -1: "E_ARG", -2: "E_SHAPE", -3: "E_INDEX", -4: "E_NONFINITE",
           -5: "E_WORKSPACE", -6: "E_DEVICE", -7: "E_STATE", -8: "E_NOT_IMPLEMENTED"}
@@ -74,7 +74,8 @@ class PlanInfo(ct.Structure):
                 ("obj_entries", ct.c_int64),
                 ("storage", ct.c_int32), ("lanes_per_row", ct.c_int32),
                 ("fwd_grid", ct.c_int32), ("tr_chunk", ct.c_int32), ("lds_x", ct.c_int32),
-                ("schedule", ct.c_int32)]
+                ("schedule", ct.c_int32), ("scatter_wgs", ct.c_int32),
+                ("scatter_max_rows", ct.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -84,7 +85,8 @@ EXPORTED = ("fredopt_workspace_bytes", "fredopt_workspace_bytes_csr",
             "fredopt_load_matrices", "fredopt_free_plan",
             "fredopt_dose_let", "fredopt_project_sweep", "fredopt_superiorize_step",
             "fredopt_solve", "fredopt_last_error", "fredopt_get_plan_info",
-            "fredopt_profile_kernels", "fredopt_autotune", "fredopt_set_tuning")
+            "fredopt_profile_kernels", "fredopt_autotune", "fredopt_set_tuning",
+            "fredopt_set_scatter")
 
 _lib = None
 
@@ -120,6 +122,7 @@ def lib():
                                               ct.POINTER(ct.c_double), ct.POINTER(ct.c_int64)]
         L.fredopt_autotune.argtypes = [P, P, P]
         L.fredopt_set_tuning.argtypes = [P, ct.c_int32, ct.c_int32]
+        L.fredopt_set_scatter.argtypes = [P, ct.c_int32, ct.c_int64]
         for name in EXPORTED:
             if name not in ("fredopt_workspace_bytes", "fredopt_workspace_bytes_csr",
                             "fredopt_last_error"):
@@ -333,6 +336,12 @@ def autotune(plan: Plan, x, stream=None):
 
 def set_tuning(plan: Plan, fwd_wgs_per_cu: int = 0, tr_chunk: int = 0):
     _check(lib().fredopt_set_tuning(plan.handle, int(fwd_wgs_per_cu), int(tr_chunk)))
+
+
+def set_scatter(plan: Plan, n_workgroups: int = 0, max_active_rows: int = -1):
+    """Active-row projection path: ``n_workgroups`` 0 default, -1 off;
+    ``max_active_rows`` -1 default (a quarter of the rows)."""
+    _check(lib().fredopt_set_scatter(plan.handle, int(n_workgroups), int(max_active_rows)))
 
 
 # ----------------------------------------------------------------------- phantoms

@@ -128,13 +128,33 @@ def test_dose_linearity_gpu(fo, cfg0):
     assert np.max(np.abs(d12[m] - d1[m] - d2[m]) / d12[m]) <= 1e-6 * 4
 
 
+# projection paths: the column-major copy for every row ("csc"), the active-row
+# scatter whenever rows are violated ("scatter", with the default and with an odd
+# workgroup count), and the plan's own choice ("auto")
+PATHS = {"csc": (-1, -1), "scatter": (0, 1 << 40), "scatter7": (7, 1 << 40), "auto": (0, -1)}
+
+
+def _set_path(fo, plan, path):
+    n_wg, max_rows = PATHS[path]
+    fo.set_scatter(plan, n_wg, max_rows)
+    info = plan.info()
+    if path == "csc":
+        assert info["scatter_wgs"] == 0
+    elif path == "scatter7":
+        assert info["scatter_wgs"] == 7
+    else:
+        assert info["scatter_wgs"] > 0
+
+
+@pytest.mark.parametrize("path", ["csc", "scatter", "scatter7"])
 @pytest.mark.parametrize("norm", [0, 1, 2])
 @pytest.mark.parametrize("seed", [11, 12])
-def test_project_sweep_tiny(fo, norm, seed):
+def test_project_sweep_tiny(fo, norm, seed, path):
     import torch
     p = ph.tiny_problem(200, 24, 0.2, seed=seed)
-    print(f"project_sweep tiny seed={seed} norm={norm}", flush=True)
+    print(f"project_sweep tiny seed={seed} norm={norm} path={path}", flush=True)
     plan, prob, _ = fo.load_phantom(p)
+    _set_path(fo, plan, path)
     x = np.random.default_rng(seed).uniform(0.5, 1.5, p.n_cols).astype(np.float32)
     xt = torch.from_numpy(x).cuda()
     q = _params(fo, lam=1.3, normalization=norm)
@@ -145,9 +165,12 @@ def test_project_sweep_tiny(fo, norm, seed):
     assert prox == pytest.approx(prox_ref, rel=1e-4)
 
 
-def test_project_sweep_config0(fo, cfg0):
+@pytest.mark.parametrize("path", ["csc", "scatter", "auto"])
+def test_project_sweep_config0(fo, cfg0, path):
     import torch
+    print(f"project_sweep config0 path={path}", flush=True)
     plan, prob, x0 = fo.load_phantom(cfg0)
+    _set_path(fo, plan, path)
     q = _params(fo)
     o = Oracle(cfg0)
     x = x0.clone()
@@ -161,17 +184,19 @@ def test_project_sweep_config0(fo, cfg0):
     assert np.linalg.norm(xg - xr) <= T2 * np.linalg.norm(xr)
 
 
+@pytest.mark.parametrize("path", ["csc", "scatter"])
 @pytest.mark.parametrize("reserve", [0, 100])
 @pytest.mark.parametrize("lpr", [1, 4])
 @pytest.mark.parametrize("r", [0, 1, 2])
-def test_superiorize_step_tiny(fo, r, lpr, reserve):
+def test_superiorize_step_tiny(fo, r, lpr, reserve, path):
     """Both iteration schedules (objective-row view with a 100 % reserve, two
     all-row forward products with the default reserve on this 2/3-objective
-    problem) against the oracle."""
+    problem) and both projection paths against the oracle."""
     import torch
     p = ph.tiny_problem(300, 30, 0.15, seed=21)
-    print(f"superiorize_step tiny r={r} lpr={lpr} reserve={reserve}", flush=True)
+    print(f"superiorize_step tiny r={r} lpr={lpr} reserve={reserve} path={path}", flush=True)
     plan, prob, x0 = fo.load_phantom(p, lanes_per_row=lpr, gradient_reserve_pct=reserve)
+    _set_path(fo, plan, path)
     q = _params(fo, alpha=0.9, reductions_n=r)
     st = fo.new_state()
     o = Oracle(p)
@@ -189,8 +214,11 @@ def test_superiorize_step_tiny(fo, r, lpr, reserve):
             assert st.cost_perturbed < st.cost
 
 
-def test_superiorize_step_config0(fo, cfg0):
+@pytest.mark.parametrize("path", ["csc", "scatter", "auto"])
+def test_superiorize_step_config0(fo, cfg0, path):
+    print(f"superiorize_step config0 path={path}", flush=True)
     plan, prob, x0 = fo.load_phantom(cfg0)
+    _set_path(fo, plan, path)
     q = _params(fo)
     st = fo.new_state()
     o = Oracle(cfg0)
@@ -230,8 +258,11 @@ def test_solve_config0_plan_quality(fo, cfg0):
     print("normwise x error", np.linalg.norm(xg - xr) / np.linalg.norm(xr), flush=True)
 
 
-def test_solve_deterministic_and_resumable(fo, cfg0):
+@pytest.mark.parametrize("path", ["csc", "scatter"])
+def test_solve_deterministic_and_resumable(fo, cfg0, path):
+    print(f"determinism config0 path={path}", flush=True)
     plan, prob, x0 = fo.load_phantom(cfg0)
+    _set_path(fo, plan, path)
     q = _params(fo, iter_max=20)
     xa = x0.clone()
     sa = fo.new_state()
@@ -337,3 +368,28 @@ def test_gradient_copy_follows_kind_changes(fo):
     xr, k, s, _ = Oracle(p, problem=arr).solve(p.x0, 3, _oparams(q))
     assert (st2.k, st2.s) == (k, s)
     assert np.linalg.norm(_np(x2) - xr) <= T2 * np.linalg.norm(xr)
+
+
+def test_scatter_and_csc_paths_agree(fo, cfg0):
+    """The two projection paths differ only by the rounding of the column sums."""
+    import torch
+    xs = {}
+    for path in ("csc", "scatter"):
+        plan, prob, x0 = fo.load_phantom(cfg0)
+        _set_path(fo, plan, path)
+        x = x0.clone()
+        st = fo.new_state()
+        for _ in range(3):
+            fo.superiorize_step(plan, prob, _params(fo), st, x)
+        xs[path] = (_np(x), (st.k, st.s))
+    assert xs["csc"][1] == xs["scatter"][1]
+    a, b = xs["csc"][0], xs["scatter"][0]
+    assert np.linalg.norm(a - b) <= 2e-6 * np.linalg.norm(a)
+
+
+def test_set_scatter_arguments(fo):
+    p = ph.tiny_problem(20, 5, 0.5, seed=4)
+    plan, _, _ = fo.load_phantom(p)
+    for bad in [(-2, -1), (257, -1), (0, -2)]:
+        with pytest.raises(fo.FredoptError):
+            fo.set_scatter(plan, *bad)
