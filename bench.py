@@ -33,7 +33,7 @@ KERNEL_SYMBOLS = {  # fredopt kernel id -> device symbol in profiler output (vt:
     "fwd_resid": "fo::k_forward<{vt}, 3, 0>", "tr_grad": "fo::k_tr_chunks<{vt}, 0>",
     "tr_proj": "fo::k_tr_chunks<{vt}, 1>", "rows": "fo::k_rows<1>", "col": "fo::k_tcol",
     "finalize": "fo::k_finalize", "active_list": "fo::k_active_list",
-    "scatter": "fo::k_scatter<{vt}>"}
+    "scatter": "fo::k_scatter<{vt}>", "scatter_sum": "fo::k_scatter_sum"}
 
 
 def log(msg: str):
@@ -73,19 +73,19 @@ def algorithmic_bytes(kernel: str, R: int, C: int, nnz: int, vb: int, n_tr_items
         return n_tr_items * 4 + C * 16
     if kernel == "rows":        # d, l, Dg, Lg in; d, l, coef out; problem data in
         return R * (16 + 8 + 8 + 2 + 20 + 4 + 24 + 12)
-    if kernel in ("finalize", "active_list", "scatter"):
+    if kernel in ("finalize", "active_list", "scatter", "scatter_sum"):
         return 0  # scalars; the active-row work depends on the iterate (not priced)
     raise KeyError(kernel)
 
 
 def make_workload(name: str):
     from paper_2509_20012_amd import phantom as ph
-    if name == "config1":
-        return ph.config1(progress=log)
-    if name == "config0":
-        return ph.config0()
-    if name.startswith("config1x"):
-        return ph.config1(scale=float(name[len("config1x"):]), progress=log)
+    if name == "clinical":
+        return ph.clinical(progress=log)
+    if name == "water32":
+        return ph.water32()
+    if name.startswith("clinical_x"):
+        return ph.clinical(scale=float(name[len("clinical_x"):]), progress=log)
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -116,7 +116,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="config1")
+    ap.add_argument("--workload", default="clinical",
+                    help="clinical (160x160x120 grid, 12k beamlets), water32 (32^3, 400 "
+                         "beamlets) or clinical_x<scale>")
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--reductions", type=int, default=1)
     ap.add_argument("--autotune", action="store_true")

@@ -238,7 +238,8 @@ fredopt_status fredopt_get_plan_info(const fredopt_plan *p, fredopt_plan_info *i
 #define FREDOPT_KERNEL_FINALIZE 7  /* plan scalars: step decision, weights          */
 #define FREDOPT_KERNEL_ACTIVE_LIST 8 /* list of rows with a projection coefficient  */
 #define FREDOPT_KERNEL_SCATTER 9   /* transposed product over those rows only       */
-#define FREDOPT_NUM_KERNELS 10
+#define FREDOPT_KERNEL_SCATTER_SUM 10 /* its per-workgroup sums; projection update  */
+#define FREDOPT_NUM_KERNELS 11
 
 /* Runs n_iters outer iterations (as fredopt_superiorize_step would) launching each
  * kernel separately with HIP events around it on `stream`, and writes the mean

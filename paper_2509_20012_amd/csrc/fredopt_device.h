@@ -108,11 +108,12 @@ struct SellView {
   const void* sdv;
   const void* slv;
   int32_t n_slices, n_groups;
+  int32_t lpr_log2, pad;      // lanes per row of this view (log2)
 };
 
 struct DevPlan {
   int64_t R, C;
-  int32_t vtype, lpr_log2;
+  int32_t vtype, lpr_log2;    // lanes per row (log2) of the all-row view
   int32_t n_row_items, n_col_blocks;
   SellView sell;              // every row
   SellView osell;             // rows with objective terms (per problem), for Eq. (2)
@@ -157,6 +158,7 @@ struct DevPlan {
   int32_t* goff;              // [groups] first list position of each group's rows
   ActRow* alist;              // [R] the active rows in slice order
   int64_t* spart;             // [n_scatter * C] per-workgroup fixed-point sums
+  uint64_t* smask;            // [n_scatter * ceil(C / 64)] which of them are written
   int32_t n_scatter, scatter_max_rows;  // workgroups; largest list that uses it
   DevParams prm;
   DevState* st;

@@ -22,6 +22,8 @@ void launch_active_list(const DevPlan* plans, const FwdGroup* groups, int n_grou
                         hipStream_t s);
 void launch_scatter(int vtype, const DevPlan* plans, int n_scatter, int C, hipStream_t s);
 hipError_t set_scatter_lds_limit(size_t bytes);
+// mode: the ColMode of the projection update (kColProj, kColProjMove, kColProjY)
+void launch_scatter_sum(int mode, const DevPlan* plans, int n_scatter, int C, hipStream_t s);
 
 // load kernels (kernels_load.hip)
 // flags bits: 1 column index out of range, 2 columns not strictly increasing,
@@ -57,7 +59,7 @@ void launch_obj_fill(int vtype, int64_t C, const int64_t* cp, const uint32_t* le
 // copies the objective rows' entries from the all-row sliced-ELL view into the
 // objective-row view: row obj_row[i] sits at slice position src_pos[i] of the full
 // view and dst_pos[i] of the objective view and has len[i] entries
-void launch_pack_sub(int vtype, int lpr_log2, int64_t n, const int32_t* src_pos,
+void launch_pack_sub(int vtype, int src_lg2, int dst_lg2, int64_t n, const int32_t* src_pos,
                      const int32_t* dst_pos, const int32_t* len, const int64_t* src_base,
                      const int32_t* src_ci, const void* src_dv, const void* src_lv,
                      const int64_t* dst_base, int32_t* dst_ci, void* dst_dv, void* dst_lv,

@@ -81,15 +81,42 @@ __device__ __forceinline__ float wave_sumf(float v) {
 }
 
 // Sum over a 256-thread block in a fixed order; every thread gets the result.
-__device__ __forceinline__ double block_sum(double v, double* sh4) {
+// Sum over a workgroup of NW waves (result in every thread; fixed order).
+template <int NW = kBlock / kWave>
+__device__ __forceinline__ double block_sum(double v, double* sh) {
   v = wave_sum(v);
   const int tid = threadIdx.x;
   __syncthreads();
-  if ((tid & (kWave - 1)) == 0) sh4[tid / kWave] = v;
+  if ((tid & (kWave - 1)) == 0) sh[tid / kWave] = v;
   __syncthreads();
-  const double r = (sh4[0] + sh4[1]) + (sh4[2] + sh4[3]);
+  double r = 0.0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) r += sh[w];
   __syncthreads();
   return r;
+}
+
+// Exclusive prefix sum over a workgroup of NW waves; *total gets the sum.
+template <int NW>
+__device__ __forceinline__ int block_scan(int v, int* sh, int* total) {
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  __syncthreads();
+  if (lane == kWave - 1) sh[wave] = x;
+  __syncthreads();
+  int before = 0, all = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    before += w < wave ? sh[w] : 0;
+    all += sh[w];
+  }
+  *total = all;
+  return before + x - v;
 }
 
 // ---------------------------------------------------------------- epilogues ----
@@ -282,7 +309,7 @@ __device__ __forceinline__ void forward_slice(const DevPlan* __restrict__ P, int
                                               const float* __restrict__ vec, int lane,
                                               double* wpart) {
   const SellView& V = SUB ? P->osell : P->sell;
-  const int lg2 = P->lpr_log2;
+  const int lg2 = uniform(V.lpr_log2);
   const int lpr = 1 << lg2;
   const int rpw = kWave >> lg2;
   const int pos = lane >> lg2;
@@ -611,8 +638,57 @@ __global__ __launch_bounds__(kScatterBlock) void k_scatter(const DevPlan* __rest
     }
   }
   __syncthreads();
+  // non-zero sums only, with a bit mask per 64 columns saying which were written
+  const int nwords = (C + kWave - 1) / kWave;
   FO_GLOBAL int64_t* out = gmut(P->spart) + (int64_t)blockIdx.x * C;
-  for (int j = tid; j < C; j += kScatterBlock) out[j] = (int64_t)facc[j];
+  FO_GLOBAL uint64_t* msk = gmut(P->smask) + (int64_t)blockIdx.x * nwords;
+  for (int w = wave; w < nwords; w += kScatterBlock / kWave) {
+    const int j = w * kWave + lane;
+    const int64_t v = j < C ? (int64_t)facc[j] : 0;
+    const uint64_t m = __ballot(v != 0);
+    if (v != 0) out[j] = v;
+    if (lane == 0) msk[w] = m;
+  }
+}
+
+// The projection update of column j (Fig. 2, last loop) from the transposed sum t
+// in stored units: x = max(0, y - scale t), with y = x, x - beta g or the perturbed
+// point, by MODE.
+template <int MODE>
+__device__ __forceinline__ void project_column(const DevPlan* __restrict__ P, int j, float t) {
+  if (P->cscale) t *= gconst(P->cscale)[j];
+  double y = MODE == kColProjY ? gconst(P->y)[j] : gconst(P->x)[j];
+  if constexpr (MODE == kColProjMove) y -= P->st->beta * (double)gconst(P->g)[j];
+  const double xn = y - P->st->scale * (double)t;
+  const float xf = xn > 0.0 ? (float)xn : 0.f;
+  gmut(P->x)[j] = xf;
+  if constexpr (MODE == kColProjY) gmut(P->y)[j] = xf;
+}
+
+// Sum of the scatter workgroups' shares for 64 columns (16 waves take every 16th
+// share; integer sums, so the grouping does not matter), then the update.
+template <int MODE>
+__global__ __launch_bounds__(kScatterBlock) void k_scatter_sum(const DevPlan* __restrict__ plans) {
+  __shared__ int64_t part[kScatterBlock / kWave][kWave];
+  const DevPlan* __restrict__ P = plans;
+  if (!P->st->proj_scatter) return;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+  const int C = (int)P->C, nwords = (C + kWave - 1) / kWave;
+  const int j = blockIdx.x * kWave + lane;
+  const FO_GLOBAL int64_t* sp = gconst(P->spart) + j;
+  const FO_GLOBAL uint64_t* mk = gconst(P->smask) + blockIdx.x;
+  int64_t S = 0;
+#pragma unroll 4
+  for (int w = wave; w < P->n_scatter; w += kScatterBlock / kWave) {
+    const uint64_t m = mk[(int64_t)w * nwords];
+    if ((m >> lane) & 1ull) S += sp[(int64_t)w * C];  // a set bit implies j < C
+  }
+  part[wave][lane] = S;
+  __syncthreads();
+  if (wave == 0) {
+    for (int v = 1; v < kScatterBlock / kWave; ++v) S += part[v][lane];
+    if (j < C) project_column<MODE>(P, j, (float)((double)S / P->st->fx_scale));
+  }
 }
 
 template <int MODE>
@@ -630,22 +706,13 @@ __global__ __launch_bounds__(kBlock) void k_tcol(const DevPlan* __restrict__ pla
     } else if constexpr (MODE == kColYMove) {
       const double b = P->st->beta;
       gmut(P->y)[j] = (float)((double)gconst(P->y)[j] - b * (double)gconst(P->g)[j]);
-    } else {
+    } else if (grad || !P->st->proj_scatter) {  // else the scatter sum updated x
       float t = 0.f;
-      if (!grad && P->st->proj_scatter) {
-        // fixed-point shares of the active-row scatter (exact integer sum)
-        const FO_GLOBAL int64_t* sp = gconst(P->spart) + j;
-        int64_t S = 0;
-#pragma unroll 8
-        for (int w = 0; w < P->n_scatter; ++w) S += sp[(int64_t)w * P->C];
-        t = (float)((double)S / P->st->fx_scale);
-      } else {
-        const int ts = grad ? gconst(P->gcol_tslot0)[j] : gconst(P->col_tslot0)[j];
-        const int n = grad ? gconst(P->gcol_nch)[j] : gconst(P->col_nch)[j];
-        for (int c = 0; c < n; ++c) t += gconst(P->tpart)[ts + c];
-      }
-      if (P->cscale) t *= gconst(P->cscale)[j];
+      const int ts = grad ? gconst(P->gcol_tslot0)[j] : gconst(P->col_tslot0)[j];
+      const int n = grad ? gconst(P->gcol_nch)[j] : gconst(P->col_nch)[j];
+      for (int c = 0; c < n; ++c) t += gconst(P->tpart)[ts + c];
       if constexpr (grad) {
+        if (P->cscale) t *= gconst(P->cscale)[j];
         if constexpr (MODE == kColGradMove) {
           const double b = P->st->beta;
           gmut(P->x)[j] = (float)((double)gconst(P->x)[j] - b * (double)gconst(P->g)[j]);
@@ -653,12 +720,7 @@ __global__ __launch_bounds__(kBlock) void k_tcol(const DevPlan* __restrict__ pla
         gmut(P->g)[j] = t;
         cv = (double)t * (double)t;
       } else {
-        double y = MODE == kColProjY ? gconst(P->y)[j] : gconst(P->x)[j];
-        if constexpr (MODE == kColProjMove) y -= P->st->beta * (double)gconst(P->g)[j];
-        const double xn = y - P->st->scale * (double)t;
-        const float xf = xn > 0.0 ? (float)xn : 0.f;
-        gmut(P->x)[j] = xf;
-        if constexpr (MODE == kColProjY) gmut(P->y)[j] = xf;
+        project_column<MODE>(P, j, t);
       }
     }
   }
@@ -670,26 +732,31 @@ __global__ __launch_bounds__(kBlock) void k_tcol(const DevPlan* __restrict__ pla
 
 // ------------------------------------------------------------ finalisation ----
 
+constexpr int kFinBlock = 1024;  // finalisation: one workgroup of 16 waves per plan
+constexpr int kFinWaves = kFinBlock / kWave;
+
 __device__ __forceinline__ void sum_slots(const double* part_, int n, double* out,
-                                          unsigned used, double* sh4) {
+                                          unsigned used, double* sh) {
   const FO_GLOBAL double* part = gconst(part_);
   double s[kNPart];
 #pragma unroll
   for (int k = 0; k < kNPart; ++k) s[k] = 0.0;
-  for (int i = threadIdx.x; i < n; i += kBlock) {
+#pragma unroll 4
+  for (int i = threadIdx.x; i < n; i += kFinBlock) {
     const FO_GLOBAL double* p = part + (int64_t)i * kNPart;
 #pragma unroll
     for (int k = 0; k < kNPart; ++k)
       if (used & (1u << k)) s[k] += p[k];
   }
 #pragma unroll
-  for (int k = 0; k < kNPart; ++k) out[k] = (used & (1u << k)) ? block_sum(s[k], sh4) : 0.0;
+  for (int k = 0; k < kNPart; ++k)
+    out[k] = (used & (1u << k)) ? block_sum<kFinWaves>(s[k], sh) : 0.0;
 }
 
 // SUB: the objective and direction partials come from the objective-row view.
 template <int MODE, int SUB>
-__global__ __launch_bounds__(kBlock) void k_finalize(const DevPlan* __restrict__ plans) {
-  __shared__ double sh4[kBlock / kWave];
+__global__ __launch_bounds__(kFinBlock) void k_finalize(const DevPlan* __restrict__ plans) {
+  __shared__ double sh4[kFinWaves];
   const DevPlan* __restrict__ P = plans + blockIdx.x;
   const int ng = SUB ? P->osell.n_groups : P->sell.n_groups;
   double a[kNPart];
@@ -697,8 +764,8 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const DevPlan* __restrict__
     double b[kNPart];
     sum_slots(P->spart_b, ng, b, 0x21u, sh4);
     double g = 0.0;
-    for (int i = threadIdx.x; i < P->n_col_blocks; i += kBlock) g += gconst(P->gpart)[i];
-    const double G = block_sum(g, sh4);
+    for (int i = threadIdx.x; i < P->n_col_blocks; i += kFinBlock) g += gconst(P->gpart)[i];
+    const double G = block_sum<kFinWaves>(g, sh4);
     if constexpr (MODE == kFinDir0) sum_slots(P->spart_a, ng, a, 0x21u, sh4);
     if (threadIdx.x == 0) {
       DevState* st = P->st;
@@ -735,23 +802,16 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const DevPlan* __restrict__
     const bool scatter = P->n_scatter > 0 && A <= P->scatter_max_rows && B < 1e300;
     if (scatter) {
       // exclusive scan of the groups' active-row counts (list offsets), in group order
-      __shared__ int sc[kBlock];
+      __shared__ int sc[kFinWaves];
       int carry = 0;
       const FO_GLOBAL double* part = gconst(P->spart_a);
-      for (int g0 = 0; g0 < P->sell.n_groups; g0 += kBlock) {
+      for (int g0 = 0; g0 < P->sell.n_groups; g0 += kFinBlock) {
         const int g = g0 + threadIdx.x;
         const int v = g < P->sell.n_groups ? (int)part[(int64_t)g * kNPart + 7] : 0;
-        sc[threadIdx.x] = v;
-        __syncthreads();
-        for (int o = 1; o < kBlock; o <<= 1) {
-          const int add = threadIdx.x >= o ? sc[threadIdx.x - o] : 0;
-          __syncthreads();
-          sc[threadIdx.x] += add;
-          __syncthreads();
-        }
-        if (g < P->sell.n_groups) gmut(P->goff)[g] = carry + sc[threadIdx.x] - v;
-        carry += sc[kBlock - 1];
-        __syncthreads();
+        int total;
+        const int ex = block_scan<kFinWaves>(v, sc, &total);
+        if (g < P->sell.n_groups) gmut(P->goff)[g] = carry + ex;
+        carry += total;
       }
     }
     if (threadIdx.x == 0) {
@@ -852,6 +912,17 @@ void launch_scatter(int vtype, const DevPlan* plans, int n_scatter, int C, hipSt
     k_scatter<kF32><<<n_scatter, kScatterBlock, lds, s>>>(plans);
 }
 
+void launch_scatter_sum(int mode, const DevPlan* plans, int n_scatter, int C, hipStream_t s) {
+  if (n_scatter <= 0) return;
+  const int nb = (C + kWave - 1) / kWave;
+  if (mode == kColProjY)
+    k_scatter_sum<kColProjY><<<nb, kScatterBlock, 0, s>>>(plans);
+  else if (mode == kColProjMove)
+    k_scatter_sum<kColProjMove><<<nb, kScatterBlock, 0, s>>>(plans);
+  else
+    k_scatter_sum<kColProj><<<nb, kScatterBlock, 0, s>>>(plans);
+}
+
 hipError_t set_scatter_lds_limit(size_t bytes) {
   hipError_t e = hipSuccess;
   for (const void* f : {(const void*)k_scatter<kF32>, (const void*)k_scatter<kF16>,
@@ -879,16 +950,16 @@ void launch_tcol(int mode, const DevPlan* plans, const ColBlock* blocks, int n_b
 void launch_finalize(int mode, int sub, const DevPlan* plans, int n_plans, hipStream_t s) {
   switch (mode) {
     case kFinDir0:
-      if (sub) k_finalize<kFinDir0, 1><<<n_plans, kBlock, 0, s>>>(plans);
-      else k_finalize<kFinDir0, 0><<<n_plans, kBlock, 0, s>>>(plans);
+      if (sub) k_finalize<kFinDir0, 1><<<n_plans, kFinBlock, 0, s>>>(plans);
+      else k_finalize<kFinDir0, 0><<<n_plans, kFinBlock, 0, s>>>(plans);
       break;
     case kFinDir:
-      if (sub) k_finalize<kFinDir, 1><<<n_plans, kBlock, 0, s>>>(plans);
-      else k_finalize<kFinDir, 0><<<n_plans, kBlock, 0, s>>>(plans);
+      if (sub) k_finalize<kFinDir, 1><<<n_plans, kFinBlock, 0, s>>>(plans);
+      else k_finalize<kFinDir, 0><<<n_plans, kFinBlock, 0, s>>>(plans);
       break;
-    case kFinMoveObj: k_finalize<kFinMoveObj, 0><<<n_plans, kBlock, 0, s>>>(plans); break;
-    case kFinResidRows: k_finalize<kFinResidRows, 0><<<n_plans, kBlock, 0, s>>>(plans); break;
-    default: k_finalize<kFinResidFwd, 0><<<n_plans, kBlock, 0, s>>>(plans); break;
+    case kFinMoveObj: k_finalize<kFinMoveObj, 0><<<n_plans, kFinBlock, 0, s>>>(plans); break;
+    case kFinResidRows: k_finalize<kFinResidRows, 0><<<n_plans, kFinBlock, 0, s>>>(plans); break;
+    default: k_finalize<kFinResidFwd, 0><<<n_plans, kFinBlock, 0, s>>>(plans); break;
   }
 }
 

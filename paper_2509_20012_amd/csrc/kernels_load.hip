@@ -323,7 +323,7 @@ __global__ __launch_bounds__(kBlock) void k_obj_fill(int vtype, int64_t C,
 // Objective-row view: every listed row is copied by one wavefront from its slice
 // position in the all-row view to its position in the objective-row view (values
 // as stored).  Unreached slots keep the zero fill.
-__global__ __launch_bounds__(kBlock) void k_pack_sub(int vtype, int lpr_log2, int64_t n,
+__global__ __launch_bounds__(kBlock) void k_pack_sub(int vtype, int src_lg2, int dst_lg2, int64_t n,
                                                      const int32_t* __restrict__ src_pos,
                                                      const int32_t* __restrict__ dst_pos,
                                                      const int32_t* __restrict__ len,
@@ -337,15 +337,16 @@ __global__ __launch_bounds__(kBlock) void k_pack_sub(int vtype, int lpr_log2, in
   const int64_t i = (int64_t)blockIdx.x * kRowsPerWg + threadIdx.x / kWave;
   const int lane = threadIdx.x % kWave;
   if (i >= n) return;
-  const int rpw_log2 = 6 - lpr_log2;
-  const int lpr = 1 << lpr_log2;
+  // the two views may spread a row over different lane counts
+  const int srpw = 6 - src_lg2, drpw = 6 - dst_lg2;
+  const int slpr = 1 << src_lg2, dlpr = 1 << dst_lg2;
   const int sp = src_pos[i], dp = dst_pos[i];
-  const int64_t sb = src_base[sp >> rpw_log2], db = dst_base[dp >> rpw_log2];
-  const int64_t spp = sp & ((1 << rpw_log2) - 1), dpp = dp & ((1 << rpw_log2) - 1);
+  const int64_t sb = src_base[sp >> srpw], db = dst_base[dp >> drpw];
+  const int64_t spp = sp & ((1 << srpw) - 1), dpp = dp & ((1 << drpw) - 1);
   for (int64_t e = lane; e < len[i]; e += kWave) {
-    const int64_t quad = e >> 2, t = quad >> lpr_log2, j = quad & (lpr - 1);
-    const int64_t os = sb + t * 256 + (spp * lpr + j) * 4 + (e & 3);
-    const int64_t od = db + t * 256 + (dpp * lpr + j) * 4 + (e & 3);
+    const int64_t quad = e >> 2;
+    const int64_t os = sb + (quad >> src_lg2) * 256 + (spp * slpr + (quad & (slpr - 1))) * 4 + (e & 3);
+    const int64_t od = db + (quad >> dst_lg2) * 256 + (dpp * dlpr + (quad & (dlpr - 1))) * 4 + (e & 3);
     dst_ci[od] = src_ci[os];
     if (vtype == kF32) {
       static_cast<float*>(dst_dv)[od] = static_cast<const float*>(src_dv)[os];
@@ -428,13 +429,13 @@ void launch_obj_fill(int vtype, int64_t C, const int64_t* cp, const uint32_t* le
                                                ocdv, oclv);
 }
 
-void launch_pack_sub(int vtype, int lpr_log2, int64_t n, const int32_t* src_pos,
+void launch_pack_sub(int vtype, int src_lg2, int dst_lg2, int64_t n, const int32_t* src_pos,
                      const int32_t* dst_pos, const int32_t* len, const int64_t* src_base,
                      const int32_t* src_ci, const void* src_dv, const void* src_lv,
                      const int64_t* dst_base, int32_t* dst_ci, void* dst_dv, void* dst_lv,
                      hipStream_t s) {
   if (n > 0)
-    k_pack_sub<<<row_grid(n), kBlock, 0, s>>>(vtype, lpr_log2, n, src_pos, dst_pos, len, src_base,
+    k_pack_sub<<<row_grid(n), kBlock, 0, s>>>(vtype, src_lg2, dst_lg2, n, src_pos, dst_pos, len, src_base,
                                                src_ci, src_dv, src_lv, dst_base, dst_ci, dst_dv,
                                                dst_lv);
 }

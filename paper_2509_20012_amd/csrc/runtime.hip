@@ -136,9 +136,9 @@ struct Layout {
   size_t gri, gcdv, gclv, gcol_tslot0, gcol_nch, ocp, ocount, gtr_items;
   size_t y, osbase, oswidth, osrow, osci, osdv, oslv, ogroups, pk_src, pk_dst, pk_len;
   size_t spart_a, spart_b, rpart, gpart, tpart, groups, row_items, tr_items, col_blocks;
-  size_t bc, colcount, colmax, flags, rslice, rsum, goff, alist, spart, total;
+  size_t bc, colcount, colmax, flags, rslice, rsum, goff, alist, spart, smask, total;
   int64_t sell_slots, n_slices, csc_slots, obj_slots, max_rows, max_tr, n_groups, n_col_blocks;
-  int64_t obj_sell_slots, max_obj_slices, max_obj_groups;
+  int64_t obj_sell_slots, max_obj_slices, max_obj_groups, max_obj_srow;
   int64_t rows_per_block, nb;
 };
 
@@ -161,7 +161,8 @@ bool make_layout(int64_t R, int64_t C, int64_t nnz, int storage, int lpr_log2,
   L->csc_slots = csc;
   L->obj_slots = ((csc * reserve_pct) / 100 + 3) & ~int64_t(3);
   L->obj_sell_slots = reserve_pct > 0 ? (((sell_slots * reserve_pct) / 100 + 255) & ~int64_t(255)) : 0;
-  L->max_obj_slices = reserve_pct > 0 ? R / rpw + R / kSortWindow + 2 : 0;
+  // the objective-row view may use up to 16 lanes per row (4 rows per slice)
+  L->max_obj_slices = reserve_pct > 0 ? R / 4 + R / kSortWindow + 2 : 0;
   L->max_obj_groups = (L->max_obj_slices + kFwdWaves - 1) / kFwdWaves + 1;
   L->max_rows = R / kRowItemRows + 2;
   L->max_tr = C + csc / kTrChunkMin + 2;
@@ -204,7 +205,8 @@ bool make_layout(int64_t R, int64_t C, int64_t nnz, int storage, int lpr_log2,
   L->y = take(sizeof(float) * C);
   L->osbase = take(sizeof(int64_t) * (L->max_obj_slices + 1));
   L->oswidth = take(sizeof(int32_t) * (L->max_obj_slices + 1));
-  L->osrow = take(sizeof(int32_t) * (L->max_obj_slices * rpw + 1));
+  L->max_obj_srow = reserve_pct > 0 ? R + (R / kSortWindow + 2) * kWave + 1 : 1;
+  L->osrow = take(sizeof(int32_t) * L->max_obj_srow);
   L->osci = take(sizeof(int32_t) * L->obj_sell_slots);
   L->osdv = take((size_t)vb * L->obj_sell_slots);
   L->oslv = take((size_t)vb * L->obj_sell_slots);
@@ -238,6 +240,8 @@ bool make_layout(int64_t R, int64_t C, int64_t nnz, int storage, int lpr_log2,
   L->goff = take(sizeof(int32_t) * L->n_groups);
   L->alist = take(sizeof(ActRow) * Rm);
   L->spart = take(scatter_fits(C) ? sizeof(int64_t) * kScatterMaxWGs * C : sizeof(int64_t));
+  L->smask = take(scatter_fits(C) ? sizeof(uint64_t) * kScatterMaxWGs * ((C + 63) / 64)
+                                  : sizeof(uint64_t));
   L->total = o;
   return true;
 }
@@ -553,10 +557,24 @@ fredopt_status prepare_objective_view(fredopt_plan* p, const fredopt_problem* pr
     if (kind[i] & (FREDOPT_OBJ_DOSE | FREDOPT_OBJ_CDL)) rows.push_back((int32_t)i);
   const int64_t n = (int64_t)rows.size();
   Sell& O = p->osell;
-  build_sell_list(n, [&](int64_t i) { return (int64_t)rows[i]; },
-                  [&](int64_t i) { return (int64_t)p->row_len[rows[i]]; }, p->sell.lpr_log2, true,
-                  &O);
-  if (O.slots > L.obj_sell_slots || O.n_slices > L.max_obj_slices) return FREDOPT_OK;
+  // more lanes per row than the all-row view when that leaves too few workgroups,
+  // as long as every lane still gets 4 quads of an average row
+  int64_t obj_nnz = 0;
+  for (int64_t i = 0; i < n; ++i) obj_nnz += p->row_len[rows[i]];
+  int olg = p->sell.lpr_log2;
+  while (olg < 4 && n / ((kWave >> olg) * kFwdWaves) < 2 * (int64_t)p->n_cu &&
+         (int64_t(16) << (olg + 1)) * n <= obj_nnz)
+    ++olg;
+  auto fits = [&]() {
+    return O.slots <= L.obj_sell_slots && O.n_slices <= L.max_obj_slices &&
+           (int64_t)O.srow.size() <= L.max_obj_srow;
+  };
+  for (;; --olg) {
+    build_sell_list(n, [&](int64_t i) { return (int64_t)rows[i]; },
+                    [&](int64_t i) { return (int64_t)p->row_len[rows[i]]; }, olg, true, &O);
+    if (fits()) break;
+    if (olg == p->sell.lpr_log2) return FREDOPT_OK;  // the all-row view serves instead
+  }
   build_groups(O.n_slices, &p->ogroups);
   if ((int64_t)p->ogroups.size() > L.max_obj_groups) return FREDOPT_OK;
   std::vector<int32_t> src(n), len(n);
@@ -584,7 +602,7 @@ fredopt_status prepare_objective_view(fredopt_plan* p, const fredopt_problem* pr
   HIPCHK(hipMemsetAsync(p->ws + L.osci, 0, sizeof(int32_t) * O.slots, s));
   HIPCHK(hipMemsetAsync(p->ws + L.osdv, 0, (size_t)vb * O.slots, s));
   HIPCHK(hipMemsetAsync(p->ws + L.oslv, 0, (size_t)vb * O.slots, s));
-  launch_pack_sub(p->storage, p->sell.lpr_log2, n, at<int32_t>(p, L.pk_src),
+  launch_pack_sub(p->storage, p->sell.lpr_log2, olg, n, at<int32_t>(p, L.pk_src),
                   at<int32_t>(p, L.pk_dst), at<int32_t>(p, L.pk_len), h.sell.sbase, h.sell.sci,
                   h.sell.sdv, h.sell.slv, at<int64_t>(p, L.osbase), at<int32_t>(p, L.osci),
                   p->ws + L.osdv, p->ws + L.oslv, s);
@@ -598,6 +616,7 @@ fredopt_status prepare_objective_view(fredopt_plan* p, const fredopt_problem* pr
   h.osell.slv = p->ws + L.oslv;
   h.osell.n_slices = (int32_t)O.n_slices;
   h.osell.n_groups = (int32_t)p->ogroups.size();
+  h.osell.lpr_log2 = olg;
   p->sched_obj = true;
   drop_graph(p);
   return FREDOPT_OK;
@@ -638,7 +657,9 @@ void export_state(const DevState& d, fredopt_state* st) {
   st->q = d.Q;
 }
 
-enum Kind { kKindFwd, kKindRows, kKindChunks, kKindCol, kKindFin, kKindList, kKindScatter };
+enum Kind {
+  kKindFwd, kKindRows, kKindChunks, kKindCol, kKindFin, kKindList, kKindScatter, kKindScatterSum
+};
 
 struct Launch {
   int id;        // FREDOPT_KERNEL_*
@@ -662,6 +683,7 @@ std::vector<Launch> iteration_sequence(int r, bool obj) {
     seq.push_back({FREDOPT_KERNEL_FINALIZE, kKindFin, kFinResidFwd});
     seq.push_back({FREDOPT_KERNEL_ACTIVE_LIST, kKindList, 0});
     seq.push_back({FREDOPT_KERNEL_SCATTER, kKindScatter, 0});
+    seq.push_back({FREDOPT_KERNEL_SCATTER_SUM, kKindScatterSum, kColProj});
     seq.push_back({FREDOPT_KERNEL_TR_PROJ, kKindChunks, 1});
     seq.push_back({FREDOPT_KERNEL_COL, kKindCol, kColProj});
     return seq;
@@ -679,6 +701,7 @@ std::vector<Launch> iteration_sequence(int r, bool obj) {
     seq.push_back({FREDOPT_KERNEL_FINALIZE, kKindFin, kFinResidFwd});
     seq.push_back({FREDOPT_KERNEL_ACTIVE_LIST, kKindList, 0});
     seq.push_back({FREDOPT_KERNEL_SCATTER, kKindScatter, 0});
+    seq.push_back({FREDOPT_KERNEL_SCATTER_SUM, kKindScatterSum, kColProjY});
     seq.push_back({FREDOPT_KERNEL_TR_PROJ, kKindChunks, 1});
     seq.push_back({FREDOPT_KERNEL_COL, kKindCol, kColProjY});
     return seq;
@@ -726,6 +749,9 @@ void enqueue(fredopt_plan* p, const Launch& l, hipStream_t s) {
       break;
     case kKindScatter:
       if (p->n_scatter > 0) launch_scatter(p->storage, p->d_table, p->n_scatter, (int)p->C, s);
+      break;
+    case kKindScatterSum:
+      if (p->n_scatter > 0) launch_scatter_sum(l.mode, p->d_table, p->n_scatter, (int)p->C, s);
       break;
     default:
       launch_finalize(l.mode, l.sub, p->d_table, 1, s);
@@ -1034,6 +1060,7 @@ fredopt_status fredopt_load_matrices(const fredopt_matrices* m, void* workspace,
   h.C = C;
   h.vtype = m->storage;
   h.lpr_log2 = S.lpr_log2;
+  h.sell.lpr_log2 = S.lpr_log2;
   h.n_row_items = (int32_t)p->rows.size();
   h.n_col_blocks = (int32_t)p->cblocks.size();
   h.sell.n_slices = (int32_t)S.n_slices;
@@ -1073,6 +1100,7 @@ fredopt_status fredopt_load_matrices(const fredopt_matrices* m, void* workspace,
   h.goff = reinterpret_cast<int32_t*>(ws + L.goff);
   h.alist = reinterpret_cast<ActRow*>(ws + L.alist);
   h.spart = reinterpret_cast<int64_t*>(ws + L.spart);
+  h.smask = reinterpret_cast<uint64_t*>(ws + L.smask);
   h.n_scatter = p->n_scatter;
   h.scatter_max_rows = (int32_t)std::min<int64_t>(p->scatter_max_rows, INT32_MAX);
   h.st = p->d_state;

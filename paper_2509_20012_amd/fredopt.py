@@ -21,7 +21,7 @@ F32, F16, BF16 = 0, 1, 2
 STORAGE = {"f32": F32, "fp32": F32, "f16": F16, "fp16": F16, "bf16": BF16}
 NORM_CONVEX_ALL, NORM_CONVEX_VIOLATED, NORM_RAW = 0, 1, 2
 KERNEL_NAMES = ("fwd_obj", "tr_grad", "fwd_dir", "rows", "tr_proj", "fwd_resid", "col",
-                "finalize", "active_list", "scatter")
+                "finalize", "active_list", "scatter", "scatter_sum")
 
 STATUS = {0: "OK", -1: "E_ARG", -2: "E_SHAPE", -3: "E_INDEX", -4: "E_NONFINITE",
           -5: "E_WORKSPACE", -6: "E_DEVICE", -7: "E_STATE", -8: "E_NOT_IMPLEMENTED"}

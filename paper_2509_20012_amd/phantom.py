@@ -374,7 +374,7 @@ def _finish(name, shape, h_mm, kept, row_ptr, col, d_raw, let, C, masks, bounds,
                    meta=meta, **p)
 
 
-def config0(seed: int = 0) -> Phantom:
+def water32(seed: int = 0) -> Phantom:
     """Tiny phantom: 32^3 water grid at 3 mm, all voxels kept; two opposed fields
     along +-x with a 20 x 10 spot grid each (400 beamlets); sigma 1.5 voxels cut at
     3 sigma; ranges U[30, 80] mm; spherical PTV (r = 8 voxels, centre) bounded to
@@ -397,11 +397,11 @@ def config0(seed: int = 0) -> Phantom:
     masks = {"PTV": ptv, "OAR_cyl": oar & ~ptv}
     bounds = {"ptv_lo": 1.9, "ptv_hi": 2.14, "rx": 2.0, "oar_dose_hi": 1.0,
               "oar_letd_max": 2.0}
-    return _finish("config0_tiny_32cube", shape, h, kept, row_ptr, col, d_raw, let, C,
+    return _finish("water32_400beamlets", shape, h, kept, row_ptr, col, d_raw, let, C,
                    masks, bounds, seed, {"iterations": 100, "sigma_mm": sigma})
 
 
-def config1(seed: int = 1, progress: Optional[Callable[[str], None]] = None,
+def clinical(seed: int = 1, progress: Optional[Callable[[str], None]] = None,
             scale: float = 1.0) -> Phantom:
     """Clinical-scale phantom: 160 x 160 x 120 grid at 2 mm; three coplanar fields
     (0, 120, 240 degrees) with an 80 x 50 spot grid each (12,000 beamlets); ranges
@@ -437,7 +437,7 @@ def config1(seed: int = 1, progress: Optional[Callable[[str], None]] = None,
     masks = {"PTV": ptv, "OAR_brainstem": brainstem & ~ptv, "OAR_chiasm": chiasm & ~ptv & ~brainstem}
     bounds = {"ptv_lo": 1.9, "ptv_hi": 2.14, "rx": 2.0, "oar_dose_hi": 1.0,
               "oar_letd_max": 2.0, "normal_dose_hi": 2.14}
-    return _finish("config1_clinical_160x160x120" if scale == 1.0 else f"config1_scaled_{scale:g}",
+    return _finish("clinical_160x160x120_12k" if scale == 1.0 else f"clinical_scaled_{scale:g}",
                    shape, h, kept, row_ptr, col, d_raw, let, C, masks, bounds, seed,
                    {"iterations": 1000, "sigma_mm": sigma})
 
@@ -445,7 +445,7 @@ def config1(seed: int = 1, progress: Optional[Callable[[str], None]] = None,
 def small_plan(seed: int, n_rows_target: int, n_cols_target: int) -> Phantom:
     """One plan of the batched workload: a cubic water grid holding about
     n_rows_target voxels (all kept), two opposed fields with n_cols_target/2 spots
-    each, config-0 density (sigma 1.5 voxels, 3 mm voxels, ranges spanning 30-90 %
+    each, the density of the 32^3 water phantom (sigma 1.5 voxels, 3 mm voxels, ranges spanning 30-90 %
     of the grid depth)."""
     rng = np.random.default_rng(seed)
     n = max(8, int(round(n_rows_target ** (1.0 / 3.0))))

@@ -32,8 +32,8 @@ def fo():
 
 
 @pytest.fixture(scope="module")
-def cfg0():
-    return ph.config0()
+def w32():
+    return ph.water32()
 
 
 def _np(t):
@@ -100,13 +100,13 @@ def test_dose_let_every_layout_width(fo, lpr):
     assert np.all(_np(dose)[np.diff(p.row_ptr) == 0] == 0.0)
 
 
-def test_dose_let_config0(fo, cfg0):
+def test_dose_let_water32(fo, w32):
     import torch
-    plan, prob, x0 = fo.load_phantom(cfg0)
-    x = np.random.default_rng(0).uniform(0.0, 2.0, cfg0.n_cols).astype(np.float32)
-    dose, letd, cdl = fo.dose_let(plan, torch.from_numpy(x).cuda(), cfg0.c)
+    plan, prob, x0 = fo.load_phantom(w32)
+    x = np.random.default_rng(0).uniform(0.0, 2.0, w32.n_cols).astype(np.float32)
+    dose, letd, cdl = fo.dose_let(plan, torch.from_numpy(x).cuda(), w32.c)
     torch.cuda.synchronize()
-    d_ref, l_ref, letd_ref, cdl_ref = Oracle(cfg0).dose_let(x)
+    d_ref, l_ref, letd_ref, cdl_ref = Oracle(w32).dose_let(x)
     assert _rel_rows(_np(dose), d_ref) <= T1
     assert _rel_rows(_np(letd), letd_ref, d_ref > 0) <= T1
     assert _rel_rows(_np(cdl), cdl_ref) <= T1
@@ -115,12 +115,12 @@ def test_dose_let_config0(fo, cfg0):
     assert lg.min() >= 0.5 * (1 - 1e-6) and lg.max() <= 10.0 * (1 + 1e-6)
 
 
-def test_dose_linearity_gpu(fo, cfg0):
+def test_dose_linearity_gpu(fo, w32):
     import torch
-    plan, _, _ = fo.load_phantom(cfg0)
+    plan, _, _ = fo.load_phantom(w32)
     rng = np.random.default_rng(1)
-    x1 = rng.uniform(0, 1, cfg0.n_cols).astype(np.float32)
-    x2 = rng.uniform(0, 1, cfg0.n_cols).astype(np.float32)
+    x1 = rng.uniform(0, 1, w32.n_cols).astype(np.float32)
+    x2 = rng.uniform(0, 1, w32.n_cols).astype(np.float32)
     d1 = _np(fo.dose_let(plan, torch.from_numpy(x1).cuda(), want=("dose",))[0])
     d2 = _np(fo.dose_let(plan, torch.from_numpy(x2).cuda(), want=("dose",))[0])
     d12 = _np(fo.dose_let(plan, torch.from_numpy(x1 + x2).cuda(), want=("dose",))[0])
@@ -166,15 +166,15 @@ def test_project_sweep_tiny(fo, norm, seed, path):
 
 
 @pytest.mark.parametrize("path", ["csc", "scatter", "auto"])
-def test_project_sweep_config0(fo, cfg0, path):
+def test_project_sweep_water32(fo, w32, path):
     import torch
-    print(f"project_sweep config0 path={path}", flush=True)
-    plan, prob, x0 = fo.load_phantom(cfg0)
+    print(f"project_sweep water32 path={path}", flush=True)
+    plan, prob, x0 = fo.load_phantom(w32)
     _set_path(fo, plan, path)
     q = _params(fo)
-    o = Oracle(cfg0)
+    o = Oracle(w32)
     x = x0.clone()
-    xr = cfg0.x0.astype(np.float64)
+    xr = w32.x0.astype(np.float64)
     for it in range(3):
         prox = fo.project_sweep(plan, prob, q, x, weight_scale=0.999 ** it)
         xr, prox_ref, nv = o.ams_simultaneous(xr, lam=1.0, weight_scale=0.999 ** it,
@@ -215,15 +215,15 @@ def test_superiorize_step_tiny(fo, r, lpr, reserve, path):
 
 
 @pytest.mark.parametrize("path", ["csc", "scatter", "auto"])
-def test_superiorize_step_config0(fo, cfg0, path):
-    print(f"superiorize_step config0 path={path}", flush=True)
-    plan, prob, x0 = fo.load_phantom(cfg0)
+def test_superiorize_step_water32(fo, w32, path):
+    print(f"superiorize_step water32 path={path}", flush=True)
+    plan, prob, x0 = fo.load_phantom(w32)
     _set_path(fo, plan, path)
     q = _params(fo)
     st = fo.new_state()
-    o = Oracle(cfg0)
+    o = Oracle(w32)
     x = x0.clone()
-    xr = cfg0.x0.astype(np.float64)
+    xr = w32.x0.astype(np.float64)
     k, s = 0, -1
     for it in range(3):
         fo.superiorize_step(plan, prob, q, st, x)
@@ -235,22 +235,22 @@ def test_superiorize_step_config0(fo, cfg0, path):
         assert st.grad_sq == pytest.approx(info["grad_sq"], rel=1e-4)
 
 
-def test_solve_config0_plan_quality(fo, cfg0):
+def test_solve_water32_plan_quality(fo, w32):
     """T3: 100 superiorized iterations on the 32^3 phantom."""
     import torch
-    plan, prob, x0 = fo.load_phantom(cfg0)
+    plan, prob, x0 = fo.load_phantom(w32)
     q = _params(fo, iter_max=100)
     st = fo.new_state()
     x = x0.clone()
     fo.solve(plan, prob, q, st, x)
-    xr, k, s, info = Oracle(cfg0).solve(cfg0.x0, 100, _oparams(q))
+    xr, k, s, info = Oracle(w32).solve(w32.x0, 100, _oparams(q))
     assert st.k == k == 100
     print(f"gpu s={st.s} oracle s={s} cost={st.cost:.6g}/{info['cost_before']:.6g}", flush=True)
-    dose, letd, _ = fo.dose_let(plan, x, cfg0.c)
+    dose, letd, _ = fo.dose_let(plan, x, w32.c)
     torch.cuda.synchronize()
-    d_ref, _, letd_ref, _ = Oracle(cfg0).dose_let(xr)
-    rg = metrics.plan_report(_np(dose), _np(letd), cfg0.roi)
-    rr = metrics.plan_report(d_ref, letd_ref, cfg0.roi)
+    d_ref, _, letd_ref, _ = Oracle(w32).dose_let(xr)
+    rg = metrics.plan_report(_np(dose), _np(letd), w32.roi)
+    rr = metrics.plan_report(d_ref, letd_ref, w32.roi)
     print("gpu", rg, "\noracle", rr, flush=True)
     assert rg["PTV_D95"] == pytest.approx(rr["PTV_D95"], rel=T3)
     assert rg["OAR_cyl_mean_LETd"] == pytest.approx(rr["OAR_cyl_mean_LETd"], rel=T3)
@@ -259,9 +259,9 @@ def test_solve_config0_plan_quality(fo, cfg0):
 
 
 @pytest.mark.parametrize("path", ["csc", "scatter"])
-def test_solve_deterministic_and_resumable(fo, cfg0, path):
-    print(f"determinism config0 path={path}", flush=True)
-    plan, prob, x0 = fo.load_phantom(cfg0)
+def test_solve_deterministic_and_resumable(fo, w32, path):
+    print(f"determinism water32 path={path}", flush=True)
+    plan, prob, x0 = fo.load_phantom(w32)
     _set_path(fo, plan, path)
     q = _params(fo, iter_max=20)
     xa = x0.clone()
@@ -370,12 +370,12 @@ def test_gradient_copy_follows_kind_changes(fo):
     assert np.linalg.norm(_np(x2) - xr) <= T2 * np.linalg.norm(xr)
 
 
-def test_scatter_and_csc_paths_agree(fo, cfg0):
+def test_scatter_and_csc_paths_agree(fo, w32):
     """The two projection paths differ only by the rounding of the column sums."""
     import torch
     xs = {}
     for path in ("csc", "scatter"):
-        plan, prob, x0 = fo.load_phantom(cfg0)
+        plan, prob, x0 = fo.load_phantom(w32)
         _set_path(fo, plan, path)
         x = x0.clone()
         st = fo.new_state()
