@@ -223,6 +223,8 @@ typedef struct {
                        outer iteration), 0: two all-row forward products */
   int32_t scatter_wgs;      /* workgroups of the active-row projection (0: off)  */
   int64_t scatter_max_rows; /* largest active-row count that takes that path     */
+  int32_t obj_lanes_per_row; /* lanes per row of the objective-row view (0: unused) */
+  int32_t fwd_schedule;      /* all-row forward: 1 groups from a counter, 2 round robin */
 } fredopt_plan_info;
 
 fredopt_status fredopt_get_plan_info(const fredopt_plan *p, fredopt_plan_info *info);
@@ -256,9 +258,12 @@ fredopt_status fredopt_profile_kernels(fredopt_plan *p, const fredopt_problem *p
  * and keeps the fastest.  Synchronises `stream`. */
 fredopt_status fredopt_autotune(fredopt_plan *p, const float *x, void *stream);
 
-/* Sets the forward workgroups per CU (1..8, capped by LDS) and the transposed chunk
- * size (slots per work item, a multiple of 256); 0 keeps the current value. */
-fredopt_status fredopt_set_tuning(fredopt_plan *p, int32_t fwd_wgs_per_cu, int32_t tr_chunk);
+/* Sets the forward workgroups per CU (1..8, capped by LDS), the transposed chunk
+ * size (slots per work item, a multiple of 256) and how the all-row forward pass
+ * hands out its slice groups (1: from a counter, 2: round robin); 0 keeps the
+ * current value. */
+fredopt_status fredopt_set_tuning(fredopt_plan *p, int32_t fwd_wgs_per_cu, int32_t tr_chunk,
+                                  int32_t fwd_schedule);
 
 /* The projection of Fig. 2 needs D^T and L^T applied to the rows' coefficients, which
  * are zero for every satisfied constraint.  When at most max_active_rows rows have a

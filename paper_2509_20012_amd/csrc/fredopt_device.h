@@ -34,6 +34,7 @@ constexpr int kFwdBlock = 512;         // forward kernel: 8 waves, one slice eac
 constexpr int kFwdWaves = kFwdBlock / kWave;
 constexpr int kBlock = 256;            // other kernels
 constexpr int kScatterBlock = 1024;    // active-row scatter: 16 waves, one row each
+constexpr int kScatterMaxWGs = 256;    // workgroups of the active-row scatter (max)
 constexpr int kNPart = 16;             // doubles per partial-sum slot
 constexpr int kCounters = 4;           // scheduling counters per batch
 constexpr double kDegenerateRel = 1e-12;

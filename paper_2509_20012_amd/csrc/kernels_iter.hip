@@ -33,6 +33,17 @@
 
 namespace fo {
 
+// Matrix entries are streamed once per pass and never re-read within it: the loads
+// carry the non-temporal hint so they do not displace the vectors held in cache.
+template <typename T>
+__device__ __forceinline__ T stream_load(const FO_GLOBAL T* p) {
+  return __builtin_nontemporal_load(p);
+}
+
+__device__ __forceinline__ v4i load_idx4(const FO_GLOBAL int32_t* p) {
+  return stream_load((const FO_GLOBAL v4i*)p);
+}
+
 // Four consecutive stored values starting at element e of a global array, as floats.
 template <int VT>
 struct VLoad;
@@ -40,7 +51,7 @@ struct VLoad;
 template <>
 struct VLoad<kF32> {
   static __device__ __forceinline__ v4f q4(const FO_GLOBAL void* p, uint32_t e) {
-    return *((const FO_GLOBAL v4f*)((const FO_GLOBAL float*)p + e));
+    return stream_load((const FO_GLOBAL v4f*)((const FO_GLOBAL float*)p + e));
   }
 };
 
@@ -48,7 +59,7 @@ template <>
 struct VLoad<kF16> {
   typedef _Float16 h4 __attribute__((ext_vector_type(4)));
   static __device__ __forceinline__ v4f q4(const FO_GLOBAL void* p, uint32_t e) {
-    const h4 h = *((const FO_GLOBAL h4*)((const FO_GLOBAL _Float16*)p + e));
+    const h4 h = stream_load((const FO_GLOBAL h4*)((const FO_GLOBAL _Float16*)p + e));
     return v4f{(float)h.x, (float)h.y, (float)h.z, (float)h.w};
   }
 };
@@ -56,7 +67,7 @@ struct VLoad<kF16> {
 template <>
 struct VLoad<kBF16> {
   static __device__ __forceinline__ v4f q4(const FO_GLOBAL void* p, uint32_t e) {
-    const v2u u = *((const FO_GLOBAL v2u*)((const FO_GLOBAL uint16_t*)p + e));
+    const v2u u = stream_load((const FO_GLOBAL v2u*)((const FO_GLOBAL uint16_t*)p + e));
     return v4f{__uint_as_float(u.x << 16), __uint_as_float(u.x & 0xffff0000u),
                __uint_as_float(u.y << 16), __uint_as_float(u.y & 0xffff0000u)};
   }
@@ -231,7 +242,7 @@ __device__ __forceinline__ bool finite2(float a, float b) { return isfinite(a) &
 
 // Plan-level completion of a residual pass: proximity, weights, the projection
 // scale weight_scale / W, and the outer counter (Fig. 3: weights eta^k w).
-__device__ __noinline__ void finalize_residuals(const DevPlan* P, const double* s) {
+__device__ __forceinline__ void finalize_residuals(const DevPlan* P, const double* s) {
   DevState* st = P->st;
   const double wall = s[0], wviol = s[1];
   st->w_all = wall;
@@ -254,7 +265,7 @@ __device__ __noinline__ void finalize_residuals(const DevPlan* P, const double* 
 // strictly lowers it iff beta Q < G.  s is the smallest integer above the previous
 // s with that property (the inner loop of Fig. 3 tries s+1, s+2, ...).  A search
 // that would need alpha^s < 1e-300 skips the perturbation and leaves s unchanged.
-__device__ __noinline__ void decide_step(const DevPlan* P, double G, double Q) {
+__device__ __forceinline__ void decide_step(const DevPlan* P, double G, double Q) {
   DevState* st = P->st;
   st->G = G;
   st->Q = Q;
@@ -325,7 +336,7 @@ __device__ __forceinline__ void forward_slice(const DevPlan* __restrict__ P, int
 #pragma unroll 4
     for (int t = 0; t < W; ++t) {
       const uint32_t e = (uint32_t)t * 256u + 4u * (uint32_t)lane;
-      const v4i c4 = *((const FO_GLOBAL v4i*)(ci + e));
+      const v4i c4 = load_idx4(ci + e);
       const v4f d4 = VLoad<VT>::q4(dv, e);
       const v4f l4 = VLoad<VT>::q4(lv, e);
       const float x0 = xs[c4.x], x1 = xs[c4.y], x2 = xs[c4.z], x3 = xs[c4.w];
@@ -344,7 +355,7 @@ __device__ __forceinline__ void forward_slice(const DevPlan* __restrict__ P, int
     const bool scaled = P->cscale != nullptr;
     for (int t = 0; t < W; ++t) {
       const uint32_t e = (uint32_t)t * 256u + 4u * (uint32_t)lane;
-      const v4i c4 = *((const FO_GLOBAL v4i*)(ci + e));
+      const v4i c4 = load_idx4(ci + e);
       const v4f d4 = VLoad<VT>::q4(dv, e);
       const v4f l4 = VLoad<VT>::q4(lv, e);
       const float x0 = scaled ? gv[c4.x] * cs[c4.x] : gv[c4.x];
@@ -422,20 +433,26 @@ __global__ __launch_bounds__(kFwdBlock) void k_forward(const DevPlan* __restrict
   int cur = -1;
   bool use_lds = false;
   const float* vec = nullptr;
-  for (;;) {
-    if (tid == 0) s_g = (int)atomicAdd(&ctr[0], 1u);
-    __syncthreads();
-    const int gi = s_g;
-    if (gi >= n_groups) {
-      // the last workgroup to run out of work re-arms the counters for the next launch
-      if (tid == 0) {
-        const unsigned e = atomicAdd(&ctr[1], 1u);
-        if (e == gridDim.x - 1) {
-          atomicExch(&ctr[0], 0u);
-          atomicExch(&ctr[1], 0u);
+  for (int it = 0;; ++it) {
+    int gi;
+    if (ctr) {  // dynamic: next group from a counter
+      if (tid == 0) s_g = (int)atomicAdd(&ctr[0], 1u);
+      __syncthreads();
+      gi = s_g;
+      if (gi >= n_groups) {
+        // the last workgroup to run out of work re-arms the counters for the next launch
+        if (tid == 0) {
+          const unsigned e = atomicAdd(&ctr[1], 1u);
+          if (e == gridDim.x - 1) {
+            atomicExch(&ctr[0], 0u);
+            atomicExch(&ctr[1], 0u);
+          }
         }
+        break;
       }
-      break;
+    } else {    // static: groups b, b + grid, b + 2 grid, ...
+      gi = blockIdx.x + it * gridDim.x;
+      if (gi >= n_groups) break;
     }
     const FwdGroup G = groups[gi];
     const DevPlan* __restrict__ P = plans + G.plan;
@@ -533,7 +550,7 @@ __global__ __launch_bounds__(kBlock) void k_tr_chunks(const DevPlan* __restrict_
   float acc = 0.f;
 #pragma unroll 4
   for (uint32_t e = 4u * (uint32_t)lane; e < n; e += 4u * kWave) {
-    const v4i r4 = *((const FO_GLOBAL v4i*)(ri + e));
+    const v4i r4 = load_idx4(ri + e);
     const v4f d4 = VLoad<VT>::q4(cdv, e);
     const v4f l4 = VLoad<VT>::q4(clv, e);
     const v2f c0 = cf[(uint32_t)r4.x], c1 = cf[(uint32_t)r4.y];
@@ -627,7 +644,7 @@ __global__ __launch_bounds__(kScatterBlock) void k_scatter(const DevPlan* __rest
     const FO_GLOBAL void* lv = value_ptr<VT>(P->sell.slv, sb);
     for (int q = lane; q < nq; q += kWave) {
       const uint32_t e = (uint32_t)(q >> lg2) * 256u + (uint32_t)(p * lpr + (q & (lpr - 1))) * 4u;
-      const v4i c4 = *((const FO_GLOBAL v4i*)(ci + e));
+      const v4i c4 = load_idx4(ci + e);
       const v4f d4 = VLoad<VT>::q4(dv, e);
       const v4f l4 = VLoad<VT>::q4(lv, e);
       // padding slots hold the value 0 and add nothing
@@ -677,12 +694,19 @@ __global__ __launch_bounds__(kScatterBlock) void k_scatter_sum(const DevPlan* __
   const int j = blockIdx.x * kWave + lane;
   const FO_GLOBAL int64_t* sp = gconst(P->spart) + j;
   const FO_GLOBAL uint64_t* mk = gconst(P->smask) + blockIdx.x;
-  int64_t S = 0;
-#pragma unroll 4
-  for (int w = wave; w < P->n_scatter; w += kScatterBlock / kWave) {
-    const uint64_t m = mk[(int64_t)w * nwords];
-    if ((m >> lane) & 1ull) S += sp[(int64_t)w * C];  // a set bit implies j < C
+  // all masks first, then the shares they mark: two dependent rounds of loads
+  constexpr int kNW = kScatterBlock / kWave, kPer = kScatterMaxWGs / kNW;
+  const int NW = P->n_scatter;
+  uint64_t m[kPer];
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) {
+    const int w = wave + i * kNW;
+    m[i] = w < NW ? mk[(int64_t)w * nwords] : 0ull;
   }
+  int64_t S = 0;
+#pragma unroll
+  for (int i = 0; i < kPer; ++i)  // a set bit implies j < C
+    if ((m[i] >> lane) & 1ull) S += sp[(int64_t)(wave + i * kNW) * C];
   part[wave][lane] = S;
   __syncthreads();
   if (wave == 0) {
@@ -732,11 +756,14 @@ __global__ __launch_bounds__(kBlock) void k_tcol(const DevPlan* __restrict__ pla
 
 // ------------------------------------------------------------ finalisation ----
 
-constexpr int kFinBlock = 1024;  // finalisation: one workgroup of 16 waves per plan
+constexpr int kFinBlock = 512;   // finalisation: one workgroup of 8 waves per plan
 constexpr int kFinWaves = kFinBlock / kWave;
 
+// Slot-wise sums of n partial slots over the finalisation workgroup: per-thread sums
+// in index order, wave sums, then the waves in order (one pair of barriers for all
+// slots).  Every thread gets the result.
 __device__ __forceinline__ void sum_slots(const double* part_, int n, double* out,
-                                          unsigned used, double* sh) {
+                                          unsigned used, double (*sh)[kNPart]) {
   const FO_GLOBAL double* part = gconst(part_);
   double s[kNPart];
 #pragma unroll
@@ -748,25 +775,42 @@ __device__ __forceinline__ void sum_slots(const double* part_, int n, double* ou
     for (int k = 0; k < kNPart; ++k)
       if (used & (1u << k)) s[k] += p[k];
   }
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
 #pragma unroll
   for (int k = 0; k < kNPart; ++k)
-    out[k] = (used & (1u << k)) ? block_sum<kFinWaves>(s[k], sh) : 0.0;
+    if (used & (1u << k)) s[k] = wave_sum(s[k]);
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < kNPart; ++k)
+      if (used & (1u << k)) sh[wave][k] = s[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kNPart; ++k) {
+    double r = 0.0;
+    if (used & (1u << k))
+      for (int w = 0; w < kFinWaves; ++w) r += sh[w][k];
+    out[k] = r;
+  }
+  __syncthreads();
 }
 
 // SUB: the objective and direction partials come from the objective-row view.
 template <int MODE, int SUB>
 __global__ __launch_bounds__(kFinBlock) void k_finalize(const DevPlan* __restrict__ plans) {
   __shared__ double sh4[kFinWaves];
+  __shared__ double shs[kFinWaves][kNPart];
   const DevPlan* __restrict__ P = plans + blockIdx.x;
   const int ng = SUB ? P->osell.n_groups : P->sell.n_groups;
   double a[kNPart];
   if constexpr (MODE == kFinDir0 || MODE == kFinDir) {
     double b[kNPart];
-    sum_slots(P->spart_b, ng, b, 0x21u, sh4);
+    sum_slots(P->spart_b, ng, b, 0x21u, shs);
     double g = 0.0;
     for (int i = threadIdx.x; i < P->n_col_blocks; i += kFinBlock) g += gconst(P->gpart)[i];
     const double G = block_sum<kFinWaves>(g, sh4);
-    if constexpr (MODE == kFinDir0) sum_slots(P->spart_a, ng, a, 0x21u, sh4);
+    if constexpr (MODE == kFinDir0) sum_slots(P->spart_a, ng, a, 0x21u, shs);
     if (threadIdx.x == 0) {
       DevState* st = P->st;
       if constexpr (MODE == kFinDir0) {
@@ -781,20 +825,20 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(const DevPlan* __restric
       decide_step(P, G, b[0]);
     }
   } else if constexpr (MODE == kFinMoveObj) {
-    sum_slots(P->rpart, P->n_row_items, a, 0x21u, sh4);
+    sum_slots(P->rpart, P->n_row_items, a, 0x21u, shs);
     if (threadIdx.x == 0) {
       P->st->cost_y = a[0];
       if (a[5] > 0.0) P->st->nonfinite = 1;
     }
   } else if constexpr (MODE == kFinResidRows) {
-    sum_slots(P->rpart, P->n_row_items, a, 0x1FFu, sh4);
+    sum_slots(P->rpart, P->n_row_items, a, 0x1FFu, shs);
     if (threadIdx.x == 0) {
       finalize_residuals(P, a);
       P->st->n_active = (int)a[7];
       P->st->proj_scatter = 0;
     }
   } else {
-    sum_slots(P->spart_a, P->sell.n_groups, a, 0x1FFu, sh4);
+    sum_slots(P->spart_a, P->sell.n_groups, a, 0x1FFu, shs);
     const int A = (int)a[7];
     // contributions are rounded to multiples of 1 / fx_scale; with every column
     // total bounded by a[8], 2^61 / a[8] keeps all sums far inside int64

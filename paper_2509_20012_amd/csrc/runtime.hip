@@ -46,7 +46,6 @@ constexpr int64_t kRowItemRows = 2048;
 constexpr int64_t kTrChunkMin = 256;
 constexpr int64_t kTrChunkDefault = 4096;
 constexpr int64_t kBlockCountCap = int64_t(1) << 24;
-constexpr int64_t kScatterMaxWGs = 256;   // workgroups of the active-row scatter (max)
 constexpr size_t kScatterLdsMax = 159744; // its LDS accumulator: C 64-bit sums
 
 inline size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
@@ -313,6 +312,7 @@ struct fredopt_plan {
   hipStream_t cap = nullptr;
   hipGraphExec_t graph = nullptr;
   int graph_r = -1;
+  bool fwd_dynamic = true;            // all-row forward: groups from a counter
 };
 
 namespace {
@@ -724,10 +724,13 @@ std::vector<Launch> iteration_sequence(int r, bool obj) {
 void enqueue(fredopt_plan* p, const Launch& l, hipStream_t s) {
   switch (l.kind) {
     case kKindFwd: {
+      // the small objective-row passes take their groups round robin (no counter)
       const std::vector<FwdGroup>& G = l.sub ? p->ogroups : p->groups;
+      const bool dyn = !l.sub && p->fwd_dynamic;
       const int grid = (int)std::min<int64_t>((int64_t)G.size(), (int64_t)p->n_cu * p->wgs_per_cu);
       launch_forward(p->storage, l.mode, l.sub, p->d_table, l.sub ? p->d_ogroups : p->d_groups,
-                     (int)G.size(), std::max(grid, 1), p->lds_floats, p->d_ctr, l.vsel, s);
+                     (int)G.size(), std::max(grid, 1), p->lds_floats, dyn ? p->d_ctr : nullptr,
+                     l.vsel, s);
       break;
     }
     case kKindRows:
@@ -1167,6 +1170,8 @@ fredopt_status fredopt_get_plan_info(const fredopt_plan* p, fredopt_plan_info* i
   info->lds_x = p->lds_floats > 0 ? 1 : 0;
   info->scatter_wgs = p->n_scatter;
   info->scatter_max_rows = p->scatter_max_rows;
+  info->obj_lanes_per_row = p->sched_obj ? 1 << p->hp.osell.lpr_log2 : 0;
+  info->fwd_schedule = p->fwd_dynamic ? 1 : 2;
   return FREDOPT_OK;
 }
 
@@ -1312,14 +1317,18 @@ fredopt_status fredopt_profile_kernels(fredopt_plan* p, const fredopt_problem* p
   return FREDOPT_OK;
 }
 
-fredopt_status fredopt_set_tuning(fredopt_plan* p, int32_t fwd_wgs_per_cu, int32_t tr_chunk) {
+fredopt_status fredopt_set_tuning(fredopt_plan* p, int32_t fwd_wgs_per_cu, int32_t tr_chunk,
+                                  int32_t fwd_schedule) {
   if (!p) return fail(FREDOPT_E_ARG, "plan is NULL");
+  if (fwd_schedule < 0 || fwd_schedule > 2)
+    return fail(FREDOPT_E_ARG, "fwd_schedule must be 0, 1 or 2");
   if (fwd_wgs_per_cu < 0 || fwd_wgs_per_cu > 8)
     return fail(FREDOPT_E_ARG, "fwd_wgs_per_cu must lie in [0, 8]");
   if (tr_chunk != 0 && (tr_chunk < kTrChunkMin || tr_chunk % 256 != 0))
     return fail(FREDOPT_E_ARG, "tr_chunk must be a multiple of 256");
   DeviceGuard guard(p->device);
   if (fwd_wgs_per_cu) p->wgs_per_cu = std::min(fwd_wgs_per_cu, p->max_wgs_per_cu);
+  if (fwd_schedule) p->fwd_dynamic = fwd_schedule == 1;
   if (tr_chunk) {
     p->tr_chunk = tr_chunk;
     build_tr_items(p);

@@ -75,7 +75,8 @@ class PlanInfo(ct.Structure):
                 ("storage", ct.c_int32), ("lanes_per_row", ct.c_int32),
                 ("fwd_grid", ct.c_int32), ("tr_chunk", ct.c_int32), ("lds_x", ct.c_int32),
                 ("schedule", ct.c_int32), ("scatter_wgs", ct.c_int32),
-                ("scatter_max_rows", ct.c_int64)]
+                ("scatter_max_rows", ct.c_int64), ("obj_lanes_per_row", ct.c_int32),
+                ("fwd_schedule", ct.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -121,7 +122,7 @@ def lib():
                                               ct.POINTER(State), P, ct.c_int32, P,
                                               ct.POINTER(ct.c_double), ct.POINTER(ct.c_int64)]
         L.fredopt_autotune.argtypes = [P, P, P]
-        L.fredopt_set_tuning.argtypes = [P, ct.c_int32, ct.c_int32]
+        L.fredopt_set_tuning.argtypes = [P, ct.c_int32, ct.c_int32, ct.c_int32]
         L.fredopt_set_scatter.argtypes = [P, ct.c_int32, ct.c_int64]
         for name in EXPORTED:
             if name not in ("fredopt_workspace_bytes", "fredopt_workspace_bytes_csr",
@@ -334,8 +335,10 @@ def autotune(plan: Plan, x, stream=None):
     return plan.info()
 
 
-def set_tuning(plan: Plan, fwd_wgs_per_cu: int = 0, tr_chunk: int = 0):
-    _check(lib().fredopt_set_tuning(plan.handle, int(fwd_wgs_per_cu), int(tr_chunk)))
+def set_tuning(plan: Plan, fwd_wgs_per_cu: int = 0, tr_chunk: int = 0, fwd_schedule: int = 0):
+    """0 keeps a value; fwd_schedule 1 = groups from a counter, 2 = round robin."""
+    _check(lib().fredopt_set_tuning(plan.handle, int(fwd_wgs_per_cu), int(tr_chunk),
+                                    int(fwd_schedule)))
 
 
 def set_scatter(plan: Plan, n_workgroups: int = 0, max_active_rows: int = -1):

@@ -67,7 +67,7 @@ def test_null_arguments_rejected_without_device():
     assert L.fredopt_superiorize_step(None, ct.byref(pr), ct.byref(q), ct.byref(st), None,
                                       None) == -1
     assert L.fredopt_solve(None, ct.byref(pr), ct.byref(q), ct.byref(st), None, None) == -1
-    assert L.fredopt_set_tuning(None, 0, 0) == -1
+    assert L.fredopt_set_tuning(None, 0, 0, 0) == -1
     assert L.fredopt_profile_kernels(None, None, None, None, None, 1, None, None, None) == -1
     assert L.fredopt_autotune(None, None, None) == -1
     assert L.fredopt_get_plan_info(None, None) == -1
