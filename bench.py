@@ -14,6 +14,7 @@ Prints one JSON line on stdout; progress goes to stderr.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import hashlib
 import json
 import math
@@ -111,6 +112,112 @@ def cpu_baseline(p, q, n_iters: int):
             "seconds": dt}, (x, k, s)
 
 
+def _timed(fn):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fn()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def bench_batch(args):
+    """48 plans of uneven size (5k-120k rows, 200-4,000 beamlets, one draw per plan),
+    iterated by batched launches, against the same plans solved one at a time."""
+    import torch
+    from paper_2509_20012_amd import fredopt, phantom as ph
+    sizes = ph.batch_sizes(48, seed=3)
+    t0 = time.perf_counter()
+    phs = [ph.small_plan(sd, r, c) for sd, r, c in sizes]
+    nnz = sum(p.nnz for p in phs)
+    log(f"48 plans: rows {sum(p.n_rows for p in phs)}, nnz {nnz} in {time.perf_counter() - t0:.1f} s")
+    storage = fredopt.STORAGE[args.storage]
+    loaded = [fredopt.load_phantom(p, storage=storage) for p in phs]
+    q = fredopt.SolverParams(reductions_n=args.reductions)
+    # one at a time (the plain single-plan form, default projection path)
+    k_alone = max(1, args.steps // 4)
+    t_alone = 0.0
+    for plan, prob, x0 in loaded:
+        x = x0.clone()
+        st = fredopt.new_state()
+        q.iter_max = args.warmup
+        fredopt.solve(plan, prob, q, st, x)
+        q.iter_max = k_alone
+        t_alone += _timed(lambda: fredopt.solve(plan, prob, q, st, x))
+    alone_rate = len(loaded) * k_alone / t_alone
+    log(f"one at a time: {alone_rate:.1f} plan-iterations/s ({k_alone} iterations per plan)")
+    batch = fredopt.Batch([l[0] for l in loaded], [l[1] for l in loaded])
+    xs = [l[2].clone() for l in loaded]
+    states = [fredopt.new_state() for _ in loaded]
+    batch.solve(q, states, xs, args.warmup)
+    dt = _timed(lambda: batch.solve(q, states, xs, args.steps))
+    rate = len(loaded) * args.steps / dt
+    log(f"batched: {rate:.1f} plan-iterations/s ({args.steps} iterations, {dt:.3f} s)")
+    return {
+        "metric": METRIC, "value": round(rate, 2), "unit": "iters/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if storage == fredopt.F32 else f"f32 (values stored {args.storage})",
+        "data": "synthetic",
+        "config": {"workload": "batch48: 48 water plans, 5k-120k rows, 200-4000 beamlets",
+                   "plans": len(loaded), "nnz_total": nnz, "storage": args.storage,
+                   "reductions_n": args.reductions},
+        "value_meaning": "plan-iterations per second summed over the 48 plans",
+        "one_at_a_time_iters_per_s": round(alone_rate, 2),
+        "speedup_vs_one_at_a_time": round(rate / alone_rate, 3),
+    }
+
+
+def bench_serve(args):
+    """Poisson stream of re-optimisation requests (4/s), sizes as the batched plans
+    plus 10 % at clinical scale, 200-1,000 iterations each, memory budget 200 GB;
+    continuous batching against first-come-first-served single-plan solves."""
+    from paper_2509_20012_amd import fredopt, phantom as ph, serve
+    rng = np.random.default_rng(4)
+    n_req = args.requests
+    arrivals = serve.poisson_trace(n_req, 4.0, seed=4)
+    pool = [ph.small_plan(sd, r, c) for sd, r, c in ph.batch_sizes(48, seed=3)]
+    big = ph.clinical(progress=log) if not args.serve_small_only else None
+    reqs = []
+    for i in range(n_req):
+        p = big if (big is not None and rng.random() < 0.10) else pool[rng.integers(len(pool))]
+        reqs.append(serve.Request(i, p, int(rng.integers(200, 1001)), float(arrivals[i])))
+    n_big = sum(r.phantom is big for r in reqs)
+    log(f"{n_req} requests over {arrivals[-1]:.1f} s, {n_big} at clinical scale")
+    q = fredopt.SolverParams(reductions_n=args.reductions)
+    srv = serve.Server(200 * 10**9, q, quantum=args.quantum, log=log)
+    t0 = time.perf_counter()
+    done = srv.run([dataclasses.replace(r) for r in reqs])
+    wall = time.perf_counter() - t0
+    lat = [r.latency for r in done]
+    iters = sum(r.iters for r in done)
+    log(f"continuous batching: p50 {serve.percentile(lat, 50):.3f} s, p99 "
+        f"{serve.percentile(lat, 99):.3f} s, {iters / wall:.1f} plan-iterations/s, "
+        f"{srv.batches_built} batches, peak {srv.peak_active} resident")
+    t0 = time.perf_counter()
+    base = serve.serve_one_at_a_time([dataclasses.replace(r) for r in reqs], q)
+    wall_b = time.perf_counter() - t0
+    lat_b = [r.latency for r in base]
+    log(f"one at a time: p50 {serve.percentile(lat_b, 50):.3f} s, p99 "
+        f"{serve.percentile(lat_b, 99):.3f} s, {iters / wall_b:.1f} plan-iterations/s")
+    return {
+        "metric": METRIC, "value": round(iters / wall, 2), "unit": "iters/s", "n_gpus": 1,
+        "steps": iters, "warmup": 0, "ms_per_step": round(wall / iters * 1e3, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"serve: {n_req} Poisson requests at 4/s, {n_big} at clinical "
+                               f"scale, 200-1000 iterations, 200 GB budget",
+                   "quantum": args.quantum, "reductions_n": args.reductions},
+        "value_meaning": "plan-iterations per second over the whole trace (wall clock)",
+        "latency_p50_s": round(serve.percentile(lat, 50), 4),
+        "latency_p99_s": round(serve.percentile(lat, 99), 4),
+        "one_at_a_time": {"latency_p50_s": round(serve.percentile(lat_b, 50), 4),
+                          "latency_p99_s": round(serve.percentile(lat_b, 99), 4),
+                          "iters_per_s": round(iters / wall_b, 2)},
+        "peak_resident_plans": srv.peak_active, "batches_built": srv.batches_built,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -118,7 +225,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="clinical",
                     help="clinical (160x160x120 grid, 12k beamlets), water32 (32^3, 400 "
-                         "beamlets) or clinical_x<scale>")
+                         "beamlets), clinical_x<scale>, batch48 (48 plans in batched "
+                         "launches) or serve (request stream, continuous batching)")
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--reductions", type=int, default=1)
     ap.add_argument("--autotune", action="store_true")
@@ -127,6 +235,10 @@ def main():
     ap.add_argument("--profile-iters", type=int, default=5)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (for PMC scaling)")
+    ap.add_argument("--requests", type=int, default=120, help="serve: trace length")
+    ap.add_argument("--quantum", type=int, default=50, help="serve: iterations per round")
+    ap.add_argument("--serve-small-only", action="store_true",
+                    help="serve: no clinical-scale requests")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -140,6 +252,10 @@ def main():
         raise SystemExit("bench.py needs a HIP device")
     torch.cuda.set_device(0)
     fredopt.lib()
+    if args.workload in ("batch48", "serve"):
+        res = bench_batch(args) if args.workload == "batch48" else bench_serve(args)
+        print(json.dumps(res), flush=True)
+        return
     log(f"generating workload {args.workload}")
     t0 = time.perf_counter()
     p = make_workload(args.workload)

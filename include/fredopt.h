@@ -278,6 +278,41 @@ fredopt_status fredopt_set_tuning(fredopt_plan *p, int32_t fwd_wgs_per_cu, int32
 fredopt_status fredopt_set_scatter(fredopt_plan *p, int32_t n_workgroups,
                                    int64_t max_active_rows);
 
+/* ---- batches: many plans iterated by the same launches ------------------------
+ *
+ * Fig. 3 run for several independent plans (patients, or robustness scenarios of
+ * one patient, each with its own matrices and problem) by one sequence of kernel
+ * launches: each launch takes the work items of every plan, each outer iteration is
+ * one hipGraph replay.  A plan's arithmetic is the one it has alone with the
+ * column-major projection (fredopt_set_scatter(p, -1, -1)), so its iterates are the
+ * same bit for bit.  Plans keep their own workspaces and states; the batch only adds
+ * a table of descriptors and the concatenated work lists. */
+typedef struct fredopt_batch fredopt_batch;
+
+/* Device bytes of the batch workspace for these plans (0 on a NULL plan). */
+size_t fredopt_batch_workspace_bytes(fredopt_plan *const *plans, int32_t n);
+
+/* Binds plans[i] to problems[i] (checked and prepared as by fredopt_solve) and
+ * builds the batch in the caller's workspace (device memory, at least
+ * fredopt_batch_workspace_bytes, owned by the caller, kept until
+ * fredopt_batch_free).  All plans need the same storage and device; a plan may
+ * belong to one batch at a time and must not be used on its own meanwhile.  The
+ * problem structs are copied; the device arrays they point to must stay valid
+ * while the batch lives.  Synchronises `stream`. */
+fredopt_status fredopt_batch_create(fredopt_plan *const *plans, int32_t n,
+                                    const fredopt_problem *problems, void *workspace,
+                                    size_t workspace_bytes, void *stream,
+                                    fredopt_batch **out);
+
+/* n_iters outer iterations of every plan of the batch, plan i from states[i] and
+ * the device fluence x[i] (in place); the states are updated as by fredopt_solve.
+ * Synchronises `stream`. */
+fredopt_status fredopt_batch_solve(fredopt_batch *b, const fredopt_params *q,
+                                   fredopt_state *states, float *const *x, int32_t n_iters,
+                                   void *stream);
+
+fredopt_status fredopt_batch_free(fredopt_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

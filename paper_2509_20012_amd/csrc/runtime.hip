@@ -721,72 +721,129 @@ std::vector<Launch> iteration_sequence(int r, bool obj) {
   return seq;
 }
 
-void enqueue(fredopt_plan* p, const Launch& l, hipStream_t s) {
+// What a launch sequence needs: the plan table and the work lists of one plan or
+// of a batch of plans (every work item names its plan).
+struct Exec {
+  int storage = 0, n_cu = 256, wgs_per_cu = 2, lds_floats = 0, n_plans = 1;
+  bool fwd_dynamic = true;
+  DevPlan* table = nullptr;
+  const FwdGroup* groups = nullptr;
+  int n_groups = 0;
+  const FwdGroup* ogroups = nullptr;
+  int n_ogroups = 0;
+  const RowItem* rows = nullptr;
+  int n_rows = 0;
+  const TrItem* tr = nullptr;
+  int n_tr = 0;
+  const TrItem* gtr = nullptr;
+  int n_gtr = 0;
+  const ColBlock* cblocks = nullptr;
+  int n_cblocks = 0;
+  uint32_t* ctr = nullptr;
+  int n_scatter = 0, C = 0;   // active-row scatter (single plans only)
+};
+
+Exec exec_of(const fredopt_plan* p) {
+  Exec e;
+  e.storage = p->storage;
+  e.n_cu = p->n_cu;
+  e.wgs_per_cu = p->wgs_per_cu;
+  e.lds_floats = p->lds_floats;
+  e.fwd_dynamic = p->fwd_dynamic;
+  e.table = p->d_table;
+  e.groups = p->d_groups;
+  e.n_groups = (int)p->groups.size();
+  e.ogroups = p->d_ogroups;
+  e.n_ogroups = (int)p->ogroups.size();
+  e.rows = p->d_rows;
+  e.n_rows = (int)p->rows.size();
+  e.tr = p->d_tr;
+  e.n_tr = (int)p->tr.size();
+  e.gtr = p->d_gtr;
+  e.n_gtr = (int)p->gtr.size();
+  e.cblocks = p->d_cblocks;
+  e.n_cblocks = (int)p->cblocks.size();
+  e.ctr = p->d_ctr;
+  e.n_scatter = p->n_scatter;
+  e.C = (int)p->C;
+  return e;
+}
+
+void enqueue(const Exec& e, const Launch& l, hipStream_t s) {
   switch (l.kind) {
     case kKindFwd: {
       // the small objective-row passes take their groups round robin (no counter)
-      const std::vector<FwdGroup>& G = l.sub ? p->ogroups : p->groups;
-      const bool dyn = !l.sub && p->fwd_dynamic;
-      const int grid = (int)std::min<int64_t>((int64_t)G.size(), (int64_t)p->n_cu * p->wgs_per_cu);
-      launch_forward(p->storage, l.mode, l.sub, p->d_table, l.sub ? p->d_ogroups : p->d_groups,
-                     (int)G.size(), std::max(grid, 1), p->lds_floats, dyn ? p->d_ctr : nullptr,
-                     l.vsel, s);
+      const int n = l.sub ? e.n_ogroups : e.n_groups;
+      const bool dyn = !l.sub && e.fwd_dynamic;
+      const int grid = (int)std::min<int64_t>((int64_t)n, (int64_t)e.n_cu * e.wgs_per_cu);
+      launch_forward(e.storage, l.mode, l.sub, e.table, l.sub ? e.ogroups : e.groups, n,
+                     std::max(grid, 1), e.lds_floats, dyn ? e.ctr : nullptr, l.vsel, s);
       break;
     }
     case kKindRows:
-      launch_rows(l.mode, p->d_table, p->d_rows, (int)p->rows.size(), s);
+      launch_rows(l.mode, e.table, e.rows, e.n_rows, s);
       break;
     case kKindChunks:
       if (l.mode == 0) {
-        if (!p->gtr.empty())
-          launch_tr_chunks(p->storage, 0, p->d_table, p->d_gtr, (int)p->gtr.size(), s);
-      } else if (!p->tr.empty()) {
-        launch_tr_chunks(p->storage, 1, p->d_table, p->d_tr, (int)p->tr.size(), s);
+        if (e.n_gtr > 0) launch_tr_chunks(e.storage, 0, e.table, e.gtr, e.n_gtr, s);
+      } else if (e.n_tr > 0) {
+        launch_tr_chunks(e.storage, 1, e.table, e.tr, e.n_tr, s);
       }
       break;
     case kKindCol:
-      launch_tcol(l.mode, p->d_table, p->d_cblocks, (int)p->cblocks.size(), s);
+      launch_tcol(l.mode, e.table, e.cblocks, e.n_cblocks, s);
       break;
     case kKindList:
-      if (p->n_scatter > 0) launch_active_list(p->d_table, p->d_groups, (int)p->groups.size(), s);
+      if (e.n_scatter > 0) launch_active_list(e.table, e.groups, e.n_groups, s);
       break;
     case kKindScatter:
-      if (p->n_scatter > 0) launch_scatter(p->storage, p->d_table, p->n_scatter, (int)p->C, s);
+      if (e.n_scatter > 0) launch_scatter(e.storage, e.table, e.n_scatter, e.C, s);
       break;
     case kKindScatterSum:
-      if (p->n_scatter > 0) launch_scatter_sum(l.mode, p->d_table, p->n_scatter, (int)p->C, s);
+      if (e.n_scatter > 0) launch_scatter_sum(l.mode, e.table, e.n_scatter, e.C, s);
       break;
     default:
-      launch_finalize(l.mode, l.sub, p->d_table, 1, s);
+      launch_finalize(l.mode, l.sub, e.table, e.n_plans, s);
       break;
   }
 }
 
+void enqueue(fredopt_plan* p, const Launch& l, hipStream_t s) { enqueue(exec_of(p), l, s); }
+
 fredopt_status enqueue_iteration(fredopt_plan* p, int r, hipStream_t s) {
-  for (const Launch& l : iteration_sequence(r, p->sched_obj)) enqueue(p, l, s);
+  const Exec e = exec_of(p);
+  for (const Launch& l : iteration_sequence(r, p->sched_obj)) enqueue(e, l, s);
   HIPCHK(hipGetLastError());
+  return FREDOPT_OK;
+}
+
+// One outer iteration captured on `cap` (a stream of its own) into *graph.
+fredopt_status capture_iteration(const Exec& e, int r, bool obj, hipStream_t cap,
+                                 hipGraphExec_t* graph) {
+  hipGraph_t g = nullptr;
+  HIPCHK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+  for (const Launch& l : iteration_sequence(r, obj)) enqueue(e, l, cap);
+  const hipError_t le = hipGetLastError();
+  const hipError_t ce = hipStreamEndCapture(cap, &g);
+  if (le != hipSuccess || ce != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return fail(FREDOPT_E_DEVICE, "graph capture failed: %s",
+                hipGetErrorString(le != hipSuccess ? le : ce));
+  }
+  const hipError_t ie = hipGraphInstantiate(graph, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ie != hipSuccess) {
+    *graph = nullptr;
+    return fail(FREDOPT_E_DEVICE, "graph instantiate failed: %s", hipGetErrorString(ie));
+  }
   return FREDOPT_OK;
 }
 
 fredopt_status ensure_graph(fredopt_plan* p, int r) {
   if (p->graph && p->graph_r == r) return FREDOPT_OK;
   drop_graph(p);
-  hipGraph_t g = nullptr;
-  HIPCHK(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
-  for (const Launch& l : iteration_sequence(r, p->sched_obj)) enqueue(p, l, p->cap);
-  const hipError_t le = hipGetLastError();
-  const hipError_t ce = hipStreamEndCapture(p->cap, &g);
-  if (le != hipSuccess || ce != hipSuccess) {
-    if (g) (void)hipGraphDestroy(g);
-    return fail(FREDOPT_E_DEVICE, "graph capture failed: %s",
-                hipGetErrorString(le != hipSuccess ? le : ce));
-  }
-  const hipError_t ie = hipGraphInstantiate(&p->graph, g, nullptr, nullptr, 0);
-  (void)hipGraphDestroy(g);
-  if (ie != hipSuccess) {
-    p->graph = nullptr;
-    return fail(FREDOPT_E_DEVICE, "graph instantiate failed: %s", hipGetErrorString(ie));
-  }
+  const fredopt_status st = capture_iteration(exec_of(p), r, p->sched_obj, p->cap, &p->graph);
+  if (st != FREDOPT_OK) return st;
   p->graph_r = r;
   return FREDOPT_OK;
 }
@@ -804,11 +861,15 @@ fredopt_status device_limits(fredopt_plan* p) {
     smem_sm = smem_block;
   p->n_cu = ncu > 0 ? ncu : 256;
   p->smem_block = (size_t)std::max(smem_block, 0);
-  const size_t static_lds = 64;
+  // dynamic LDS limit of the kernels that stage vectors: what the device allows
+  // next to their static LDS (plans of every size share the kernels)
+  const size_t static_lds = 2048;
+  const size_t dyn_max = p->smem_block > static_lds ? p->smem_block - static_lds : 0;
+  for (int vt = FREDOPT_F32; vt <= FREDOPT_BF16; ++vt) HIPCHK(set_forward_lds_limit(vt, dyn_max));
+  HIPCHK(set_scatter_lds_limit(dyn_max));
   const size_t need = (size_t)p->C * sizeof(float);
-  if (need + static_lds <= (size_t)std::max(smem_block, 0)) {
+  if (need <= dyn_max) {
     p->lds_floats = (int)p->C;
-    HIPCHK(set_forward_lds_limit(p->storage, need));
     const int fit = (int)std::max<size_t>(1, (size_t)std::max(smem_sm, 1) / (need + static_lds));
     p->max_wgs_per_cu = std::min(4, fit);  // 4 x 512 threads = 32 waves per CU
   } else {
@@ -816,15 +877,15 @@ fredopt_status device_limits(fredopt_plan* p) {
     p->max_wgs_per_cu = 4;
   }
   const size_t sneed = (size_t)p->C * sizeof(int64_t);
-  if (scatter_fits(p->C) && sneed + static_lds <= (size_t)std::max(smem_block, 0)) {
-    HIPCHK(set_scatter_lds_limit(sneed));
+  if (scatter_fits(p->C) && sneed <= dyn_max) {
     p->n_scatter = (int)std::min<int64_t>(p->n_cu, kScatterMaxWGs);
     p->scatter_max_rows = p->R / 4;
   } else {
     p->n_scatter = 0;
     p->scatter_max_rows = 0;
   }
-  p->wgs_per_cu = p->max_wgs_per_cu;
+  // two 8-wave workgroups per CU measured fastest for the streaming passes
+  p->wgs_per_cu = std::min(2, p->max_wgs_per_cu);
   return FREDOPT_OK;
 }
 
@@ -1348,7 +1409,7 @@ fredopt_status fredopt_set_scatter(fredopt_plan* p, int32_t n_workgroups,
   if (max_active_rows < -1) return fail(FREDOPT_E_ARG, "max_active_rows must be >= -1");
   DeviceGuard guard(p->device);
   const bool avail = scatter_fits(p->C) && p->hp.spart != nullptr &&
-                     (size_t)p->C * sizeof(int64_t) + 64 <= p->smem_block;
+                     (size_t)p->C * sizeof(int64_t) + 2048 <= p->smem_block;
   if (n_workgroups > 0 && !avail)
     return fail(FREDOPT_E_NOT_IMPLEMENTED, "the active-row scatter needs 8 C bytes of LDS");
   if (n_workgroups == -1)
@@ -1428,6 +1489,303 @@ fredopt_status fredopt_autotune(fredopt_plan* p, const float* x, void* stream) {
   drop_graph(p);
   HIPCHK(hipStreamSynchronize(s));
   return st;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------- batches ----
+//
+// Several plans iterated by the same launches: one table of plan descriptors and
+// the concatenation of the plans' work lists (each item names its plan).  Every
+// plan keeps its own workspace, state and partial sums, and a plan's items are the
+// ones it has alone, so its arithmetic (and result) does not depend on the batch.
+// Plans with and without the objective-row view follow different iteration
+// schedules: they form two sub-batches whose launch sequences are captured one
+// after the other into the same graph.
+
+struct SubBatch {
+  std::vector<int32_t> idx;   // caller's plan indices, in table order
+  bool obj = false;
+  Exec ex;
+};
+
+struct fredopt_batch {
+  std::vector<fredopt_plan*> plans;        // caller's order
+  std::vector<fredopt_problem> problems;   // copies; the arrays stay the caller's
+  std::vector<int32_t> pos;                // table position of the caller's plan i
+  std::vector<SubBatch> subs;
+  int device = 0, storage = 0;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  DevPlan* d_table = nullptr;
+  std::vector<DevPlan> table;
+  hipStream_t cap = nullptr;
+  hipGraphExec_t graph = nullptr;
+  int graph_r = -1;
+};
+
+namespace {
+
+struct BatchLayout {
+  size_t table, ctr, groups, ogroups, rows, tr, gtr, cblocks, total;
+};
+
+// Bounds from each plan's own layout, so the size is known before the problems
+// are prepared.
+BatchLayout batch_layout(fredopt_plan* const* plans, int32_t n) {
+  int64_t g = 0, og = 0, rw = 0, t = 0, gt = 0, cb = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    const Layout& L = plans[i]->L;
+    g += L.n_groups;
+    og += L.max_obj_groups;
+    rw += L.max_rows;
+    t += L.max_tr;
+    gt += L.max_tr;
+    cb += L.n_col_blocks;
+  }
+  BatchLayout B{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at_ = o;
+    o = align_up(o + std::max<size_t>(bytes, 1));
+    return at_;
+  };
+  B.table = take(sizeof(DevPlan) * (size_t)n);
+  B.ctr = take(sizeof(uint32_t) * kCounters * 2);  // one set per sub-batch
+  B.groups = take(sizeof(FwdGroup) * g);
+  B.ogroups = take(sizeof(FwdGroup) * og);
+  B.rows = take(sizeof(RowItem) * rw);
+  B.tr = take(sizeof(TrItem) * t);
+  B.gtr = take(sizeof(TrItem) * gt);
+  B.cblocks = take(sizeof(ColBlock) * cb);
+  B.total = o;
+  return B;
+}
+
+void drop_batch_graph(fredopt_batch* b) {
+  if (b->graph) (void)hipGraphExecDestroy(b->graph);
+  b->graph = nullptr;
+  b->graph_r = -1;
+}
+
+template <typename T>
+void append(std::vector<T>* dst, const std::vector<T>& src, int32_t plan) {
+  for (T v : src) {
+    v.plan = plan;
+    dst->push_back(v);
+  }
+}
+
+// Copies v to ws + *off (advancing *off) and returns the device address.
+template <typename T>
+const T* place(char* ws, size_t* off, const std::vector<T>& v, hipStream_t s, bool* ok) {
+  const T* at_ = reinterpret_cast<const T*>(ws + *off);
+  if (!v.empty() &&
+      hipMemcpyAsync(ws + *off, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, s) !=
+          hipSuccess)
+    *ok = false;
+  *off += sizeof(T) * v.size();
+  return at_;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t fredopt_batch_workspace_bytes(fredopt_plan* const* plans, int32_t n) {
+  if (!plans || n < 1) return 0;
+  for (int32_t i = 0; i < n; ++i)
+    if (!plans[i]) return 0;
+  return batch_layout(plans, n).total;
+}
+
+fredopt_status fredopt_batch_create(fredopt_plan* const* plans, int32_t n,
+                                    const fredopt_problem* problems, void* workspace,
+                                    size_t workspace_bytes, void* stream, fredopt_batch** out) {
+  if (!plans || !problems || !workspace || !out || n < 1)
+    return fail(FREDOPT_E_ARG, "plans, problems, workspace and out must be non-NULL, n >= 1");
+  *out = nullptr;
+  for (int32_t i = 0; i < n; ++i) {
+    if (!plans[i]) return fail(FREDOPT_E_ARG, "plan %d is NULL", i);
+    for (int32_t j = 0; j < i; ++j)
+      if (plans[j] == plans[i]) return fail(FREDOPT_E_ARG, "plan %d appears twice", i);
+    if (plans[i]->storage != plans[0]->storage)
+      return fail(FREDOPT_E_ARG, "all plans of a batch need the same value storage");
+    if (plans[i]->device != plans[0]->device)
+      return fail(FREDOPT_E_ARG, "all plans of a batch need the same device");
+    fredopt_status st = check_problem_ptrs(&problems[i]);
+    if (st != FREDOPT_OK) return st;
+  }
+  const BatchLayout B = batch_layout(plans, n);
+  if (workspace_bytes < B.total)
+    return fail(FREDOPT_E_WORKSPACE, "batch workspace too small: %zu < %zu", workspace_bytes,
+                B.total);
+  DeviceGuard guard(plans[0]->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  for (int32_t i = 0; i < n; ++i) {
+    fredopt_status st = run_problem_check(plans[i], &problems[i], s);
+    if (st == FREDOPT_OK) st = prepare_problem(plans[i], &problems[i], s);
+    if (st != FREDOPT_OK) return st;
+  }
+  fredopt_batch* b = new fredopt_batch;
+  b->device = plans[0]->device;
+  b->storage = plans[0]->storage;
+  b->ws = static_cast<char*>(workspace);
+  b->ws_bytes = workspace_bytes;
+  b->d_table = reinterpret_cast<DevPlan*>(b->ws + B.table);
+  b->pos.assign(n, 0);
+  for (int32_t i = 0; i < n; ++i) {
+    b->plans.push_back(plans[i]);
+    b->problems.push_back(problems[i]);
+  }
+  // sub-batches by schedule: objective-row view first
+  for (int obj = 1; obj >= 0; --obj) {
+    SubBatch sb;
+    sb.obj = obj == 1;
+    for (int32_t i = 0; i < n; ++i)
+      if (plans[i]->sched_obj == sb.obj) sb.idx.push_back(i);
+    if (!sb.idx.empty()) b->subs.push_back(sb);
+  }
+  size_t off_g = B.groups, off_og = B.ogroups, off_r = B.rows, off_t = B.tr, off_gt = B.gtr,
+         off_c = B.cblocks;
+  int32_t base = 0;
+  bool ok = true;
+  for (size_t k = 0; k < b->subs.size(); ++k) {
+    SubBatch& sb = b->subs[k];
+    std::vector<FwdGroup> groups, ogroups;
+    std::vector<RowItem> rows;
+    std::vector<TrItem> tr, gtr;
+    std::vector<ColBlock> cblocks;
+    int lds = 0, wgs = 4;
+    bool all_lds = true;
+    for (size_t j = 0; j < sb.idx.size(); ++j) {
+      fredopt_plan* p = plans[sb.idx[j]];
+      b->pos[sb.idx[j]] = base + (int32_t)j;
+      append(&groups, p->groups, (int32_t)j);
+      if (sb.obj) append(&ogroups, p->ogroups, (int32_t)j);
+      append(&rows, p->rows, (int32_t)j);
+      append(&tr, p->tr, (int32_t)j);
+      append(&gtr, p->gtr, (int32_t)j);
+      append(&cblocks, p->cblocks, (int32_t)j);
+      lds = std::max(lds, p->lds_floats);
+      all_lds = all_lds && p->lds_floats > 0;
+      wgs = std::min(wgs, p->wgs_per_cu);
+    }
+    Exec& e = sb.ex;
+    e.storage = b->storage;
+    e.n_cu = plans[0]->n_cu;
+    e.wgs_per_cu = std::max(1, wgs);
+    e.lds_floats = all_lds ? lds : 0;
+    e.n_plans = (int)sb.idx.size();
+    e.fwd_dynamic = true;
+    e.table = b->d_table + base;
+    e.groups = place(b->ws, &off_g, groups, s, &ok);
+    e.n_groups = (int)groups.size();
+    e.ogroups = place(b->ws, &off_og, ogroups, s, &ok);
+    e.n_ogroups = (int)ogroups.size();
+    e.rows = place(b->ws, &off_r, rows, s, &ok);
+    e.n_rows = (int)rows.size();
+    e.tr = place(b->ws, &off_t, tr, s, &ok);
+    e.n_tr = (int)tr.size();
+    e.gtr = place(b->ws, &off_gt, gtr, s, &ok);
+    e.n_gtr = (int)gtr.size();
+    e.cblocks = place(b->ws, &off_c, cblocks, s, &ok);
+    e.n_cblocks = (int)cblocks.size();
+    e.ctr = reinterpret_cast<uint32_t*>(b->ws + B.ctr) + kCounters * k;
+    e.n_scatter = 0;  // the projection of a batch streams the column-major copies
+    base += (int32_t)sb.idx.size();
+  }
+  fredopt_status st = FREDOPT_OK;
+  if (!ok) st = fail(FREDOPT_E_DEVICE, "batch upload failed");
+  if (st == FREDOPT_OK &&
+      hipMemsetAsync(b->ws + B.ctr, 0, sizeof(uint32_t) * kCounters * 2, s) != hipSuccess)
+    st = fail(FREDOPT_E_DEVICE, "counter reset failed");
+  if (st == FREDOPT_OK && hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess)
+    st = fail(FREDOPT_E_DEVICE, "stream creation failed");
+  if (st == FREDOPT_OK && hipStreamSynchronize(s) != hipSuccess)
+    st = fail(FREDOPT_E_DEVICE, "batch upload failed");
+  if (st != FREDOPT_OK) {
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    delete b;
+    return st;
+  }
+  *out = b;
+  return FREDOPT_OK;
+}
+
+fredopt_status fredopt_batch_free(fredopt_batch* b) {
+  if (!b) return fail(FREDOPT_E_ARG, "batch is NULL");
+  {
+    DeviceGuard guard(b->device);
+    drop_batch_graph(b);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+  }
+  delete b;
+  return FREDOPT_OK;
+}
+
+fredopt_status fredopt_batch_solve(fredopt_batch* b, const fredopt_params* q,
+                                   fredopt_state* states, float* const* x, int32_t n_iters,
+                                   void* stream) {
+  if (!b || !states || !x) return fail(FREDOPT_E_ARG, "batch, states and x must be non-NULL");
+  fredopt_status st = check_params(q, false);
+  if (st != FREDOPT_OK) return st;
+  if (n_iters < 0) return fail(FREDOPT_E_ARG, "n_iters must be >= 0");
+  const int32_t n = (int32_t)b->plans.size();
+  for (int32_t i = 0; i < n; ++i) {
+    if (!x[i]) return fail(FREDOPT_E_ARG, "x[%d] is NULL", i);
+    if (states[i].k < 0 || states[i].s < -1)
+      return fail(FREDOPT_E_STATE, "state %d needs k >= 0 and s >= -1", i);
+  }
+  DeviceGuard guard(b->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  b->table.resize(n);
+  for (int32_t i = 0; i < n; ++i) {
+    fredopt_plan* p = b->plans[i];
+    set_problem(p, &b->problems[i], q, -1.0, x[i]);
+    b->table[b->pos[i]] = p->hp;
+    b->table[b->pos[i]].n_scatter = 0;
+    if ((st = upload_state(p, &states[i], s)) != FREDOPT_OK) return st;
+  }
+  HIPCHK(hipMemcpyAsync(b->d_table, b->table.data(), sizeof(DevPlan) * n, hipMemcpyHostToDevice,
+                        s));
+  if (n_iters > 0) {
+    for (const SubBatch& sb : b->subs)
+      enqueue(sb.ex, Launch{FREDOPT_KERNEL_COL, kKindCol, kColYCopy}, s);
+    const int r = q->reductions_n;
+    if (!(b->graph && b->graph_r == r)) {
+      drop_batch_graph(b);
+      hipGraph_t g = nullptr;
+      HIPCHK(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+      for (const SubBatch& sb : b->subs)
+        for (const Launch& l : iteration_sequence(r, sb.obj)) enqueue(sb.ex, l, b->cap);
+      const hipError_t le = hipGetLastError();
+      const hipError_t ce = hipStreamEndCapture(b->cap, &g);
+      if (le != hipSuccess || ce != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(FREDOPT_E_DEVICE, "graph capture failed: %s",
+                    hipGetErrorString(le != hipSuccess ? le : ce));
+      }
+      const hipError_t ie = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (ie != hipSuccess) {
+        b->graph = nullptr;
+        return fail(FREDOPT_E_DEVICE, "graph instantiate failed: %s", hipGetErrorString(ie));
+      }
+      b->graph_r = r;
+    }
+    for (int32_t i = 0; i < n_iters; ++i) HIPCHK(hipGraphLaunch(b->graph, s));
+  }
+  HIPCHK(hipGetLastError());
+  bool nonfinite = false;
+  for (int32_t i = 0; i < n; ++i) {
+    DevState d;
+    if ((st = download_state(b->plans[i], &d, s)) != FREDOPT_OK) return st;
+    if (n_iters > 0) export_state(d, &states[i]);
+    nonfinite = nonfinite || d.nonfinite;
+  }
+  if (nonfinite) return fail(FREDOPT_E_NONFINITE, "non-finite value during an iteration");
+  return FREDOPT_OK;
 }
 
 }  // extern "C"

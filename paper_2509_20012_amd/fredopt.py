@@ -87,7 +87,8 @@ EXPORTED = ("fredopt_workspace_bytes", "fredopt_workspace_bytes_csr",
             "fredopt_dose_let", "fredopt_project_sweep", "fredopt_superiorize_step",
             "fredopt_solve", "fredopt_last_error", "fredopt_get_plan_info",
             "fredopt_profile_kernels", "fredopt_autotune", "fredopt_set_tuning",
-            "fredopt_set_scatter")
+            "fredopt_set_scatter", "fredopt_batch_workspace_bytes", "fredopt_batch_create",
+            "fredopt_batch_solve", "fredopt_batch_free")
 
 _lib = None
 
@@ -124,9 +125,16 @@ def lib():
         L.fredopt_autotune.argtypes = [P, P, P]
         L.fredopt_set_tuning.argtypes = [P, ct.c_int32, ct.c_int32, ct.c_int32]
         L.fredopt_set_scatter.argtypes = [P, ct.c_int32, ct.c_int64]
+        L.fredopt_batch_workspace_bytes.argtypes = [ct.POINTER(ct.c_void_p), ct.c_int32]
+        L.fredopt_batch_workspace_bytes.restype = ct.c_size_t
+        L.fredopt_batch_create.argtypes = [ct.POINTER(ct.c_void_p), ct.c_int32,
+                                           ct.POINTER(Problem), P, ct.c_size_t, P, PP]
+        L.fredopt_batch_solve.argtypes = [P, ct.POINTER(Params), ct.POINTER(State),
+                                          ct.POINTER(ct.c_void_p), ct.c_int32, P]
+        L.fredopt_batch_free.argtypes = [P]
         for name in EXPORTED:
             if name not in ("fredopt_workspace_bytes", "fredopt_workspace_bytes_csr",
-                            "fredopt_last_error"):
+                            "fredopt_last_error", "fredopt_batch_workspace_bytes"):
                 getattr(L, name).restype = ct.c_int
         _lib = L
     return _lib
@@ -310,6 +318,50 @@ def solve(plan: Plan, problem: DeviceProblem, params: SolverParams, state: State
     _check(lib().fredopt_solve(plan.handle, ct.byref(pr), ct.byref(q), ct.byref(state),
                                _ptr(x), _stream(stream)))
     return state
+
+
+class Batch:
+    """Several plans iterated by the same kernel launches (fredopt_batch_*)."""
+
+    def __init__(self, plans, problems, stream=None):
+        torch = _torch()
+        n = len(plans)
+        assert n == len(problems) and n > 0
+        hp = (ct.c_void_p * n)(*[p.handle for p in plans])
+        nbytes = int(lib().fredopt_batch_workspace_bytes(hp, n))
+        if nbytes == 0:
+            raise FredoptError(-1, "batch workspace size: a plan is invalid")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        prs = (Problem * n)(*[pr.struct() for pr in problems])
+        h = ct.c_void_p()
+        _check(lib().fredopt_batch_create(hp, n, prs, _ptr(self.ws), nbytes, _stream(stream),
+                                          ct.byref(h)))
+        self._h = h
+        self.plans, self.problems, self.n = list(plans), list(problems), n
+
+    def solve(self, params: "SolverParams", states, xs, n_iters: int, stream=None):
+        assert len(states) == self.n and len(xs) == self.n
+        sts = (State * self.n)(*states)
+        xp = (ct.c_void_p * self.n)(*[_ptr(x) for x in xs])
+        q = params.struct()
+        _check(lib().fredopt_batch_solve(self._h, ct.byref(q), sts, xp, int(n_iters),
+                                         _stream(stream)))
+        for i in range(self.n):
+            ct.memmove(ct.byref(states[i]), ct.byref(sts[i]), ct.sizeof(State))
+        return states
+
+    def free(self):
+        if self._h:
+            _check(lib().fredopt_batch_free(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            if self._h and _lib is not None:
+                _lib.fredopt_batch_free(self._h)
+                self._h = None
+        except Exception:
+            pass
 
 
 def new_state(k: int = 0, s: int = -1) -> State:

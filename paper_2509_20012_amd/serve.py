@@ -1,0 +1,172 @@
+"""Serving loop for re-optimisation requests (host logic over the fredopt C ABI).
+
+Requests (a plan's influence matrices and problem, an iteration count, an arrival
+time) are admitted while the device memory they need fits a budget; admitted plans
+stay resident and are iterated together by batched launches (fredopt_batch_*):
+continuous batching, where the batch is rebuilt whenever a request joins or
+leaves, between quanta of outer iterations.  A request's latency runs from its
+arrival to its result (the fluence) being on the host, and includes the load.
+
+Every batched iteration of a plan equals its single-plan iteration with the
+column-major projection bit for bit, and quanta resume exactly, so a request's
+result does not depend on what else was served with it.
+
+The comparison form ("one at a time") serves the same trace first come, first
+served, each request solved alone with the plain single-plan call.
+"""
+from __future__ import annotations
+
+import dataclasses
+import time
+from typing import Callable, List, Optional
+
+import numpy as np
+
+from . import fredopt
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    phantom: object            # phantom.Phantom
+    iters: int
+    arrival: float             # seconds after the start of the trace
+    admitted: Optional[float] = None
+    finished: Optional[float] = None
+    x: Optional[np.ndarray] = None
+    k: int = 0
+    s: int = -1
+
+    @property
+    def latency(self) -> float:
+        return self.finished - self.arrival
+
+
+def plan_bytes(ph, storage: int = fredopt.F32) -> int:
+    """Device bytes a request holds while resident: the plan workspace, the input
+    CSR copies used during the load, the problem arrays and the fluence."""
+    ws = fredopt.workspace_bytes_csr(ph.row_ptr, ph.n_cols, storage)
+    csr = ph.row_ptr.nbytes + ph.col_idx.nbytes + ph.d_val.nbytes + ph.l_val.nbytes
+    return int(ws + csr + ph.n_rows * 38 + ph.n_cols * 4)
+
+
+class _Active:
+    def __init__(self, req: Request, storage: int):
+        self.req = req
+        self.plan, self.prob, self.x = fredopt.load_phantom(req.phantom, storage=storage)
+        fredopt.set_scatter(self.plan, -1, -1)
+        self.state = fredopt.new_state()
+        self.left = req.iters
+        self.bytes = plan_bytes(req.phantom, storage)
+
+
+class Server:
+    """Continuous batching under a device-memory budget."""
+
+    def __init__(self, budget_bytes: int, params: fredopt.SolverParams, quantum: int = 50,
+                 storage: int = fredopt.F32, log: Optional[Callable[[str], None]] = None):
+        self.budget = int(budget_bytes)
+        self.params = params
+        self.quantum = int(quantum)
+        self.storage = storage
+        self.log = log or (lambda m: None)
+        self.batches_built = 0
+        self.peak_active = 0
+        self.peak_bytes = 0
+
+    def run(self, requests: List[Request]) -> List[Request]:
+        import torch
+        queue = sorted(requests, key=lambda r: (r.arrival, r.rid))
+        for r in queue:
+            if plan_bytes(r.phantom, self.storage) > self.budget:
+                raise ValueError(f"request {r.rid} alone exceeds the memory budget")
+        active: List[_Active] = []
+        done: List[Request] = []
+        batch = None
+        used = 0
+        t0 = time.perf_counter()
+        now = lambda: time.perf_counter() - t0  # noqa: E731
+        qi = 0
+        while qi < len(queue) or active:
+            changed = False
+            # admit what has arrived, in arrival order, while it fits
+            while qi < len(queue) and queue[qi].arrival <= now():
+                need = plan_bytes(queue[qi].phantom, self.storage)
+                if used + need > self.budget:
+                    break
+                req = queue[qi]
+                qi += 1
+                req.admitted = now()
+                active.append(_Active(req, self.storage))
+                used += need
+                changed = True
+            if not active:
+                # idle until the next arrival
+                time.sleep(max(0.0, queue[qi].arrival - now()))
+                continue
+            self.peak_active = max(self.peak_active, len(active))
+            self.peak_bytes = max(self.peak_bytes, used)
+            if changed or batch is None:
+                if batch is not None:
+                    batch.free()
+                batch = fredopt.Batch([a.plan for a in active], [a.prob for a in active])
+                self.batches_built += 1
+            n = min(self.quantum, min(a.left for a in active))
+            self.params.iter_max = n
+            batch.solve(self.params, [a.state for a in active], [a.x for a in active], n)
+            for a in active:
+                a.left -= n
+            finished = [a for a in active if a.left == 0]
+            if finished:
+                for a in finished:
+                    req = a.req
+                    req.x = a.x.cpu().numpy()
+                    req.k, req.s = a.state.k, a.state.s
+                    req.finished = now()
+                    done.append(req)
+                    used -= a.bytes
+                batch.free()
+                batch = None
+                active = [a for a in active if a.left > 0]
+                for a in finished:
+                    a.plan.free()
+                del finished
+                torch.cuda.synchronize()
+        return done
+
+
+def serve_one_at_a_time(requests: List[Request], params: fredopt.SolverParams,
+                        storage: int = fredopt.F32) -> List[Request]:
+    """First come, first served; each request solved alone by fredopt_solve."""
+    queue = sorted(requests, key=lambda r: (r.arrival, r.rid))
+    t0 = time.perf_counter()
+    now = lambda: time.perf_counter() - t0  # noqa: E731
+    for req in queue:
+        wait = req.arrival - now()
+        if wait > 0:
+            time.sleep(wait)
+        req.admitted = now()
+        plan, prob, x = fredopt.load_phantom(req.phantom, storage=storage)
+        st = fredopt.new_state()
+        params.iter_max = req.iters
+        fredopt.solve(plan, prob, params, st, x)
+        req.x = x.cpu().numpy()
+        req.k, req.s = st.k, st.s
+        req.finished = now()
+        plan.free()
+    return queue
+
+
+def percentile(values, q: float) -> float:
+    """Nearest-rank percentile (q in [0, 100])."""
+    v = np.sort(np.asarray(values, np.float64))
+    if v.size == 0:
+        return float("nan")
+    rank = max(1, int(np.ceil(q / 100.0 * v.size)))
+    return float(v[rank - 1])
+
+
+def poisson_trace(n: int, rate: float, seed: int) -> np.ndarray:
+    """Arrival times of n requests of a Poisson process of the given rate (1/s)."""
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate, n))
