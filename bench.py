@@ -42,9 +42,11 @@ def log(msg: str):
 
 
 def kernel_source_hash() -> str:
+    """Hash of the sources that define the iteration kernels (the counters in
+    profiles/ are valid only for the kernels they were taken on)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2509_20012_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
+    for f in ("fredopt_device.h", "kernels_iter.hip"):
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -231,7 +233,7 @@ def main():
     ap.add_argument("--reductions", type=int, default=1)
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=3)
+    ap.add_argument("--cpu-iters", type=int, default=100)
     ap.add_argument("--profile-iters", type=int, default=5)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (for PMC scaling)")
@@ -310,11 +312,19 @@ def main():
     R, C, nnz = p.n_rows, p.n_cols, p.nnz
     vb = 4 if storage == fredopt.F32 else 2
     per_kernel = {}
+    scatter_path = sp.projection_path == 1
+    log(f"projection: {'active rows' if scatter_path else 'column-major'}, "
+        f"{sp.n_active} active rows")
     for name, (ms, cnt) in prof.items():
         if cnt == 0:
             continue
         ab = algorithmic_bytes(name, R, C, nnz, vb, info["tr_items"], info["grad_entries"],
                                n_obj_rows, info["obj_entries"])
+        if name == "tr_proj" and scatter_path:
+            ab = 0  # its workgroups see the active-row path and return at once
+        if name == "scatter" and scatter_path:
+            # estimate: active rows times the mean row length (the rows are not known here)
+            ab = int(sp.n_active * (nnz / max(R, 1)) * (4 + 2 * vb) + 32 * sp.n_active)
         per_kernel[name] = {"ms": ms, "launches_per_iter": cnt / args.profile_iters,
                             "alg_bytes": ab, "gbps": ab / (ms * 1e-3) / 1e9 if ms > 0 else 0.0}
     dom = max((k for k in per_kernel if per_kernel[k]["alg_bytes"] > 0),

@@ -142,6 +142,9 @@ typedef struct {
   double proximity;        /* 1/2 sum (w_i / W_all) v_i^2 / ||a_i||^2 at that point */
   double grad_sq;          /* ||grad chi^2||^2 of the last perturbation         */
   double q;                /* sum w (D g)^2 + sum w c^2 (L g)^2 of that direction */
+  int64_t n_active;        /* rows with a non-zero projection coefficient        */
+  int32_t projection_path; /* 1: the last sweep used the active-row path, 0: CSC  */
+  int32_t reserved;
 } fredopt_state;
 
 /* Bytes of device workspace a plan of this size needs: an upper bound valid for

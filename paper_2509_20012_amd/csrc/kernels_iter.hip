@@ -154,8 +154,8 @@ __device__ __forceinline__ void objective_row(const DevPlan* P, int r, float d, 
   ((FO_GLOBAL v2f*)(P->coef))[r] = v2f{(float)uD, (float)uL};
 }
 
-__device__ __forceinline__ double objective_value(const DevPlan* P, int r, float d, float l) {
-  const unsigned k = gconst(P->kind)[r];
+__device__ __forceinline__ double objective_value(const DevPlan* P, int r, unsigned k, float d,
+                                                  float l) {
   double s = 0.0;
   if (k & (kObjDose | kObjCdl)) {
     const double w = gconst(P->wo)[r], c = P->prm.c;
@@ -176,9 +176,8 @@ __device__ __forceinline__ double objective_value(const DevPlan* P, int r, float
 // folded into the (D, L) coefficient pair of the row.  ||a||^2 comes from the row
 // moments: ||D_i||^2, c^2 ||L_i||^2, ||L_i - T D_i||^2 = sum L^2 - 2T sum DL +
 // T^2 sum D^2.  Accumulates slots [0]..[4] of the residual layout.
-__device__ __forceinline__ void residual_row(const DevPlan* P, int r, float d, float l,
-                                             double* acc) {
-  const unsigned k = gconst(P->kind)[r];
+__device__ __forceinline__ void residual_row(const DevPlan* P, int r, unsigned k, float d,
+                                             float l, double* acc) {
   double kD = 0.0, kL = 0.0;
   if (k & kConstraintBits) {
     const double w = gconst(P->wf)[r], lam = P->prm.lambda, c = P->prm.c;
@@ -404,8 +403,9 @@ __device__ __forceinline__ void forward_slice(const DevPlan* __restrict__ P, int
     } else {
       gmut(P->d)[row] = ad;
       gmut(P->l)[row] = al;
-      residual_row(P, row, ad, al, acc);
-      acc[6] += objective_value(P, row, ad, al);
+      const unsigned rkind = gconst(P->kind)[row];
+      residual_row(P, row, rkind, ad, al, acc);
+      acc[6] += objective_value(P, row, rkind, ad, al);
       if (!finite2(ad, al)) acc[5] += 1.0;
     }
   }
@@ -435,7 +435,8 @@ __global__ __launch_bounds__(kFwdBlock) void k_forward(const DevPlan* __restrict
   const float* vec = nullptr;
   for (int it = 0;; ++it) {
     int gi;
-    if (ctr) {  // dynamic: next group from a counter
+    if (ctr) {  // dynamic: next group from a counter (taken only when this one is done,
+                // so the last groups go to whichever workgroups are free)
       if (tid == 0) s_g = (int)atomicAdd(&ctr[0], 1u);
       __syncthreads();
       gi = s_g;
@@ -451,6 +452,7 @@ __global__ __launch_bounds__(kFwdBlock) void k_forward(const DevPlan* __restrict
         break;
       }
     } else {    // static: groups b, b + grid, b + 2 grid, ...
+      __syncthreads();  // the previous group's partials are read before wpart is reused
       gi = blockIdx.x + it * gridDim.x;
       if (gi >= n_groups) break;
     }
@@ -507,8 +509,9 @@ __global__ __launch_bounds__(kBlock) void k_rows(const DevPlan* __restrict__ pla
     if constexpr (MODE == kRowsMoveObj) {
       objective_row(P, r, d, l, &acc[0]);
     } else {
-      residual_row(P, r, d, l, acc);
-      acc[6] += objective_value(P, r, d, l);
+      const unsigned kr = gconst(P->kind)[r];
+      residual_row(P, r, kr, d, l, acc);
+      acc[6] += objective_value(P, r, kr, d, l);
     }
     if (!finite2(d, l)) acc[5] += 1.0;
   }

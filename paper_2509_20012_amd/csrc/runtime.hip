@@ -655,6 +655,9 @@ void export_state(const DevState& d, fredopt_state* st) {
   st->proximity = d.proximity;
   st->grad_sq = d.G;
   st->q = d.Q;
+  st->n_active = d.n_active;
+  st->projection_path = d.proj_scatter;
+  st->reserved = 0;
 }
 
 enum Kind {

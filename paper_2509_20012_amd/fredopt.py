@@ -59,7 +59,9 @@ class Params(ct.Structure):
 class State(ct.Structure):
     _fields_ = [("k", ct.c_int64), ("s", ct.c_int64), ("n_violated", ct.c_int64),
                 ("beta", ct.c_double), ("cost", ct.c_double), ("cost_perturbed", ct.c_double),
-                ("proximity", ct.c_double), ("grad_sq", ct.c_double), ("q", ct.c_double)]
+                ("proximity", ct.c_double), ("grad_sq", ct.c_double), ("q", ct.c_double),
+                ("n_active", ct.c_int64), ("projection_path", ct.c_int32),
+                ("reserved", ct.c_int32)]
 
     def as_dict(self) -> Dict[str, float]:
         return {f: getattr(self, f) for f, _ in self._fields_}
