@@ -53,11 +53,13 @@ def kernel_source_hash() -> str:
 
 
 def algorithmic_bytes(kernel: str, R: int, C: int, nnz: int, vb: int, n_tr_items: int,
-                      grad_entries: int, n_obj_rows: int, obj_entries: int) -> int:
+                      grad_entries: int, n_obj_rows: int, obj_entries: int, ib: int = 4) -> int:
     """Bytes a kernel launch must move: the unpadded matrix entries (shared index, D
     and L values), the input vector once, per-row problem data and outputs.  Padding
-    and re-reads are not counted."""
-    b = 4 + 2 * vb
+    and re-reads are not counted.  vb: bytes per stored value; ib: bytes per column
+    index of the row-major copy (the column-major copy keeps 4-byte row indices)."""
+    b = ib + 2 * vb      # row-major entry
+    bt = 4 + 2 * vb      # column-major entry
     if kernel == "fwd_obj" and obj_entries:   # objective rows only
         return obj_entries * b + 4 * C + n_obj_rows * (8 + 8 + 2 + 12)
     if kernel == "fwd_dir" and obj_entries:   # objective rows only; Q
@@ -69,9 +71,9 @@ def algorithmic_bytes(kernel: str, R: int, C: int, nnz: int, vb: int, n_tr_items
     if kernel == "fwd_resid":   # x in; d, l, coef out; kind, bounds, weights, moments in
         return nnz * b + 4 * C + R * (8 + 8 + 2 + 20 + 4 + 24 + 12)
     if kernel == "tr_grad":     # entries of rows with objective terms only
-        return grad_entries * b + 8 * n_obj_rows + C * (32 + 4)
+        return grad_entries * bt + 8 * n_obj_rows + C * (32 + 4)
     if kernel == "tr_proj":     # coefficient pair per row once; chunk sums
-        return nnz * b + 8 * R + n_tr_items * (32 + 4)
+        return nnz * bt + 8 * R + n_tr_items * (32 + 4)
     if kernel == "col":         # chunk sums in; x, g in and out
         return n_tr_items * 4 + C * 16
     if kernel == "rows":        # d, l, Dg, Lg in; d, l, coef out; problem data in
@@ -177,7 +179,7 @@ def bench_serve(args):
     from paper_2509_20012_amd import fredopt, phantom as ph, serve
     rng = np.random.default_rng(4)
     n_req = args.requests
-    arrivals = serve.poisson_trace(n_req, 4.0, seed=4)
+    arrivals = serve.poisson_trace(n_req, args.rate, seed=4)
     pool = [ph.small_plan(sd, r, c) for sd, r, c in ph.batch_sizes(48, seed=3)]
     big = ph.clinical(progress=log) if not args.serve_small_only else None
     reqs = []
@@ -185,7 +187,7 @@ def bench_serve(args):
         p = big if (big is not None and rng.random() < 0.10) else pool[rng.integers(len(pool))]
         reqs.append(serve.Request(i, p, int(rng.integers(200, 1001)), float(arrivals[i])))
     n_big = sum(r.phantom is big for r in reqs)
-    log(f"{n_req} requests over {arrivals[-1]:.1f} s, {n_big} at clinical scale")
+    log(f"{n_req} requests over {arrivals[-1]:.1f} s ({args.rate:g}/s), {n_big} at clinical scale")
     q = fredopt.SolverParams(reductions_n=args.reductions)
     srv = serve.Server(200 * 10**9, q, quantum=args.quantum, log=log)
     t0 = time.perf_counter()
@@ -207,8 +209,8 @@ def bench_serve(args):
         "steps": iters, "warmup": 0, "ms_per_step": round(wall / iters * 1e3, 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"serve: {n_req} Poisson requests at 4/s, {n_big} at clinical "
-                               f"scale, 200-1000 iterations, 200 GB budget",
+        "config": {"workload": f"serve: {n_req} Poisson requests at {args.rate:g}/s, {n_big} at "
+                               f"clinical scale, 200-1000 iterations, 200 GB budget",
                    "quantum": args.quantum, "reductions_n": args.reductions},
         "value_meaning": "plan-iterations per second over the whole trace (wall clock)",
         "latency_p50_s": round(serve.percentile(lat, 50), 4),
@@ -229,7 +231,9 @@ def main():
                     help="clinical (160x160x120 grid, 12k beamlets), water32 (32^3, 400 "
                          "beamlets), clinical_x<scale>, batch48 (48 plans in batched "
                          "launches) or serve (request stream, continuous batching)")
-    ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
+    ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16", "f16i16", "bf16i16"],
+                    help="matrix values in FP32, FP16 or BF16 (per-beamlet FP32 scale); the "
+                         "i16 forms also keep column indices in 16 bits")
     ap.add_argument("--reductions", type=int, default=1)
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -239,6 +243,7 @@ def main():
                     help="also run a plain device copy of known size (for PMC scaling)")
     ap.add_argument("--requests", type=int, default=120, help="serve: trace length")
     ap.add_argument("--quantum", type=int, default=50, help="serve: iterations per round")
+    ap.add_argument("--rate", type=float, default=4.0, help="serve: requests per second")
     ap.add_argument("--serve-small-only", action="store_true",
                     help="serve: no clinical-scale requests")
     args = ap.parse_args()
@@ -311,6 +316,7 @@ def main():
     n_obj_rows = int(np.count_nonzero(p.kind & (ph_mod.OBJ_DOSE | ph_mod.OBJ_CDL)))
     R, C, nnz = p.n_rows, p.n_cols, p.nnz
     vb = 4 if storage == fredopt.F32 else 2
+    ib = 2 if storage in (fredopt.F16_IDX16, fredopt.BF16_IDX16) else 4
     per_kernel = {}
     scatter_path = sp.projection_path == 1
     log(f"projection: {'active rows' if scatter_path else 'column-major'}, "
@@ -319,12 +325,12 @@ def main():
         if cnt == 0:
             continue
         ab = algorithmic_bytes(name, R, C, nnz, vb, info["tr_items"], info["grad_entries"],
-                               n_obj_rows, info["obj_entries"])
+                               n_obj_rows, info["obj_entries"], ib)
         if name == "tr_proj" and scatter_path:
             ab = 0  # its workgroups see the active-row path and return at once
         if name == "scatter" and scatter_path:
             # estimate: active rows times the mean row length (the rows are not known here)
-            ab = int(sp.n_active * (nnz / max(R, 1)) * (4 + 2 * vb) + 32 * sp.n_active)
+            ab = int(sp.n_active * (nnz / max(R, 1)) * (ib + 2 * vb) + 32 * sp.n_active)
         per_kernel[name] = {"ms": ms, "launches_per_iter": cnt / args.profile_iters,
                             "alg_bytes": ab, "gbps": ab / (ms * 1e-3) / 1e9 if ms > 0 else 0.0}
     dom = max((k for k in per_kernel if per_kernel[k]["alg_bytes"] > 0),

@@ -64,7 +64,15 @@ typedef enum {
   FREDOPT_E_NOT_IMPLEMENTED = -8
 } fredopt_status;
 
-typedef enum { FREDOPT_F32 = 0, FREDOPT_F16 = 1, FREDOPT_BF16 = 2 } fredopt_dtype;
+/* Value storage of the influence matrices.  16-bit forms store D_ij / s_j and
+ * L_ij / s_j rounded to nearest-even, with one FP32 scale s_j per beamlet (the
+ * largest D or L value of column j); products accumulate in FP32.  The _IDX16 forms
+ * also keep the column indices of the row-major copy in 16 bits (n_cols <= 65536):
+ * 6 bytes per stored entry instead of 12. */
+typedef enum {
+  FREDOPT_F32 = 0, FREDOPT_F16 = 1, FREDOPT_BF16 = 2, FREDOPT_F16_IDX16 = 3,
+  FREDOPT_BF16_IDX16 = 4
+} fredopt_dtype;
 
 #define FREDOPT_DOSE_LO 0x01u
 #define FREDOPT_DOSE_HI 0x02u
@@ -286,10 +294,11 @@ fredopt_status fredopt_set_scatter(fredopt_plan *p, int32_t n_workgroups,
  * Fig. 3 run for several independent plans (patients, or robustness scenarios of
  * one patient, each with its own matrices and problem) by one sequence of kernel
  * launches: each launch takes the work items of every plan, each outer iteration is
- * one hipGraph replay.  A plan's arithmetic is the one it has alone with the
- * column-major projection (fredopt_set_scatter(p, -1, -1)), so its iterates are the
- * same bit for bit.  Plans keep their own workspaces and states; the batch only adds
- * a table of descriptors and the concatenated work lists. */
+ * one hipGraph replay.  A plan's arithmetic is the one it has alone (its schedule,
+ * its work items; the active-row projection gets workgroups in proportion to the
+ * plan, which its exact integer sums do not see), so its iterates are the same bit
+ * for bit.  Plans keep their own workspaces and states; the batch only adds a table
+ * of descriptors and the concatenated work lists. */
 typedef struct fredopt_batch fredopt_batch;
 
 /* Device bytes of the batch workspace for these plans (0 on a NULL plan). */

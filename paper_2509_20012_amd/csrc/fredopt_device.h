@@ -45,7 +45,11 @@ enum : unsigned {
   kObjDose = 0x20u, kObjCdl = 0x40u, kConstraintBits = 0x1Fu
 };
 
-enum ValueType : int { kF32 = 0, kF16 = 1, kBF16 = 2 };
+// stored value type of a plan's matrices; kF16I / kBF16I also keep the column
+// indices of the sliced-ELL copy in 16 bits (the column-major copy keeps int32 rows)
+enum ValueType : int { kF32 = 0, kF16 = 1, kBF16 = 2, kF16I = 3, kBF16I = 4 };
+__host__ __device__ constexpr int value_of(int vt) { return vt >= kF16I ? vt - 2 : vt; }
+__host__ __device__ constexpr bool index16(int vt) { return vt >= kF16I; }
 
 // forward-kernel epilogues
 enum FwdMode : int { kFwdDoseLet = 0, kFwdObj = 1, kFwdDir = 2, kFwdResid = 3 };
@@ -105,7 +109,7 @@ struct SellView {
   const int64_t* sbase;       // [n_slices + 1]
   const int32_t* swidth;      // [n_slices] steps
   const int32_t* srow;        // [n_slices * rpw] original row, -1 for padding
-  const int32_t* sci;
+  const void* sci;            // int32, or uint16 for kF16I / kBF16I
   const void* sdv;
   const void* slv;
   int32_t n_slices, n_groups;
@@ -181,6 +185,10 @@ struct TrItem {    // a chunk of one column of one plan
 
 struct ColBlock {  // up to kBlock consecutive columns of one plan
   int32_t plan, slot, c0, c1;
+};
+
+struct ScItem {    // a workgroup of the active-row scatter or of its share sum
+  int32_t plan, idx;  // idx: the workgroup's share, or the 64-column word
 };
 
 }  // namespace fo

@@ -20,10 +20,14 @@ void launch_finalize(int mode, int sub, const DevPlan* plans, int n_plans, hipSt
 hipError_t set_forward_lds_limit(int vtype, size_t bytes);
 void launch_active_list(const DevPlan* plans, const FwdGroup* groups, int n_groups,
                         hipStream_t s);
-void launch_scatter(int vtype, const DevPlan* plans, int n_scatter, int C, hipStream_t s);
+// one workgroup per item: items[i] = {plan, share}; lds_bytes = 8 x the widest plan's C
+void launch_scatter(int vtype, const DevPlan* plans, const ScItem* items, int n_items,
+                    size_t lds_bytes, hipStream_t s);
 hipError_t set_scatter_lds_limit(size_t bytes);
 // mode: the ColMode of the projection update (kColProj, kColProjMove, kColProjY)
-void launch_scatter_sum(int mode, const DevPlan* plans, int n_scatter, int C, hipStream_t s);
+// items[i] = {plan, 64-column word}
+void launch_scatter_sum(int mode, const DevPlan* plans, const ScItem* items, int n_items,
+                        hipStream_t s);
 
 // load kernels (kernels_load.hip)
 // flags bits: 1 column index out of range, 2 columns not strictly increasing,
@@ -34,10 +38,11 @@ void launch_col_stats(int64_t nnz, const int64_t* row_ptr, const int32_t* col, c
                       const float* lv, uint32_t* col_count, uint32_t* col_max_bits,
                       hipStream_t s);
 void launch_col_scale(int64_t C, const uint32_t* col_max_bits, float* scale, hipStream_t s);
+// vtype: value type (kF32, kF16, kBF16); idx16: column indices stored as uint16
 void launch_pack_sell(int vtype, int64_t R, int lpr_log2, const int64_t* row_ptr,
                       const int32_t* col, const float* dv, const float* lv, const float* scale,
-                      const int32_t* rslice, const int64_t* sbase, int32_t* sci, void* sdv,
-                      void* slv, hipStream_t s);
+                      const int32_t* rslice, const int64_t* sbase, void* sci, int idx16,
+                      void* sdv, void* slv, hipStream_t s);
 void launch_block_count(int64_t R, int64_t C, int rows_per_block, const int64_t* row_ptr,
                         const int32_t* col, uint32_t* bc, hipStream_t s);
 void launch_block_offsets(int64_t C, int nb, const int64_t* cp, uint32_t* bc, hipStream_t s);
@@ -61,9 +66,9 @@ void launch_obj_fill(int vtype, int64_t C, const int64_t* cp, const uint32_t* le
 // view and dst_pos[i] of the objective view and has len[i] entries
 void launch_pack_sub(int vtype, int src_lg2, int dst_lg2, int64_t n, const int32_t* src_pos,
                      const int32_t* dst_pos, const int32_t* len, const int64_t* src_base,
-                     const int32_t* src_ci, const void* src_dv, const void* src_lv,
-                     const int64_t* dst_base, int32_t* dst_ci, void* dst_dv, void* dst_lv,
-                     hipStream_t s);
+                     const void* src_ci, const void* src_dv, const void* src_lv,
+                     const int64_t* dst_base, void* dst_ci, int idx16, void* dst_dv,
+                     void* dst_lv, hipStream_t s);
 void launch_check_problem(int64_t R, const uint16_t* kind, const float* dlo, const float* dhi,
                           const float* clo, const float* chi, const float* tmax,
                           const float* wf, const float* wo, const float* dt, const float* ct,

@@ -44,6 +44,23 @@ __device__ __forceinline__ v4i load_idx4(const FO_GLOBAL int32_t* p) {
   return stream_load((const FO_GLOBAL v4i*)p);
 }
 
+// Column indices of the sliced-ELL copy: the slice starting at element sb, and the
+// four indices at element e of it.
+template <int VT>
+__device__ __forceinline__ const FO_GLOBAL void* sell_idx_ptr(const void* base, int64_t sb) {
+  return (const FO_GLOBAL char*)(base) + sb * (index16(VT) ? 2 : 4);
+}
+
+template <int VT>
+__device__ __forceinline__ v4i sell_idx4(const FO_GLOBAL void* ci, uint32_t e) {
+  if constexpr (index16(VT)) {
+    const v2u u = stream_load((const FO_GLOBAL v2u*)((const FO_GLOBAL uint16_t*)ci + e));
+    return v4i{(int)(u.x & 0xffffu), (int)(u.x >> 16), (int)(u.y & 0xffffu), (int)(u.y >> 16)};
+  } else {
+    return load_idx4((const FO_GLOBAL int32_t*)ci + e);
+  }
+}
+
 // Four consecutive stored values starting at element e of a global array, as floats.
 template <int VT>
 struct VLoad;
@@ -72,6 +89,11 @@ struct VLoad<kBF16> {
                __uint_as_float(u.y << 16), __uint_as_float(u.y & 0xffff0000u)};
   }
 };
+
+template <>
+struct VLoad<kF16I> : VLoad<kF16> {};
+template <>
+struct VLoad<kBF16I> : VLoad<kBF16> {};
 
 template <int VT>
 __device__ __forceinline__ const FO_GLOBAL void* value_ptr(const void* base, int64_t e) {
@@ -327,7 +349,8 @@ __device__ __forceinline__ void forward_slice(const DevPlan* __restrict__ P, int
   const int W = uniform(gconst(V.swidth)[s]);
   const int row = gconst(V.srow)[(int64_t)s * rpw + pos];
   // slice-relative element offsets fit 32 bits; the slice bases are wave-uniform
-  const FO_GLOBAL int32_t* ci = gconst(V.sci) + sb;
+
+  const FO_GLOBAL void* ci = sell_idx_ptr<VT>(V.sci, sb);
   const FO_GLOBAL void* dv = value_ptr<VT>(V.sdv, sb);
   const FO_GLOBAL void* lv = value_ptr<VT>(V.slv, sb);
   float ad = 0.f, al = 0.f;
@@ -335,7 +358,7 @@ __device__ __forceinline__ void forward_slice(const DevPlan* __restrict__ P, int
 #pragma unroll 4
     for (int t = 0; t < W; ++t) {
       const uint32_t e = (uint32_t)t * 256u + 4u * (uint32_t)lane;
-      const v4i c4 = load_idx4(ci + e);
+      const v4i c4 = sell_idx4<VT>(ci, e);
       const v4f d4 = VLoad<VT>::q4(dv, e);
       const v4f l4 = VLoad<VT>::q4(lv, e);
       const float x0 = xs[c4.x], x1 = xs[c4.y], x2 = xs[c4.z], x3 = xs[c4.w];
@@ -354,7 +377,7 @@ __device__ __forceinline__ void forward_slice(const DevPlan* __restrict__ P, int
     const bool scaled = P->cscale != nullptr;
     for (int t = 0; t < W; ++t) {
       const uint32_t e = (uint32_t)t * 256u + 4u * (uint32_t)lane;
-      const v4i c4 = load_idx4(ci + e);
+      const v4i c4 = sell_idx4<VT>(ci, e);
       const v4f d4 = VLoad<VT>::q4(dv, e);
       const v4f l4 = VLoad<VT>::q4(lv, e);
       const float x0 = scaled ? gv[c4.x] * cs[c4.x] : gv[c4.x];
@@ -623,16 +646,19 @@ __device__ __forceinline__ void fx_add(unsigned long long* acc, int col, double 
 // bit.  Workgroup w takes a contiguous share of the list; the column kernel adds
 // the shares.
 template <int VT>
-__global__ __launch_bounds__(kScatterBlock) void k_scatter(const DevPlan* __restrict__ plans) {
+__global__ __launch_bounds__(kScatterBlock) void k_scatter(const DevPlan* __restrict__ plans,
+                                                          const ScItem* __restrict__ items) {
   extern __shared__ unsigned long long facc[];
-  const DevPlan* __restrict__ P = plans;
+  const ScItem item = items[blockIdx.x];
+  const DevPlan* __restrict__ P = plans + item.plan;
+  const int wg = item.idx;
   if (!P->st->proj_scatter) return;
   const int C = (int)P->C;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   for (int j = tid; j < C; j += kScatterBlock) facc[j] = 0ull;
   __syncthreads();
   const int64_t A = P->st->n_active, NW = P->n_scatter;
-  const int i0 = (int)(blockIdx.x * A / NW), i1 = (int)((blockIdx.x + 1) * A / NW);
+  const int i0 = (int)(wg * A / NW), i1 = (int)((wg + 1) * A / NW);
   const int lg2 = P->lpr_log2, lpr = 1 << lg2;
   const double fs = P->st->fx_scale;
   const ActRow* list = P->alist;
@@ -642,12 +668,13 @@ __global__ __launch_bounds__(kScatterBlock) void k_scatter(const DevPlan* __rest
     const int64_t sb = (int64_t)(((uint64_t)(uint32_t)uniform(a0.y) << 32) | (uint32_t)uniform(a0.x));
     const int nq = uniform(a0.z), p = uniform(a0.w);
     const double cd = __int_as_float(uniform(a1.x)), cl = __int_as_float(uniform(a1.y));
-    const FO_GLOBAL int32_t* ci = gconst(P->sell.sci) + sb;
+
+    const FO_GLOBAL void* ci = sell_idx_ptr<VT>(P->sell.sci, sb);
     const FO_GLOBAL void* dv = value_ptr<VT>(P->sell.sdv, sb);
     const FO_GLOBAL void* lv = value_ptr<VT>(P->sell.slv, sb);
     for (int q = lane; q < nq; q += kWave) {
       const uint32_t e = (uint32_t)(q >> lg2) * 256u + (uint32_t)(p * lpr + (q & (lpr - 1))) * 4u;
-      const v4i c4 = load_idx4(ci + e);
+      const v4i c4 = sell_idx4<VT>(ci, e);
       const v4f d4 = VLoad<VT>::q4(dv, e);
       const v4f l4 = VLoad<VT>::q4(lv, e);
       // padding slots hold the value 0 and add nothing
@@ -660,8 +687,8 @@ __global__ __launch_bounds__(kScatterBlock) void k_scatter(const DevPlan* __rest
   __syncthreads();
   // non-zero sums only, with a bit mask per 64 columns saying which were written
   const int nwords = (C + kWave - 1) / kWave;
-  FO_GLOBAL int64_t* out = gmut(P->spart) + (int64_t)blockIdx.x * C;
-  FO_GLOBAL uint64_t* msk = gmut(P->smask) + (int64_t)blockIdx.x * nwords;
+  FO_GLOBAL int64_t* out = gmut(P->spart) + (int64_t)wg * C;
+  FO_GLOBAL uint64_t* msk = gmut(P->smask) + (int64_t)wg * nwords;
   for (int w = wave; w < nwords; w += kScatterBlock / kWave) {
     const int j = w * kWave + lane;
     const int64_t v = j < C ? (int64_t)facc[j] : 0;
@@ -688,15 +715,17 @@ __device__ __forceinline__ void project_column(const DevPlan* __restrict__ P, in
 // Sum of the scatter workgroups' shares for 64 columns (16 waves take every 16th
 // share; integer sums, so the grouping does not matter), then the update.
 template <int MODE>
-__global__ __launch_bounds__(kScatterBlock) void k_scatter_sum(const DevPlan* __restrict__ plans) {
+__global__ __launch_bounds__(kScatterBlock) void k_scatter_sum(const DevPlan* __restrict__ plans,
+                                                              const ScItem* __restrict__ items) {
   __shared__ int64_t part[kScatterBlock / kWave][kWave];
-  const DevPlan* __restrict__ P = plans;
+  const ScItem item = items[blockIdx.x];
+  const DevPlan* __restrict__ P = plans + item.plan;
   if (!P->st->proj_scatter) return;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   const int C = (int)P->C, nwords = (C + kWave - 1) / kWave;
-  const int j = blockIdx.x * kWave + lane;
+  const int j = item.idx * kWave + lane;
   const FO_GLOBAL int64_t* sp = gconst(P->spart) + j;
-  const FO_GLOBAL uint64_t* mk = gconst(P->smask) + blockIdx.x;
+  const FO_GLOBAL uint64_t* mk = gconst(P->smask) + item.idx;
   // all masks first, then the shares they mark: two dependent rounds of loads
   constexpr int kNW = kScatterBlock / kWave, kPer = kScatterMaxWGs / kNW;
   const int NW = P->n_scatter;
@@ -900,7 +929,13 @@ static void launch_forward_vs(int mode, const DevPlan* plans, const FwdGroup* gr
 void launch_forward(int vtype, int mode, int sub, const DevPlan* plans, const FwdGroup* groups,
                     int n_groups, int grid, int lds_floats, uint32_t* ctr, int vsel,
                     hipStream_t s) {
-  if (vtype == kF16) {
+  if (vtype == kF16I) {
+    if (sub) launch_forward_vs<kF16I, 1>(mode, plans, groups, n_groups, grid, lds_floats, ctr, vsel, s);
+    else launch_forward_vs<kF16I, 0>(mode, plans, groups, n_groups, grid, lds_floats, ctr, vsel, s);
+  } else if (vtype == kBF16I) {
+    if (sub) launch_forward_vs<kBF16I, 1>(mode, plans, groups, n_groups, grid, lds_floats, ctr, vsel, s);
+    else launch_forward_vs<kBF16I, 0>(mode, plans, groups, n_groups, grid, lds_floats, ctr, vsel, s);
+  } else if (vtype == kF16) {
     if (sub) launch_forward_vs<kF16, 1>(mode, plans, groups, n_groups, grid, lds_floats, ctr, vsel, s);
     else launch_forward_vs<kF16, 0>(mode, plans, groups, n_groups, grid, lds_floats, ctr, vsel, s);
   } else if (vtype == kBF16) {
@@ -923,6 +958,7 @@ void launch_rows(int mode, const DevPlan* plans, const RowItem* items, int n_ite
 template <int TAG>
 static void launch_tr_tag(int vtype, const DevPlan* plans, const TrItem* items, int n_items,
                           int grid, int nb8, hipStream_t s) {
+  vtype = value_of(vtype);  // the column-major copy keeps int32 row indices
   if (vtype == kF16)
     k_tr_chunks<kF16, TAG><<<grid, kBlock, 0, s>>>(plans, items, n_items, nb8);
   else if (vtype == kBF16)
@@ -948,32 +984,37 @@ void launch_active_list(const DevPlan* plans, const FwdGroup* groups, int n_grou
   if (n_groups > 0) k_active_list<<<n_groups, kFwdBlock, 0, s>>>(plans, groups, n_groups);
 }
 
-void launch_scatter(int vtype, const DevPlan* plans, int n_scatter, int C, hipStream_t s) {
-  if (n_scatter <= 0) return;
-  const size_t lds = (size_t)C * sizeof(unsigned long long);
-  if (vtype == kF16)
-    k_scatter<kF16><<<n_scatter, kScatterBlock, lds, s>>>(plans);
+void launch_scatter(int vtype, const DevPlan* plans, const ScItem* items, int n_items,
+                    size_t lds_bytes, hipStream_t s) {
+  if (n_items <= 0) return;
+  if (vtype == kF16I)
+    k_scatter<kF16I><<<n_items, kScatterBlock, lds_bytes, s>>>(plans, items);
+  else if (vtype == kBF16I)
+    k_scatter<kBF16I><<<n_items, kScatterBlock, lds_bytes, s>>>(plans, items);
+  else if (vtype == kF16)
+    k_scatter<kF16><<<n_items, kScatterBlock, lds_bytes, s>>>(plans, items);
   else if (vtype == kBF16)
-    k_scatter<kBF16><<<n_scatter, kScatterBlock, lds, s>>>(plans);
+    k_scatter<kBF16><<<n_items, kScatterBlock, lds_bytes, s>>>(plans, items);
   else
-    k_scatter<kF32><<<n_scatter, kScatterBlock, lds, s>>>(plans);
+    k_scatter<kF32><<<n_items, kScatterBlock, lds_bytes, s>>>(plans, items);
 }
 
-void launch_scatter_sum(int mode, const DevPlan* plans, int n_scatter, int C, hipStream_t s) {
-  if (n_scatter <= 0) return;
-  const int nb = (C + kWave - 1) / kWave;
+void launch_scatter_sum(int mode, const DevPlan* plans, const ScItem* items, int n_items,
+                        hipStream_t s) {
+  if (n_items <= 0) return;
   if (mode == kColProjY)
-    k_scatter_sum<kColProjY><<<nb, kScatterBlock, 0, s>>>(plans);
+    k_scatter_sum<kColProjY><<<n_items, kScatterBlock, 0, s>>>(plans, items);
   else if (mode == kColProjMove)
-    k_scatter_sum<kColProjMove><<<nb, kScatterBlock, 0, s>>>(plans);
+    k_scatter_sum<kColProjMove><<<n_items, kScatterBlock, 0, s>>>(plans, items);
   else
-    k_scatter_sum<kColProj><<<nb, kScatterBlock, 0, s>>>(plans);
+    k_scatter_sum<kColProj><<<n_items, kScatterBlock, 0, s>>>(plans, items);
 }
 
 hipError_t set_scatter_lds_limit(size_t bytes) {
   hipError_t e = hipSuccess;
   for (const void* f : {(const void*)k_scatter<kF32>, (const void*)k_scatter<kF16>,
-                        (const void*)k_scatter<kBF16>}) {
+                        (const void*)k_scatter<kBF16>, (const void*)k_scatter<kF16I>,
+                        (const void*)k_scatter<kBF16I>}) {
     const hipError_t r =
         hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (r != hipSuccess) e = r;
@@ -1029,6 +1070,8 @@ static hipError_t set_lds_vt(size_t bytes) {
 }
 
 hipError_t set_forward_lds_limit(int vtype, size_t bytes) {
+  if (vtype == kF16I) return set_lds_vt<kF16I>(bytes);
+  if (vtype == kBF16I) return set_lds_vt<kBF16I>(bytes);
   if (vtype == kF16) return set_lds_vt<kF16>(bytes);
   if (vtype == kBF16) return set_lds_vt<kBF16>(bytes);
   return set_lds_vt<kF32>(bytes);

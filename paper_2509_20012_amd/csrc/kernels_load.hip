@@ -94,7 +94,8 @@ __global__ __launch_bounds__(kBlock) void k_pack_sell(int vtype, int64_t R, int 
                                                       const float* __restrict__ scale,
                                                       const int32_t* __restrict__ rslice,
                                                       const int64_t* __restrict__ sbase,
-                                                      int32_t* sci, void* sdv, void* slv) {
+                                                      void* sci, int idx16, void* sdv,
+                                                      void* slv) {
   const int64_t row = (int64_t)blockIdx.x * kRowsPerWg + threadIdx.x / kWave;
   const int lane = threadIdx.x % kWave;
   if (row >= R) return;
@@ -112,7 +113,10 @@ __global__ __launch_bounds__(kBlock) void k_pack_sell(int vtype, int64_t R, int 
     const int64_t slot = base + t * 256 + ((int64_t)p * lpr + j) * 4 + (e & 3);
     const int32_t c = col[a + e];
     const float sc = scale ? scale[c] : 1.f;
-    sci[slot] = c;
+    if (idx16)
+      static_cast<uint16_t*>(sci)[slot] = (uint16_t)c;
+    else
+      static_cast<int32_t*>(sci)[slot] = c;
     store_value(vtype, sdv, slot, dv[a + e], sc);
     store_value(vtype, slv, slot, lv[a + e], sc);
   }
@@ -328,11 +332,11 @@ __global__ __launch_bounds__(kBlock) void k_pack_sub(int vtype, int src_lg2, int
                                                      const int32_t* __restrict__ dst_pos,
                                                      const int32_t* __restrict__ len,
                                                      const int64_t* __restrict__ src_base,
-                                                     const int32_t* __restrict__ src_ci,
+                                                     const void* __restrict__ src_ci,
                                                      const void* __restrict__ src_dv,
                                                      const void* __restrict__ src_lv,
                                                      const int64_t* __restrict__ dst_base,
-                                                     int32_t* dst_ci, void* dst_dv,
+                                                     void* dst_ci, int idx16, void* dst_dv,
                                                      void* dst_lv) {
   const int64_t i = (int64_t)blockIdx.x * kRowsPerWg + threadIdx.x / kWave;
   const int lane = threadIdx.x % kWave;
@@ -347,7 +351,10 @@ __global__ __launch_bounds__(kBlock) void k_pack_sub(int vtype, int src_lg2, int
     const int64_t quad = e >> 2;
     const int64_t os = sb + (quad >> src_lg2) * 256 + (spp * slpr + (quad & (slpr - 1))) * 4 + (e & 3);
     const int64_t od = db + (quad >> dst_lg2) * 256 + (dpp * dlpr + (quad & (dlpr - 1))) * 4 + (e & 3);
-    dst_ci[od] = src_ci[os];
+    if (idx16)
+      static_cast<uint16_t*>(dst_ci)[od] = static_cast<const uint16_t*>(src_ci)[os];
+    else
+      static_cast<int32_t*>(dst_ci)[od] = static_cast<const int32_t*>(src_ci)[os];
     if (vtype == kF32) {
       static_cast<float*>(dst_dv)[od] = static_cast<const float*>(src_dv)[os];
       static_cast<float*>(dst_lv)[od] = static_cast<const float*>(src_lv)[os];
@@ -382,11 +389,11 @@ void launch_col_scale(int64_t C, const uint32_t* bits, float* scale, hipStream_t
 
 void launch_pack_sell(int vtype, int64_t R, int lpr_log2, const int64_t* row_ptr,
                       const int32_t* col, const float* dv, const float* lv, const float* scale,
-                      const int32_t* rslice, const int64_t* sbase, int32_t* sci, void* sdv,
-                      void* slv, hipStream_t s) {
+                      const int32_t* rslice, const int64_t* sbase, void* sci, int idx16,
+                      void* sdv, void* slv, hipStream_t s) {
   if (R > 0)
     k_pack_sell<<<row_grid(R), kBlock, 0, s>>>(vtype, R, lpr_log2, row_ptr, col, dv, lv, scale,
-                                                rslice, sbase, sci, sdv, slv);
+                                                rslice, sbase, sci, idx16, sdv, slv);
 }
 
 void launch_block_count(int64_t R, int64_t C, int rows_per_block, const int64_t* row_ptr,
@@ -431,13 +438,13 @@ void launch_obj_fill(int vtype, int64_t C, const int64_t* cp, const uint32_t* le
 
 void launch_pack_sub(int vtype, int src_lg2, int dst_lg2, int64_t n, const int32_t* src_pos,
                      const int32_t* dst_pos, const int32_t* len, const int64_t* src_base,
-                     const int32_t* src_ci, const void* src_dv, const void* src_lv,
-                     const int64_t* dst_base, int32_t* dst_ci, void* dst_dv, void* dst_lv,
-                     hipStream_t s) {
+                     const void* src_ci, const void* src_dv, const void* src_lv,
+                     const int64_t* dst_base, void* dst_ci, int idx16, void* dst_dv,
+                     void* dst_lv, hipStream_t s) {
   if (n > 0)
-    k_pack_sub<<<row_grid(n), kBlock, 0, s>>>(vtype, src_lg2, dst_lg2, n, src_pos, dst_pos, len, src_base,
-                                               src_ci, src_dv, src_lv, dst_base, dst_ci, dst_dv,
-                                               dst_lv);
+    k_pack_sub<<<row_grid(n), kBlock, 0, s>>>(vtype, src_lg2, dst_lg2, n, src_pos, dst_pos, len,
+                                               src_base, src_ci, src_dv, src_lv, dst_base, dst_ci,
+                                               idx16, dst_dv, dst_lv);
 }
 
 void launch_check_problem(int64_t R, const uint16_t* kind, const float* dlo, const float* dhi,

@@ -53,6 +53,7 @@ inline size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 inline bool scatter_fits(int64_t C) { return (size_t)C * sizeof(int64_t) <= kScatterLdsMax; }
 
 int value_bytes(int storage) { return storage == FREDOPT_F32 ? 4 : 2; }
+int index_bytes(int storage) { return index16(storage) ? 2 : 4; }  // row-major copy
 
 int auto_lpr_log2(int64_t R, int64_t nnz) {
   const double avg = R > 0 ? (double)nnz / (double)R : 0.0;
@@ -135,7 +136,8 @@ struct Layout {
   size_t gri, gcdv, gclv, gcol_tslot0, gcol_nch, ocp, ocount, gtr_items;
   size_t y, osbase, oswidth, osrow, osci, osdv, oslv, ogroups, pk_src, pk_dst, pk_len;
   size_t spart_a, spart_b, rpart, gpart, tpart, groups, row_items, tr_items, col_blocks;
-  size_t bc, colcount, colmax, flags, rslice, rsum, goff, alist, spart, smask, total;
+  size_t bc, colcount, colmax, flags, rslice, rsum, goff, alist, spart, smask, sc_items,
+      ss_items, total;
   int64_t sell_slots, n_slices, csc_slots, obj_slots, max_rows, max_tr, n_groups, n_col_blocks;
   int64_t obj_sell_slots, max_obj_slices, max_obj_groups, max_obj_srow;
   int64_t rows_per_block, nb;
@@ -150,7 +152,8 @@ bool make_layout(int64_t R, int64_t C, int64_t nnz, int storage, int lpr_log2,
                  int64_t sell_slots, int64_t n_slices, int reserve_pct, Layout* L) {
   if (R < 0 || C < 1 || nnz < 0 || R >= (int64_t(1) << 31) || C >= (int64_t(1) << 31))
     return false;
-  if (storage < FREDOPT_F32 || storage > FREDOPT_BF16) return false;
+  if (storage < FREDOPT_F32 || storage > FREDOPT_BF16_IDX16) return false;
+  if (index16(storage) && C > 65536) return false;
   const int64_t csc = nnz + 3 * C;
   if (csc >= (int64_t(1) << 32) - 4) return false;
   const int rpw = kWave >> lpr_log2;
@@ -184,7 +187,7 @@ bool make_layout(int64_t R, int64_t C, int64_t nnz, int storage, int lpr_log2,
   L->sbase = take(sizeof(int64_t) * (n_slices + 1));
   L->swidth = take(sizeof(int32_t) * (n_slices + 1));
   L->srow = take(sizeof(int32_t) * (n_slices * rpw + 1));
-  L->sci = take(sizeof(int32_t) * sell_slots);
+  L->sci = take((size_t)index_bytes(storage) * sell_slots);
   L->sdv = take((size_t)vb * sell_slots);
   L->slv = take((size_t)vb * sell_slots);
   L->cp = take(sizeof(int64_t) * (C + 1));
@@ -206,7 +209,7 @@ bool make_layout(int64_t R, int64_t C, int64_t nnz, int storage, int lpr_log2,
   L->oswidth = take(sizeof(int32_t) * (L->max_obj_slices + 1));
   L->max_obj_srow = reserve_pct > 0 ? R + (R / kSortWindow + 2) * kWave + 1 : 1;
   L->osrow = take(sizeof(int32_t) * L->max_obj_srow);
-  L->osci = take(sizeof(int32_t) * L->obj_sell_slots);
+  L->osci = take((size_t)index_bytes(storage) * L->obj_sell_slots);
   L->osdv = take((size_t)vb * L->obj_sell_slots);
   L->oslv = take((size_t)vb * L->obj_sell_slots);
   L->ogroups = take(sizeof(FwdGroup) * L->max_obj_groups);
@@ -241,6 +244,8 @@ bool make_layout(int64_t R, int64_t C, int64_t nnz, int storage, int lpr_log2,
   L->spart = take(scatter_fits(C) ? sizeof(int64_t) * kScatterMaxWGs * C : sizeof(int64_t));
   L->smask = take(scatter_fits(C) ? sizeof(uint64_t) * kScatterMaxWGs * ((C + 63) / 64)
                                   : sizeof(uint64_t));
+  L->sc_items = take(sizeof(ScItem) * kScatterMaxWGs);
+  L->ss_items = take(sizeof(ScItem) * ((C + 63) / 64));
   L->total = o;
   return true;
 }
@@ -309,6 +314,9 @@ struct fredopt_plan {
   TrItem* d_tr = nullptr;
   TrItem* d_gtr = nullptr;
   ColBlock* d_cblocks = nullptr;
+  std::vector<ScItem> sc_items, ss_items;  // active-row scatter and share-sum workgroups
+  ScItem* d_sc = nullptr;
+  ScItem* d_ss = nullptr;
   hipStream_t cap = nullptr;
   hipGraphExec_t graph = nullptr;
   int graph_r = -1;
@@ -387,6 +395,28 @@ fredopt_status upload_tr(fredopt_plan* p, hipStream_t s) {
                         hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(p->d_cblocks, p->cblocks.data(), sizeof(ColBlock) * p->cblocks.size(),
                         hipMemcpyHostToDevice, s));
+  return FREDOPT_OK;
+}
+
+// Workgroups of the active-row scatter of a plan (n shares, share w -> {plan, w})
+// and of its share sum (one per 64 columns).
+void scatter_items(int32_t plan, int n, int64_t C, std::vector<ScItem>* sc,
+                   std::vector<ScItem>* ss) {
+  for (int w = 0; w < n; ++w) sc->push_back(ScItem{plan, w});
+  if (n > 0)
+    for (int64_t j = 0; j < (C + 63) / 64; ++j) ss->push_back(ScItem{plan, (int32_t)j});
+}
+
+fredopt_status upload_scatter_items(fredopt_plan* p, hipStream_t s) {
+  p->sc_items.clear();
+  p->ss_items.clear();
+  scatter_items(0, p->n_scatter, p->C, &p->sc_items, &p->ss_items);
+  if (!p->sc_items.empty()) {
+    HIPCHK(hipMemcpyAsync(p->d_sc, p->sc_items.data(), sizeof(ScItem) * p->sc_items.size(),
+                          hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(p->d_ss, p->ss_items.data(), sizeof(ScItem) * p->ss_items.size(),
+                          hipMemcpyHostToDevice, s));
+  }
   return FREDOPT_OK;
 }
 
@@ -498,7 +528,7 @@ fredopt_status prepare_gradient(fredopt_plan* p, const fredopt_problem* pr, hipS
     HIPCHK(hipMemsetAsync(p->ws + L.gri, 0, sizeof(int32_t) * ocp[p->C], s));
     HIPCHK(hipMemsetAsync(p->ws + L.gcdv, 0, (size_t)vb * ocp[p->C], s));
     HIPCHK(hipMemsetAsync(p->ws + L.gclv, 0, (size_t)vb * ocp[p->C], s));
-    launch_obj_fill(p->storage, p->C, d_cp, at<uint32_t>(p, L.colcount), h.ri, h.cdv, h.clv,
+    launch_obj_fill(value_of(p->storage), p->C, d_cp, at<uint32_t>(p, L.colcount), h.ri, h.cdv, h.clv,
                     pr->kind, at<int64_t>(p, L.ocp), at<int32_t>(p, L.gri), p->ws + L.gcdv,
                     p->ws + L.gclv, s);
     HIPCHK(hipGetLastError());
@@ -599,19 +629,19 @@ fredopt_status prepare_objective_view(fredopt_plan* p, const fredopt_problem* pr
                           hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(p->ws + L.pk_len, len.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
   }
-  HIPCHK(hipMemsetAsync(p->ws + L.osci, 0, sizeof(int32_t) * O.slots, s));
+  HIPCHK(hipMemsetAsync(p->ws + L.osci, 0, (size_t)index_bytes(p->storage) * O.slots, s));
   HIPCHK(hipMemsetAsync(p->ws + L.osdv, 0, (size_t)vb * O.slots, s));
   HIPCHK(hipMemsetAsync(p->ws + L.oslv, 0, (size_t)vb * O.slots, s));
-  launch_pack_sub(p->storage, p->sell.lpr_log2, olg, n, at<int32_t>(p, L.pk_src),
+  launch_pack_sub(value_of(p->storage), p->sell.lpr_log2, olg, n, at<int32_t>(p, L.pk_src),
                   at<int32_t>(p, L.pk_dst), at<int32_t>(p, L.pk_len), h.sell.sbase, h.sell.sci,
-                  h.sell.sdv, h.sell.slv, at<int64_t>(p, L.osbase), at<int32_t>(p, L.osci),
-                  p->ws + L.osdv, p->ws + L.oslv, s);
+                  h.sell.sdv, h.sell.slv, at<int64_t>(p, L.osbase), p->ws + L.osci,
+                  index16(p->storage) ? 1 : 0, p->ws + L.osdv, p->ws + L.oslv, s);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));
   h.osell.sbase = at<int64_t>(p, L.osbase);
   h.osell.swidth = at<int32_t>(p, L.oswidth);
   h.osell.srow = at<int32_t>(p, L.osrow);
-  h.osell.sci = at<int32_t>(p, L.osci);
+  h.osell.sci = p->ws + L.osci;
   h.osell.sdv = p->ws + L.osdv;
   h.osell.slv = p->ws + L.oslv;
   h.osell.n_slices = (int32_t)O.n_slices;
@@ -743,7 +773,11 @@ struct Exec {
   const ColBlock* cblocks = nullptr;
   int n_cblocks = 0;
   uint32_t* ctr = nullptr;
-  int n_scatter = 0, C = 0;   // active-row scatter (single plans only)
+  const ScItem* sc = nullptr;  // active-row scatter workgroups (0: off)
+  int n_sc = 0;
+  const ScItem* ss = nullptr;  // their share sums, 64 columns each
+  int n_ss = 0;
+  size_t sc_lds = 0;           // LDS bytes of a scatter workgroup (widest plan)
 };
 
 Exec exec_of(const fredopt_plan* p) {
@@ -767,8 +801,11 @@ Exec exec_of(const fredopt_plan* p) {
   e.cblocks = p->d_cblocks;
   e.n_cblocks = (int)p->cblocks.size();
   e.ctr = p->d_ctr;
-  e.n_scatter = p->n_scatter;
-  e.C = (int)p->C;
+  e.sc = p->d_sc;
+  e.n_sc = (int)p->sc_items.size();
+  e.ss = p->d_ss;
+  e.n_ss = (int)p->ss_items.size();
+  e.sc_lds = (size_t)p->C * sizeof(int64_t);
   return e;
 }
 
@@ -797,13 +834,13 @@ void enqueue(const Exec& e, const Launch& l, hipStream_t s) {
       launch_tcol(l.mode, e.table, e.cblocks, e.n_cblocks, s);
       break;
     case kKindList:
-      if (e.n_scatter > 0) launch_active_list(e.table, e.groups, e.n_groups, s);
+      if (e.n_sc > 0) launch_active_list(e.table, e.groups, e.n_groups, s);
       break;
     case kKindScatter:
-      if (e.n_scatter > 0) launch_scatter(e.storage, e.table, e.n_scatter, e.C, s);
+      launch_scatter(e.storage, e.table, e.sc, e.n_sc, e.sc_lds, s);
       break;
     case kKindScatterSum:
-      if (e.n_scatter > 0) launch_scatter_sum(l.mode, e.table, e.n_scatter, e.C, s);
+      if (e.n_sc > 0) launch_scatter_sum(l.mode, e.table, e.ss, e.n_ss, s);
       break;
     default:
       launch_finalize(l.mode, l.sub, e.table, e.n_plans, s);
@@ -868,7 +905,8 @@ fredopt_status device_limits(fredopt_plan* p) {
   // next to their static LDS (plans of every size share the kernels)
   const size_t static_lds = 2048;
   const size_t dyn_max = p->smem_block > static_lds ? p->smem_block - static_lds : 0;
-  for (int vt = FREDOPT_F32; vt <= FREDOPT_BF16; ++vt) HIPCHK(set_forward_lds_limit(vt, dyn_max));
+  for (int vt = FREDOPT_F32; vt <= FREDOPT_BF16_IDX16; ++vt)
+    HIPCHK(set_forward_lds_limit(vt, dyn_max));
   HIPCHK(set_scatter_lds_limit(dyn_max));
   const size_t need = (size_t)p->C * sizeof(float);
   if (need <= dyn_max) {
@@ -1073,7 +1111,8 @@ fredopt_status fredopt_load_matrices(const fredopt_matrices* m, void* workspace,
   const Sell& S = p->sell;
   int64_t* d_sbase = reinterpret_cast<int64_t*>(ws + L.sbase);
   int32_t* d_rslice = reinterpret_cast<int32_t*>(ws + L.rslice);
-  int32_t* sci = reinterpret_cast<int32_t*>(ws + L.sci);
+  void* sci = ws + L.sci;
+  const int vt = value_of(m->storage);  // value conversion of the load kernels
   LCHK(hipMemcpyAsync(d_sbase, S.base.data(), sizeof(int64_t) * (S.n_slices + 1),
                       hipMemcpyHostToDevice, s));
   if (S.n_slices > 0) {
@@ -1084,12 +1123,12 @@ fredopt_status fredopt_load_matrices(const fredopt_matrices* m, void* workspace,
   }
   if (R > 0)
     LCHK(hipMemcpyAsync(d_rslice, S.rslice.data(), sizeof(int32_t) * R, hipMemcpyHostToDevice, s));
-  LCHK(hipMemsetAsync(sci, 0, sizeof(int32_t) * S.slots, s));
+  LCHK(hipMemsetAsync(sci, 0, (size_t)index_bytes(m->storage) * S.slots, s));
   LCHK(hipMemsetAsync(ws + L.sdv, 0, (size_t)vb * S.slots, s));
   LCHK(hipMemsetAsync(ws + L.slv, 0, (size_t)vb * S.slots, s));
   const float* scale = q16 ? cscale : nullptr;
-  launch_pack_sell(m->storage, R, S.lpr_log2, in_rp, in_col, in_dv, in_lv, scale, d_rslice,
-                   d_sbase, sci, ws + L.sdv, ws + L.slv, s);
+  launch_pack_sell(vt, R, S.lpr_log2, in_rp, in_col, in_dv, in_lv, scale, d_rslice, d_sbase,
+                   sci, index16(m->storage) ? 1 : 0, ws + L.sdv, ws + L.slv, s);
 
   // CSC: zero (padding slots keep row 0, value 0), per-block counts, offsets, fill
   int64_t* d_cp = reinterpret_cast<int64_t*>(ws + L.cp);
@@ -1102,9 +1141,9 @@ fredopt_status fredopt_load_matrices(const fredopt_matrices* m, void* workspace,
   LCHK(hipMemsetAsync(bc, 0, sizeof(uint32_t) * L.nb * C, s));
   launch_block_count(R, C, (int)L.rows_per_block, in_rp, in_col, bc, s);
   launch_block_offsets(C, (int)L.nb, d_cp, bc, s);
-  launch_fill_csc(m->storage, R, C, (int)L.rows_per_block, in_rp, in_col, in_dv, in_lv, scale, bc,
+  launch_fill_csc(vt, R, C, (int)L.rows_per_block, in_rp, in_col, in_dv, in_lv, scale, bc,
                   ri, ws + L.cdv, ws + L.clv, s);
-  launch_moments(m->storage, R, in_rp, in_col, in_dv, in_lv, scale,
+  launch_moments(vt, R, in_rp, in_col, in_dv, in_lv, scale,
                  reinterpret_cast<double*>(ws + L.mom), reinterpret_cast<float*>(ws + L.rsum), s);
   LCHK(hipGetLastError());
 
@@ -1171,6 +1210,10 @@ fredopt_status fredopt_load_matrices(const fredopt_matrices* m, void* workspace,
   h.n_scatter = p->n_scatter;
   h.scatter_max_rows = (int32_t)std::min<int64_t>(p->scatter_max_rows, INT32_MAX);
   h.st = p->d_state;
+  p->d_sc = reinterpret_cast<ScItem*>(ws + L.sc_items);
+  p->d_ss = reinterpret_cast<ScItem*>(ws + L.ss_items);
+  st = upload_scatter_items(p, s);
+  if (st != FREDOPT_OK) return cleanup(st);
   h.prm.ws_fixed = -1.0;
   if ((int64_t)p->groups.size() > L.n_groups || (int64_t)p->rows.size() > L.max_rows)
     return cleanup(fail(FREDOPT_E_WORKSPACE, "work lists exceed the workspace bound"));
@@ -1213,7 +1256,7 @@ fredopt_status fredopt_get_plan_info(const fredopt_plan* p, fredopt_plan_info* i
   info->nnz = p->nnz;
   info->sell_slots = p->sell.slots;
   info->csc_slots = p->cp.empty() ? 0 : p->cp[p->C];
-  info->bytes_per_sell_slot = 4 + 2 * value_bytes(p->storage);
+  info->bytes_per_sell_slot = index_bytes(p->storage) + 2 * value_bytes(p->storage);
   info->bytes_per_csc_slot = 4 + 2 * value_bytes(p->storage);
   info->n_slices = p->sell.n_slices;
   info->tr_items = (int64_t)p->tr.size();
@@ -1424,7 +1467,8 @@ fredopt_status fredopt_set_scatter(fredopt_plan* p, int32_t n_workgroups,
   p->scatter_max_rows = max_active_rows >= 0 ? max_active_rows : p->R / 4;
   p->hp.n_scatter = p->n_scatter;
   p->hp.scatter_max_rows = (int32_t)std::min<int64_t>(p->scatter_max_rows, INT32_MAX);
-  fredopt_status st = upload_table(p, nullptr);
+  fredopt_status st = upload_scatter_items(p, nullptr);
+  if (st == FREDOPT_OK) st = upload_table(p, nullptr);
   if (st != FREDOPT_OK) return st;
   drop_graph(p);
   HIPCHK(hipStreamSynchronize(nullptr));
@@ -1501,7 +1545,9 @@ fredopt_status fredopt_autotune(fredopt_plan* p, const float* x, void* stream) {
 // Several plans iterated by the same launches: one table of plan descriptors and
 // the concatenation of the plans' work lists (each item names its plan).  Every
 // plan keeps its own workspace, state and partial sums, and a plan's items are the
-// ones it has alone, so its arithmetic (and result) does not depend on the batch.
+// ones it has alone, so its arithmetic (and result) does not depend on the batch
+// (the active-row scatter of a plan may get fewer workgroups than alone: its exact
+// integer sums do not depend on how the rows are shared out).
 // Plans with and without the objective-row view follow different iteration
 // schedules: they form two sub-batches whose launch sequences are captured one
 // after the other into the same graph.
@@ -1516,6 +1562,7 @@ struct fredopt_batch {
   std::vector<fredopt_plan*> plans;        // caller's order
   std::vector<fredopt_problem> problems;   // copies; the arrays stay the caller's
   std::vector<int32_t> pos;                // table position of the caller's plan i
+  std::vector<int32_t> nsc;                // active-row scatter workgroups of plan i
   std::vector<SubBatch> subs;
   int device = 0, storage = 0;
   char* ws = nullptr;
@@ -1530,15 +1577,17 @@ struct fredopt_batch {
 namespace {
 
 struct BatchLayout {
-  size_t table, ctr, groups, ogroups, rows, tr, gtr, cblocks, total;
+  size_t table, ctr, groups, ogroups, rows, tr, gtr, cblocks, sc, ss, total;
 };
 
 // Bounds from each plan's own layout, so the size is known before the problems
 // are prepared.
 BatchLayout batch_layout(fredopt_plan* const* plans, int32_t n) {
-  int64_t g = 0, og = 0, rw = 0, t = 0, gt = 0, cb = 0;
+  int64_t g = 0, og = 0, rw = 0, t = 0, gt = 0, cb = 0, sc = 0, ss = 0;
   for (int32_t i = 0; i < n; ++i) {
     const Layout& L = plans[i]->L;
+    sc += kScatterMaxWGs;
+    ss += (plans[i]->C + 63) / 64;
     g += L.n_groups;
     og += L.max_obj_groups;
     rw += L.max_rows;
@@ -1561,6 +1610,8 @@ BatchLayout batch_layout(fredopt_plan* const* plans, int32_t n) {
   B.tr = take(sizeof(TrItem) * t);
   B.gtr = take(sizeof(TrItem) * gt);
   B.cblocks = take(sizeof(ColBlock) * cb);
+  B.sc = take(sizeof(ScItem) * sc);
+  B.ss = take(sizeof(ScItem) * ss);
   B.total = o;
   return B;
 }
@@ -1637,6 +1688,7 @@ fredopt_status fredopt_batch_create(fredopt_plan* const* plans, int32_t n,
   b->ws_bytes = workspace_bytes;
   b->d_table = reinterpret_cast<DevPlan*>(b->ws + B.table);
   b->pos.assign(n, 0);
+  b->nsc.assign(n, 0);
   for (int32_t i = 0; i < n; ++i) {
     b->plans.push_back(plans[i]);
     b->problems.push_back(problems[i]);
@@ -1650,7 +1702,7 @@ fredopt_status fredopt_batch_create(fredopt_plan* const* plans, int32_t n,
     if (!sb.idx.empty()) b->subs.push_back(sb);
   }
   size_t off_g = B.groups, off_og = B.ogroups, off_r = B.rows, off_t = B.tr, off_gt = B.gtr,
-         off_c = B.cblocks;
+         off_c = B.cblocks, off_sc = B.sc, off_ss = B.ss;
   int32_t base = 0;
   bool ok = true;
   for (size_t k = 0; k < b->subs.size(); ++k) {
@@ -1659,7 +1711,9 @@ fredopt_status fredopt_batch_create(fredopt_plan* const* plans, int32_t n,
     std::vector<RowItem> rows;
     std::vector<TrItem> tr, gtr;
     std::vector<ColBlock> cblocks;
+    std::vector<ScItem> sc, ss;
     int lds = 0, wgs = 4;
+    size_t sc_lds = 0;
     bool all_lds = true;
     for (size_t j = 0; j < sb.idx.size(); ++j) {
       fredopt_plan* p = plans[sb.idx[j]];
@@ -1670,6 +1724,14 @@ fredopt_status fredopt_batch_create(fredopt_plan* const* plans, int32_t n,
       append(&tr, p->tr, (int32_t)j);
       append(&gtr, p->gtr, (int32_t)j);
       append(&cblocks, p->cblocks, (int32_t)j);
+      // the active-row path, with workgroups in proportion to the plan (its integer
+      // sums do not depend on how its rows are shared out)
+      const int nsc = p->n_scatter > 0
+                          ? (int)std::min<int64_t>(p->n_scatter, 1 + p->nnz / (int64_t(2) << 20))
+                          : 0;
+      b->nsc[sb.idx[j]] = nsc;
+      scatter_items((int32_t)j, nsc, p->C, &sc, &ss);
+      if (nsc > 0) sc_lds = std::max(sc_lds, (size_t)p->C * sizeof(int64_t));
       lds = std::max(lds, p->lds_floats);
       all_lds = all_lds && p->lds_floats > 0;
       wgs = std::min(wgs, p->wgs_per_cu);
@@ -1695,7 +1757,11 @@ fredopt_status fredopt_batch_create(fredopt_plan* const* plans, int32_t n,
     e.cblocks = place(b->ws, &off_c, cblocks, s, &ok);
     e.n_cblocks = (int)cblocks.size();
     e.ctr = reinterpret_cast<uint32_t*>(b->ws + B.ctr) + kCounters * k;
-    e.n_scatter = 0;  // the projection of a batch streams the column-major copies
+    e.sc = place(b->ws, &off_sc, sc, s, &ok);
+    e.n_sc = (int)sc.size();
+    e.ss = place(b->ws, &off_ss, ss, s, &ok);
+    e.n_ss = (int)ss.size();
+    e.sc_lds = sc_lds;
     base += (int32_t)sb.idx.size();
   }
   fredopt_status st = FREDOPT_OK;
@@ -1747,7 +1813,7 @@ fredopt_status fredopt_batch_solve(fredopt_batch* b, const fredopt_params* q,
     fredopt_plan* p = b->plans[i];
     set_problem(p, &b->problems[i], q, -1.0, x[i]);
     b->table[b->pos[i]] = p->hp;
-    b->table[b->pos[i]].n_scatter = 0;
+    b->table[b->pos[i]].n_scatter = b->nsc[i];
     if ((st = upload_state(p, &states[i], s)) != FREDOPT_OK) return st;
   }
   HIPCHK(hipMemcpyAsync(b->d_table, b->table.data(), sizeof(DevPlan) * n, hipMemcpyHostToDevice,

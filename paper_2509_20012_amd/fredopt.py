@@ -17,8 +17,9 @@ import numpy as np
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libfredopt.so")
 
-F32, F16, BF16 = 0, 1, 2
-STORAGE = {"f32": F32, "fp32": F32, "f16": F16, "fp16": F16, "bf16": BF16}
+F32, F16, BF16, F16_IDX16, BF16_IDX16 = 0, 1, 2, 3, 4
+STORAGE = {"f32": F32, "fp32": F32, "f16": F16, "fp16": F16, "bf16": BF16,
+           "f16i16": F16_IDX16, "bf16i16": BF16_IDX16}
 NORM_CONVEX_ALL, NORM_CONVEX_VIOLATED, NORM_RAW = 0, 1, 2
 KERNEL_NAMES = ("fwd_obj", "tr_grad", "fwd_dir", "rows", "tr_proj", "fwd_resid", "col",
                 "finalize", "active_list", "scatter", "scatter_sum")

@@ -7,9 +7,9 @@ continuous batching, where the batch is rebuilt whenever a request joins or
 leaves, between quanta of outer iterations.  A request's latency runs from its
 arrival to its result (the fluence) being on the host, and includes the load.
 
-Every batched iteration of a plan equals its single-plan iteration with the
-column-major projection bit for bit, and quanta resume exactly, so a request's
-result does not depend on what else was served with it.
+Every batched iteration of a plan equals its single-plan iteration bit for bit,
+and quanta resume exactly, so a request's result does not depend on what else was
+served with it.
 
 The comparison form ("one at a time") serves the same trace first come, first
 served, each request solved alone with the plain single-plan call.
@@ -54,66 +54,104 @@ class _Active:
     def __init__(self, req: Request, storage: int):
         self.req = req
         self.plan, self.prob, self.x = fredopt.load_phantom(req.phantom, storage=storage)
-        fredopt.set_scatter(self.plan, -1, -1)
         self.state = fredopt.new_state()
         self.left = req.iters
         self.bytes = plan_bytes(req.phantom, storage)
 
 
 class Server:
-    """Continuous batching under a device-memory budget."""
+    """Continuous batching under a device-memory budget.
+
+    Requests are split into lanes by size (plans above `big_nnz` entries form their
+    own lane): each lane is a host thread with its own stream and its own batch, so
+    the small plans' launch-bound iterations overlap on the device with the large
+    plans' bandwidth-bound passes instead of waiting for them.  Within a lane,
+    requests are admitted in arrival order while the shared budget allows."""
 
     def __init__(self, budget_bytes: int, params: fredopt.SolverParams, quantum: int = 50,
-                 storage: int = fredopt.F32, log: Optional[Callable[[str], None]] = None):
+                 storage: int = fredopt.F32, big_nnz: int = 20_000_000,
+                 log: Optional[Callable[[str], None]] = None):
+        fredopt.lib()
         self.budget = int(budget_bytes)
         self.params = params
         self.quantum = int(quantum)
         self.storage = storage
+        self.big_nnz = int(big_nnz)
         self.log = log or (lambda m: None)
         self.batches_built = 0
         self.peak_active = 0
         self.peak_bytes = 0
 
     def run(self, requests: List[Request]) -> List[Request]:
-        import torch
+        import threading
         queue = sorted(requests, key=lambda r: (r.arrival, r.rid))
         for r in queue:
             if plan_bytes(r.phantom, self.storage) > self.budget:
                 raise ValueError(f"request {r.rid} alone exceeds the memory budget")
-        active: List[_Active] = []
+        lanes = [[r for r in queue if r.phantom.nnz <= self.big_nnz],
+                 [r for r in queue if r.phantom.nnz > self.big_nnz]]
+        lock = threading.Lock()
+        state = {"used": 0, "active": 0}
         done: List[Request] = []
-        batch = None
-        used = 0
+        errors: List[BaseException] = []
         t0 = time.perf_counter()
         now = lambda: time.perf_counter() - t0  # noqa: E731
+
+        def lane_loop(reqs: List[Request]):
+            import torch
+            stream = torch.cuda.Stream()
+            with torch.cuda.stream(stream):
+                self._lane(reqs, lock, state, done, now)
+
+        def guarded(reqs):
+            try:
+                lane_loop(reqs)
+            except BaseException as e:  # surfaced after the join
+                errors.append(e)
+
+        threads = [threading.Thread(target=guarded, args=(l,)) for l in lanes if l]
+        for t in threads:
+            t.start()
+        for t in threads:
+            t.join()
+        if errors:
+            raise errors[0]
+        return sorted(done, key=lambda r: r.rid)
+
+    def _lane(self, queue, lock, state, done, now):
+        import torch
+        params = dataclasses.replace(self.params)
+        active: List[_Active] = []
+        batch = None
         qi = 0
         while qi < len(queue) or active:
             changed = False
-            # admit what has arrived, in arrival order, while it fits
             while qi < len(queue) and queue[qi].arrival <= now():
                 need = plan_bytes(queue[qi].phantom, self.storage)
-                if used + need > self.budget:
-                    break
+                with lock:
+                    if state["used"] + need > self.budget:
+                        break
+                    state["used"] += need
+                    state["active"] += 1
+                    self.peak_bytes = max(self.peak_bytes, state["used"])
+                    self.peak_active = max(self.peak_active, state["active"])
                 req = queue[qi]
                 qi += 1
                 req.admitted = now()
                 active.append(_Active(req, self.storage))
-                used += need
                 changed = True
             if not active:
-                # idle until the next arrival
-                time.sleep(max(0.0, queue[qi].arrival - now()))
+                wait = queue[qi].arrival - now() if qi < len(queue) else 0.0
+                time.sleep(wait if wait > 0 else 0.001)  # next arrival, or budget freed
                 continue
-            self.peak_active = max(self.peak_active, len(active))
-            self.peak_bytes = max(self.peak_bytes, used)
             if changed or batch is None:
                 if batch is not None:
                     batch.free()
                 batch = fredopt.Batch([a.plan for a in active], [a.prob for a in active])
-                self.batches_built += 1
+                with lock:
+                    self.batches_built += 1
             n = min(self.quantum, min(a.left for a in active))
-            self.params.iter_max = n
-            batch.solve(self.params, [a.state for a in active], [a.x for a in active], n)
+            batch.solve(params, [a.state for a in active], [a.x for a in active], n)
             for a in active:
                 a.left -= n
             finished = [a for a in active if a.left == 0]
@@ -123,16 +161,20 @@ class Server:
                     req.x = a.x.cpu().numpy()
                     req.k, req.s = a.state.k, a.state.s
                     req.finished = now()
-                    done.append(req)
-                    used -= a.bytes
                 batch.free()
                 batch = None
                 active = [a for a in active if a.left > 0]
                 for a in finished:
                     a.plan.free()
+                torch.cuda.current_stream().synchronize()
+                with lock:
+                    for a in finished:
+                        done.append(a.req)
+                        state["used"] -= a.bytes
+                        state["active"] -= 1
                 del finished
-                torch.cuda.synchronize()
-        return done
+        if batch is not None:
+            batch.free()
 
 
 def serve_one_at_a_time(requests: List[Request], params: fredopt.SolverParams,

@@ -53,6 +53,11 @@ def test_workspace_bytes():
     # the matrices alone: two copies of 4-byte indices + two FP32 values per slot
     assert b >= 2 * 12 * 20_000
     assert b % 256 == 0
+    # 16-bit column indices: smaller than 16-bit values alone; only up to 65,536 columns
+    h16 = fredopt.workspace_bytes(1000, 100, 20_000, fredopt.F16_IDX16)
+    assert 0 < h16 < h
+    assert fredopt.workspace_bytes(1000, 65_536, 20_000, fredopt.BF16_IDX16) > 0
+    assert fredopt.workspace_bytes(1000, 65_537, 20_000, fredopt.BF16_IDX16) == 0
 
 
 def test_null_arguments_rejected_without_device():

@@ -1,8 +1,9 @@
 """Batched form: several plans of uneven size iterated by the same launches.
 
-A plan's iterates in a batch must equal, bit for bit, its iterates alone with the
-column-major projection (the batch uses that path); and they must match the oracle
-to the T2 tier.
+A plan's iterates in a batch must equal, bit for bit, its iterates alone (the
+active-row projection sums in exact fixed point, so sharing its rows among a
+different number of workgroups changes nothing); and they must match the oracle to
+the T2 tier.
 """
 import numpy as np
 import pytest
@@ -40,7 +41,6 @@ def _mix():
 
 def _alone(fo, p, q, iters, reserve):
     plan, prob, x0 = fo.load_phantom(p, gradient_reserve_pct=reserve)
-    fo.set_scatter(plan, -1, -1)
     x = x0.clone()
     st = fo.new_state()
     q.iter_max = iters

@@ -26,7 +26,9 @@ pytestmark = pytest.mark.gpu
 T1 = 1e-5
 T2 = 1e-5
 T3 = 5e-3
-UNIT_ROUNDOFF = {"f16": 2.0 ** -11, "bf16": 2.0 ** -8}
+UNIT_ROUNDOFF = {"f16": 2.0 ** -11, "bf16": 2.0 ** -8, "f16i16": 2.0 ** -11,
+                 "bf16i16": 2.0 ** -8}
+NAMES = ["f16", "bf16", "f16i16", "bf16i16"]   # i16: 16-bit column indices as well
 
 
 @pytest.fixture(scope="module")
@@ -45,7 +47,8 @@ def w32():
 
 
 def _storage(fo, name):
-    return {"f16": fo.F16, "bf16": fo.BF16}[name]
+    return {"f16": fo.F16, "bf16": fo.BF16, "f16i16": fo.F16_IDX16,
+            "bf16i16": fo.BF16_IDX16}[name]
 
 
 def _bf16_rne(v32: np.ndarray) -> np.ndarray:
@@ -63,7 +66,7 @@ def dequantised(p, name):
     out = []
     for v in (p.d_val, p.l_val):
         q = (v / s[col]).astype(np.float32)
-        qs = q.astype(np.float16).astype(np.float64) if name == "f16" else \
+        qs = q.astype(np.float16).astype(np.float64) if name.startswith("f16") else \
             _bf16_rne(q).astype(np.float64)
         out.append(qs * s[col].astype(np.float64))
     return out
@@ -84,7 +87,7 @@ def _oparams(q):
                         normalization=q.normalization, line_search=1)
 
 
-@pytest.mark.parametrize("name", ["f16", "bf16"])
+@pytest.mark.parametrize("name", NAMES)
 def test_dose_let_precision(fo, w32, name):
     import torch
     print(f"precision dose_let water32 {name}", flush=True)
@@ -108,13 +111,13 @@ def test_dose_let_precision(fo, w32, name):
     u = UNIT_ROUNDOFF[name]
     assert errs_o[0] <= u + T1 and errs_o[1] <= u + T1
     assert errs_o[2] <= 2 * u / (1 - u) + T1
-    if name == "f16":
+    if name.startswith("f16"):
         assert max(errs_o) <= 1e-3
     assert np.all(dg[~m] == 0.0)
 
 
 @pytest.mark.parametrize("path", ["csc", "scatter"])
-@pytest.mark.parametrize("name", ["f16", "bf16"])
+@pytest.mark.parametrize("name", NAMES)
 def test_superiorize_step_precision(fo, w32, name, path):
     """T2 against the oracle on the dequantised values, both projection paths."""
     print(f"precision superiorize_step water32 {name} {path}", flush=True)
@@ -136,7 +139,7 @@ def test_superiorize_step_precision(fo, w32, name, path):
         assert st.cost == pytest.approx(info["cost_before"], rel=1e-5)
 
 
-@pytest.mark.parametrize("name", ["f16", "bf16"])
+@pytest.mark.parametrize("name", NAMES)
 def test_solve_precision_plan_quality(fo, w32, name):
     """T3 against the oracle on the original FP32 values (100 iterations)."""
     import torch
