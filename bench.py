@@ -126,17 +126,30 @@ def _timed(fn):
 
 
 def bench_batch(args):
-    """48 plans of uneven size (5k-120k rows, 200-4,000 beamlets, one draw per plan),
-    iterated by batched launches, against the same plans solved one at a time."""
+    """48 plans iterated by batched launches, against the same plans solved one at a
+    time.  batch48: uneven sizes (5k-120k rows, 200-4,000 beamlets, one draw per
+    plan); scenarios48: 6 of those plans under 8 robustness scenarios each."""
     import torch
-    from paper_2509_20012_amd import fredopt, phantom as ph
-    sizes = ph.batch_sizes(48, seed=3)
+    from paper_2509_20012_amd import autotune, fredopt, phantom as ph
     t0 = time.perf_counter()
-    phs = [ph.small_plan(sd, r, c) for sd, r, c in sizes]
+    if args.workload == "scenarios48":
+        phs = ph.scenario_plans(6, seed=3)
+        desc = "scenarios48: 6 water plans x 8 robustness scenarios (range +-3.5 %, +-3 mm shifts)"
+    else:
+        phs = [ph.small_plan(sd, r, c) for sd, r, c in ph.batch_sizes(48, seed=3)]
+        desc = "batch48: 48 water plans, 5k-120k rows, 200-4000 beamlets"
     nnz = sum(p.nnz for p in phs)
-    log(f"48 plans: rows {sum(p.n_rows for p in phs)}, nnz {nnz} in {time.perf_counter() - t0:.1f} s")
+    log(f"{len(phs)} plans: rows {sum(p.n_rows for p in phs)}, nnz {nnz} in "
+        f"{time.perf_counter() - t0:.1f} s")
     storage = fredopt.STORAGE[args.storage]
-    loaded = [fredopt.load_phantom(p, storage=storage) for p in phs]
+    lanes = [0] * len(phs)
+    if args.autotune:
+        t0 = time.perf_counter()
+        lanes = [autotune.choose_lanes(p, storage, reps=3)[0] for p in phs]
+        log(f"autotuned lanes per row in {time.perf_counter() - t0:.1f} s: "
+            f"{ {k: lanes.count(k) for k in sorted(set(lanes))} }")
+    loaded = [fredopt.load_phantom(p, storage=storage, lanes_per_row=lw)
+              for p, lw in zip(phs, lanes)]
     q = fredopt.SolverParams(reductions_n=args.reductions)
     # one at a time (the plain single-plan form, default projection path)
     k_alone = max(1, args.steps // 4)
@@ -163,10 +176,10 @@ def bench_batch(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32" if storage == fredopt.F32 else f"f32 (values stored {args.storage})",
         "data": "synthetic",
-        "config": {"workload": "batch48: 48 water plans, 5k-120k rows, 200-4000 beamlets",
-                   "plans": len(loaded), "nnz_total": nnz, "storage": args.storage,
-                   "reductions_n": args.reductions},
-        "value_meaning": "plan-iterations per second summed over the 48 plans",
+        "config": {"workload": desc, "plans": len(loaded), "nnz_total": nnz,
+                   "storage": args.storage, "reductions_n": args.reductions,
+                   "lanes_per_row": "autotuned" if args.autotune else "rule"},
+        "value_meaning": "plan-iterations per second summed over the plans",
         "one_at_a_time_iters_per_s": round(alone_rate, 2),
         "speedup_vs_one_at_a_time": round(rate / alone_rate, 3),
     }
@@ -230,7 +243,8 @@ def main():
     ap.add_argument("--workload", default="clinical",
                     help="clinical (160x160x120 grid, 12k beamlets), water32 (32^3, 400 "
                          "beamlets), clinical_x<scale>, batch48 (48 plans in batched "
-                         "launches) or serve (request stream, continuous batching)")
+                         "launches), scenarios48 (6 plans x 8 robustness scenarios) or "
+                         "serve (request stream, continuous batching)")
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16", "f16i16", "bf16i16"],
                     help="matrix values in FP32, FP16 or BF16 (per-beamlet FP32 scale); the "
                          "i16 forms also keep column indices in 16 bits")
@@ -259,8 +273,8 @@ def main():
         raise SystemExit("bench.py needs a HIP device")
     torch.cuda.set_device(0)
     fredopt.lib()
-    if args.workload in ("batch48", "serve"):
-        res = bench_batch(args) if args.workload == "batch48" else bench_serve(args)
+    if args.workload in ("batch48", "scenarios48", "serve"):
+        res = bench_serve(args) if args.workload == "serve" else bench_batch(args)
         print(json.dumps(res), flush=True)
         return
     log(f"generating workload {args.workload}")

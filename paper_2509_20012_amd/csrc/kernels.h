@@ -12,8 +12,9 @@ void launch_forward(int vtype, int mode, int sub, const DevPlan* plans, const Fw
                     hipStream_t s);
 void launch_rows(int mode, const DevPlan* plans, const RowItem* items, int n_items,
                  hipStream_t s);
+// persistent grid of at most max_grid workgroups; single: every item is plans[0]'s
 void launch_tr_chunks(int vtype, int tag, const DevPlan* plans, const TrItem* items,
-                      int n_items, hipStream_t s);
+                      int n_items, int max_grid, int single, hipStream_t s);
 void launch_tcol(int mode, const DevPlan* plans, const ColBlock* blocks, int n_blocks,
                  hipStream_t s);
 void launch_finalize(int mode, int sub, const DevPlan* plans, int n_plans, hipStream_t s);

@@ -556,17 +556,34 @@ __global__ __launch_bounds__(kBlock) void k_rows(const DevPlan* __restrict__ pla
 // (b % 8) * nb8 + b / 8 and each XCD's L2 sees a contiguous column range.
 // TAG only separates the gradient (0) and projection (1) launches in profiles.
 template <int VT, int TAG>
+__device__ __forceinline__ void tr_chunk(const DevPlan* __restrict__ plans, const TrItem& w,
+                                         int lane);
+
+// A persistent grid (a multiple of 8 workgroups) walks the virtual blocks
+// vb = b, b + grid, ...; virtual block vb covers items of block
+// (vb mod 8) nb8 + vb / 8, so each workgroup stays on one XCD's contiguous share of
+// columns.  single: every item belongs to plans[0] (its projection path is checked
+// once).
+template <int VT, int TAG>
 __global__ __launch_bounds__(kBlock) void k_tr_chunks(const DevPlan* __restrict__ plans,
                                                       const TrItem* __restrict__ items,
-                                                      int n_items, int nb8) {
-  const int b = blockIdx.x;
-  const int lb = (b & 7) * nb8 + (b >> 3);
+                                                      int n_items, int nb8, int single) {
+  if (TAG == 1 && single && plans[0].st->proj_scatter) return;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-  const int it = lb * (kBlock / kWave) + wave;
-  if (it >= n_items) return;
-  const TrItem w = items[uniform(it)];
+  for (int vb = blockIdx.x; vb < nb8 * 8; vb += gridDim.x) {
+    const int lb = (vb & 7) * nb8 + (vb >> 3);
+    const int it = lb * (kBlock / kWave) + wave;
+    if (it >= n_items) continue;
+    const TrItem w = items[uniform(it)];
+    if (TAG == 1 && !single && plans[w.plan].st->proj_scatter) continue;
+    tr_chunk<VT, TAG>(plans, w, lane);
+  }
+}
+
+template <int VT, int TAG>
+__device__ __forceinline__ void tr_chunk(const DevPlan* __restrict__ plans, const TrItem& w,
+                                         int lane) {
   const DevPlan* __restrict__ P = plans + w.plan;
-  if (TAG == 1 && P->st->proj_scatter) return;
   // chunk-relative element offsets fit 32 bits; the chunk base is wave-uniform
   const FO_GLOBAL int32_t* ri = gconst(TAG == 0 ? P->gri : P->ri) + w.q0;
   const FO_GLOBAL void* cdv = value_ptr<VT>(TAG == 0 ? P->gcdv : P->cdv, w.q0);
@@ -605,6 +622,8 @@ __global__ __launch_bounds__(kFwdBlock) void k_active_list(const DevPlan* __rest
   const FwdGroup G = groups[blockIdx.x];
   const DevPlan* __restrict__ P = plans + G.plan;
   if (!P->st->proj_scatter) return;
+  // the residual pass counted the group's active rows
+  if (gconst(P->spart_a)[(int64_t)G.slot * kNPart + 7] == 0.0) return;
   const int rpw_log2 = 6 - P->lpr_log2;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   const int n = G.n << rpw_log2;
@@ -791,17 +810,20 @@ __global__ __launch_bounds__(kBlock) void k_tcol(const DevPlan* __restrict__ pla
 constexpr int kFinBlock = 512;   // finalisation: one workgroup of 8 waves per plan
 constexpr int kFinWaves = kFinBlock / kWave;
 
-// Slot-wise sums of n partial slots over the finalisation workgroup: per-thread sums
-// in index order, wave sums, then the waves in order (one pair of barriers for all
-// slots).  Every thread gets the result.
+// Slot-wise sums of n partial slots over the finalisation workgroup: thread t sums
+// the contiguous segment [t per, (t + 1) per) in index order, then wave sums and the
+// waves in order (one pair of barriers for all slots).  Every thread gets the result.
+__device__ __forceinline__ int seg_len(int n) { return (n + kFinBlock - 1) / kFinBlock; }
+
 __device__ __forceinline__ void sum_slots(const double* part_, int n, double* out,
                                           unsigned used, double (*sh)[kNPart]) {
   const FO_GLOBAL double* part = gconst(part_);
   double s[kNPart];
 #pragma unroll
   for (int k = 0; k < kNPart; ++k) s[k] = 0.0;
+  const int per = seg_len(n), i0 = threadIdx.x * per, i1 = min(n, i0 + per);
 #pragma unroll 4
-  for (int i = threadIdx.x; i < n; i += kFinBlock) {
+  for (int i = i0; i < i1; ++i) {
     const FO_GLOBAL double* p = part + (int64_t)i * kNPart;
 #pragma unroll
     for (int k = 0; k < kNPart; ++k)
@@ -877,17 +899,20 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(const DevPlan* __restric
     const double B = a[8];
     const bool scatter = P->n_scatter > 0 && A <= P->scatter_max_rows && B < 1e300;
     if (scatter) {
-      // exclusive scan of the groups' active-row counts (list offsets), in group order
+      // exclusive scan of the groups' active-row counts (list offsets), in group
+      // order: each thread scans its segment of groups after one workgroup scan of
+      // the segment totals
       __shared__ int sc[kFinWaves];
-      int carry = 0;
       const FO_GLOBAL double* part = gconst(P->spart_a);
-      for (int g0 = 0; g0 < P->sell.n_groups; g0 += kFinBlock) {
-        const int g = g0 + threadIdx.x;
-        const int v = g < P->sell.n_groups ? (int)part[(int64_t)g * kNPart + 7] : 0;
-        int total;
-        const int ex = block_scan<kFinWaves>(v, sc, &total);
-        if (g < P->sell.n_groups) gmut(P->goff)[g] = carry + ex;
-        carry += total;
+      const int n = P->sell.n_groups, per = seg_len(n);
+      const int i0 = threadIdx.x * per, i1 = min(n, i0 + per);
+      int mine = 0;
+      for (int i = i0; i < i1; ++i) mine += (int)part[(int64_t)i * kNPart + 7];
+      int total;
+      int off = block_scan<kFinWaves>(mine, sc, &total);
+      for (int i = i0; i < i1; ++i) {
+        gmut(P->goff)[i] = off;
+        off += (int)part[(int64_t)i * kNPart + 7];
       }
     }
     if (threadIdx.x == 0) {
@@ -957,26 +982,27 @@ void launch_rows(int mode, const DevPlan* plans, const RowItem* items, int n_ite
 
 template <int TAG>
 static void launch_tr_tag(int vtype, const DevPlan* plans, const TrItem* items, int n_items,
-                          int grid, int nb8, hipStream_t s) {
+                          int grid, int nb8, int single, hipStream_t s) {
   vtype = value_of(vtype);  // the column-major copy keeps int32 row indices
   if (vtype == kF16)
-    k_tr_chunks<kF16, TAG><<<grid, kBlock, 0, s>>>(plans, items, n_items, nb8);
+    k_tr_chunks<kF16, TAG><<<grid, kBlock, 0, s>>>(plans, items, n_items, nb8, single);
   else if (vtype == kBF16)
-    k_tr_chunks<kBF16, TAG><<<grid, kBlock, 0, s>>>(plans, items, n_items, nb8);
+    k_tr_chunks<kBF16, TAG><<<grid, kBlock, 0, s>>>(plans, items, n_items, nb8, single);
   else
-    k_tr_chunks<kF32, TAG><<<grid, kBlock, 0, s>>>(plans, items, n_items, nb8);
+    k_tr_chunks<kF32, TAG><<<grid, kBlock, 0, s>>>(plans, items, n_items, nb8, single);
 }
 
 void launch_tr_chunks(int vtype, int tag, const DevPlan* plans, const TrItem* items,
-                      int n_items, hipStream_t s) {
+                      int n_items, int max_grid, int single, hipStream_t s) {
   const int per = kBlock / kWave;
   const int nblocks = (n_items + per - 1) / per;
   const int nb8 = (nblocks + 7) / 8;
-  const int grid = nb8 * 8;
+  const int cap = std::max(8, max_grid / 8 * 8);
+  const int grid = std::min(nb8 * 8, cap);
   if (tag == 0)
-    launch_tr_tag<0>(vtype, plans, items, n_items, grid, nb8, s);
+    launch_tr_tag<0>(vtype, plans, items, n_items, grid, nb8, single, s);
   else
-    launch_tr_tag<1>(vtype, plans, items, n_items, grid, nb8, s);
+    launch_tr_tag<1>(vtype, plans, items, n_items, grid, nb8, single, s);
 }
 
 void launch_active_list(const DevPlan* plans, const FwdGroup* groups, int n_groups,

@@ -46,6 +46,7 @@ constexpr int64_t kRowItemRows = 2048;
 constexpr int64_t kTrChunkMin = 256;
 constexpr int64_t kTrChunkDefault = 4096;
 constexpr int64_t kBlockCountCap = int64_t(1) << 24;
+constexpr int kTrWgsPerCu = 8;            // persistent grid of the column-major passes
 constexpr size_t kScatterLdsMax = 159744; // its LDS accumulator: C 64-bit sums
 
 inline size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
@@ -825,9 +826,12 @@ void enqueue(const Exec& e, const Launch& l, hipStream_t s) {
       break;
     case kKindChunks:
       if (l.mode == 0) {
-        if (e.n_gtr > 0) launch_tr_chunks(e.storage, 0, e.table, e.gtr, e.n_gtr, s);
+        if (e.n_gtr > 0)
+          launch_tr_chunks(e.storage, 0, e.table, e.gtr, e.n_gtr, e.n_cu * kTrWgsPerCu,
+                           e.n_plans == 1, s);
       } else if (e.n_tr > 0) {
-        launch_tr_chunks(e.storage, 1, e.table, e.tr, e.n_tr, s);
+        launch_tr_chunks(e.storage, 1, e.table, e.tr, e.n_tr, e.n_cu * kTrWgsPerCu,
+                         e.n_plans == 1, s);
       }
       break;
     case kKindCol:

@@ -442,11 +442,17 @@ def clinical(seed: int = 1, progress: Optional[Callable[[str], None]] = None,
                    {"iterations": 1000, "sigma_mm": sigma})
 
 
-def small_plan(seed: int, n_rows_target: int, n_cols_target: int) -> Phantom:
+def small_plan(seed: int, n_rows_target: int, n_cols_target: int, range_scale: float = 1.0,
+               shift_mm: Sequence[float] = (0.0, 0.0, 0.0), tag: str = "") -> Phantom:
     """One plan of the batched workload: a cubic water grid holding about
     n_rows_target voxels (all kept), two opposed fields with n_cols_target/2 spots
-    each, the density of the 32^3 water phantom (sigma 1.5 voxels, 3 mm voxels, ranges spanning 30-90 %
-    of the grid depth)."""
+    each, the density of the 32^3 water phantom (sigma 1.5 voxels, 3 mm voxels, ranges
+    spanning 30-90 % of the grid depth).
+
+    Robustness scenarios of the same plan: range_scale multiplies every beamlet
+    range (a stopping-power error), shift_mm moves the beams against the patient (a
+    setup error); structures, bounds and targets stay where the nominal plan has
+    them."""
     rng = np.random.default_rng(seed)
     n = max(8, int(round(n_rows_target ** (1.0 / 3.0))))
     shape, h = (n, n, n), 3.0
@@ -460,8 +466,9 @@ def small_plan(seed: int, n_rows_target: int, n_cols_target: int) -> Phantom:
     fields = [Field(0.0, nu, nv, span, span), Field(180.0, nu, nv, span, span)]
     C = 2 * nu * nv
     depth = n * h
-    ranges = rng.uniform(0.3 * depth, 0.9 * depth, C)
-    kept, row_ptr, col, d_raw, let = beam_matrices(shape, h, iso, fields, sigma, ranges,
+    ranges = rng.uniform(0.3 * depth, 0.9 * depth, C) * float(range_scale)
+    beam_iso = iso + np.asarray(shift_mm, np.float64)
+    kept, row_ptr, col, d_raw, let = beam_matrices(shape, h, beam_iso, fields, sigma, ranges,
                                                    keep_all=True)
     p = _voxel_centres(shape, h, kept)
     ptv = np.sum((p - iso) ** 2, axis=1) <= r_ptv ** 2
@@ -470,8 +477,27 @@ def small_plan(seed: int, n_rows_target: int, n_cols_target: int) -> Phantom:
     masks = {"PTV": ptv, "OAR_cyl": oar & ~ptv}
     bounds = {"ptv_lo": 1.9, "ptv_hi": 2.14, "rx": 2.0, "oar_dose_hi": 1.0,
               "oar_letd_max": 2.0}
-    return _finish(f"plan_s{seed}_{n}cube_C{C}", shape, h, kept, row_ptr, col, d_raw, let, C,
-                   masks, bounds, seed, {"iterations": 100})
+    return _finish(f"plan_s{seed}_{n}cube_C{C}{tag}", shape, h, kept, row_ptr, col, d_raw, let,
+                   C, masks, bounds, seed, {"iterations": 100, "range_scale": float(range_scale),
+                                            "shift_mm": [float(v) for v in shift_mm]})
+
+
+# range errors and setup shifts of the robustness scenarios (8 per base plan)
+SCENARIOS = [(1.035, (0.0, 0.0, 0.0)), (0.965, (0.0, 0.0, 0.0)),
+             (1.0, (3.0, 0.0, 0.0)), (1.0, (-3.0, 0.0, 0.0)),
+             (1.0, (0.0, 3.0, 0.0)), (1.0, (0.0, -3.0, 0.0)),
+             (1.0, (0.0, 0.0, 3.0)), (1.0, (0.0, 0.0, -3.0))]
+
+
+def scenario_plans(n_base: int = 6, seed: int = 3) -> List[Phantom]:
+    """n_base plans of the batched workload (the first draws), each regenerated from
+    the same seed under the eight robustness scenarios: ranges x (1 +- 3.5 %) and
+    +-3 mm setup shifts along each axis."""
+    out = []
+    for sd, r, c in batch_sizes(n_base, seed):
+        for k, (rs, sh) in enumerate(SCENARIOS):
+            out.append(small_plan(sd, r, c, range_scale=rs, shift_mm=sh, tag=f"_sc{k}"))
+    return out
 
 
 def batch_sizes(n_plans: int = 48, seed: int = 3) -> List[Tuple[int, int, int]]:

@@ -109,3 +109,27 @@ def test_batch_arguments(fo):
     plan16, prob16, _ = fo.load_phantom(p, storage=fo.F16)
     with pytest.raises(fo.FredoptError):
         fo.Batch([plan, plan16], [prob, prob16])  # mixed storage
+
+
+def test_lane_autotuner_picks_a_timed_candidate(fo):
+    from paper_2509_20012_amd import autotune
+    p = ph.small_plan(3001, 5000, 200)
+    best, times = autotune.choose_lanes(p, candidates=(1, 2, 4), reps=2)
+    assert set(times) == {1, 2, 4} and best in times
+    assert all(t > 0 for t in times.values())
+    assert times[best] == min(times.values())
+
+
+def test_scenario_batch_equals_alone(fo):
+    """Robustness scenarios of one plan iterated together equal their solo runs."""
+    phs = ph.scenario_plans(1, seed=3)
+    q = fo.SolverParams(alpha=0.9)
+    ref = [_alone(fo, p, q, 4, 0) for p in phs]
+    loaded = [fo.load_phantom(p) for p in phs]
+    batch = fo.Batch([l[0] for l in loaded], [l[1] for l in loaded])
+    xs = [l[2].clone() for l in loaded]
+    states = [fo.new_state() for _ in phs]
+    batch.solve(q, states, xs, 4)
+    for i, p in enumerate(phs):
+        assert (states[i].k, states[i].s) == ref[i][1], p.name
+        assert np.array_equal(_np(xs[i]), ref[i][0]), p.name

@@ -27,3 +27,25 @@ def test_batch_sizes_log_uniform_and_correlated():
     assert cols.min() >= 200 and cols.max() <= 4000
     # one draw per plan sets both sizes: their logarithms are linearly related
     assert np.corrcoef(np.log(rows), np.log(cols))[0, 1] > 0.999
+
+
+def test_scenarios_shift_and_range():
+    """Setup shifts move the dose with the beams; range scaling moves the Bragg
+    peaks; the nominal structures and bounds stay put."""
+    base = ph.small_plan(3001, 5000, 200)
+    sx = ph.small_plan(3001, 5000, 200, shift_mm=(0.0, 3.0, 0.0))
+    lr = ph.small_plan(3001, 5000, 200, range_scale=1.035)
+    assert np.array_equal(base.kind, sx.kind) and np.array_equal(base.dose_hi, sx.dose_hi)
+    n = round(base.n_rows ** (1 / 3))
+    centres = (np.indices((n, n, n)).reshape(3, -1)[::-1].T + 0.5) * 3.0  # x, y, z in mm
+    def centroid(p):
+        rid = np.repeat(np.arange(p.n_rows), np.diff(p.row_ptr))
+        dose = np.bincount(rid, weights=p.d_val.astype(np.float64), minlength=p.n_rows)
+        return (dose[:, None] * centres).sum(0) / dose.sum()
+    c0, c1 = centroid(base), centroid(sx)
+    # the beams travel along x: a shift along y moves the dose by the shift
+    assert abs((c1 - c0)[1] - 3.0) < 0.6
+    assert abs((c1 - c0)[2]) < 0.6
+    # longer ranges deposit dose deeper: more entries, same beamlets
+    assert lr.n_cols == base.n_cols and lr.nnz > base.nnz
+    assert len(ph.scenario_plans(1)) == 8
