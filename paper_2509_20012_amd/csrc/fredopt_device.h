@@ -116,8 +116,16 @@ struct SellView {
   int32_t lpr_log2, pad;      // lanes per row of this view (log2)
 };
 
+// Per-row data lives in slice-position order: the row at position sp = slice * rpw +
+// place of the all-row view has its bounds, weights, moments, d, l and projection
+// coefficients at index sp (padding positions hold kind 0 and zeros), so a slice's
+// rows are read and written contiguously.  The objective-row view has its own
+// positions for its objective terms.  The column-major copies keep row indices (a
+// column's neighbouring entries are neighbouring voxels): the coefficients they
+// gather are kept in row order (coef_row, gcoef).
 struct DevPlan {
   int64_t R, C;
+  int64_t NP;                 // positions of the all-row view (slices * rpw)
   int32_t vtype, lpr_log2;    // lanes per row (log2) of the all-row view
   int32_t n_row_items, n_col_blocks;
   SellView sell;              // every row
@@ -136,11 +144,16 @@ struct DevPlan {
   const int32_t* gcol_tslot0;
   const int32_t* gcol_nch;
   const float* cscale;        // per-column scale of 16-bit storage (null for FP32)
-  const double* mom;          // [3R] sum D^2, sum L^2, sum D L per row
-  const float* rsum;          // [2R] sum of the stored D and L values of a row
-  // problem (device arrays of R)
+  const double* mom;          // [3 NP] sum D^2, sum L^2, sum D L per row
+  const float* rsum;          // [2 NP] sum of the stored D and L values of a row
+  // problem in position order (gathered from the caller's row-order arrays)
   const uint16_t* kind;
   const float *dlo, *dhi, *clo, *chi, *tmax, *wf, *wo, *dt, *ct;
+  // objective terms in the objective-row view's position order
+  const uint16_t* okind;
+  const float *owo, *odt, *oct;
+  float2* gcoef;              // [R] Eq. (2) gradient coefficients by row
+  float2* coef_row;           // [R] projection coefficients by row (column-major path)
   // vectors
   float* x;                   // fluence (caller's array during a call)
   float* y;                   // perturbed point fed to the feasibility step
@@ -148,7 +161,7 @@ struct DevPlan {
   float* l;
   float* dg;
   float* lg;
-  float2* coef;               // per-row coefficients (dose part, LET part)
+  float2* coef;               // per-position coefficients (dose part, LET part)
   float* g;
   float* out_dose;
   float* out_letd;
@@ -161,7 +174,7 @@ struct DevPlan {
   float* tpart;               // [sum of chunks]
   // projection restricted to rows with non-zero coefficients
   int32_t* goff;              // [groups] first list position of each group's rows
-  ActRow* alist;              // [R] the active rows in slice order
+  ActRow* alist;              // [NP] the active rows in slice order
   int64_t* spart;             // [n_scatter * C] per-workgroup fixed-point sums
   uint64_t* smask;            // [n_scatter * ceil(C / 64)] which of them are written
   int32_t n_scatter, scatter_max_rows;  // workgroups; largest list that uses it

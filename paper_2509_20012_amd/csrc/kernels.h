@@ -47,21 +47,25 @@ void launch_pack_sell(int vtype, int64_t R, int lpr_log2, const int64_t* row_ptr
 void launch_block_count(int64_t R, int64_t C, int rows_per_block, const int64_t* row_ptr,
                         const int32_t* col, uint32_t* bc, hipStream_t s);
 void launch_block_offsets(int64_t C, int nb, const int64_t* cp, uint32_t* bc, hipStream_t s);
+// rows ascending within each column; ri holds row indices
 void launch_fill_csc(int vtype, int64_t R, int64_t C, int rows_per_block,
                      const int64_t* row_ptr, const int32_t* col, const float* dv,
-                     const float* lv, const float* scale, uint32_t* bc, int32_t* ri,
-                     void* cdv, void* clv, hipStream_t s);
+                     const float* lv, const float* scale, uint32_t* bc, int32_t* ri, void* cdv,
+                     void* clv, hipStream_t s);
 // mom: sum D^2, sum L^2, sum D L per row; rsum: sum of the stored D and L values
+// written at the rows' positions rslice[row]
 void launch_moments(int vtype, int64_t R, const int64_t* row_ptr, const int32_t* col,
-                    const float* dv, const float* lv, const float* scale, double* mom,
-                    float* rsum, hipStream_t s);
+                    const float* dv, const float* lv, const float* scale, const int32_t* rslice,
+                    double* mom, float* rsum, hipStream_t s);
 // count[j]: entries of column j (len[j] real entries from cp[j]) in rows with
 // objective terms.
 void launch_obj_count(int64_t C, const int64_t* cp, const uint32_t* len, const int32_t* ri,
                       const uint16_t* kind, uint32_t* count, hipStream_t s);
+// kind in row order
 void launch_obj_fill(int vtype, int64_t C, const int64_t* cp, const uint32_t* len,
                      const int32_t* ri, const void* cdv, const void* clv, const uint16_t* kind,
-                     const int64_t* ocp, int32_t* ori, void* ocdv, void* oclv, hipStream_t s);
+                     const int64_t* ocp, int32_t* ori, void* ocdv,
+                     void* oclv, hipStream_t s);
 // copies the objective rows' entries from the all-row sliced-ELL view into the
 // objective-row view: row obj_row[i] sits at slice position src_pos[i] of the full
 // view and dst_pos[i] of the objective view and has len[i] entries
@@ -70,6 +74,12 @@ void launch_pack_sub(int vtype, int src_lg2, int dst_lg2, int64_t n, const int32
                      const void* src_ci, const void* src_dv, const void* src_lv,
                      const int64_t* dst_base, void* dst_ci, int idx16, void* dst_dv,
                      void* dst_lv, hipStream_t s);
+struct GatherArrays {  // kind and up to 9 float arrays of a problem
+  uint16_t* kind;
+  float* f[9];
+};
+void launch_gather_problem(int64_t n, const int32_t* pos_row, const GatherArrays& src,
+                           const GatherArrays& dst, int nf, hipStream_t s);
 void launch_check_problem(int64_t R, const uint16_t* kind, const float* dlo, const float* dhi,
                           const float* clo, const float* chi, const float* tmax,
                           const float* wf, const float* wo, const float* dt, const float* ct,

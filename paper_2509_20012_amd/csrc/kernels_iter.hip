@@ -154,26 +154,39 @@ __device__ __forceinline__ int block_scan(int v, int* sh, int* total) {
 
 // ---------------------------------------------------------------- epilogues ----
 
-// Eq. (2) terms of row r at (d, l): adds the value to *chi and stores the gradient
-// coefficients (-2 w (Dhat - d), -2 c w (cDLhat - c l)) of the row.
-__device__ __forceinline__ void objective_row(const DevPlan* P, int r, float d, float l,
-                                              double* chi) {
-  const unsigned k = gconst(P->kind)[r];
+// The Eq. (2) data of one view in its position order.
+struct ObjArrays {
+  const uint16_t* kind;
+  const float *wo, *dt, *ct;
+  float2* coef;
+};
+
+template <int SUB>
+__device__ __forceinline__ ObjArrays obj_arrays(const DevPlan* P) {
+  if constexpr (SUB) return ObjArrays{P->okind, P->owo, P->odt, P->oct, P->gcoef};
+  else return ObjArrays{P->kind, P->wo, P->dt, P->ct, P->gcoef};
+}
+
+// Eq. (2) terms of the row with data at position r (kinds k) at (d, l): adds the
+// value to *chi and stores the gradient coefficients (-2 w (Dhat - d),
+// -2 c w (cDLhat - c l)) at index rc (the row).
+__device__ __forceinline__ void objective_row(const DevPlan* P, const ObjArrays& A, int r, int rc,
+                                              unsigned k, float d, float l, double* chi) {
   double uD = 0.0, uL = 0.0;
   if (k & (kObjDose | kObjCdl)) {
-    const double w = gconst(P->wo)[r], c = P->prm.c;
+    const double w = gconst(A.wo)[r], c = P->prm.c;
     if (k & kObjDose) {
-      const double e = (double)gconst(P->dt)[r] - (double)d;
+      const double e = (double)gconst(A.dt)[r] - (double)d;
       *chi += w * e * e;
       uD = -2.0 * w * e;
     }
     if (k & kObjCdl) {
-      const double f = (double)gconst(P->ct)[r] - c * (double)l;
+      const double f = (double)gconst(A.ct)[r] - c * (double)l;
       *chi += w * f * f;
       uL = -2.0 * c * w * f;
     }
   }
-  ((FO_GLOBAL v2f*)(P->coef))[r] = v2f{(float)uD, (float)uL};
+  ((FO_GLOBAL v2f*)(A.coef))[rc] = v2f{(float)uD, (float)uL};
 }
 
 __device__ __forceinline__ double objective_value(const DevPlan* P, int r, unsigned k, float d,
@@ -347,7 +360,14 @@ __device__ __forceinline__ void forward_slice(const DevPlan* __restrict__ P, int
   const int pos = lane >> lg2;
   const int64_t sb = gconst(V.sbase)[s];
   const int W = uniform(gconst(V.swidth)[s]);
-  const int row = gconst(V.srow)[(int64_t)s * rpw + pos];
+  // the row's position: its data are indexed by it (padding positions have kind 0)
+  const int sp = s * rpw + pos;
+  const ObjArrays A = obj_arrays<SUB>(P);
+  unsigned kind = 0;
+  if constexpr (MODE != kFwdDoseLet) kind = gconst(A.kind)[sp];
+  // the gradient coefficients are stored by row (the column-major gradient gathers them)
+  int crow = 0;
+  if constexpr (MODE == kFwdObj) crow = gconst(V.srow)[sp];
   // slice-relative element offsets fit 32 bits; the slice bases are wave-uniform
 
   const FO_GLOBAL void* ci = sell_idx_ptr<VT>(V.sci, sb);
@@ -401,34 +421,38 @@ __device__ __forceinline__ void forward_slice(const DevPlan* __restrict__ P, int
   double acc[kNPart];
 #pragma unroll
   for (int k = 0; k < kNPart; ++k) acc[k] = 0.0;
-  if ((lane & (lpr - 1)) == 0 && row >= 0) {
+  if ((lane & (lpr - 1)) == 0) {
     if constexpr (MODE == kFwdDoseLet) {
-      if (P->out_dose) gmut(P->out_dose)[row] = ad;
-      if (P->out_letd) gmut(P->out_letd)[row] = ad > 0.f ? al / ad : 0.f;
-      if (P->out_cdl) gmut(P->out_cdl)[row] = (float)(P->prm.c * (double)al);
+      // outputs in the caller's row order
+      const int row = gconst(V.srow)[sp];
+      if (row >= 0) {
+        if (P->out_dose) gmut(P->out_dose)[row] = ad;
+        if (P->out_letd) gmut(P->out_letd)[row] = ad > 0.f ? al / ad : 0.f;
+        if (P->out_cdl) gmut(P->out_cdl)[row] = (float)(P->prm.c * (double)al);
+      }
     } else if constexpr (MODE == kFwdObj) {
-      gmut(P->d)[row] = ad;
-      gmut(P->l)[row] = al;
-      objective_row(P, row, ad, al, &acc[0]);
+      if constexpr (!SUB) {  // the all-row pass keeps d and l for the moves
+        gmut(P->d)[sp] = ad;
+        gmut(P->l)[sp] = al;
+      }
+      if (crow >= 0) objective_row(P, A, sp, crow, kind, ad, al, &acc[0]);
       if (!finite2(ad, al)) acc[5] += 1.0;
     } else if constexpr (MODE == kFwdDir) {
       if constexpr (!SUB) {
-        gmut(P->dg)[row] = ad;
-        gmut(P->lg)[row] = al;
+        gmut(P->dg)[sp] = ad;
+        gmut(P->lg)[sp] = al;
       }
-      const unsigned k = gconst(P->kind)[row];
-      if (k & (kObjDose | kObjCdl)) {
-        const double wo = gconst(P->wo)[row], c = P->prm.c;
-        if (k & kObjDose) acc[0] += wo * (double)ad * (double)ad;
-        if (k & kObjCdl) acc[0] += wo * c * c * (double)al * (double)al;
+      if (kind & (kObjDose | kObjCdl)) {
+        const double wo = gconst(A.wo)[sp], c = P->prm.c;
+        if (kind & kObjDose) acc[0] += wo * (double)ad * (double)ad;
+        if (kind & kObjCdl) acc[0] += wo * c * c * (double)al * (double)al;
       }
       if (!finite2(ad, al)) acc[5] += 1.0;
     } else {
-      gmut(P->d)[row] = ad;
-      gmut(P->l)[row] = al;
-      const unsigned rkind = gconst(P->kind)[row];
-      residual_row(P, row, rkind, ad, al, acc);
-      acc[6] += objective_value(P, row, rkind, ad, al);
+      gmut(P->d)[sp] = ad;
+      gmut(P->l)[sp] = al;
+      residual_row(P, sp, kind, ad, al, acc);
+      acc[6] += objective_value(P, sp, kind, ad, al);
       if (!finite2(ad, al)) acc[5] += 1.0;
     }
   }
@@ -530,7 +554,8 @@ __global__ __launch_bounds__(kBlock) void k_rows(const DevPlan* __restrict__ pla
     gmut(P->d)[r] = d;
     gmut(P->l)[r] = l;
     if constexpr (MODE == kRowsMoveObj) {
-      objective_row(P, r, d, l, &acc[0]);
+      const int row = gconst(P->sell.srow)[r];
+      if (row >= 0) objective_row(P, obj_arrays<0>(P), r, row, gconst(P->kind)[r], d, l, &acc[0]);
     } else {
       const unsigned kr = gconst(P->kind)[r];
       residual_row(P, r, kr, d, l, acc);
@@ -588,7 +613,7 @@ __device__ __forceinline__ void tr_chunk(const DevPlan* __restrict__ plans, cons
   const FO_GLOBAL int32_t* ri = gconst(TAG == 0 ? P->gri : P->ri) + w.q0;
   const FO_GLOBAL void* cdv = value_ptr<VT>(TAG == 0 ? P->gcdv : P->cdv, w.q0);
   const FO_GLOBAL void* clv = value_ptr<VT>(TAG == 0 ? P->gclv : P->clv, w.q0);
-  const FO_GLOBAL v2f* cf = (const FO_GLOBAL v2f*)(P->coef);
+  const FO_GLOBAL v2f* cf = (const FO_GLOBAL v2f*)(TAG == 0 ? P->gcoef : P->coef_row);
   const uint32_t n = (uint32_t)(w.q1 - w.q0);
   float acc = 0.f;
 #pragma unroll 4
@@ -614,28 +639,34 @@ __device__ __forceinline__ void tr_chunk(const DevPlan* __restrict__ plans, cons
 // ---------------------------------------------- projection over active rows ----
 
 // The rows with a non-zero projection coefficient, group by group in slice order
-// (list offsets from the residual finalisation), with what the scatter needs.
+// (list offsets from the residual finalisation), with what the scatter needs; when
+// the sweep takes the column-major path instead, the coefficients in row order.
 __global__ __launch_bounds__(kFwdBlock) void k_active_list(const DevPlan* __restrict__ plans,
                                                            const FwdGroup* __restrict__ groups,
                                                            int n_groups) {
   __shared__ int wsum[kFwdWaves];
   const FwdGroup G = groups[blockIdx.x];
   const DevPlan* __restrict__ P = plans + G.plan;
-  if (!P->st->proj_scatter) return;
-  // the residual pass counted the group's active rows
-  if (gconst(P->spart_a)[(int64_t)G.slot * kNPart + 7] == 0.0) return;
   const int rpw_log2 = 6 - P->lpr_log2;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   const int n = G.n << rpw_log2;
   const int sp = (G.slice0 << rpw_log2) + tid;
+  if (!P->st->proj_scatter) {
+    // the column-major path gathers the coefficients by row
+    if (tid < n) {
+      const int row = gconst(P->sell.srow)[sp];
+      if (row >= 0)
+        ((FO_GLOBAL v2f*)(P->coef_row))[row] = ((const FO_GLOBAL v2f*)(P->coef))[sp];
+    }
+    return;
+  }
+  // the residual pass counted the group's active rows
+  if (gconst(P->spart_a)[(int64_t)G.slot * kNPart + 7] == 0.0) return;
   bool act = false;
   v2f c = v2f{0.f, 0.f};
   if (tid < n) {
-    const int row = gconst(P->sell.srow)[sp];
-    if (row >= 0) {
-      c = ((const FO_GLOBAL v2f*)(P->coef))[row];
-      act = c.x != 0.f || c.y != 0.f;
-    }
+    c = ((const FO_GLOBAL v2f*)(P->coef))[sp];
+    act = c.x != 0.f || c.y != 0.f;
   }
   const uint64_t m = __ballot(act);
   if (lane == 0) wsum[wave] = __popcll(m);

@@ -151,6 +151,9 @@ __global__ void k_block_offsets(int64_t C, int nb, const int64_t* __restrict__ c
 // of one row in parallel (a row's columns are distinct, so no two lanes share a
 // cursor), with a barrier between rows.  Inside every column the rows therefore come
 // out ascending, independent of scheduling.
+// One workgroup per block of rows, rows in order: within a column the entries end up
+// in ascending row order (neighbouring voxels next to each other, which keeps the
+// coefficient gathers of the transposed products local).
 __global__ __launch_bounds__(kBlock) void k_fill_csc(int vtype, int64_t R, int64_t C,
                                                      int rows_per_block,
                                                      const int64_t* __restrict__ row_ptr,
@@ -187,6 +190,7 @@ __global__ __launch_bounds__(kBlock) void k_moments(int vtype, int64_t R,
                                                     const float* __restrict__ dv,
                                                     const float* __restrict__ lv,
                                                     const float* __restrict__ scale,
+                                                    const int32_t* __restrict__ rslice,
                                                     double* mom, float* rsum) {
   const int64_t row = (int64_t)blockIdx.x * kRowsPerWg + threadIdx.x / kWave;
   const int lane = threadIdx.x % kWave;
@@ -217,11 +221,12 @@ __global__ __launch_bounds__(kBlock) void k_moments(int vtype, int64_t R,
     sl += __shfl_xor(sl, o);
   }
   if (lane == 0) {
-    mom[3 * row] = sdd;
-    mom[3 * row + 1] = sll;
-    mom[3 * row + 2] = sdl;
-    rsum[2 * row] = __double2float_ru(sd);
-    rsum[2 * row + 1] = __double2float_ru(sl);
+    const int64_t sp = rslice[row];
+    mom[3 * sp] = sdd;
+    mom[3 * sp + 1] = sll;
+    mom[3 * sp + 2] = sdl;
+    rsum[2 * sp] = __double2float_ru(sd);
+    rsum[2 * sp + 1] = __double2float_ru(sl);
   }
 }
 
@@ -365,6 +370,19 @@ __global__ __launch_bounds__(kBlock) void k_pack_sub(int vtype, int src_lg2, int
   }
 }
 
+// Problem arrays from the caller's row order into a view's position order: position
+// i takes row pos_row[i] (padding positions, row -1, get kind 0 and zeros).
+__global__ __launch_bounds__(kBlock) void k_gather_problem(int64_t n,
+                                                           const int32_t* __restrict__ pos_row,
+                                                           GatherArrays src, GatherArrays dst,
+                                                           int nf) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const int row = pos_row[i];
+  dst.kind[i] = row >= 0 ? src.kind[row] : (uint16_t)0;
+  for (int f = 0; f < nf; ++f) dst.f[f][i] = row >= 0 ? src.f[f][row] : 0.f;
+}
+
 inline unsigned row_grid(int64_t R) { return (unsigned)((R + kRowsPerWg - 1) / kRowsPerWg); }
 
 }  // namespace
@@ -408,8 +426,8 @@ void launch_block_offsets(int64_t C, int nb, const int64_t* cp, uint32_t* bc, hi
 
 void launch_fill_csc(int vtype, int64_t R, int64_t C, int rows_per_block,
                      const int64_t* row_ptr, const int32_t* col, const float* dv,
-                     const float* lv, const float* scale, uint32_t* bc, int32_t* ri,
-                     void* cdv, void* clv, hipStream_t s) {
+                     const float* lv, const float* scale, uint32_t* bc, int32_t* ri, void* cdv,
+                     void* clv, hipStream_t s) {
   if (R <= 0) return;
   const unsigned nb = (unsigned)((R + rows_per_block - 1) / rows_per_block);
   k_fill_csc<<<nb, kBlock, 0, s>>>(vtype, R, C, rows_per_block, row_ptr, col, dv, lv, scale, bc,
@@ -417,10 +435,11 @@ void launch_fill_csc(int vtype, int64_t R, int64_t C, int rows_per_block,
 }
 
 void launch_moments(int vtype, int64_t R, const int64_t* row_ptr, const int32_t* col,
-                    const float* dv, const float* lv, const float* scale, double* mom,
-                    float* rsum, hipStream_t s) {
+                    const float* dv, const float* lv, const float* scale, const int32_t* rslice,
+                    double* mom, float* rsum, hipStream_t s) {
   if (R > 0)
-    k_moments<<<row_grid(R), kBlock, 0, s>>>(vtype, R, row_ptr, col, dv, lv, scale, mom, rsum);
+    k_moments<<<row_grid(R), kBlock, 0, s>>>(vtype, R, row_ptr, col, dv, lv, scale, rslice, mom,
+                                             rsum);
 }
 
 void launch_obj_count(int64_t C, const int64_t* cp, const uint32_t* len, const int32_t* ri,
@@ -430,10 +449,11 @@ void launch_obj_count(int64_t C, const int64_t* cp, const uint32_t* len, const i
 
 void launch_obj_fill(int vtype, int64_t C, const int64_t* cp, const uint32_t* len,
                      const int32_t* ri, const void* cdv, const void* clv, const uint16_t* kind,
-                     const int64_t* ocp, int32_t* ori, void* ocdv, void* oclv, hipStream_t s) {
+                     const int64_t* ocp, int32_t* ori, void* ocdv,
+                     void* oclv, hipStream_t s) {
   if (C > 0)
-    k_obj_fill<<<row_grid(C), kBlock, 0, s>>>(vtype, C, cp, len, ri, cdv, clv, kind, ocp, ori,
-                                               ocdv, oclv);
+    k_obj_fill<<<row_grid(C), kBlock, 0, s>>>(vtype, C, cp, len, ri, cdv, clv, kind, ocp,
+                                               ori, ocdv, oclv);
 }
 
 void launch_pack_sub(int vtype, int src_lg2, int dst_lg2, int64_t n, const int32_t* src_pos,
@@ -445,6 +465,13 @@ void launch_pack_sub(int vtype, int src_lg2, int dst_lg2, int64_t n, const int32
     k_pack_sub<<<row_grid(n), kBlock, 0, s>>>(vtype, src_lg2, dst_lg2, n, src_pos, dst_pos, len,
                                                src_base, src_ci, src_dv, src_lv, dst_base, dst_ci,
                                                idx16, dst_dv, dst_lv);
+}
+
+void launch_gather_problem(int64_t n, const int32_t* pos_row, const GatherArrays& src,
+                           const GatherArrays& dst, int nf, hipStream_t s) {
+  if (n > 0)
+    k_gather_problem<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(n, pos_row, src,
+                                                                            dst, nf);
 }
 
 void launch_check_problem(int64_t R, const uint16_t* kind, const float* dlo, const float* dhi,

@@ -138,7 +138,8 @@ struct Layout {
   size_t y, osbase, oswidth, osrow, osci, osdv, oslv, ogroups, pk_src, pk_dst, pk_len;
   size_t spart_a, spart_b, rpart, gpart, tpart, groups, row_items, tr_items, col_blocks;
   size_t bc, colcount, colmax, flags, rslice, rsum, goff, alist, spart, smask, sc_items,
-      ss_items, total;
+      ss_items, pkind, pf, okind, of, gcoef, coef_row, total;
+  int64_t NP;                 // positions of the all-row view
   int64_t sell_slots, n_slices, csc_slots, obj_slots, max_rows, max_tr, n_groups, n_col_blocks;
   int64_t obj_sell_slots, max_obj_slices, max_obj_groups, max_obj_srow;
   int64_t rows_per_block, nb;
@@ -167,6 +168,7 @@ bool make_layout(int64_t R, int64_t C, int64_t nnz, int storage, int lpr_log2,
   // the objective-row view may use up to 16 lanes per row (4 rows per slice)
   L->max_obj_slices = reserve_pct > 0 ? R / 4 + R / kSortWindow + 2 : 0;
   L->max_obj_groups = (L->max_obj_slices + kFwdWaves - 1) / kFwdWaves + 1;
+  L->max_obj_srow = reserve_pct > 0 ? R + (R / kSortWindow + 2) * kWave + 1 : 1;
   L->max_rows = R / kRowItemRows + 2;
   L->max_tr = C + csc / kTrChunkMin + 2;
   L->n_groups = (n_slices + kFwdWaves - 1) / kFwdWaves + 1;
@@ -182,6 +184,9 @@ bool make_layout(int64_t R, int64_t C, int64_t nnz, int storage, int lpr_log2,
     return at;
   };
   const size_t Rm = (size_t)std::max<int64_t>(R, 1);
+  L->NP = n_slices * rpw;     // per-row data of the all-row view, in position order
+  const size_t Pm = (size_t)std::max<int64_t>(L->NP, 1);
+  const size_t Om = (size_t)std::max<int64_t>(L->max_obj_srow, 1);
   L->table = take(sizeof(DevPlan));
   L->state = take(sizeof(DevState));
   L->ctr = take(sizeof(uint32_t) * kCounters);
@@ -208,7 +213,6 @@ bool make_layout(int64_t R, int64_t C, int64_t nnz, int storage, int lpr_log2,
   L->y = take(sizeof(float) * C);
   L->osbase = take(sizeof(int64_t) * (L->max_obj_slices + 1));
   L->oswidth = take(sizeof(int32_t) * (L->max_obj_slices + 1));
-  L->max_obj_srow = reserve_pct > 0 ? R + (R / kSortWindow + 2) * kWave + 1 : 1;
   L->osrow = take(sizeof(int32_t) * L->max_obj_srow);
   L->osci = take((size_t)index_bytes(storage) * L->obj_sell_slots);
   L->osdv = take((size_t)vb * L->obj_sell_slots);
@@ -218,12 +222,18 @@ bool make_layout(int64_t R, int64_t C, int64_t nnz, int storage, int lpr_log2,
   L->pk_dst = take(sizeof(int32_t) * (reserve_pct > 0 ? Rm : 1));
   L->pk_len = take(sizeof(int32_t) * (reserve_pct > 0 ? Rm : 1));
   L->cscale = take(sizeof(float) * C);
-  L->mom = take(sizeof(double) * 3 * Rm);
-  L->d = take(sizeof(float) * Rm);
-  L->l = take(sizeof(float) * Rm);
-  L->dg = take(sizeof(float) * Rm);
-  L->lg = take(sizeof(float) * Rm);
-  L->coef = take(sizeof(float2) * Rm);
+  L->mom = take(sizeof(double) * 3 * Pm);
+  L->d = take(sizeof(float) * Pm);
+  L->l = take(sizeof(float) * Pm);
+  L->dg = take(sizeof(float) * Pm);
+  L->lg = take(sizeof(float) * Pm);
+  L->coef = take(sizeof(float2) * Pm);
+  L->pkind = take(sizeof(uint16_t) * Pm);
+  L->pf = take(sizeof(float) * 9 * Pm);          // dlo dhi clo chi tmax wf wo dt ct
+  L->okind = take(sizeof(uint16_t) * Om);
+  L->of = take(sizeof(float) * 3 * Om);          // wo dt ct of the objective-row view
+  L->gcoef = take(sizeof(float2) * Rm);          // gradient coefficients by row
+  L->coef_row = take(sizeof(float2) * Rm);       // projection coefficients by row
   L->g = take(sizeof(float) * C);
   L->spart_a = take(sizeof(double) * kNPart * std::max(L->n_groups, L->max_obj_groups));
   L->spart_b = take(sizeof(double) * kNPart * std::max(L->n_groups, L->max_obj_groups));
@@ -239,9 +249,9 @@ bool make_layout(int64_t R, int64_t C, int64_t nnz, int storage, int lpr_log2,
   L->colmax = take(sizeof(uint32_t) * C);
   L->flags = take(sizeof(uint32_t) * 4);
   L->rslice = take(sizeof(int32_t) * Rm);
-  L->rsum = take(sizeof(float) * 2 * Rm);
+  L->rsum = take(sizeof(float) * 2 * Pm);
   L->goff = take(sizeof(int32_t) * L->n_groups);
-  L->alist = take(sizeof(ActRow) * Rm);
+  L->alist = take(sizeof(ActRow) * Pm);
   L->spart = take(scatter_fits(C) ? sizeof(int64_t) * kScatterMaxWGs * C : sizeof(int64_t));
   L->smask = take(scatter_fits(C) ? sizeof(uint64_t) * kScatterMaxWGs * ((C + 63) / 64)
                                   : sizeof(uint64_t));
@@ -339,11 +349,13 @@ void build_groups(int64_t n_slices, std::vector<FwdGroup>* groups) {
                                (int32_t)groups->size()});
 }
 
+// Ranges of positions of the all-row view (per-row data are in position order).
 void build_row_items(fredopt_plan* p) {
   p->rows.clear();
-  for (int64_t r0 = 0; r0 < p->R; r0 += kRowItemRows)
+  const int64_t np = p->L.NP;
+  for (int64_t r0 = 0; r0 < np; r0 += kRowItemRows)
     p->rows.push_back(RowItem{0, (int32_t)p->rows.size(), (int32_t)r0,
-                              (int32_t)std::min(p->R, r0 + kRowItemRows)});
+                              (int32_t)std::min(np, r0 + kRowItemRows)});
   if (p->rows.empty()) p->rows.push_back(RowItem{0, 0, 0, 0});
 }
 
@@ -457,16 +469,7 @@ fredopt_status check_problem_ptrs(const fredopt_problem* pr) {
 void set_problem(fredopt_plan* p, const fredopt_problem* pr, const fredopt_params* q,
                  double ws_fixed, float* x) {
   DevPlan& h = p->hp;
-  h.kind = pr->kind;
-  h.dlo = pr->dose_lo;
-  h.dhi = pr->dose_hi;
-  h.clo = pr->cdl_lo;
-  h.chi = pr->cdl_hi;
-  h.tmax = pr->letd_max;
-  h.wf = pr->w_feas;
-  h.wo = pr->w_obj;
-  h.dt = pr->dose_target;
-  h.ct = pr->cdl_target;
+  (void)pr;  // the kernels read the gathered copies (gather_problem)
   h.prm.lambda = q->lambda;
   h.prm.alpha = q->alpha;
   h.prm.eta = q->eta;
@@ -529,9 +532,9 @@ fredopt_status prepare_gradient(fredopt_plan* p, const fredopt_problem* pr, hipS
     HIPCHK(hipMemsetAsync(p->ws + L.gri, 0, sizeof(int32_t) * ocp[p->C], s));
     HIPCHK(hipMemsetAsync(p->ws + L.gcdv, 0, (size_t)vb * ocp[p->C], s));
     HIPCHK(hipMemsetAsync(p->ws + L.gclv, 0, (size_t)vb * ocp[p->C], s));
-    launch_obj_fill(value_of(p->storage), p->C, d_cp, at<uint32_t>(p, L.colcount), h.ri, h.cdv, h.clv,
-                    pr->kind, at<int64_t>(p, L.ocp), at<int32_t>(p, L.gri), p->ws + L.gcdv,
-                    p->ws + L.gclv, s);
+    launch_obj_fill(value_of(p->storage), p->C, d_cp, at<uint32_t>(p, L.colcount), h.ri, h.cdv,
+                    h.clv, pr->kind, at<int64_t>(p, L.ocp), at<int32_t>(p, L.gri),
+                    p->ws + L.gcdv, p->ws + L.gclv, s);
     HIPCHK(hipGetLastError());
     chunk_columns(ocp, p->C, p->tr_chunk, &p->gtr, &p->gcol_ts0, &p->gcol_nch);
     h.gri = at<int32_t>(p, L.gri);
@@ -648,6 +651,7 @@ fredopt_status prepare_objective_view(fredopt_plan* p, const fredopt_problem* pr
   h.osell.n_slices = (int32_t)O.n_slices;
   h.osell.n_groups = (int32_t)p->ogroups.size();
   h.osell.lpr_log2 = olg;
+
   p->sched_obj = true;
   drop_graph(p);
   return FREDOPT_OK;
@@ -657,9 +661,61 @@ fredopt_status prepare_objective_view(fredopt_plan* p, const fredopt_problem* pr
 // kind array keeps its address and fingerprint.
 fredopt_status prepare_problem(fredopt_plan* p, const fredopt_problem* pr, hipStream_t s) {
   if (p->grad_valid && p->grad_kind == pr->kind && p->grad_fp == p->last_fp) return FREDOPT_OK;
-  fredopt_status st = prepare_gradient(p, pr, s);
+  // the objective-row view first: the gradient copy then stores that view's positions
+  fredopt_status st = prepare_objective_view(p, pr, s);
   if (st != FREDOPT_OK) return st;
-  return prepare_objective_view(p, pr, s);
+  if ((st = prepare_gradient(p, pr, s)) != FREDOPT_OK) return st;
+  if (p->sched_obj && !p->grad_sub) {  // the view needs the objective-row gradient copy
+    p->sched_obj = false;
+    p->hp.osell = p->hp.sell;
+  }
+  drop_graph(p);
+  return FREDOPT_OK;
+}
+
+// The caller's problem (row order) in the views' position orders, for one call: the
+// all-row view, and (obj) the objective-row view's objective terms.
+fredopt_status gather_problem(fredopt_plan* p, const fredopt_problem* pr, bool obj,
+                              hipStream_t s) {
+  DevPlan& h = p->hp;
+  GatherArrays src{}, dst{};
+  src.kind = const_cast<uint16_t*>(pr->kind);
+  const float* in[9] = {pr->dose_lo, pr->dose_hi, pr->cdl_lo, pr->cdl_hi, pr->letd_max,
+                        pr->w_feas, pr->w_obj, pr->dose_target, pr->cdl_target};
+  const float* out[9] = {h.dlo, h.dhi, h.clo, h.chi, h.tmax, h.wf, h.wo, h.dt, h.ct};
+  for (int k = 0; k < 9; ++k) {
+    src.f[k] = const_cast<float*>(in[k]);
+    dst.f[k] = const_cast<float*>(out[k]);
+  }
+  dst.kind = const_cast<uint16_t*>(h.kind);
+  if (!obj) launch_gather_problem(p->L.NP, h.sell.srow, src, dst, 9, s);
+  if (obj && p->sched_obj) {
+    GatherArrays osrc{}, odst{};
+    osrc.kind = src.kind;
+    osrc.f[0] = src.f[6];  // wo, dt, ct
+    osrc.f[1] = src.f[7];
+    osrc.f[2] = src.f[8];
+    odst.kind = const_cast<uint16_t*>(h.okind);
+    odst.f[0] = const_cast<float*>(h.owo);
+    odst.f[1] = const_cast<float*>(h.odt);
+    odst.f[2] = const_cast<float*>(h.oct);
+    launch_gather_problem((int64_t)p->osell.srow.size(), h.osell.srow, osrc, odst, 3, s);
+  }
+  HIPCHK(hipGetLastError());
+  return FREDOPT_OK;
+}
+
+// Checks the problem, gathers it into position order and prepares the per-problem
+// copies (r > 0) for one call.
+fredopt_status bind_problem(fredopt_plan* p, const fredopt_problem* pr, bool prepare,
+                            hipStream_t s) {
+  fredopt_status st = run_problem_check(p, pr, s);
+  if (st != FREDOPT_OK) return st;
+  // the gradient copy's preparation reads the kinds in position order
+  if ((st = gather_problem(p, pr, false, s)) != FREDOPT_OK) return st;
+  if (!prepare) return FREDOPT_OK;
+  if ((st = prepare_problem(p, pr, s)) != FREDOPT_OK) return st;
+  return gather_problem(p, pr, true, s);
 }
 
 fredopt_status upload_state(fredopt_plan* p, const fredopt_state* st, hipStream_t s) {
@@ -750,6 +806,7 @@ std::vector<Launch> iteration_sequence(int r, bool obj) {
     seq.push_back({FREDOPT_KERNEL_ROWS, kKindRows, last ? kRowsMoveResid : kRowsMoveObj});
     seq.push_back({FREDOPT_KERNEL_FINALIZE, kKindFin, last ? kFinResidRows : kFinMoveObj});
   }
+  seq.push_back({FREDOPT_KERNEL_ACTIVE_LIST, kKindList, 0});  // coefficients by row
   seq.push_back({FREDOPT_KERNEL_TR_PROJ, kKindChunks, 1});
   seq.push_back({FREDOPT_KERNEL_COL, kKindCol, kColProjMove});
   return seq;
@@ -837,8 +894,8 @@ void enqueue(const Exec& e, const Launch& l, hipStream_t s) {
     case kKindCol:
       launch_tcol(l.mode, e.table, e.cblocks, e.n_cblocks, s);
       break;
-    case kKindList:
-      if (e.n_sc > 0) launch_active_list(e.table, e.groups, e.n_groups, s);
+    case kKindList:  // active-row list, or the coefficients by row for the CSC path
+      launch_active_list(e.table, e.groups, e.n_groups, s);
       break;
     case kKindScatter:
       launch_scatter(e.storage, e.table, e.sc, e.n_sc, e.sc_lds, s);
@@ -1145,9 +1202,13 @@ fredopt_status fredopt_load_matrices(const fredopt_matrices* m, void* workspace,
   LCHK(hipMemsetAsync(bc, 0, sizeof(uint32_t) * L.nb * C, s));
   launch_block_count(R, C, (int)L.rows_per_block, in_rp, in_col, bc, s);
   launch_block_offsets(C, (int)L.nb, d_cp, bc, s);
-  launch_fill_csc(vt, R, C, (int)L.rows_per_block, in_rp, in_col, in_dv, in_lv, scale, bc,
-                  ri, ws + L.cdv, ws + L.clv, s);
-  launch_moments(vt, R, in_rp, in_col, in_dv, in_lv, scale,
+  launch_fill_csc(vt, R, C, (int)L.rows_per_block, in_rp, in_col, in_dv, in_lv, scale, bc, ri,
+                  ws + L.cdv, ws + L.clv, s);
+  // per-row data in position order; padding positions stay zero
+  const size_t Pm = (size_t)std::max<int64_t>(L.NP, 1);
+  LCHK(hipMemsetAsync(ws + L.mom, 0, sizeof(double) * 3 * Pm, s));
+  LCHK(hipMemsetAsync(ws + L.rsum, 0, sizeof(float) * 2 * Pm, s));
+  launch_moments(vt, R, in_rp, in_col, in_dv, in_lv, scale, d_rslice,
                  reinterpret_cast<double*>(ws + L.mom), reinterpret_cast<float*>(ws + L.rsum), s);
   LCHK(hipGetLastError());
 
@@ -1200,6 +1261,21 @@ fredopt_status fredopt_load_matrices(const fredopt_matrices* m, void* workspace,
   h.dg = reinterpret_cast<float*>(ws + L.dg);
   h.lg = reinterpret_cast<float*>(ws + L.lg);
   h.coef = reinterpret_cast<float2*>(ws + L.coef);
+  h.NP = L.NP;
+  {
+    float* pf = reinterpret_cast<float*>(ws + L.pf);
+    h.kind = reinterpret_cast<const uint16_t*>(ws + L.pkind);
+    const float** fp[9] = {&h.dlo, &h.dhi, &h.clo, &h.chi, &h.tmax, &h.wf, &h.wo, &h.dt, &h.ct};
+    for (int k = 0; k < 9; ++k) *fp[k] = pf + (size_t)k * Pm;
+    const size_t Om = (size_t)std::max<int64_t>(L.max_obj_srow, 1);
+    float* of = reinterpret_cast<float*>(ws + L.of);
+    h.okind = reinterpret_cast<const uint16_t*>(ws + L.okind);
+    h.owo = of;
+    h.odt = of + Om;
+    h.oct = of + 2 * Om;
+    h.gcoef = reinterpret_cast<float2*>(ws + L.gcoef);
+    h.coef_row = reinterpret_cast<float2*>(ws + L.coef_row);
+  }
   h.g = reinterpret_cast<float*>(ws + L.g);
   h.spart_a = reinterpret_cast<double*>(ws + L.spart_a);
   h.spart_b = reinterpret_cast<double*>(ws + L.spart_b);
@@ -1229,7 +1305,9 @@ fredopt_status fredopt_load_matrices(const fredopt_matrices* m, void* workspace,
   st = upload_tr(p, s);
   if (st != FREDOPT_OK) return cleanup(st);
   LCHK(hipMemsetAsync(h.g, 0, sizeof(float) * C, s));
-  LCHK(hipMemsetAsync(h.coef, 0, sizeof(float2) * std::max<int64_t>(R, 1), s));
+  LCHK(hipMemsetAsync(h.coef, 0, sizeof(float2) * Pm, s));
+  LCHK(hipMemsetAsync(ws + L.pkind, 0, sizeof(uint16_t) * Pm, s));
+  LCHK(hipMemsetAsync(ws + L.pf, 0, sizeof(float) * 9 * Pm, s));
   LCHK(hipMemsetAsync(h.spart_a, 0, sizeof(double) * kNPart * L.n_groups, s));
   LCHK(hipMemsetAsync(h.spart_b, 0, sizeof(double) * kNPart * L.n_groups, s));
   st = upload_table(p, s);
@@ -1317,7 +1395,7 @@ fredopt_status fredopt_project_sweep(fredopt_plan* p, const fredopt_problem* pr,
     return fail(FREDOPT_E_ARG, "weight_scale must be positive and finite");
   DeviceGuard guard(p->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if ((st = run_problem_check(p, pr, s)) != FREDOPT_OK) return st;
+  if ((st = bind_problem(p, pr, false, s)) != FREDOPT_OK) return st;
   set_problem(p, pr, q, weight_scale, x_inout);
   if ((st = upload_table(p, s)) != FREDOPT_OK) return st;
   fredopt_state zero{};
@@ -1341,9 +1419,8 @@ static fredopt_status step_common(fredopt_plan* p, const fredopt_problem* pr,
   if (stt->k < 0 || stt->s < -1) return fail(FREDOPT_E_STATE, "state needs k >= 0 and s >= -1");
   DeviceGuard guard(p->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if ((st = run_problem_check(p, pr, s)) != FREDOPT_OK) return st;
   const int r = q->reductions_n;
-  if (r > 0 && (st = prepare_problem(p, pr, s)) != FREDOPT_OK) return st;
+  if ((st = bind_problem(p, pr, r > 0, s)) != FREDOPT_OK) return st;
   set_problem(p, pr, q, -1.0, x);
   if ((st = upload_table(p, s)) != FREDOPT_OK) return st;
   if ((st = upload_state(p, stt, s)) != FREDOPT_OK) return st;
@@ -1385,8 +1462,7 @@ fredopt_status fredopt_profile_kernels(fredopt_plan* p, const fredopt_problem* p
   if ((st = check_params(q, false)) != FREDOPT_OK) return st;
   DeviceGuard guard(p->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if ((st = run_problem_check(p, pr, s)) != FREDOPT_OK) return st;
-  if (q->reductions_n > 0 && (st = prepare_problem(p, pr, s)) != FREDOPT_OK) return st;
+  if ((st = bind_problem(p, pr, q->reductions_n > 0, s)) != FREDOPT_OK) return st;
   set_problem(p, pr, q, -1.0, x);
   if ((st = upload_table(p, s)) != FREDOPT_OK) return st;
   if ((st = upload_state(p, stt, s)) != FREDOPT_OK) return st;
@@ -1516,7 +1592,7 @@ fredopt_status fredopt_autotune(fredopt_plan* p, const float* x, void* stream) {
   }
   p->wgs_per_cu = best_w;
   // transposed chunks (coefficients zero: the timing does not depend on them)
-  HIPCHK(hipMemsetAsync(p->hp.coef, 0, sizeof(float2) * std::max<int64_t>(p->R, 1), s));
+  HIPCHK(hipMemsetAsync(p->hp.coef, 0, sizeof(float2) * std::max<int64_t>(p->L.NP, 1), s));
   int best_chunk = p->tr_chunk;
   best = 1e30;
   for (int ch : {1024, 2048, 4096, 8192, 16384}) {
@@ -1681,8 +1757,7 @@ fredopt_status fredopt_batch_create(fredopt_plan* const* plans, int32_t n,
   DeviceGuard guard(plans[0]->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
   for (int32_t i = 0; i < n; ++i) {
-    fredopt_status st = run_problem_check(plans[i], &problems[i], s);
-    if (st == FREDOPT_OK) st = prepare_problem(plans[i], &problems[i], s);
+    fredopt_status st = bind_problem(plans[i], &problems[i], true, s);
     if (st != FREDOPT_OK) return st;
   }
   fredopt_batch* b = new fredopt_batch;
@@ -1815,6 +1890,9 @@ fredopt_status fredopt_batch_solve(fredopt_batch* b, const fredopt_params* q,
   b->table.resize(n);
   for (int32_t i = 0; i < n; ++i) {
     fredopt_plan* p = b->plans[i];
+    // the problem values may have changed since the last call (the kinds may not)
+    if ((st = gather_problem(p, &b->problems[i], false, s)) != FREDOPT_OK) return st;
+    if ((st = gather_problem(p, &b->problems[i], true, s)) != FREDOPT_OK) return st;
     set_problem(p, &b->problems[i], q, -1.0, x[i]);
     b->table[b->pos[i]] = p->hp;
     b->table[b->pos[i]].n_scatter = b->nsc[i];
