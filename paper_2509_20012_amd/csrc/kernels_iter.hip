@@ -847,7 +847,8 @@ constexpr int kFinWaves = kFinBlock / kWave;
 __device__ __forceinline__ int seg_len(int n) { return (n + kFinBlock - 1) / kFinBlock; }
 
 __device__ __forceinline__ void sum_slots(const double* part_, int n, double* out,
-                                          unsigned used, double (*sh)[kNPart]) {
+                                          unsigned used, double (*sh)[kNPart],
+                                          double* own = nullptr) {
   const FO_GLOBAL double* part = gconst(part_);
   double s[kNPart];
 #pragma unroll
@@ -861,6 +862,10 @@ __device__ __forceinline__ void sum_slots(const double* part_, int n, double* ou
       if (used & (1u << k)) s[k] += p[k];
   }
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  if (own) {  // the thread's own segment sums
+#pragma unroll
+    for (int k = 0; k < kNPart; ++k) own[k] = s[k];
+  }
 #pragma unroll
   for (int k = 0; k < kNPart; ++k)
     if (used & (1u << k)) s[k] = wave_sum(s[k]);
@@ -923,7 +928,8 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(const DevPlan* __restric
       P->st->proj_scatter = 0;
     }
   } else {
-    sum_slots(P->spart_a, P->sell.n_groups, a, 0x1FFu, shs);
+    double own[kNPart];
+    sum_slots(P->spart_a, P->sell.n_groups, a, 0x1FFu, shs, own);
     const int A = (int)a[7];
     // contributions are rounded to multiples of 1 / fx_scale; with every column
     // total bounded by a[8], 2^61 / a[8] keeps all sums far inside int64
@@ -937,10 +943,8 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(const DevPlan* __restric
       const FO_GLOBAL double* part = gconst(P->spart_a);
       const int n = P->sell.n_groups, per = seg_len(n);
       const int i0 = threadIdx.x * per, i1 = min(n, i0 + per);
-      int mine = 0;
-      for (int i = i0; i < i1; ++i) mine += (int)part[(int64_t)i * kNPart + 7];
       int total;
-      int off = block_scan<kFinWaves>(mine, sc, &total);
+      int off = block_scan<kFinWaves>((int)own[7], sc, &total);
       for (int i = i0; i < i1; ++i) {
         gmut(P->goff)[i] = off;
         off += (int)part[(int64_t)i * kNPart + 7];

@@ -47,6 +47,7 @@ constexpr int64_t kTrChunkMin = 256;
 constexpr int64_t kTrChunkDefault = 4096;
 constexpr int64_t kBlockCountCap = int64_t(1) << 24;
 constexpr int kTrWgsPerCu = 8;            // persistent grid of the column-major passes
+constexpr int kObjWgsPerCu = 2;           // forward passes over the objective-row view
 constexpr size_t kScatterLdsMax = 159744; // its LDS accumulator: C 64-bit sums
 
 inline size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
@@ -873,7 +874,10 @@ void enqueue(const Exec& e, const Launch& l, hipStream_t s) {
       // the small objective-row passes take their groups round robin (no counter)
       const int n = l.sub ? e.n_ogroups : e.n_groups;
       const bool dyn = !l.sub && e.fwd_dynamic;
-      const int grid = (int)std::min<int64_t>((int64_t)n, (int64_t)e.n_cu * e.wgs_per_cu);
+      // the all-row pass streams best with one workgroup per CU; the objective-row
+      // passes, one group per workgroup, want more of them in flight
+      const int wgs = l.sub ? kObjWgsPerCu : e.wgs_per_cu;
+      const int grid = (int)std::min<int64_t>((int64_t)n, (int64_t)e.n_cu * wgs);
       launch_forward(e.storage, l.mode, l.sub, e.table, l.sub ? e.ogroups : e.groups, n,
                      std::max(grid, 1), e.lds_floats, dyn ? e.ctr : nullptr, l.vsel, s);
       break;
@@ -986,8 +990,8 @@ fredopt_status device_limits(fredopt_plan* p) {
     p->n_scatter = 0;
     p->scatter_max_rows = 0;
   }
-  // two 8-wave workgroups per CU measured fastest for the streaming passes
-  p->wgs_per_cu = std::min(2, p->max_wgs_per_cu);
+  // one 8-wave workgroup per CU measured fastest for the all-row streaming pass
+  p->wgs_per_cu = 1;
   return FREDOPT_OK;
 }
 
