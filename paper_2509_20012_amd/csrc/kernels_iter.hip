@@ -468,6 +468,29 @@ __device__ __forceinline__ void forward_slice(const DevPlan* __restrict__ P, int
   }
 }
 
+// Copies v (times the per-column scales when SCALED) into LDS.  Each thread has
+// kStage loads in flight before its first store, so the copy costs a few memory
+// round trips instead of one per kFwdBlock elements.
+constexpr int kStage = 16;
+
+template <bool SCALED>
+__device__ __forceinline__ void stage_vector(const FO_GLOBAL float* v, const FO_GLOBAL float* cs,
+                                             int C, float* xs, int tid) {
+  for (int j0 = tid; j0 < C; j0 += kStage * kFwdBlock) {
+    float t[kStage];
+#pragma unroll
+    for (int u = 0; u < kStage; ++u) {
+      const int j = j0 + u * kFwdBlock;
+      t[u] = j < C ? (SCALED ? v[j] * cs[j] : v[j]) : 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < kStage; ++u) {
+      const int j = j0 + u * kFwdBlock;
+      if (j < C) xs[j] = t[u];
+    }
+  }
+}
+
 template <int VT, int MODE, int SUB>
 __global__ __launch_bounds__(kFwdBlock) void k_forward(const DevPlan* __restrict__ plans,
                                                        const FwdGroup* __restrict__ groups,
@@ -513,9 +536,9 @@ __global__ __launch_bounds__(kFwdBlock) void k_forward(const DevPlan* __restrict
         const FO_GLOBAL float* cs = gconst(P->cscale);
         const int C = (int)P->C;
         if (P->cscale)
-          for (int j = tid; j < C; j += kFwdBlock) xs[j] = gv[j] * cs[j];
+          stage_vector<true>(gv, cs, C, xs, tid);
         else
-          for (int j = tid; j < C; j += kFwdBlock) xs[j] = gv[j];
+          stage_vector<false>(gv, cs, C, xs, tid);
       }
       __syncthreads();
       cur = G.plan;
