@@ -603,6 +603,8 @@ __global__ __launch_bounds__(kBlock) void k_rows(const DevPlan* __restrict__ pla
 // columns; the hardware hands block b to XCD b % 8, so block b runs logical block
 // (b % 8) * nb8 + b / 8 and each XCD's L2 sees a contiguous column range.
 // TAG only separates the gradient (0) and projection (1) launches in profiles.
+constexpr int kTrRound = 2;  // steps of a chunk whose loads are in flight together
+
 template <int VT, int TAG>
 __device__ __forceinline__ void tr_chunk(const DevPlan* __restrict__ plans, const TrItem& w,
                                          int lane);
@@ -639,21 +641,46 @@ __device__ __forceinline__ void tr_chunk(const DevPlan* __restrict__ plans, cons
   const FO_GLOBAL v2f* cf = (const FO_GLOBAL v2f*)(TAG == 0 ? P->gcoef : P->coef_row);
   const uint32_t n = (uint32_t)(w.q1 - w.q0);
   float acc = 0.f;
-#pragma unroll 4
-  for (uint32_t e = 4u * (uint32_t)lane; e < n; e += 4u * kWave) {
-    const v4i r4 = load_idx4(ri + e);
-    const v4f d4 = VLoad<VT>::q4(cdv, e);
-    const v4f l4 = VLoad<VT>::q4(clv, e);
-    const v2f c0 = cf[(uint32_t)r4.x], c1 = cf[(uint32_t)r4.y];
-    const v2f c2 = cf[(uint32_t)r4.z], c3 = cf[(uint32_t)r4.w];
-    acc = fmaf(d4.x, c0.x, acc);
-    acc = fmaf(l4.x, c0.y, acc);
-    acc = fmaf(d4.y, c1.x, acc);
-    acc = fmaf(l4.y, c1.y, acc);
-    acc = fmaf(d4.z, c2.x, acc);
-    acc = fmaf(l4.z, c2.y, acc);
-    acc = fmaf(d4.w, c3.x, acc);
-    acc = fmaf(l4.w, c3.y, acc);
+  // rounds of kTrRound steps of 4 kWave slots: the round's stream loads are issued
+  // together, then its coefficient gathers, so a short chunk costs two memory round
+  // trips per round (lanes past the chunk end are masked off)
+  for (uint32_t t0 = 0; t0 < n; t0 += kTrRound * 4u * kWave) {
+    v4i r4[kTrRound];
+    v4f d4[kTrRound], l4[kTrRound];
+#pragma unroll
+    for (int u = 0; u < kTrRound; ++u) {
+      const uint32_t e = t0 + (uint32_t)u * 4u * kWave + 4u * (uint32_t)lane;
+      if (e < n) {
+        r4[u] = load_idx4(ri + e);
+        d4[u] = VLoad<VT>::q4(cdv, e);
+        l4[u] = VLoad<VT>::q4(clv, e);
+      }
+    }
+    v2f c[kTrRound][4];
+#pragma unroll
+    for (int u = 0; u < kTrRound; ++u) {
+      const uint32_t e = t0 + (uint32_t)u * 4u * kWave + 4u * (uint32_t)lane;
+      if (e < n) {
+        c[u][0] = cf[(uint32_t)r4[u].x];
+        c[u][1] = cf[(uint32_t)r4[u].y];
+        c[u][2] = cf[(uint32_t)r4[u].z];
+        c[u][3] = cf[(uint32_t)r4[u].w];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kTrRound; ++u) {
+      const uint32_t e = t0 + (uint32_t)u * 4u * kWave + 4u * (uint32_t)lane;
+      if (e < n) {
+        acc = fmaf(d4[u].x, c[u][0].x, acc);
+        acc = fmaf(l4[u].x, c[u][0].y, acc);
+        acc = fmaf(d4[u].y, c[u][1].x, acc);
+        acc = fmaf(l4[u].y, c[u][1].y, acc);
+        acc = fmaf(d4[u].z, c[u][2].x, acc);
+        acc = fmaf(l4[u].z, c[u][2].y, acc);
+        acc = fmaf(d4[u].w, c[u][3].x, acc);
+        acc = fmaf(l4[u].w, c[u][3].y, acc);
+      }
+    }
   }
   acc = wave_sumf(acc);
   if (lane == 0) gmut(P->tpart)[w.tslot] = acc;
