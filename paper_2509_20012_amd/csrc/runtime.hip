@@ -45,6 +45,9 @@ constexpr int64_t kSortWindow = 8192;     // rows sorted by length inside such w
 constexpr int64_t kRowItemRows = 2048;
 constexpr int64_t kTrChunkMin = 256;
 constexpr int64_t kTrChunkDefault = 4096;
+// Chunk cap of the gradient's column-major copy (objective rows only): its columns
+// are short and few, so smaller chunks balance the waves of the single pass better.
+constexpr int64_t kGradChunk = 512;
 constexpr int64_t kBlockCountCap = int64_t(1) << 24;
 constexpr int kTrWgsPerCu = 8;            // persistent grid of the column-major passes
 constexpr int kObjWgsPerCu = 2;           // forward passes over the objective-row view
@@ -537,7 +540,8 @@ fredopt_status prepare_gradient(fredopt_plan* p, const fredopt_problem* pr, hipS
                     h.clv, pr->kind, at<int64_t>(p, L.ocp), at<int32_t>(p, L.gri),
                     p->ws + L.gcdv, p->ws + L.gclv, s);
     HIPCHK(hipGetLastError());
-    chunk_columns(ocp, p->C, p->tr_chunk, &p->gtr, &p->gcol_ts0, &p->gcol_nch);
+    chunk_columns(ocp, p->C, std::min<int64_t>(p->tr_chunk, kGradChunk), &p->gtr, &p->gcol_ts0,
+                  &p->gcol_nch);
     h.gri = at<int32_t>(p, L.gri);
     h.gcdv = p->ws + L.gcdv;
     h.gclv = p->ws + L.gclv;
