@@ -670,6 +670,10 @@ fredopt_status prepare_problem(fredopt_plan* p, const fredopt_problem* pr, hipSt
   fredopt_status st = prepare_objective_view(p, pr, s);
   if (st != FREDOPT_OK) return st;
   if ((st = prepare_gradient(p, pr, s)) != FREDOPT_OK) return st;
+  // the objective-row pass writes the gradient coefficients of objective rows only;
+  // every other row's stays zero (the column-major copies' padding slots gather
+  // row 0's, with value 0)
+  HIPCHK(hipMemsetAsync(p->hp.gcoef, 0, sizeof(float2) * (size_t)p->hp.R, s));
   if (p->sched_obj && !p->grad_sub) {  // the view needs the objective-row gradient copy
     p->sched_obj = false;
     p->hp.osell = p->hp.sell;

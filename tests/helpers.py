@@ -31,3 +31,27 @@ def dense(pht):
     D[rows, pht.col_idx] = pht.d_val
     L[rows, pht.col_idx] = pht.l_val
     return D, L
+
+
+def load_filled(fo, phantom, fill, storage=0, reserve=0):
+    """(Plan, DeviceProblem, x0) with the phantom's matrices loaded through the C ABI
+    into a workspace whose bytes all start as `fill` (0xFF makes every float and
+    double in it a NaN)."""
+    import ctypes as ct
+    import torch
+    rp = np.ascontiguousarray(phantom.row_ptr, np.int64)
+    arrays = [torch.from_numpy(np.ascontiguousarray(a)).cuda()
+              for a in (rp, phantom.col_idx.astype(np.int32), phantom.d_val.astype(np.float32),
+                        phantom.l_val.astype(np.float32))]
+    nbytes = fo.workspace_bytes_csr(rp, phantom.n_cols, storage, 0, reserve)
+    ws = torch.full((nbytes,), fill, dtype=torch.uint8, device="cuda")
+    m = fo.Matrices(rp.size - 1, phantom.n_cols, int(rp[-1]), *[fo._ptr(t) for t in arrays],
+                    storage, 1, 0, reserve)
+    h = ct.c_void_p()
+    fo._check(fo.lib().fredopt_load_matrices(ct.byref(m), fo._ptr(ws), nbytes, None,
+                                             ct.byref(h)))
+    torch.cuda.synchronize()
+    plan = fo.Plan(h, ws, rp.size - 1, phantom.n_cols, int(rp[-1]), storage)
+    prob = fo.DeviceProblem(phantom.problem_arrays(), phantom.c)
+    x0 = torch.from_numpy(np.ascontiguousarray(phantom.x0, np.float32)).cuda()
+    return plan, prob, x0

@@ -10,6 +10,7 @@ import pytest
 
 from oracle import Oracle, OracleParams
 from paper_2509_20012_amd import phantom as ph
+from tests.helpers import load_filled
 
 pytestmark = pytest.mark.gpu
 
@@ -77,6 +78,26 @@ def test_batch_equals_alone_bitwise(fo, r, reserve):
         assert np.array_equal(_np(xs[i]), xr), p.name
     if r > 0 and reserve == 0:
         assert sorted({x[2] for x in ref}) == [0, 1]   # both schedules present
+    batch.free()
+
+
+def test_batch_independent_of_workspace_contents(fo):
+    """Plans whose workspaces start as NaN bytes give, in a batch, the iterates of
+    the same plans alone (every plan with the objective-row view, r = 1)."""
+    print("batch with NaN-filled plan workspaces", flush=True)
+    phs = _mix()
+    q = fo.SolverParams(alpha=0.9, reductions_n=1)
+    iters = 6
+    ref = [_alone(fo, p, q, iters, 100) for p in phs]
+    loaded = [load_filled(fo, p, 0xFF, reserve=100) for p in phs]
+    xs = [x0.clone() for _, _, x0 in loaded]
+    states = [fo.new_state() for _ in phs]
+    batch = fo.Batch([pl for pl, _, _ in loaded], [pr for _, pr, _ in loaded])
+    batch.solve(q, states, xs, iters)
+    for i, p in enumerate(phs):
+        xr, ks, _ = ref[i]
+        assert (states[i].k, states[i].s) == ks, p.name
+        assert np.array_equal(_np(xs[i]), xr), p.name
     batch.free()
 
 

@@ -13,6 +13,7 @@ import pytest
 from oracle import Oracle, OracleParams
 from paper_2509_20012_amd import metrics
 from paper_2509_20012_amd import phantom as ph
+from tests.helpers import load_filled
 
 pytestmark = pytest.mark.gpu
 
@@ -283,6 +284,29 @@ def test_solve_deterministic_and_resumable(fo, w32, path):
     for _ in range(20):
         fo.superiorize_step(plan, prob, q, sd, xd)
     assert np.array_equal(_np(xa), _np(xd))
+
+
+@pytest.mark.parametrize("path", ["csc", "scatter"])
+def test_result_independent_of_workspace_contents(fo, w32, path):
+    """A solve reads nothing of the workspace that it has not written: workspaces
+    that start as zeros, as NaNs (0xFF bytes) or as large finite values (0x7F) give
+    the same iterates bit for bit, and they match the oracle."""
+    print(f"workspace contents water32 path={path}", flush=True)
+    q = _params(fo, iter_max=20)
+    runs = []
+    for fill in (0x00, 0xFF, 0x7F):
+        plan, prob, x0 = load_filled(fo, w32, fill)
+        _set_path(fo, plan, path)
+        st = fo.new_state()
+        x = x0.clone()
+        fo.solve(plan, prob, q, st, x)
+        runs.append((_np(x), st.k, st.s))
+        plan.free()
+    for xr_, k_, s_ in runs[1:]:
+        assert np.array_equal(runs[0][0], xr_) and (runs[0][1], runs[0][2]) == (k_, s_)
+    xr, k, s, _ = Oracle(w32).solve(w32.x0, 20, _oparams(q))
+    assert (runs[0][1], runs[0][2]) == (k, s)
+    assert np.linalg.norm(runs[0][0] - xr) / np.linalg.norm(xr) <= T2
 
 
 def test_load_errors(fo):
