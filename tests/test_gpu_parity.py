@@ -286,27 +286,34 @@ def test_solve_deterministic_and_resumable(fo, w32, path):
     assert np.array_equal(_np(xa), _np(xd))
 
 
+@pytest.mark.parametrize("reserve", [0, -1])
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16i16"])
 @pytest.mark.parametrize("path", ["csc", "scatter"])
-def test_result_independent_of_workspace_contents(fo, w32, path):
+def test_result_independent_of_workspace_contents(fo, w32, path, storage, reserve):
     """A solve reads nothing of the workspace that it has not written: workspaces
     that start as zeros, as NaNs (0xFF bytes) or as large finite values (0x7F) give
-    the same iterates bit for bit, and they match the oracle."""
-    print(f"workspace contents water32 path={path}", flush=True)
+    the same iterates bit for bit (with the objective-row view, reserve 0, and
+    without it, reserve -1), and in FP32 they match the oracle."""
+    print(f"workspace contents water32 path={path} storage={storage} reserve={reserve}",
+          flush=True)
+    st_code = {"f32": fo.F32, "f16": fo.F16, "bf16i16": fo.BF16_IDX16}[storage]
     q = _params(fo, iter_max=20)
     runs = []
     for fill in (0x00, 0xFF, 0x7F):
-        plan, prob, x0 = load_filled(fo, w32, fill)
+        plan, prob, x0 = load_filled(fo, w32, fill, storage=st_code, reserve=reserve)
         _set_path(fo, plan, path)
         st = fo.new_state()
         x = x0.clone()
         fo.solve(plan, prob, q, st, x)
         runs.append((_np(x), st.k, st.s))
         plan.free()
+    assert np.all(np.isfinite(runs[0][0]))
     for xr_, k_, s_ in runs[1:]:
         assert np.array_equal(runs[0][0], xr_) and (runs[0][1], runs[0][2]) == (k_, s_)
-    xr, k, s, _ = Oracle(w32).solve(w32.x0, 20, _oparams(q))
-    assert (runs[0][1], runs[0][2]) == (k, s)
-    assert np.linalg.norm(runs[0][0] - xr) / np.linalg.norm(xr) <= T2
+    if storage == "f32":
+        xr, k, s, _ = Oracle(w32).solve(w32.x0, 20, _oparams(q))
+        assert (runs[0][1], runs[0][2]) == (k, s)
+        assert np.linalg.norm(runs[0][0] - xr) / np.linalg.norm(xr) <= T2
 
 
 def test_load_errors(fo):
