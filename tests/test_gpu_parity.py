@@ -316,6 +316,44 @@ def test_result_independent_of_workspace_contents(fo, w32, path, storage, reserv
         assert np.linalg.norm(runs[0][0] - xr) / np.linalg.norm(xr) <= T2
 
 
+@pytest.mark.parametrize("storage", ["f32", "bf16i16"])
+def test_entry_points_independent_of_workspace_contents(fo, w32, storage):
+    """The first call on a freshly loaded plan, for each entry point (dose / LETd,
+    one sweep on both projection paths, one superiorized step), gives the same
+    result bit for bit whatever the workspace held before the load."""
+    import torch
+    print(f"entry points, workspace contents water32 storage={storage}", flush=True)
+    st_code = {"f32": fo.F32, "bf16i16": fo.BF16_IDX16}[storage]
+    x = torch.from_numpy(np.random.default_rng(4).uniform(0.5, 1.5, w32.n_cols)
+                         .astype(np.float32)).cuda()
+    q = _params(fo)
+    out = {}
+    for fill in (0x00, 0xFF, 0x7F):
+        res = []
+        plan, prob, _ = load_filled(fo, w32, fill, storage=st_code)
+        res += [_np(t) for t in fo.dose_let(plan, x, w32.c)]
+        plan.free()
+        for path in ("csc", "scatter"):
+            plan, prob, _ = load_filled(fo, w32, fill, storage=st_code)
+            _set_path(fo, plan, path)
+            xs = x.clone()
+            prox = fo.project_sweep(plan, prob, q, xs)
+            res += [_np(xs), np.array([prox])]
+            plan.free()
+        plan, prob, _ = load_filled(fo, w32, fill, storage=st_code)
+        st = fo.new_state()
+        xs = x.clone()
+        fo.superiorize_step(plan, prob, q, st, xs)
+        res += [_np(xs), np.array([st.k, st.s, st.cost])]
+        plan.free()
+        out[fill] = res
+    for a in out[0x00]:
+        assert np.all(np.isfinite(a))
+    for fill in (0xFF, 0x7F):
+        for a, b in zip(out[0x00], out[fill]):
+            assert np.array_equal(a, b), hex(fill)
+
+
 def test_load_errors(fo):
     import torch
     p = ph.tiny_problem(10, 4, 0.5, seed=3)
