@@ -998,8 +998,10 @@ fredopt_status device_limits(fredopt_plan* p) {
     p->n_scatter = 0;
     p->scatter_max_rows = 0;
   }
-  // one 8-wave workgroup per CU measured fastest for the all-row streaming pass
-  p->wgs_per_cu = 1;
+  // workgroups per CU of the all-row streaming pass, as measured on the clinical
+  // plan: one 8-wave workgroup for FP32; two for 16-bit values, whose steps carry
+  // half the bytes, so a CU needs more waves in flight to keep HBM busy
+  p->wgs_per_cu = p->storage == FREDOPT_F32 ? 1 : 2;
   return FREDOPT_OK;
 }
 
