@@ -1001,7 +1001,7 @@ fredopt_status device_limits(fredopt_plan* p) {
   // workgroups per CU of the all-row streaming pass, as measured on the clinical
   // plan: one 8-wave workgroup for FP32; two for 16-bit values, whose steps carry
   // half the bytes, so a CU needs more waves in flight to keep HBM busy
-  p->wgs_per_cu = p->storage == FREDOPT_F32 ? 1 : 2;
+  p->wgs_per_cu = std::min(p->storage == FREDOPT_F32 ? 1 : 2, p->max_wgs_per_cu);
   return FREDOPT_OK;
 }
 
