@@ -144,10 +144,12 @@ def bench_batch(args):
     storage = fredopt.STORAGE[args.storage]
     lanes = [0] * len(phs)
     if args.autotune:
+        # the batch autotuner: the batched iteration timed at each candidate width
         t0 = time.perf_counter()
-        lanes = [autotune.choose_lanes(p, storage, reps=3)[0] for p in phs]
-        log(f"autotuned lanes per row in {time.perf_counter() - t0:.1f} s: "
-            f"{ {k: lanes.count(k) for k in sorted(set(lanes))} }")
+        best, rates = autotune.choose_batch_lanes(phs, storage, reductions_n=args.reductions)
+        lanes = [best] * len(phs)
+        log(f"autotuned lanes per row in {time.perf_counter() - t0:.1f} s: {best} "
+            f"(plan-iterations/s by width: { {k: round(v) for k, v in rates.items()} })")
     loaded = [fredopt.load_phantom(p, storage=storage, lanes_per_row=lw)
               for p, lw in zip(phs, lanes)]
     q = fredopt.SolverParams(reductions_n=args.reductions)
@@ -178,7 +180,7 @@ def bench_batch(args):
         "data": "synthetic",
         "config": {"workload": desc, "plans": len(loaded), "nnz_total": nnz,
                    "storage": args.storage, "reductions_n": args.reductions,
-                   "lanes_per_row": "autotuned" if args.autotune else "rule"},
+                   "lanes_per_row": f"autotuned ({lanes[0]})" if args.autotune else "rule"},
         "value_meaning": "plan-iterations per second summed over the plans",
         "one_at_a_time_iters_per_s": round(alone_rate, 2),
         "speedup_vs_one_at_a_time": round(rate / alone_rate, 3),

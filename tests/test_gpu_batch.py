@@ -141,6 +141,16 @@ def test_lane_autotuner_picks_a_timed_candidate(fo):
     assert times[best] == min(times.values())
 
 
+def test_batch_autotuner_picks_the_fastest_timed_width(fo):
+    from paper_2509_20012_amd import autotune
+    phs = [ph.small_plan(3001, 5000, 200), ph.small_plan(3002, 8000, 300),
+           ph.tiny_problem(300, 30, 0.15, seed=21)]
+    best, rates = autotune.choose_batch_lanes(phs, candidates=(1, 2), iters=4)
+    assert set(rates) == {1, 2} and best in rates
+    assert all(r > 0 for r in rates.values())
+    assert rates[best] == max(rates.values())
+
+
 def test_scenario_batch_equals_alone(fo):
     """Robustness scenarios of one plan iterated together equal their solo runs."""
     phs = ph.scenario_plans(1, seed=3)
