@@ -35,7 +35,7 @@ constexpr int kFwdWaves = kFwdBlock / kWave;
 constexpr int kBlock = 256;            // other kernels
 constexpr int kScatterBlock = 1024;    // active-row scatter: 16 waves, one row each
 constexpr int kScatterMaxWGs = 256;    // workgroups of the active-row scatter (max)
-constexpr int kNPart = 16;             // doubles per partial-sum slot
+constexpr int kNPart = 10;             // doubles per partial-sum slot (slots 0-8 used)
 constexpr int kCounters = 4;           // scheduling counters per batch
 constexpr double kDegenerateRel = 1e-12;
 constexpr double kBetaFloor = 1e-300;
