@@ -214,7 +214,7 @@ def bench_serve(args):
         f"{serve.percentile(lat, 99):.3f} s, {iters / wall:.1f} plan-iterations/s, "
         f"{srv.batches_built} batches, peak {srv.peak_active} resident")
     t0 = time.perf_counter()
-    base = serve.serve_one_at_a_time([dataclasses.replace(r) for r in reqs], q)
+    base = serve.serve_one_at_a_time([dataclasses.replace(r) for r in reqs], q, log=log)
     wall_b = time.perf_counter() - t0
     lat_b = [r.latency for r in base]
     log(f"one at a time: p50 {serve.percentile(lat_b, 50):.3f} s, p99 "

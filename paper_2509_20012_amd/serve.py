@@ -4,7 +4,8 @@ Requests (a plan's influence matrices and problem, an iteration count, an arriva
 time) are admitted while the device memory they need fits a budget; admitted plans
 stay resident and are iterated together by batched launches (fredopt_batch_*):
 continuous batching, where the batch is rebuilt whenever a request joins or
-leaves, between quanta of outer iterations.  A request's latency runs from its
+leaves, between quanta of outer iterations.  A lane with a single active request
+runs the plain single-plan solve instead (no batch to build).  A request's latency runs from its
 arrival to its result (the fluence) being on the host, and includes the load.
 
 Every batched iteration of a plan equals its single-plan iteration bit for bit,
@@ -78,7 +79,9 @@ class Server:
         self.storage = storage
         self.big_nnz = int(big_nnz)
         self.log = log or (lambda m: None)
+        self.progress_every = 100   # a log line every this many finished requests
         self.batches_built = 0
+        self.solo_quanta = 0        # quanta run by a lane's single active request
         self.peak_active = 0
         self.peak_bytes = 0
 
@@ -144,14 +147,26 @@ class Server:
                 wait = queue[qi].arrival - now() if qi < len(queue) else 0.0
                 time.sleep(wait if wait > 0 else 0.001)  # next arrival, or budget freed
                 continue
-            if changed or batch is None:
+            n = min(self.quantum, min(a.left for a in active))
+            if len(active) == 1:
+                # alone in its lane: the plain single-plan solve (its own cached graph);
+                # it resumes from the same state, so the iterates are those of a batch
                 if batch is not None:
                     batch.free()
-                batch = fredopt.Batch([a.plan for a in active], [a.prob for a in active])
+                    batch = None
+                a = active[0]
+                params.iter_max = n
+                fredopt.solve(a.plan, a.prob, params, a.state, a.x)
                 with lock:
-                    self.batches_built += 1
-            n = min(self.quantum, min(a.left for a in active))
-            batch.solve(params, [a.state for a in active], [a.x for a in active], n)
+                    self.solo_quanta += 1
+            else:
+                if changed or batch is None:
+                    if batch is not None:
+                        batch.free()
+                    batch = fredopt.Batch([a.plan for a in active], [a.prob for a in active])
+                    with lock:
+                        self.batches_built += 1
+                batch.solve(params, [a.state for a in active], [a.x for a in active], n)
             for a in active:
                 a.left -= n
             finished = [a for a in active if a.left == 0]
@@ -161,8 +176,9 @@ class Server:
                     req.x = a.x.cpu().numpy()
                     req.k, req.s = a.state.k, a.state.s
                     req.finished = now()
-                batch.free()
-                batch = None
+                if batch is not None:
+                    batch.free()
+                    batch = None
                 active = [a for a in active if a.left > 0]
                 for a in finished:
                     a.plan.free()
@@ -172,18 +188,21 @@ class Server:
                         done.append(a.req)
                         state["used"] -= a.bytes
                         state["active"] -= 1
+                        if len(done) % self.progress_every == 0:
+                            self.log(f"served {len(done)} requests")
                 del finished
         if batch is not None:
             batch.free()
 
 
 def serve_one_at_a_time(requests: List[Request], params: fredopt.SolverParams,
-                        storage: int = fredopt.F32) -> List[Request]:
+                        storage: int = fredopt.F32,
+                        log: Optional[Callable[[str], None]] = None) -> List[Request]:
     """First come, first served; each request solved alone by fredopt_solve."""
     queue = sorted(requests, key=lambda r: (r.arrival, r.rid))
     t0 = time.perf_counter()
     now = lambda: time.perf_counter() - t0  # noqa: E731
-    for req in queue:
+    for i, req in enumerate(queue):
         wait = req.arrival - now()
         if wait > 0:
             time.sleep(wait)
@@ -196,6 +215,8 @@ def serve_one_at_a_time(requests: List[Request], params: fredopt.SolverParams,
         req.k, req.s = st.k, st.s
         req.finished = now()
         plan.free()
+        if log and (i + 1) % 100 == 0:
+            log(f"served {i + 1} requests one at a time")
     return queue
 
 

@@ -44,11 +44,12 @@ def test_served_results_equal_alone(fo):
     # the water plans (> 100k entries) form the second lane
     srv = serve.Server(budget, q, quantum=4, big_nnz=100_000)
     done = srv.run(reqs)
-    print(f"batches built {srv.batches_built}, peak active {srv.peak_active}, "
-          f"peak bytes {srv.peak_bytes} of {budget}", flush=True)
+    print(f"batches built {srv.batches_built}, solo quanta {srv.solo_quanta}, peak active "
+          f"{srv.peak_active}, peak bytes {srv.peak_bytes} of {budget}", flush=True)
     assert len(done) == len(reqs)
     assert srv.peak_bytes <= budget
-    assert srv.batches_built > 2
+    # requests joined and left batches, and ran alone in their lane between them
+    assert srv.batches_built >= 2 and srv.solo_quanta >= 1 and srv.peak_active >= 3
     for r in done:
         x_ref, ks = _alone(fo, r.phantom, fo.SolverParams(alpha=0.9), r.iters)
         assert (r.k, r.s) == ks, r.rid
