@@ -354,6 +354,40 @@ def test_entry_points_independent_of_workspace_contents(fo, w32, storage):
             assert np.array_equal(a, b), hex(fill)
 
 
+def test_wide_plan_without_lds_staging(fo):
+    """70,000 beamlets: the input vector does not fit in LDS, so the forward passes
+    gather it from global memory; the active-row scatter's column sums do not fit
+    either (column-major projection only); 16-bit column indices are refused.
+    T1 for dose / LETd / cDL, T2 for a sweep and a superiorized step."""
+    import torch
+    print("wide plan R=600 C=70000", flush=True)
+    p = ph.tiny_problem(600, 70000, 0.001, seed=31)
+    plan, prob, x0 = fo.load_phantom(p)
+    info = plan.info()
+    assert info["lds_x"] == 0 and info["scatter_wgs"] == 0
+    x = torch.from_numpy(np.random.default_rng(8).uniform(0.5, 1.5, p.n_cols)
+                         .astype(np.float32)).cuda()
+    dose, letd, cdl = fo.dose_let(plan, x, p.c)
+    d_r, l_r, t_r, c_r = Oracle(p).dose_let(_np(x))
+    assert _rel_rows(_np(dose), d_r) <= T1
+    assert _rel_rows(_np(letd), t_r, d_r > 0) <= T1
+    assert _rel_rows(_np(cdl), c_r, d_r > 0) <= T1
+    q = _params(fo)
+    xs = x0.clone()
+    fo.project_sweep(plan, prob, q, xs)
+    xr = Oracle(p).ams_simultaneous(p.x0, lam=q.lam, weight_scale=1.0,
+                                    normalization=q.normalization)[0]
+    assert np.linalg.norm(_np(xs) - xr) / np.linalg.norm(xr) <= T2
+    st = fo.new_state()
+    xs = x0.clone()
+    fo.superiorize_step(plan, prob, q, st, xs)
+    xo, k, s, _ = Oracle(p).sa_iteration(p.x0.astype(np.float64), 0, -1, _oparams(q))
+    assert (st.k, st.s) == (k, s)
+    assert np.linalg.norm(_np(xs) - xo) / np.linalg.norm(xo) <= T2
+    with pytest.raises(fo.FredoptError):
+        fo.load_phantom(p, storage=fo.F16_IDX16)
+
+
 def test_load_errors(fo):
     import torch
     p = ph.tiny_problem(10, 4, 0.5, seed=3)
