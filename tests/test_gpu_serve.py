@@ -36,7 +36,10 @@ def test_served_results_equal_alone(fo):
            ph.tiny_problem(64, 16, 0.3, seed=6, empty_rows=[0, 5, 63], empty_cols=[3, 15]),
            ph.small_plan(3004, 5000, 220)]
     iters = [7, 12, 5, 20, 9, 3]
-    arrivals = [0.0, 0.0, 0.01, 0.02, 0.03, 0.2]
+    # the three small requests (one lane) arrive together: they form a batch, leave
+    # it at different times and the longest finishes alone; the water plans (the
+    # other lane) queue on the budget
+    arrivals = [0.0, 0.0, 0.0, 0.0, 0.0, 0.05]
     reqs = [serve.Request(i, p, n, t) for i, (p, n, t) in enumerate(zip(phs, iters, arrivals))]
     sizes = [serve.plan_bytes(p) for p in phs]
     budget = sorted(sizes)[-1] + sorted(sizes)[-2]   # forces queueing
@@ -48,8 +51,7 @@ def test_served_results_equal_alone(fo):
           f"{srv.peak_active}, peak bytes {srv.peak_bytes} of {budget}", flush=True)
     assert len(done) == len(reqs)
     assert srv.peak_bytes <= budget
-    # requests joined and left batches, and ran alone in their lane between them
-    assert srv.batches_built >= 2 and srv.solo_quanta >= 1 and srv.peak_active >= 3
+    assert srv.batches_built >= 1 and srv.solo_quanta >= 1 and srv.peak_active >= 3
     for r in done:
         x_ref, ks = _alone(fo, r.phantom, fo.SolverParams(alpha=0.9), r.iters)
         assert (r.k, r.s) == ks, r.rid
