@@ -812,18 +812,29 @@ __device__ __forceinline__ void project_column(const DevPlan* __restrict__ P, in
   if constexpr (MODE == kColProjY) gmut(P->y)[j] = xf;
 }
 
-// Sum of the scatter workgroups' shares for 64 columns (16 waves take every 16th
-// share; integer sums, so the grouping does not matter), then the update.
+// The sweep's update of 64 columns: on the active-row path, the sum of the scatter
+// workgroups' shares (16 waves take every 16th share; integer sums, so the grouping
+// does not matter); on the column-major path, the column's chunk partials in chunk
+// order.  Then the projection update and clamp.
 template <int MODE>
 __global__ __launch_bounds__(kScatterBlock) void k_scatter_sum(const DevPlan* __restrict__ plans,
                                                               const ScItem* __restrict__ items) {
   __shared__ int64_t part[kScatterBlock / kWave][kWave];
   const ScItem item = items[blockIdx.x];
   const DevPlan* __restrict__ P = plans + item.plan;
-  if (!P->st->proj_scatter) return;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   const int C = (int)P->C, nwords = (C + kWave - 1) / kWave;
   const int j = item.idx * kWave + lane;
+  if (!P->st->proj_scatter) {
+    // the column-major path: the column's chunk partials in chunk order
+    if (wave == 0 && j < C) {
+      const int ts = gconst(P->col_tslot0)[j], n = gconst(P->col_nch)[j];
+      float t = 0.f;
+      for (int c = 0; c < n; ++c) t += gconst(P->tpart)[ts + c];
+      project_column<MODE>(P, j, t);
+    }
+    return;
+  }
   const FO_GLOBAL int64_t* sp = gconst(P->spart) + j;
   const FO_GLOBAL uint64_t* mk = gconst(P->smask) + item.idx;
   // all masks first, then the shares they mark: two dependent rounds of loads

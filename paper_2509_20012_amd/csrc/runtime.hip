@@ -417,23 +417,25 @@ fredopt_status upload_tr(fredopt_plan* p, hipStream_t s) {
 
 // Workgroups of the active-row scatter of a plan (n shares, share w -> {plan, w})
 // and of its share sum (one per 64 columns).
+// n scatter workgroups, and the column update's blocks of 64 columns (every plan has
+// them: the update also finishes the column-major path)
 void scatter_items(int32_t plan, int n, int64_t C, std::vector<ScItem>* sc,
                    std::vector<ScItem>* ss) {
   for (int w = 0; w < n; ++w) sc->push_back(ScItem{plan, w});
-  if (n > 0)
-    for (int64_t j = 0; j < (C + 63) / 64; ++j) ss->push_back(ScItem{plan, (int32_t)j});
+  for (int64_t j = 0; j < (C + 63) / 64; ++j) ss->push_back(ScItem{plan, (int32_t)j});
 }
 
 fredopt_status upload_scatter_items(fredopt_plan* p, hipStream_t s) {
   p->sc_items.clear();
   p->ss_items.clear();
   scatter_items(0, p->n_scatter, p->C, &p->sc_items, &p->ss_items);
-  if (!p->sc_items.empty()) {
+  if (!p->sc_items.empty())
     HIPCHK(hipMemcpyAsync(p->d_sc, p->sc_items.data(), sizeof(ScItem) * p->sc_items.size(),
                           hipMemcpyHostToDevice, s));
+  // the column update runs on both projection paths: its items always exist
+  if (!p->ss_items.empty())
     HIPCHK(hipMemcpyAsync(p->d_ss, p->ss_items.data(), sizeof(ScItem) * p->ss_items.size(),
                           hipMemcpyHostToDevice, s));
-  }
   return FREDOPT_OK;
 }
 
@@ -775,16 +777,23 @@ struct Launch {
 // Without it: the all-row forward products at x and along g, d and l moved by the
 // accepted step.  The caller sets y = x before the first iteration; the
 // projection writes x and y.
+// The sweep's transposed product and update.  The device picks the path per plan
+// and iteration (proj_scatter): the kernels of the other path return at once.  The
+// last launch updates every column: from the scatter shares, or from the chunk
+// partials of the column-major path.
+void add_projection(std::vector<Launch>* seq, int col_mode) {
+  seq->push_back({FREDOPT_KERNEL_ACTIVE_LIST, kKindList, 0});
+  seq->push_back({FREDOPT_KERNEL_SCATTER, kKindScatter, 0});
+  seq->push_back({FREDOPT_KERNEL_TR_PROJ, kKindChunks, 1});
+  seq->push_back({FREDOPT_KERNEL_SCATTER_SUM, kKindScatterSum, col_mode});
+}
+
 std::vector<Launch> iteration_sequence(int r, bool obj) {
   std::vector<Launch> seq;
   if (r == 0) {
     seq.push_back({FREDOPT_KERNEL_FWD_RESID, kKindFwd, kFwdResid, 0, kVecX});
     seq.push_back({FREDOPT_KERNEL_FINALIZE, kKindFin, kFinResidFwd});
-    seq.push_back({FREDOPT_KERNEL_ACTIVE_LIST, kKindList, 0});
-    seq.push_back({FREDOPT_KERNEL_SCATTER, kKindScatter, 0});
-    seq.push_back({FREDOPT_KERNEL_SCATTER_SUM, kKindScatterSum, kColProj});
-    seq.push_back({FREDOPT_KERNEL_TR_PROJ, kKindChunks, 1});
-    seq.push_back({FREDOPT_KERNEL_COL, kKindCol, kColProj});
+    add_projection(&seq, kColProj);
     return seq;
   }
   if (obj) {
@@ -798,11 +807,7 @@ std::vector<Launch> iteration_sequence(int r, bool obj) {
     }
     seq.push_back({FREDOPT_KERNEL_FWD_RESID, kKindFwd, kFwdResid, 0, kVecY});
     seq.push_back({FREDOPT_KERNEL_FINALIZE, kKindFin, kFinResidFwd});
-    seq.push_back({FREDOPT_KERNEL_ACTIVE_LIST, kKindList, 0});
-    seq.push_back({FREDOPT_KERNEL_SCATTER, kKindScatter, 0});
-    seq.push_back({FREDOPT_KERNEL_SCATTER_SUM, kKindScatterSum, kColProjY});
-    seq.push_back({FREDOPT_KERNEL_TR_PROJ, kKindChunks, 1});
-    seq.push_back({FREDOPT_KERNEL_COL, kKindCol, kColProjY});
+    add_projection(&seq, kColProjY);
     return seq;
   }
   seq.push_back({FREDOPT_KERNEL_FWD_OBJ, kKindFwd, kFwdObj, 0, kVecX});
@@ -913,7 +918,7 @@ void enqueue(const Exec& e, const Launch& l, hipStream_t s) {
       launch_scatter(e.storage, e.table, e.sc, e.n_sc, e.sc_lds, s);
       break;
     case kKindScatterSum:
-      if (e.n_sc > 0) launch_scatter_sum(l.mode, e.table, e.ss, e.n_ss, s);
+      if (e.n_ss > 0) launch_scatter_sum(l.mode, e.table, e.ss, e.n_ss, s);
       break;
     default:
       launch_finalize(l.mode, l.sub, e.table, e.n_plans, s);

@@ -388,6 +388,28 @@ def test_wide_plan_without_lds_staging(fo):
         fo.load_phantom(p, storage=fo.F16_IDX16)
 
 
+def test_wide_plan_independent_of_workspace_contents(fo):
+    """The 70,000-beamlet plan (no active-row scatter: every column update comes
+    from the column-major path) gives the same sweep and solve bit for bit whatever
+    its workspace held."""
+    print("wide plan, workspace contents", flush=True)
+    p = ph.tiny_problem(600, 70000, 0.001, seed=31)
+    q = _params(fo, iter_max=5)
+    out = []
+    for fill in (0x00, 0xFF, 0x7F):
+        plan, prob, x0 = load_filled(fo, p, fill)
+        xs = x0.clone()
+        fo.project_sweep(plan, prob, q, xs)
+        st = fo.new_state()
+        xg = x0.clone()
+        fo.solve(plan, prob, q, st, xg)
+        out.append((_np(xs), _np(xg), st.k, st.s))
+        plan.free()
+    for o in out[1:]:
+        assert np.array_equal(out[0][0], o[0]) and np.array_equal(out[0][1], o[1])
+        assert out[0][2:] == o[2:]
+
+
 def test_load_errors(fo):
     import torch
     p = ph.tiny_problem(10, 4, 0.5, seed=3)
