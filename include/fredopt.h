@@ -23,7 +23,8 @@
  * Conventions for every call:
  *  - Device pointers everywhere except fredopt_matrices with on_device = 0 and
  *    the host structs (problem, params, state) themselves.  Every array of a
- *    fredopt_problem is a device array of n_rows elements.
+ *    fredopt_problem is a device array of n_rows elements (NULL is accepted when
+ *    n_rows = 0).
  *  - The caller owns every buffer it passes.  The library keeps no caller pointer
  *    after a call returns; it reads or writes the caller's arrays only during the
  *    call (work is enqueued on `stream`; the call returns once the stream work that

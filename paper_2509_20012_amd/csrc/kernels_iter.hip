@@ -1090,6 +1090,7 @@ static void launch_tr_tag(int vtype, const DevPlan* plans, const TrItem* items, 
 
 void launch_tr_chunks(int vtype, int tag, const DevPlan* plans, const TrItem* items,
                       int n_items, int max_grid, int single, hipStream_t s) {
+  if (n_items <= 0) return;  // no stored entries
   const int per = kBlock / kWave;
   const int nblocks = (n_items + per - 1) / per;
   const int nb8 = (nblocks + 7) / 8;

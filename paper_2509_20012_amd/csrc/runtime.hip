@@ -462,10 +462,12 @@ fredopt_status check_params(const fredopt_params* q, bool need_iter) {
   return FREDOPT_OK;
 }
 
-fredopt_status check_problem_ptrs(const fredopt_problem* pr) {
+// R: the plan's rows (a plan without rows takes arrays of length 0, NULL allowed)
+fredopt_status check_problem_ptrs(const fredopt_problem* pr, int64_t R) {
   if (!pr) return fail(FREDOPT_E_ARG, "problem is NULL");
-  if (!pr->kind || !pr->dose_lo || !pr->dose_hi || !pr->cdl_lo || !pr->cdl_hi || !pr->letd_max ||
-      !pr->w_feas || !pr->w_obj || !pr->dose_target || !pr->cdl_target)
+  if (R > 0 && (!pr->kind || !pr->dose_lo || !pr->dose_hi || !pr->cdl_lo || !pr->cdl_hi ||
+                !pr->letd_max || !pr->w_feas || !pr->w_obj || !pr->dose_target ||
+                !pr->cdl_target))
     return fail(FREDOPT_E_ARG, "a problem array is NULL");
   if (!(pr->c > 0.0) || !std::isfinite(pr->c))
     return fail(FREDOPT_E_ARG, "c must be positive and finite, got %g", pr->c);
@@ -1407,7 +1409,7 @@ fredopt_status fredopt_project_sweep(fredopt_plan* p, const fredopt_problem* pr,
                                      const fredopt_params* q, double weight_scale,
                                      float* x_inout, double* proximity_out, void* stream) {
   if (!p || !x_inout) return fail(FREDOPT_E_ARG, "plan and x must be non-NULL");
-  fredopt_status st = check_problem_ptrs(pr);
+  fredopt_status st = check_problem_ptrs(pr, p->R);
   if (st != FREDOPT_OK) return st;
   if ((st = check_params(q, false)) != FREDOPT_OK) return st;
   if (!(weight_scale > 0.0) || !std::isfinite(weight_scale))
@@ -1432,7 +1434,7 @@ static fredopt_status step_common(fredopt_plan* p, const fredopt_problem* pr,
                                   const fredopt_params* q, fredopt_state* stt, float* x,
                                   void* stream, int iters, bool use_graph) {
   if (!p || !x || !stt) return fail(FREDOPT_E_ARG, "plan, state and x must be non-NULL");
-  fredopt_status st = check_problem_ptrs(pr);
+  fredopt_status st = check_problem_ptrs(pr, p->R);
   if (st != FREDOPT_OK) return st;
   if ((st = check_params(q, true)) != FREDOPT_OK) return st;
   if (stt->k < 0 || stt->s < -1) return fail(FREDOPT_E_STATE, "state needs k >= 0 and s >= -1");
@@ -1476,7 +1478,7 @@ fredopt_status fredopt_profile_kernels(fredopt_plan* p, const fredopt_problem* p
                                        int64_t* count_out) {
   if (!p || !x || !stt || !ms_out) return fail(FREDOPT_E_ARG, "NULL argument");
   if (n_iters < 1) return fail(FREDOPT_E_ARG, "n_iters must be >= 1");
-  fredopt_status st = check_problem_ptrs(pr);
+  fredopt_status st = check_problem_ptrs(pr, p->R);
   if (st != FREDOPT_OK) return st;
   if ((st = check_params(q, false)) != FREDOPT_OK) return st;
   DeviceGuard guard(p->device);
@@ -1766,7 +1768,7 @@ fredopt_status fredopt_batch_create(fredopt_plan* const* plans, int32_t n,
       return fail(FREDOPT_E_ARG, "all plans of a batch need the same value storage");
     if (plans[i]->device != plans[0]->device)
       return fail(FREDOPT_E_ARG, "all plans of a batch need the same device");
-    fredopt_status st = check_problem_ptrs(&problems[i]);
+    fredopt_status st = check_problem_ptrs(&problems[i], plans[i]->R);
     if (st != FREDOPT_OK) return st;
   }
   const BatchLayout B = batch_layout(plans, n);

@@ -410,6 +410,38 @@ def test_wide_plan_independent_of_workspace_contents(fo):
         assert out[0][2:] == o[2:]
 
 
+@pytest.mark.parametrize("case", ["no_entries", "no_rows"])
+def test_empty_plans(fo, case):
+    """Degenerate plans: rows without entries (every constraint row has a zero
+    normal, so nothing moves and the gradient is zero) and a plan without rows
+    (its problem arrays have length 0).  Every call succeeds; dose, LETd and cDL
+    are 0; the fluence stays x0 (already >= 0); s stays -1; the oracle agrees."""
+    import torch
+    print(f"empty plan {case}", flush=True)
+    R = 40 if case == "no_entries" else 0
+    p = ph.tiny_problem(R, 6, 0.3, seed=9, empty_rows=list(range(R)))
+    assert p.nnz == 0
+    plan, prob, x0 = fo.load_phantom(p)
+    x = torch.from_numpy(np.linspace(0.5, 1.5, p.n_cols).astype(np.float32)).cuda()
+    dose, letd, cdl = fo.dose_let(plan, x, p.c)
+    for t in (dose, letd, cdl):
+        assert t.numel() == R and np.all(_np(t) == 0.0)
+    q = _params(fo, iter_max=4)
+    xs = x.clone()
+    fo.project_sweep(plan, prob, q, xs)
+    assert np.array_equal(_np(xs), _np(x))
+    st = fo.new_state()
+    xs = x0.clone()
+    fo.superiorize_step(plan, prob, q, st, xs)
+    assert (st.k, st.s) == (1, -1) and np.array_equal(_np(xs), _np(x0))
+    st = fo.new_state()
+    fo.solve(plan, prob, q, st, xs)
+    assert (st.k, st.s) == (4, -1) and np.array_equal(_np(xs), _np(x0))
+    if R > 0:
+        xr, k, s, _ = Oracle(p).solve(p.x0, 4, _oparams(q))
+        assert (k, s) == (4, -1) and np.array_equal(xr, p.x0.astype(np.float64))
+
+
 def test_load_errors(fo):
     import torch
     p = ph.tiny_problem(10, 4, 0.5, seed=3)
