@@ -116,6 +116,40 @@ def test_dose_let_precision(fo, w32, name):
     assert np.all(dg[~m] == 0.0)
 
 
+def _widest_plan():
+    """65,536 beamlets, the most that 16-bit column indices address, with entries in
+    the first and the last column (index 0xFFFF) of every row."""
+    R, C = 200, 65536
+    rng = np.random.default_rng(77)
+    cols = [np.unique(np.concatenate([[0, C - 1], rng.integers(1, C - 1, 30)])) for _ in range(R)]
+    row_ptr = np.zeros(R + 1, np.int64)
+    row_ptr[1:] = np.cumsum([c.size for c in cols])
+    col = np.concatenate(cols).astype(np.int32)
+    d = rng.uniform(0.05, 1.0, col.size).astype(np.float32)
+    l_ = (d * rng.uniform(0.5, 10.0, col.size)).astype(np.float32)
+    return ph.Phantom(name="widest16", n_rows=R, n_cols=C, row_ptr=row_ptr, col_idx=col,
+                      d_val=d, l_val=l_, x0=np.ones(C, np.float32), c=ph.C_DL,
+                      roi={"all": np.arange(R)}, **ph._empty_problem(R))
+
+
+@pytest.mark.parametrize("name", ["f16i16", "bf16i16"])
+def test_dose_let_widest_16bit_indices(fo, name):
+    """T1 against the oracle on the dequantised values, at the largest column count
+    the 16-bit indices allow."""
+    import torch
+    print(f"dose_let 65,536 beamlets {name}", flush=True)
+    p = _widest_plan()
+    plan, _, _ = fo.load_phantom(p, storage=_storage(fo, name))
+    x = np.random.default_rng(6).uniform(0.5, 1.5, p.n_cols).astype(np.float32)
+    dose, letd, cdl = fo.dose_let(plan, torch.from_numpy(x).cuda(), p.c)
+    dq, lq = dequantised(p, name)
+    d_q, _, t_q, c_q = Oracle(p, d_val=dq, l_val=lq).dose_let(x)
+    m = d_q > 0
+    assert m.all()
+    assert max(_max_rel(_np(dose), d_q, m), _max_rel(_np(cdl), c_q, m),
+               _max_rel(_np(letd), t_q, m)) <= T1
+
+
 @pytest.mark.parametrize("path", ["csc", "scatter"])
 @pytest.mark.parametrize("name", NAMES)
 def test_superiorize_step_precision(fo, w32, name, path):
