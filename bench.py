@@ -264,8 +264,8 @@ def main():
                     help="serve: no clinical-scale requests")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(row sharding is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (a plan would "
+              "be split by rows across GPUs); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
