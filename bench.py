@@ -146,11 +146,13 @@ def bench_batch(args):
     if args.autotune:
         # the batch autotuner: the batched iteration timed at each candidate width
         t0 = time.perf_counter()
-        best, rates = autotune.choose_batch_lanes(phs, storage, reductions_n=args.reductions)
+        best, rates = autotune.choose_batch_lanes(phs, storage, reductions_n=args.reductions,
+                                                  gradient_reserve_pct=args.reserve)
         lanes = [best] * len(phs)
         log(f"autotuned lanes per row in {time.perf_counter() - t0:.1f} s: {best} "
             f"(plan-iterations/s by width: { {k: round(v) for k, v in rates.items()} })")
-    loaded = [fredopt.load_phantom(p, storage=storage, lanes_per_row=lw)
+    loaded = [fredopt.load_phantom(p, storage=storage, lanes_per_row=lw,
+                                   gradient_reserve_pct=args.reserve)
               for p, lw in zip(phs, lanes)]
     q = fredopt.SolverParams(reductions_n=args.reductions)
     # one at a time (the plain single-plan form, default projection path)
@@ -180,6 +182,7 @@ def bench_batch(args):
         "data": "synthetic",
         "config": {"workload": desc, "plans": len(loaded), "nnz_total": nnz,
                    "storage": args.storage, "reductions_n": args.reductions,
+                   "gradient_reserve_pct": args.reserve,
                    "lanes_per_row": f"autotuned ({lanes[0]})" if args.autotune else "rule"},
         "value_meaning": "plan-iterations per second summed over the plans",
         "one_at_a_time_iters_per_s": round(alone_rate, 2),
@@ -204,7 +207,8 @@ def bench_serve(args):
     n_big = sum(r.phantom is big for r in reqs)
     log(f"{n_req} requests over {arrivals[-1]:.1f} s ({args.rate:g}/s), {n_big} at clinical scale")
     q = fredopt.SolverParams(reductions_n=args.reductions)
-    srv = serve.Server(200 * 10**9, q, quantum=args.quantum, log=log)
+    srv = serve.Server(200 * 10**9, q, quantum=args.quantum, log=log,
+                       gradient_reserve_pct=args.reserve)
     t0 = time.perf_counter()
     done = srv.run([dataclasses.replace(r) for r in reqs])
     wall = time.perf_counter() - t0
@@ -214,7 +218,8 @@ def bench_serve(args):
         f"{serve.percentile(lat, 99):.3f} s, {iters / wall:.1f} plan-iterations/s, "
         f"{srv.batches_built} batches, peak {srv.peak_active} resident")
     t0 = time.perf_counter()
-    base = serve.serve_one_at_a_time([dataclasses.replace(r) for r in reqs], q, log=log)
+    base = serve.serve_one_at_a_time([dataclasses.replace(r) for r in reqs], q, log=log,
+                                     gradient_reserve_pct=args.reserve)
     wall_b = time.perf_counter() - t0
     lat_b = [r.latency for r in base]
     log(f"one at a time: p50 {serve.percentile(lat_b, 50):.3f} s, p99 "
@@ -251,6 +256,10 @@ def main():
                     help="matrix values in FP32, FP16 or BF16 (per-beamlet FP32 scale); the "
                          "i16 forms also keep column indices in 16 bits")
     ap.add_argument("--reductions", type=int, default=1)
+    ap.add_argument("--reserve", type=int, default=None,
+                    help="gradient reserve of each plan in %% of its CSC (batch and serve "
+                         "workloads: 100, so that every plan has the objective-row view; "
+                         "0 library default)")
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=100)
@@ -263,6 +272,8 @@ def main():
     ap.add_argument("--serve-small-only", action="store_true",
                     help="serve: no clinical-scale requests")
     args = ap.parse_args()
+    if args.reserve is None:
+        args.reserve = 100 if args.workload in ("batch48", "scenarios48", "serve") else 0
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path (a plan would "
               "be split by rows across GPUs); run with --gpus 1", file=sys.stderr)

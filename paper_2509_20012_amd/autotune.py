@@ -49,14 +49,17 @@ def choose_lanes(ph, storage: int = fredopt.F32, candidates: Sequence[int] = (1,
 
 
 def choose_batch_lanes(phantoms, storage: int = fredopt.F32, candidates: Sequence[int] = (1, 2, 4),
-                       iters: int = 20, reductions_n: int = 1) -> Tuple[int, Dict[int, float]]:
+                       iters: int = 20, reductions_n: int = 1,
+                       gradient_reserve_pct: int = 0) -> Tuple[int, Dict[int, float]]:
     """(fastest lanes per row for the whole batch, {lanes: plan-iterations/s})."""
     import time
     import torch
     rates: Dict[int, float] = {}
     q = fredopt.SolverParams(reductions_n=reductions_n)
     for lanes in candidates:
-        loaded = [fredopt.load_phantom(p, storage=storage, lanes_per_row=lanes) for p in phantoms]
+        loaded = [fredopt.load_phantom(p, storage=storage, lanes_per_row=lanes,
+                                       gradient_reserve_pct=gradient_reserve_pct)
+                  for p in phantoms]
         batch = fredopt.Batch([l[0] for l in loaded], [l[1] for l in loaded])
         xs = [l[2].clone() for l in loaded]
         states = [fredopt.new_state() for _ in loaded]

@@ -43,21 +43,22 @@ class Request:
         return self.finished - self.arrival
 
 
-def plan_bytes(ph, storage: int = fredopt.F32) -> int:
+def plan_bytes(ph, storage: int = fredopt.F32, gradient_reserve_pct: int = 0) -> int:
     """Device bytes a request holds while resident: the plan workspace, the input
     CSR copies used during the load, the problem arrays and the fluence."""
-    ws = fredopt.workspace_bytes_csr(ph.row_ptr, ph.n_cols, storage)
+    ws = fredopt.workspace_bytes_csr(ph.row_ptr, ph.n_cols, storage, 0, gradient_reserve_pct)
     csr = ph.row_ptr.nbytes + ph.col_idx.nbytes + ph.d_val.nbytes + ph.l_val.nbytes
     return int(ws + csr + ph.n_rows * 38 + ph.n_cols * 4)
 
 
 class _Active:
-    def __init__(self, req: Request, storage: int):
+    def __init__(self, req: Request, storage: int, reserve: int):
         self.req = req
-        self.plan, self.prob, self.x = fredopt.load_phantom(req.phantom, storage=storage)
+        self.plan, self.prob, self.x = fredopt.load_phantom(req.phantom, storage=storage,
+                                                            gradient_reserve_pct=reserve)
         self.state = fredopt.new_state()
         self.left = req.iters
-        self.bytes = plan_bytes(req.phantom, storage)
+        self.bytes = plan_bytes(req.phantom, storage, reserve)
 
 
 class Server:
@@ -71,8 +72,9 @@ class Server:
 
     def __init__(self, budget_bytes: int, params: fredopt.SolverParams, quantum: int = 50,
                  storage: int = fredopt.F32, big_nnz: int = 20_000_000,
-                 log: Optional[Callable[[str], None]] = None):
+                 log: Optional[Callable[[str], None]] = None, gradient_reserve_pct: int = 0):
         fredopt.lib()
+        self.reserve = int(gradient_reserve_pct)   # per plan, % of its CSC (0 default)
         self.budget = int(budget_bytes)
         self.params = params
         self.quantum = int(quantum)
@@ -89,7 +91,7 @@ class Server:
         import threading
         queue = sorted(requests, key=lambda r: (r.arrival, r.rid))
         for r in queue:
-            if plan_bytes(r.phantom, self.storage) > self.budget:
+            if plan_bytes(r.phantom, self.storage, self.reserve) > self.budget:
                 raise ValueError(f"request {r.rid} alone exceeds the memory budget")
         lanes = [[r for r in queue if r.phantom.nnz <= self.big_nnz],
                  [r for r in queue if r.phantom.nnz > self.big_nnz]]
@@ -130,7 +132,7 @@ class Server:
         while qi < len(queue) or active:
             changed = False
             while qi < len(queue) and queue[qi].arrival <= now():
-                need = plan_bytes(queue[qi].phantom, self.storage)
+                need = plan_bytes(queue[qi].phantom, self.storage, self.reserve)
                 with lock:
                     if state["used"] + need > self.budget:
                         break
@@ -141,7 +143,7 @@ class Server:
                 req = queue[qi]
                 qi += 1
                 req.admitted = now()
-                active.append(_Active(req, self.storage))
+                active.append(_Active(req, self.storage, self.reserve))
                 changed = True
             if not active:
                 wait = queue[qi].arrival - now() if qi < len(queue) else 0.0
@@ -197,7 +199,8 @@ class Server:
 
 def serve_one_at_a_time(requests: List[Request], params: fredopt.SolverParams,
                         storage: int = fredopt.F32,
-                        log: Optional[Callable[[str], None]] = None) -> List[Request]:
+                        log: Optional[Callable[[str], None]] = None,
+                        gradient_reserve_pct: int = 0) -> List[Request]:
     """First come, first served; each request solved alone by fredopt_solve."""
     queue = sorted(requests, key=lambda r: (r.arrival, r.rid))
     t0 = time.perf_counter()
@@ -207,7 +210,8 @@ def serve_one_at_a_time(requests: List[Request], params: fredopt.SolverParams,
         if wait > 0:
             time.sleep(wait)
         req.admitted = now()
-        plan, prob, x = fredopt.load_phantom(req.phantom, storage=storage)
+        plan, prob, x = fredopt.load_phantom(req.phantom, storage=storage,
+                                             gradient_reserve_pct=gradient_reserve_pct)
         st = fredopt.new_state()
         params.iter_max = req.iters
         fredopt.solve(plan, prob, params, st, x)
