@@ -968,6 +968,13 @@ fredopt_status ensure_graph(fredopt_plan* p, int r) {
   return FREDOPT_OK;
 }
 
+// Default workgroups of the active-row scatter: one per 64k stored entries (each
+// zeroes and writes C column sums, so a small plan wants few), at most one per CU.
+int default_scatter_wgs(const fredopt_plan* p) {
+  return (int)std::min<int64_t>(std::min<int64_t>(p->n_cu, kScatterMaxWGs),
+                                1 + p->nnz / (int64_t(1) << 16));
+}
+
 fredopt_status device_limits(fredopt_plan* p) {
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
@@ -999,7 +1006,7 @@ fredopt_status device_limits(fredopt_plan* p) {
   }
   const size_t sneed = (size_t)p->C * sizeof(int64_t);
   if (scatter_fits(p->C) && sneed <= dyn_max) {
-    p->n_scatter = (int)std::min<int64_t>(p->n_cu, kScatterMaxWGs);
+    p->n_scatter = default_scatter_wgs(p);
     p->scatter_max_rows = p->R / 4;
   } else {
     p->n_scatter = 0;
@@ -1564,7 +1571,7 @@ fredopt_status fredopt_set_scatter(fredopt_plan* p, int32_t n_workgroups,
   else if (n_workgroups > 0)
     p->n_scatter = n_workgroups;
   else
-    p->n_scatter = avail ? (int)std::min<int64_t>(p->n_cu, kScatterMaxWGs) : 0;
+    p->n_scatter = avail ? default_scatter_wgs(p) : 0;
   p->scatter_max_rows = max_active_rows >= 0 ? max_active_rows : p->R / 4;
   p->hp.n_scatter = p->n_scatter;
   p->hp.scatter_max_rows = (int32_t)std::min<int64_t>(p->scatter_max_rows, INT32_MAX);
