@@ -283,10 +283,11 @@ fredopt_status fredopt_set_tuning(fredopt_plan *p, int32_t fwd_wgs_per_cu, int32
  * through the forward layout, summed in 64-bit fixed point, order independent);
  * otherwise it streams the column-major copy.  The choice is made on the device at
  * every sweep.  Both paths give the same result up to FP32 rounding of the sums.
- * n_workgroups: 0 default (one per compute unit), -1 disables the active-row path,
- * 1..256 sets the count.  max_active_rows: -1 default (a quarter of the rows).
- * Needs 8 * n_cols bytes of LDS per workgroup (FREDOPT_E_NOT_IMPLEMENTED if the
- * columns do not fit). */
+ * n_workgroups: 0 default (one per 64k stored entries, at most one per compute
+ * unit), -1 disables the active-row path, 1..256 sets the count.  max_active_rows:
+ * -1 default (a quarter of the rows).  The column sums live in LDS (8 * n_cols bytes
+ * per workgroup) when they fit, otherwise in the workspace, added with device-scope
+ * integer atomics (still order independent). */
 fredopt_status fredopt_set_scatter(fredopt_plan *p, int32_t n_workgroups,
                                    int64_t max_active_rows);
 

@@ -175,9 +175,11 @@ struct DevPlan {
   // projection restricted to rows with non-zero coefficients
   int32_t* goff;              // [groups] first list position of each group's rows
   ActRow* alist;              // [NP] the active rows in slice order
-  int64_t* spart;             // [n_scatter * C] per-workgroup fixed-point sums
+  int64_t* spart;             // [n_scatter * C] per-workgroup fixed-point sums; with
+                              // scatter_global, [C] column sums in global memory
   uint64_t* smask;            // [n_scatter * ceil(C / 64)] which of them are written
   int32_t n_scatter, scatter_max_rows;  // workgroups; largest list that uses it
+  int32_t scatter_global, pad_sg;       // 1: the C column sums do not fit in LDS
   DevParams prm;
   DevState* st;
 };

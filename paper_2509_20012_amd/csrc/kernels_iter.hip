@@ -739,6 +739,13 @@ __device__ __forceinline__ void fx_add(unsigned long long* acc, int col, double 
   if (v != 0.0) atomicAdd(&acc[col], (unsigned long long)__double2ll_rn(v * fs));
 }
 
+// The same fixed-point sum kept in global memory (device-scope integer atomics) for
+// plans whose C column sums do not fit in LDS.
+__device__ __forceinline__ void fx_add_global(unsigned long long* acc, int col, double v,
+                                              double fs) {
+  if (v != 0.0) atomicAdd(&acc[col], (unsigned long long)__double2ll_rn(v * fs));
+}
+
 // D^T cD + L^T cL over the active rows only.  Contributions are rounded to 64-bit
 // fixed point (scale 2^61 / bound from the residual pass) and added with integer LDS
 // atomics: integer sums do not depend on the order of the additions, so the waves of
@@ -755,7 +762,12 @@ __global__ __launch_bounds__(kScatterBlock) void k_scatter(const DevPlan* __rest
   if (!P->st->proj_scatter) return;
   const int C = (int)P->C;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-  for (int j = tid; j < C; j += kScatterBlock) facc[j] = 0ull;
+  // column sums in LDS, or (plans too wide for LDS) in global memory, where the
+  // column update reads them and leaves them zero for the next sweep
+  const bool glob = P->scatter_global != 0;
+  unsigned long long* acc = glob ? (unsigned long long*)P->spart : facc;
+  if (!glob)
+    for (int j = tid; j < C; j += kScatterBlock) facc[j] = 0ull;
   __syncthreads();
   const int64_t A = P->st->n_active, NW = P->n_scatter;
   const int i0 = (int)(wg * A / NW), i1 = (int)((wg + 1) * A / NW);
@@ -778,12 +790,20 @@ __global__ __launch_bounds__(kScatterBlock) void k_scatter(const DevPlan* __rest
       const v4f d4 = VLoad<VT>::q4(dv, e);
       const v4f l4 = VLoad<VT>::q4(lv, e);
       // padding slots hold the value 0 and add nothing
-      fx_add(facc, c4.x, cd * d4.x + cl * l4.x, fs);
-      fx_add(facc, c4.y, cd * d4.y + cl * l4.y, fs);
-      fx_add(facc, c4.z, cd * d4.z + cl * l4.z, fs);
-      fx_add(facc, c4.w, cd * d4.w + cl * l4.w, fs);
+      if (glob) {
+        fx_add_global(acc, c4.x, cd * d4.x + cl * l4.x, fs);
+        fx_add_global(acc, c4.y, cd * d4.y + cl * l4.y, fs);
+        fx_add_global(acc, c4.z, cd * d4.z + cl * l4.z, fs);
+        fx_add_global(acc, c4.w, cd * d4.w + cl * l4.w, fs);
+      } else {
+        fx_add(facc, c4.x, cd * d4.x + cl * l4.x, fs);
+        fx_add(facc, c4.y, cd * d4.y + cl * l4.y, fs);
+        fx_add(facc, c4.z, cd * d4.z + cl * l4.z, fs);
+        fx_add(facc, c4.w, cd * d4.w + cl * l4.w, fs);
+      }
     }
   }
+  if (glob) return;  // no shares: the sums are already in global memory
   __syncthreads();
   // non-zero sums only, with a bit mask per 64 columns saying which were written
   const int nwords = (C + kWave - 1) / kWave;
@@ -832,6 +852,16 @@ __global__ __launch_bounds__(kScatterBlock) void k_scatter_sum(const DevPlan* __
       float t = 0.f;
       for (int c = 0; c < n; ++c) t += gconst(P->tpart)[ts + c];
       project_column<MODE>(P, j, t);
+    }
+    return;
+  }
+  if (P->scatter_global) {
+    // the column sums in global memory; each is read once and set back to zero
+    if (wave == 0 && j < C) {
+      FO_GLOBAL int64_t* g = gmut(P->spart) + j;
+      const int64_t S = *g;
+      *g = 0;
+      project_column<MODE>(P, j, (float)((double)S / P->st->fx_scale));
     }
     return;
   }

@@ -256,7 +256,8 @@ bool make_layout(int64_t R, int64_t C, int64_t nnz, int storage, int lpr_log2,
   L->rsum = take(sizeof(float) * 2 * Pm);
   L->goff = take(sizeof(int32_t) * L->n_groups);
   L->alist = take(sizeof(ActRow) * Pm);
-  L->spart = take(scatter_fits(C) ? sizeof(int64_t) * kScatterMaxWGs * C : sizeof(int64_t));
+  // per-workgroup shares, or C sums in global memory when they do not fit in LDS
+  L->spart = take(scatter_fits(C) ? sizeof(int64_t) * kScatterMaxWGs * C : sizeof(int64_t) * C);
   L->smask = take(scatter_fits(C) ? sizeof(uint64_t) * kScatterMaxWGs * ((C + 63) / 64)
                                   : sizeof(uint64_t));
   L->sc_items = take(sizeof(ScItem) * kScatterMaxWGs);
@@ -304,6 +305,7 @@ struct fredopt_plan {
   int n_cu = 256, wgs_per_cu = 2, max_wgs_per_cu = 2, lds_floats = 0;
   size_t smem_block = 0;              // LDS bytes a workgroup may use
   int n_scatter = 0;                  // active-row scatter workgroups (0: off)
+  bool scatter_global = false;        // its column sums in global memory (C too wide)
   int64_t scatter_max_rows = 0;       // largest active-row count that uses it
   std::vector<FwdGroup> groups;
   std::vector<RowItem> rows;
@@ -879,7 +881,7 @@ Exec exec_of(const fredopt_plan* p) {
   e.n_sc = (int)p->sc_items.size();
   e.ss = p->d_ss;
   e.n_ss = (int)p->ss_items.size();
-  e.sc_lds = (size_t)p->C * sizeof(int64_t);
+  e.sc_lds = p->scatter_global ? 0 : (size_t)p->C * sizeof(int64_t);
   return e;
 }
 
@@ -1004,14 +1006,11 @@ fredopt_status device_limits(fredopt_plan* p) {
     p->lds_floats = 0;
     p->max_wgs_per_cu = 4;
   }
+  // the scatter's C column sums: in LDS when they fit, else in global memory
   const size_t sneed = (size_t)p->C * sizeof(int64_t);
-  if (scatter_fits(p->C) && sneed <= dyn_max) {
-    p->n_scatter = default_scatter_wgs(p);
-    p->scatter_max_rows = p->R / 4;
-  } else {
-    p->n_scatter = 0;
-    p->scatter_max_rows = 0;
-  }
+  p->scatter_global = !(scatter_fits(p->C) && sneed <= dyn_max);
+  p->n_scatter = default_scatter_wgs(p);
+  p->scatter_max_rows = p->R / 4;
   // workgroups per CU of the all-row streaming pass, as measured on the clinical
   // plan: one 8-wave workgroup for FP32; two for 16-bit values, whose steps carry
   // half the bytes, so a CU needs more waves in flight to keep HBM busy
@@ -1316,6 +1315,7 @@ fredopt_status fredopt_load_matrices(const fredopt_matrices* m, void* workspace,
   h.spart = reinterpret_cast<int64_t*>(ws + L.spart);
   h.smask = reinterpret_cast<uint64_t*>(ws + L.smask);
   h.n_scatter = p->n_scatter;
+  h.scatter_global = p->scatter_global ? 1 : 0;
   h.scatter_max_rows = (int32_t)std::min<int64_t>(p->scatter_max_rows, INT32_MAX);
   h.st = p->d_state;
   p->d_sc = reinterpret_cast<ScItem*>(ws + L.sc_items);
@@ -1338,6 +1338,8 @@ fredopt_status fredopt_load_matrices(const fredopt_matrices* m, void* workspace,
   LCHK(hipMemsetAsync(ws + L.pf, 0, sizeof(float) * 9 * Pm, s));
   LCHK(hipMemsetAsync(h.spart_a, 0, sizeof(double) * kNPart * L.n_groups, s));
   LCHK(hipMemsetAsync(h.spart_b, 0, sizeof(double) * kNPart * L.n_groups, s));
+  // global column sums of the scatter start at zero (the column update re-zeroes them)
+  if (p->scatter_global) LCHK(hipMemsetAsync(h.spart, 0, sizeof(int64_t) * C, s));
   st = upload_table(p, s);
   if (st != FREDOPT_OK) return cleanup(st);
   LCHK(hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking));
@@ -1562,16 +1564,12 @@ fredopt_status fredopt_set_scatter(fredopt_plan* p, int32_t n_workgroups,
     return fail(FREDOPT_E_ARG, "n_workgroups must lie in [-1, %d]", (int)kScatterMaxWGs);
   if (max_active_rows < -1) return fail(FREDOPT_E_ARG, "max_active_rows must be >= -1");
   DeviceGuard guard(p->device);
-  const bool avail = scatter_fits(p->C) && p->hp.spart != nullptr &&
-                     (size_t)p->C * sizeof(int64_t) + 2048 <= p->smem_block;
-  if (n_workgroups > 0 && !avail)
-    return fail(FREDOPT_E_NOT_IMPLEMENTED, "the active-row scatter needs 8 C bytes of LDS");
   if (n_workgroups == -1)
     p->n_scatter = 0;
   else if (n_workgroups > 0)
     p->n_scatter = n_workgroups;
   else
-    p->n_scatter = avail ? default_scatter_wgs(p) : 0;
+    p->n_scatter = default_scatter_wgs(p);
   p->scatter_max_rows = max_active_rows >= 0 ? max_active_rows : p->R / 4;
   p->hp.n_scatter = p->n_scatter;
   p->hp.scatter_max_rows = (int32_t)std::min<int64_t>(p->scatter_max_rows, INT32_MAX);
@@ -1840,7 +1838,7 @@ fredopt_status fredopt_batch_create(fredopt_plan* const* plans, int32_t n,
                           : 0;
       b->nsc[sb.idx[j]] = nsc;
       scatter_items((int32_t)j, nsc, p->C, &sc, &ss);
-      if (nsc > 0) sc_lds = std::max(sc_lds, (size_t)p->C * sizeof(int64_t));
+      if (nsc > 0 && !p->scatter_global) sc_lds = std::max(sc_lds, (size_t)p->C * sizeof(int64_t));
       lds = std::max(lds, p->lds_floats);
       all_lds = all_lds && p->lds_floats > 0;
       wgs = std::min(wgs, p->wgs_per_cu);

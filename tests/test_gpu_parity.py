@@ -357,14 +357,15 @@ def test_entry_points_independent_of_workspace_contents(fo, w32, storage):
 def test_wide_plan_without_lds_staging(fo):
     """70,000 beamlets: the input vector does not fit in LDS, so the forward passes
     gather it from global memory; the active-row scatter's column sums do not fit
-    either (column-major projection only); 16-bit column indices are refused.
-    T1 for dose / LETd / cDL, T2 for a sweep and a superiorized step."""
+    either and live in global memory; 16-bit column indices are refused.  T1 for
+    dose / LETd / cDL, T2 for a sweep and a superiorized step on both projection
+    paths."""
     import torch
     print("wide plan R=600 C=70000", flush=True)
     p = ph.tiny_problem(600, 70000, 0.001, seed=31)
     plan, prob, x0 = fo.load_phantom(p)
     info = plan.info()
-    assert info["lds_x"] == 0 and info["scatter_wgs"] == 0
+    assert info["lds_x"] == 0 and info["scatter_wgs"] > 0
     x = torch.from_numpy(np.random.default_rng(8).uniform(0.5, 1.5, p.n_cols)
                          .astype(np.float32)).cuda()
     dose, letd, cdl = fo.dose_let(plan, x, p.c)
@@ -373,31 +374,34 @@ def test_wide_plan_without_lds_staging(fo):
     assert _rel_rows(_np(letd), t_r, d_r > 0) <= T1
     assert _rel_rows(_np(cdl), c_r, d_r > 0) <= T1
     q = _params(fo)
-    xs = x0.clone()
-    fo.project_sweep(plan, prob, q, xs)
     xr = Oracle(p).ams_simultaneous(p.x0, lam=q.lam, weight_scale=1.0,
                                     normalization=q.normalization)[0]
-    assert np.linalg.norm(_np(xs) - xr) / np.linalg.norm(xr) <= T2
-    st = fo.new_state()
-    xs = x0.clone()
-    fo.superiorize_step(plan, prob, q, st, xs)
     xo, k, s, _ = Oracle(p).sa_iteration(p.x0.astype(np.float64), 0, -1, _oparams(q))
-    assert (st.k, st.s) == (k, s)
-    assert np.linalg.norm(_np(xs) - xo) / np.linalg.norm(xo) <= T2
+    for path in ("csc", "scatter"):
+        _set_path(fo, plan, path)
+        xs = x0.clone()
+        fo.project_sweep(plan, prob, q, xs)
+        assert np.linalg.norm(_np(xs) - xr) / np.linalg.norm(xr) <= T2, path
+        st = fo.new_state()
+        xs = x0.clone()
+        fo.superiorize_step(plan, prob, q, st, xs)
+        assert (st.k, st.s) == (k, s), path
+        assert np.linalg.norm(_np(xs) - xo) / np.linalg.norm(xo) <= T2, path
     with pytest.raises(fo.FredoptError):
         fo.load_phantom(p, storage=fo.F16_IDX16)
 
 
-def test_wide_plan_independent_of_workspace_contents(fo):
-    """The 70,000-beamlet plan (no active-row scatter: every column update comes
-    from the column-major path) gives the same sweep and solve bit for bit whatever
-    its workspace held."""
-    print("wide plan, workspace contents", flush=True)
+@pytest.mark.parametrize("path", ["csc", "scatter"])
+def test_wide_plan_independent_of_workspace_contents(fo, path):
+    """The 70,000-beamlet plan (the scatter's column sums in global memory) gives the
+    same sweep and solve bit for bit whatever its workspace held."""
+    print(f"wide plan, workspace contents, path={path}", flush=True)
     p = ph.tiny_problem(600, 70000, 0.001, seed=31)
     q = _params(fo, iter_max=5)
     out = []
     for fill in (0x00, 0xFF, 0x7F):
         plan, prob, x0 = load_filled(fo, p, fill)
+        _set_path(fo, plan, path)
         xs = x0.clone()
         fo.project_sweep(plan, prob, q, xs)
         st = fo.new_state()
