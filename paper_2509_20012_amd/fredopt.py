@@ -167,6 +167,26 @@ def _ptr(t) -> Optional[int]:
     return None if t is None else int(t.data_ptr())
 
 
+def _dev(t, n: int, name: str, dtype=None) -> int:
+    """Device address of tensor t after checking what the C ABI assumes of it: a
+    contiguous device tensor of n elements of the given dtype (float32 by default).
+    The library cannot check a raw pointer, and a host address or a short buffer
+    would make its kernels read out of bounds, so a mismatch raises here."""
+    torch = _torch()
+    dtype = torch.float32 if dtype is None else dtype
+    if not isinstance(t, torch.Tensor):
+        raise FredoptError(-1, f"{name} must be a torch tensor")
+    if not t.is_cuda:
+        raise FredoptError(-1, f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise FredoptError(-1, f"{name} must have dtype {dtype}, not {t.dtype}")
+    if not t.is_contiguous():
+        raise FredoptError(-1, f"{name} must be contiguous")
+    if t.numel() != n:
+        raise FredoptError(-2, f"{name} has {t.numel()} elements, expected {n}")
+    return int(t.data_ptr())
+
+
 def workspace_bytes(n_rows: int, n_cols: int, nnz: int, storage: int = F32) -> int:
     """Pattern-free upper bound of the workspace."""
     return int(lib().fredopt_workspace_bytes(n_rows, n_cols, nnz, storage))
@@ -211,7 +231,13 @@ class DeviceProblem:
         kind = np.ascontiguousarray(arrays["kind"], np.uint16).view(np.int16)
         self.t["kind"] = torch.from_numpy(kind).to(device)
 
-    def struct(self) -> Problem:
+    def struct(self, n_rows: Optional[int] = None) -> Problem:
+        """The C struct; with n_rows, every array is first checked to be a contiguous
+        device array of n_rows elements (kind int16/uint16 bits, the rest float32)."""
+        if n_rows is not None:
+            torch = _torch()
+            for k, v in self.t.items():
+                _dev(v, n_rows, f"problem.{k}", torch.int16 if k == "kind" else None)
         return Problem(**{k: _ptr(v) for k, v in self.t.items()}, c=self.c)
 
 
@@ -291,7 +317,8 @@ def dose_let(plan: Plan, x, c: float = 0.04, stream=None, want=("dose", "letd", 
     torch = _torch()
     outs = {k: (torch.empty(plan.n_rows, dtype=torch.float32, device=x.device)
                 if k in want else None) for k in ("dose", "letd", "cdl")}
-    _check(lib().fredopt_dose_let(plan.handle, _ptr(x), float(c), _ptr(outs["dose"]),
+    _check(lib().fredopt_dose_let(plan.handle, _dev(x, plan.n_cols, "x"), float(c),
+                                  _ptr(outs["dose"]),
                                   _ptr(outs["letd"]), _ptr(outs["cdl"]), _stream(stream)))
     return outs["dose"], outs["letd"], outs["cdl"]
 
@@ -300,26 +327,28 @@ def project_sweep(plan: Plan, problem: DeviceProblem, params: SolverParams, x,
                   weight_scale: float = 1.0, stream=None) -> float:
     """One simultaneous AMS sweep in place on x; returns the input proximity."""
     prox = ct.c_double(0.0)
-    pr, q = problem.struct(), params.struct()
+    pr, q = problem.struct(plan.n_rows), params.struct()
     _check(lib().fredopt_project_sweep(plan.handle, ct.byref(pr), ct.byref(q),
-                                       float(weight_scale), _ptr(x), ct.byref(prox),
+                                       float(weight_scale), _dev(x, plan.n_cols, "x"),
+                                       ct.byref(prox),
                                        _stream(stream)))
     return float(prox.value)
 
 
 def superiorize_step(plan: Plan, problem: DeviceProblem, params: SolverParams, state: State,
                      x, stream=None) -> State:
-    pr, q = problem.struct(), params.struct()
+    pr, q = problem.struct(plan.n_rows), params.struct()
     _check(lib().fredopt_superiorize_step(plan.handle, ct.byref(pr), ct.byref(q),
-                                          ct.byref(state), _ptr(x), _stream(stream)))
+                                          ct.byref(state), _dev(x, plan.n_cols, "x"),
+                                          _stream(stream)))
     return state
 
 
 def solve(plan: Plan, problem: DeviceProblem, params: SolverParams, state: State, x,
           stream=None) -> State:
-    pr, q = problem.struct(), params.struct()
+    pr, q = problem.struct(plan.n_rows), params.struct()
     _check(lib().fredopt_solve(plan.handle, ct.byref(pr), ct.byref(q), ct.byref(state),
-                               _ptr(x), _stream(stream)))
+                               _dev(x, plan.n_cols, "x"), _stream(stream)))
     return state
 
 
@@ -335,7 +364,7 @@ class Batch:
         if nbytes == 0:
             raise FredoptError(-1, "batch workspace size: a plan is invalid")
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
-        prs = (Problem * n)(*[pr.struct() for pr in problems])
+        prs = (Problem * n)(*[pr.struct(pl.n_rows) for pr, pl in zip(problems, plans)])
         h = ct.c_void_p()
         _check(lib().fredopt_batch_create(hp, n, prs, _ptr(self.ws), nbytes, _stream(stream),
                                           ct.byref(h)))
@@ -345,7 +374,8 @@ class Batch:
     def solve(self, params: "SolverParams", states, xs, n_iters: int, stream=None):
         assert len(states) == self.n and len(xs) == self.n
         sts = (State * self.n)(*states)
-        xp = (ct.c_void_p * self.n)(*[_ptr(x) for x in xs])
+        xp = (ct.c_void_p * self.n)(*[_dev(x, pl.n_cols, f"x[{i}]")
+                                      for i, (x, pl) in enumerate(zip(xs, self.plans))])
         q = params.struct()
         _check(lib().fredopt_batch_solve(self._h, ct.byref(q), sts, xp, int(n_iters),
                                          _stream(stream)))
@@ -378,15 +408,16 @@ def profile_kernels(plan: Plan, problem: DeviceProblem, params: SolverParams, st
     nk = len(KERNEL_NAMES)
     ms = (ct.c_double * nk)()
     cnt = (ct.c_int64 * nk)()
-    pr, q = problem.struct(), params.struct()
+    pr, q = problem.struct(plan.n_rows), params.struct()
     _check(lib().fredopt_profile_kernels(plan.handle, ct.byref(pr), ct.byref(q),
-                                         ct.byref(state), _ptr(x), int(n_iters),
+                                         ct.byref(state), _dev(x, plan.n_cols, "x"),
+                                         int(n_iters),
                                          _stream(stream), ms, cnt))
     return {KERNEL_NAMES[i]: (float(ms[i]), int(cnt[i])) for i in range(nk)}
 
 
 def autotune(plan: Plan, x, stream=None):
-    _check(lib().fredopt_autotune(plan.handle, _ptr(x), _stream(stream)))
+    _check(lib().fredopt_autotune(plan.handle, _dev(x, plan.n_cols, "x"), _stream(stream)))
     return plan.info()
 
 

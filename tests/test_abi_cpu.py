@@ -105,3 +105,38 @@ def test_param_ranges_documented(field, value):
     p = fredopt.SolverParams(**{field: value})
     s = p.struct()
     assert getattr(s, "lambda_" if field == "lam" else field) == value
+
+
+def test_binding_rejects_bad_tensors_before_the_call():
+    """The binding checks every tensor it hands to the library: a host tensor, a
+    wrong dtype, a non-contiguous view or a wrong length raises FredoptError before
+    the C call (the library cannot check raw pointers)."""
+    import torch
+    from paper_2509_20012_amd import phantom as ph
+    plan = fredopt.Plan(None, None, n_rows=6, n_cols=4, nnz=0, storage=0)
+    x = torch.zeros(4)
+    with pytest.raises(fredopt.FredoptError, match="device tensor"):
+        fredopt.dose_let(plan, x)
+    prob = fredopt.DeviceProblem(ph._empty_problem(6), ph.C_DL, device="cpu")
+    with pytest.raises(fredopt.FredoptError, match="device tensor"):
+        prob.struct(6)
+    with pytest.raises(fredopt.FredoptError, match="device tensor"):
+        fredopt.solve(plan, prob, fredopt.SolverParams(), fredopt.new_state(), x)
+
+    # dtype, layout and length checks, on tensors that claim to live on the device
+    class OnDevice(torch.Tensor):
+        is_cuda = True
+
+    def check(t, n, dtype=None):
+        return fredopt._dev(t.as_subclass(OnDevice), n, "x", dtype)
+
+    with pytest.raises(fredopt.FredoptError, match="dtype"):
+        check(torch.zeros(4, dtype=torch.float64), 4)
+    with pytest.raises(fredopt.FredoptError, match="contiguous"):
+        check(torch.zeros(4, 2)[:, 0], 4)
+    with pytest.raises(fredopt.FredoptError, match="elements"):
+        check(torch.zeros(3), 4)
+    t = torch.zeros(4)
+    assert check(t, 4) == t.data_ptr()
+    k = torch.zeros(6, dtype=torch.int16)
+    assert check(k, 6, torch.int16) == k.data_ptr()

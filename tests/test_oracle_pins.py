@@ -203,6 +203,35 @@ def test_sequential_hand_worked_example():
     np.testing.assert_allclose(xn, g["expected_simultaneous_raw"], rtol=1e-12)
 
 
+NORMS = {"convex_all": 0, "convex_violated": 1, "raw": 2}
+
+
+def _golden_simultaneous():
+    with open(os.path.join(GOLDEN, "ams_simultaneous_2x2.json")) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("case", [0, 1])
+def test_simultaneous_hand_worked_weights(case):
+    """The simultaneous sweep's weight totals and its proximity on 2 x 2 cases worked
+    by hand (tests/golden/ams_simultaneous_2x2.json): the total over every enabled
+    (row, kind) pair for the default normalisation, over the violated pairs for the
+    alternative, and the factor 1/2 of the proximity.  The second case has a
+    satisfied row, so the two totals differ."""
+    g = _golden_simultaneous()
+    c = g["cases"][case]
+    p = from_dense(g["D"], g["L"], c=g["c"], w_feas=c["w_feas"], **g["problem"])
+    o = Oracle(p)
+    for name, norm in NORMS.items():
+        xn, prox, nv = o.ams_simultaneous(c["x"], lam=c["lambda"],
+                                          weight_scale=c["weight_scale"], normalization=norm)
+        np.testing.assert_allclose(xn, c["expected"][name], rtol=1e-14, atol=1e-15)
+        assert nv == c["n_violated"]
+        assert prox == pytest.approx(c["proximity"], rel=1e-14)
+    prox, nv = o.proximity(c["x"])
+    assert prox == pytest.approx(c["proximity"], rel=1e-14) and nv == c["n_violated"]
+
+
 def test_clamp_is_applied():
     D = np.array([[1.0, 1.0]], np.float32)
     p = from_dense(D, D, kind=[ph.DOSE_HI], dose_hi=[0.0], w_feas=[1.0])
