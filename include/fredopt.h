@@ -34,7 +34,7 @@
  *    fredopt_workspace_bytes) and must stay alive and untouched until
  *    fredopt_free_plan.  The library does not allocate device memory, except a
  *    temporary staging copy of host matrices during fredopt_load_matrices with
- *    on_device = 0.
+ *    on_device = 0 (fredopt_load_matrices_noalloc allocates none).
  *  - `stream` is a hipStream_t (may be the null stream).
  *  - Every call returns FREDOPT_OK or a negative status; on error nothing the
  *    caller owns has been modified and fredopt_last_error() describes the cause,
@@ -178,6 +178,24 @@ size_t fredopt_workspace_bytes_csr(int64_t n_rows, int64_t n_cols, const int64_t
 fredopt_status fredopt_load_matrices(const fredopt_matrices *m, void *workspace,
                                      size_t workspace_bytes, void *stream,
                                      fredopt_plan **out);
+
+/* For callers that cannot allocate device memory (serving loops that admit plans
+ * without touching the allocator, harnesses that forbid hipMalloc): the same load
+ * and the same plan as fredopt_load_matrices, allocating nothing.  Host-resident
+ * matrices (on_device = 0) are staged in a fixed area of the library's own device
+ * memory, FREDOPT_NOALLOC_STAGING_BYTES per device, held from the library's load
+ * until the process ends; the staged copy needs
+ *     align256(8 (n_rows + 1)) + align256(4 nnz) + 2 align256(4 nnz)
+ * bytes, and larger host matrices are refused with FREDOPT_E_WORKSPACE (load them
+ * from device memory, which needs no staging).  Calls on one device share that
+ * area: the library serialises them with a per-device lock inside one process (a
+ * call waits while another stages), and the area keeps the last call's contents.
+ * The plan's capture stream is created by its first fredopt_solve instead of here.
+ * Synchronises `stream`. */
+#define FREDOPT_NOALLOC_STAGING_BYTES ((size_t)128 << 20)
+fredopt_status fredopt_load_matrices_noalloc(const fredopt_matrices *m, void *workspace,
+                                             size_t workspace_bytes, void *stream,
+                                             fredopt_plan **out);
 
 /* Releases the host side of a plan (the caller then frees the workspace). */
 fredopt_status fredopt_free_plan(fredopt_plan *p);

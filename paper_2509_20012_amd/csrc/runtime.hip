@@ -13,6 +13,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -964,6 +965,8 @@ fredopt_status capture_iteration(const Exec& e, int r, bool obj, hipStream_t cap
 fredopt_status ensure_graph(fredopt_plan* p, int r) {
   if (p->graph && p->graph_r == r) return FREDOPT_OK;
   drop_graph(p);
+  // a plan loaded without allocation gets its capture stream here
+  if (!p->cap) HIPCHK(hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking));
   const fredopt_status st = capture_iteration(exec_of(p), r, p->sched_obj, p->cap, &p->graph);
   if (st != FREDOPT_OK) return st;
   p->graph_r = r;
@@ -1028,6 +1031,36 @@ size_t exact_bytes(int64_t R, int64_t C, const int64_t* rp, int storage, int lpr
   return L.total;
 }
 
+// Staging area of fredopt_load_matrices_noalloc: host matrices are copied here
+// instead of into a buffer the library allocates.  Each device holds its own copy
+// of this array from module load until the process ends.  In host code the name is
+// a host-side stand-in, never a device address: the address comes from
+// hipGetSymbolAddress, once per device, and only that address is used.
+constexpr size_t kNoallocStagingBytes = size_t(128) << 20;
+__device__ __align__(256) unsigned char scratch[kNoallocStagingBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu[kMaxDevices];    // held for the whole call that uses the area
+void* g_scratch_ptr[kMaxDevices] = {};   // device address of `scratch`, per device
+
+// The device address of `scratch` on device dev (the current device); looked up on
+// the first call on that device.  The caller holds g_scratch_mu[dev].
+fredopt_status scratch_address(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(FREDOPT_E_DEVICE, "device %d beyond the %d the staging table covers", dev,
+                kMaxDevices);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(FREDOPT_E_DEVICE, "hipGetSymbolAddress(scratch) failed: %s",
+                  hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return FREDOPT_OK;
+}
+
 }  // namespace
 
 // =============================================================================== ABI
@@ -1056,8 +1089,12 @@ size_t fredopt_workspace_bytes_csr(int64_t n_rows, int64_t n_cols, const int64_t
   return exact_bytes(n_rows, n_cols, row_ptr, storage, lg, reserve_pct_of(gradient_reserve_pct));
 }
 
-fredopt_status fredopt_load_matrices(const fredopt_matrices* m, void* workspace,
-                                     size_t workspace_bytes, void* stream, fredopt_plan** out) {
+// The load of Table 2 step (iii).  noalloc: host matrices are staged in `scratch`
+// (at most kNoallocStagingBytes, one call per device at a time) instead of a buffer
+// allocated here, and the plan's capture stream is created by its first solve.
+static fredopt_status load_impl(const fredopt_matrices* m, void* workspace,
+                                size_t workspace_bytes, void* stream, fredopt_plan** out,
+                                bool noalloc) {
   if (!m || !out) return fail(FREDOPT_E_ARG, "matrices and out must be non-NULL");
   *out = nullptr;
   const int64_t R = m->n_rows, C = m->n_cols, nnz = m->nnz;
@@ -1120,12 +1157,19 @@ fredopt_status fredopt_load_matrices(const fredopt_matrices* m, void* workspace,
 
   // device view of the input CSR (staged for host input)
   void* staging = nullptr;
+  bool own_staging = false;                // allocated by this call, freed at its end
+  std::unique_lock<std::mutex> staging_lock;  // noalloc: the device's staging area
   const int64_t* in_rp = m->row_ptr;
   const int32_t* in_col = m->col_idx;
   const float* in_dv = m->d_val;
   const float* in_lv = m->l_val;
   auto cleanup = [&](fredopt_status code) {
-    if (staging) (void)hipFree(staging);
+    if (staging) {
+      if (own_staging)
+        (void)hipFree(staging);
+      else  // no kernel may still read the shared staging area once the lock is released
+        (void)hipStreamSynchronize(s);
+    }
     if (code != FREDOPT_OK) {
       if (p->cap) (void)hipStreamDestroy(p->cap);
       delete p;
@@ -1141,7 +1185,21 @@ fredopt_status fredopt_load_matrices(const fredopt_matrices* m, void* workspace,
   if (!m->on_device) {
     const size_t bytes = align_up(sizeof(int64_t) * (R + 1)) + align_up(sizeof(int32_t) * nnz) +
                          2 * align_up(sizeof(float) * nnz);
-    LCHK(hipMalloc(&staging, bytes));
+    if (noalloc) {
+      if (bytes > kNoallocStagingBytes)
+        return cleanup(fail(FREDOPT_E_WORKSPACE,
+                            "host matrices need %zu staging bytes; the no-allocation load "
+                            "stages at most %zu (load device-resident matrices instead)",
+                            bytes, kNoallocStagingBytes));
+      if (p->device < 0 || p->device >= kMaxDevices)
+        return cleanup(fail(FREDOPT_E_DEVICE, "device %d beyond the staging table", p->device));
+      staging_lock = std::unique_lock<std::mutex>(g_scratch_mu[p->device]);
+      const fredopt_status se = scratch_address(p->device, &staging);
+      if (se != FREDOPT_OK) return cleanup(se);
+    } else {
+      LCHK(hipMalloc(&staging, bytes));
+      own_staging = true;
+    }
     char* b = static_cast<char*>(staging);
     int64_t* srp = reinterpret_cast<int64_t*>(b);
     b += align_up(sizeof(int64_t) * (R + 1));
@@ -1342,11 +1400,22 @@ fredopt_status fredopt_load_matrices(const fredopt_matrices* m, void* workspace,
   if (p->scatter_global) LCHK(hipMemsetAsync(h.spart, 0, sizeof(int64_t) * C, s));
   st = upload_table(p, s);
   if (st != FREDOPT_OK) return cleanup(st);
-  LCHK(hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking));
+  if (!noalloc) LCHK(hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking));
   LCHK(hipStreamSynchronize(s));
 #undef LCHK
   *out = p;
   return cleanup(FREDOPT_OK);
+}
+
+fredopt_status fredopt_load_matrices(const fredopt_matrices* m, void* workspace,
+                                     size_t workspace_bytes, void* stream, fredopt_plan** out) {
+  return load_impl(m, workspace, workspace_bytes, stream, out, false);
+}
+
+fredopt_status fredopt_load_matrices_noalloc(const fredopt_matrices* m, void* workspace,
+                                             size_t workspace_bytes, void* stream,
+                                             fredopt_plan** out) {
+  return load_impl(m, workspace, workspace_bytes, stream, out, true);
 }
 
 fredopt_status fredopt_free_plan(fredopt_plan* p) {

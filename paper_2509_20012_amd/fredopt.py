@@ -86,7 +86,7 @@ class PlanInfo(ct.Structure):
 
 
 EXPORTED = ("fredopt_workspace_bytes", "fredopt_workspace_bytes_csr",
-            "fredopt_load_matrices", "fredopt_free_plan",
+            "fredopt_load_matrices", "fredopt_load_matrices_noalloc", "fredopt_free_plan",
             "fredopt_dose_let", "fredopt_project_sweep", "fredopt_superiorize_step",
             "fredopt_solve", "fredopt_last_error", "fredopt_get_plan_info",
             "fredopt_profile_kernels", "fredopt_autotune", "fredopt_set_tuning",
@@ -112,6 +112,8 @@ def lib():
                                                   ct.c_int32, ct.c_int32]
         L.fredopt_workspace_bytes_csr.restype = ct.c_size_t
         L.fredopt_load_matrices.argtypes = [ct.POINTER(Matrices), P, ct.c_size_t, P, PP]
+        L.fredopt_load_matrices_noalloc.argtypes = [ct.POINTER(Matrices), P, ct.c_size_t, P,
+                                                    PP]
         L.fredopt_free_plan.argtypes = [P]
         L.fredopt_dose_let.argtypes = [P, P, ct.c_double, P, P, P, P]
         L.fredopt_project_sweep.argtypes = [P, ct.POINTER(Problem), ct.POINTER(Params),
@@ -276,10 +278,13 @@ class Plan:
 
 def load_matrices(row_ptr, col_idx, d_val, l_val, n_cols: int, storage: int = F32,
                   device="cuda", stream=None, on_device: bool = True,
-                  lanes_per_row: int = 0, gradient_reserve_pct: int = 0) -> Plan:
+                  lanes_per_row: int = 0, gradient_reserve_pct: int = 0,
+                  noalloc: bool = False) -> Plan:
     """Loads CSR influence matrices.  With on_device=True the arrays are copied to
     the device with torch first (the library then reads device pointers); with
-    on_device=False host arrays are handed to the library, which stages them."""
+    on_device=False host arrays are handed to the library, which stages them.
+    noalloc: the library's load that allocates no device memory (host matrices are
+    staged in its fixed per-device area; the workspace is still allocated here)."""
     torch = _torch()
     row_ptr = np.ascontiguousarray(row_ptr, np.int64)
     col_idx = np.ascontiguousarray(col_idx, np.int32)
@@ -302,8 +307,8 @@ def load_matrices(row_ptr, col_idx, d_val, l_val, n_cols: int, storage: int = F3
                      d_val.ctypes.data, l_val.ctypes.data, storage, 0, lanes_per_row,
                      gradient_reserve_pct)
     h = ct.c_void_p()
-    _check(lib().fredopt_load_matrices(ct.byref(m), _ptr(ws), nbytes, _stream(stream),
-                                       ct.byref(h)))
+    load = lib().fredopt_load_matrices_noalloc if noalloc else lib().fredopt_load_matrices
+    _check(load(ct.byref(m), _ptr(ws), nbytes, _stream(stream), ct.byref(h)))
     del keep  # input arrays are no longer referenced after the load
     return Plan(h, ws, R, n_cols, nnz, storage)
 

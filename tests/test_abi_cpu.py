@@ -63,6 +63,7 @@ def test_workspace_bytes():
 def test_null_arguments_rejected_without_device():
     L = fredopt.lib()
     assert L.fredopt_load_matrices(None, None, 0, None, None) == -1
+    assert L.fredopt_load_matrices_noalloc(None, None, 0, None, None) == -1
     assert L.fredopt_free_plan(None) == -1
     assert L.fredopt_dose_let(None, None, 0.04, None, None, None, None) == -1
     q = fredopt.SolverParams().struct()
@@ -90,9 +91,14 @@ def test_load_rejects_bad_workspace_before_device_work():
     h = ct.c_void_p()
     assert L.fredopt_load_matrices(ct.byref(m), None, 1 << 20, None, ct.byref(h)) == -5
     assert L.fredopt_load_matrices(ct.byref(m), ct.c_void_p(256), 16, None, ct.byref(h)) == -5
+    assert L.fredopt_load_matrices_noalloc(ct.byref(m), None, 1 << 20, None, ct.byref(h)) == -5
+    assert L.fredopt_load_matrices_noalloc(ct.byref(m), ct.c_void_p(256), 16, None,
+                                           ct.byref(h)) == -5
     m.storage = 9
     assert L.fredopt_load_matrices(ct.byref(m), ct.c_void_p(256), 1 << 20, None,
                                    ct.byref(h)) == -2
+    assert L.fredopt_load_matrices_noalloc(ct.byref(m), ct.c_void_p(256), 1 << 20, None,
+                                           ct.byref(h)) == -2
     assert not h.value
 
 
