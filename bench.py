@@ -356,8 +356,9 @@ def main():
         if name == "tr_proj" and scatter_path:
             ab = 0  # its workgroups see the active-row path and return at once
         if name == "scatter" and scatter_path:
-            # estimate: active rows times the mean row length (the rows are not known here)
-            ab = int(sp.n_active * (nnz / max(R, 1)) * (ib + 2 * vb) + 32 * sp.n_active)
+            # the active rows' stored entries (counted on the device by the residual
+            # pass that listed them) and their 32-byte list records
+            ab = int(sp.active_entries * (ib + 2 * vb) + 32 * sp.n_active)
         per_kernel[name] = {"ms": ms, "launches_per_iter": cnt / args.profile_iters,
                             "alg_bytes": ab, "gbps": ab / (ms * 1e-3) / 1e9 if ms > 0 else 0.0}
     dom = max((k for k in per_kernel if per_kernel[k]["alg_bytes"] > 0),

@@ -154,6 +154,7 @@ typedef struct {
   int64_t n_active;        /* rows with a non-zero projection coefficient        */
   int32_t projection_path; /* 1: the last sweep used the active-row path, 0: CSC  */
   int32_t reserved;
+  int64_t active_entries;  /* stored matrix entries of those rows                 */
 } fredopt_state;
 
 /* Bytes of device workspace a plan of this size needs: an upper bound valid for
@@ -255,6 +256,8 @@ typedef struct {
   int64_t scatter_max_rows; /* largest active-row count that takes that path     */
   int32_t obj_lanes_per_row; /* lanes per row of the objective-row view (0: unused) */
   int32_t fwd_schedule;      /* all-row forward: 1 groups from a counter, 2 round robin */
+  int32_t scatter_lanes;     /* lanes of the active-row scatter per row (4..64)  */
+  int64_t row_copy_slots;    /* slots of its row-contiguous copy (rows padded to 4) */
 } fredopt_plan_info;
 
 fredopt_status fredopt_get_plan_info(const fredopt_plan *p, fredopt_plan_info *info);

@@ -89,12 +89,14 @@ struct DevState {
   int32_t n_active;           // rows with a non-zero projection coefficient
   int32_t proj_scatter;       // 1: the projection uses the active-row scatter
   double fx_scale;            // fixed-point scale of the active-row scatter
+  int64_t active_entries;     // stored entries of those rows (what the scatter reads)
 };
 
-// A row with a non-zero projection coefficient, as the scatter reads it.
+// A row with a non-zero projection coefficient, as the scatter reads it: its
+// entries in the row-contiguous copy.
 struct ActRow {
-  int64_t sb;                 // base slot of the row's slice
-  int32_t nq, p;              // quads of the slice (width * lpr); slice position
+  int64_t off;                // first slot of the row in the row-contiguous copy
+  int32_t nq, len;            // quads (4 slots, the last one zero-padded); entries
   float cd, cl;               // projection coefficients (dose part, LET part)
   int32_t pad[2];
 };
@@ -143,6 +145,13 @@ struct DevPlan {
   const void* gclv;
   const int32_t* gcol_tslot0;
   const int32_t* gcol_nch;
+  // row-contiguous copy (active-row scatter): the row at position sp holds slots
+  // [rptr[sp], rptr[sp + 1]), a multiple of 4, entries first, then zero padding
+  const int64_t* rptr;        // [NP + 1]
+  const int32_t* plen;        // [NP] entries of the row at each position
+  const void* rci;            // int32, or uint16 for kF16I / kBF16I
+  const void* rdv;
+  const void* rlv;
   const float* cscale;        // per-column scale of 16-bit storage (null for FP32)
   const double* mom;          // [3 NP] sum D^2, sum L^2, sum D L per row
   const float* rsum;          // [2 NP] sum of the stored D and L values of a row
@@ -179,7 +188,8 @@ struct DevPlan {
                               // scatter_global, [C] column sums in global memory
   uint64_t* smask;            // [n_scatter * ceil(C / 64)] which of them are written
   int32_t n_scatter, scatter_max_rows;  // workgroups; largest list that uses it
-  int32_t scatter_global, pad_sg;       // 1: the C column sums do not fit in LDS
+  int32_t scatter_global;               // 1: the C column sums do not fit in LDS
+  int32_t sc_lg2;                       // lanes per active row of the scatter (log2)
   DevParams prm;
   DevState* st;
 };

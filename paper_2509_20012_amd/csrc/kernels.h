@@ -44,6 +44,12 @@ void launch_pack_sell(int vtype, int64_t R, int lpr_log2, const int64_t* row_ptr
                       const int32_t* col, const float* dv, const float* lv, const float* scale,
                       const int32_t* rslice, const int64_t* sbase, void* sci, int idx16,
                       void* sdv, void* slv, hipStream_t s);
+// row-contiguous copy of every row at its position (active-row scatter); plen gets
+// the rows' entry counts
+void launch_pack_rows(int vtype, int64_t R, const int64_t* row_ptr, const int32_t* col,
+                      const float* dv, const float* lv, const float* scale,
+                      const int32_t* rslice, const int64_t* rptr, void* rci, int idx16,
+                      void* rdv, void* rlv, int32_t* plen, hipStream_t s);
 void launch_block_count(int64_t R, int64_t C, int rows_per_block, const int64_t* row_ptr,
                         const int32_t* col, uint32_t* bc, hipStream_t s);
 void launch_block_offsets(int64_t C, int nb, const int64_t* cp, uint32_t* bc, hipStream_t s);

@@ -26,6 +26,7 @@
 //                   [3] violated  [4] degenerate  [5] non-finite  [6] chi^2
 //                   [7] rows with a non-zero projection coefficient
 //                   [8] sum over those rows of |cD| sum D + |cL| sum L (stored units)
+//                   [9] stored entries of those rows
 #include "fredopt_device.h"
 #include "kernels.h"
 
@@ -269,6 +270,7 @@ __device__ __forceinline__ void residual_row(const DevPlan* P, int r, unsigned k
     const v2f rs = ((const FO_GLOBAL v2f*)(P->rsum))[r];
     acc[7] += 1.0;
     acc[8] += fabs((double)fD) * (double)rs.x + fabs((double)fL) * (double)rs.y;
+    acc[9] += (double)gconst(P->plen)[r];
   }
 }
 
@@ -343,7 +345,7 @@ __device__ __forceinline__ void decide_step(const DevPlan* P, double G, double Q
 
 template <int MODE>
 __device__ __forceinline__ constexpr unsigned fwd_slots() {
-  return MODE == kFwdResid ? 0x1FFu : 0x21u;
+  return MODE == kFwdResid ? 0x3FFu : 0x21u;
 }
 
 // One slice of a sliced-ELL view: d = D v, l = L v for its rows, then the epilogue
@@ -586,7 +588,7 @@ __global__ __launch_bounds__(kBlock) void k_rows(const DevPlan* __restrict__ pla
     }
     if (!finite2(d, l)) acc[5] += 1.0;
   }
-  constexpr unsigned used = MODE == kRowsMoveObj ? 0x21u : 0x1FFu;
+  constexpr unsigned used = MODE == kRowsMoveObj ? 0x21u : 0x3FFu;
   double s[kNPart];
 #pragma unroll
   for (int k = 0; k < kNPart; ++k) s[k] = (used & (1u << k)) ? block_sum(acc[k], sh4) : 0.0;
@@ -725,12 +727,11 @@ __global__ __launch_bounds__(kFwdBlock) void k_active_list(const DevPlan* __rest
   for (int w = 0; w < wave; ++w) before += wsum[w];
   before += __popcll(m & ((1ull << lane) - 1ull));
   if (act) {
-    const int s = sp >> rpw_log2;
-    const int64_t sb = gconst(P->sell.sbase)[s];
+    const int64_t off = gconst(P->rptr)[sp];
+    const int nq = (int)((gconst(P->rptr)[sp + 1] - off) >> 2);
     // ActRow as two 16-byte stores
     FO_GLOBAL v4i* dst = (FO_GLOBAL v4i*)(P->alist + gconst(P->goff)[G.slot] + before);
-    dst[0] = v4i{(int)(uint32_t)sb, (int)(sb >> 32), gconst(P->sell.swidth)[s] << P->lpr_log2,
-                 sp & ((1 << rpw_log2) - 1)};
+    dst[0] = v4i{(int)(uint32_t)off, (int)(off >> 32), nq, gconst(P->plen)[sp]};
     dst[1] = v4i{__float_as_int(c.x), __float_as_int(c.y), 0, 0};
   }
 }
@@ -771,21 +772,25 @@ __global__ __launch_bounds__(kScatterBlock) void k_scatter(const DevPlan* __rest
   __syncthreads();
   const int64_t A = P->st->n_active, NW = P->n_scatter;
   const int i0 = (int)(wg * A / NW), i1 = (int)((wg + 1) * A / NW);
-  const int lg2 = P->lpr_log2, lpr = 1 << lg2;
+  // groups of G lanes take one row each (G from the plan's mean row length); a row's
+  // entries are contiguous in the row copy, and so are neighbouring rows of the list,
+  // so a wave reads whole lines
+  const int lg2 = P->sc_lg2, G = 1 << lg2, rg = kWave >> lg2;
+  const int grp = lane >> lg2, gl = lane & (G - 1);
   const double fs = P->st->fx_scale;
   const ActRow* list = P->alist;
-  for (int i = i0 + wave; i < i1; i += kScatterBlock / kWave) {
+  for (int i = i0 + wave * rg + grp; i < i1; i += (kScatterBlock / kWave) * rg) {
     const v4i a0 = ((const FO_GLOBAL v4i*)(list + i))[0];
     const v4i a1 = ((const FO_GLOBAL v4i*)(list + i))[1];
-    const int64_t sb = (int64_t)(((uint64_t)(uint32_t)uniform(a0.y) << 32) | (uint32_t)uniform(a0.x));
-    const int nq = uniform(a0.z), p = uniform(a0.w);
-    const double cd = __int_as_float(uniform(a1.x)), cl = __int_as_float(uniform(a1.y));
+    const int64_t off = (int64_t)(((uint64_t)(uint32_t)a0.y << 32) | (uint32_t)a0.x);
+    const int nq = a0.z;
+    const double cd = __int_as_float(a1.x), cl = __int_as_float(a1.y);
 
-    const FO_GLOBAL void* ci = sell_idx_ptr<VT>(P->sell.sci, sb);
-    const FO_GLOBAL void* dv = value_ptr<VT>(P->sell.sdv, sb);
-    const FO_GLOBAL void* lv = value_ptr<VT>(P->sell.slv, sb);
-    for (int q = lane; q < nq; q += kWave) {
-      const uint32_t e = (uint32_t)(q >> lg2) * 256u + (uint32_t)(p * lpr + (q & (lpr - 1))) * 4u;
+    const FO_GLOBAL void* ci = sell_idx_ptr<VT>(P->rci, off);
+    const FO_GLOBAL void* dv = value_ptr<VT>(P->rdv, off);
+    const FO_GLOBAL void* lv = value_ptr<VT>(P->rlv, off);
+    for (int q = gl; q < nq; q += G) {
+      const uint32_t e = (uint32_t)q * 4u;
       const v4i c4 = sell_idx4<VT>(ci, e);
       const v4f d4 = VLoad<VT>::q4(dv, e);
       const v4f l4 = VLoad<VT>::q4(lv, e);
@@ -1012,15 +1017,16 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(const DevPlan* __restric
       if (a[5] > 0.0) P->st->nonfinite = 1;
     }
   } else if constexpr (MODE == kFinResidRows) {
-    sum_slots(P->rpart, P->n_row_items, a, 0x1FFu, shs);
+    sum_slots(P->rpart, P->n_row_items, a, 0x3FFu, shs);
     if (threadIdx.x == 0) {
       finalize_residuals(P, a);
       P->st->n_active = (int)a[7];
+      P->st->active_entries = (int64_t)a[9];
       P->st->proj_scatter = 0;
     }
   } else {
     double own[kNPart];
-    sum_slots(P->spart_a, P->sell.n_groups, a, 0x1FFu, shs, own);
+    sum_slots(P->spart_a, P->sell.n_groups, a, 0x3FFu, shs, own);
     const int A = (int)a[7];
     // contributions are rounded to multiples of 1 / fx_scale; with every column
     // total bounded by a[8], 2^61 / a[8] keeps all sums far inside int64
@@ -1044,6 +1050,7 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(const DevPlan* __restric
     if (threadIdx.x == 0) {
       finalize_residuals(P, a);
       P->st->n_active = A;
+      P->st->active_entries = (int64_t)a[9];
       P->st->proj_scatter = scatter ? 1 : 0;
       P->st->fx_scale = B > 0.0 ? 0x1p61 / B : 1.0;
     }

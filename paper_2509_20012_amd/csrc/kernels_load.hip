@@ -122,6 +122,39 @@ __global__ __launch_bounds__(kBlock) void k_pack_sell(int vtype, int64_t R, int 
   }
 }
 
+// Row-contiguous copy for the active-row scatter: the row at position sp = rslice[row]
+// fills slots [rptr[sp], rptr[sp] + n) in column order (the remaining slots of the
+// position, up to a multiple of 4, stay zero); plen[sp] = n.
+__global__ __launch_bounds__(kBlock) void k_pack_rows(int vtype, int64_t R,
+                                                      const int64_t* __restrict__ row_ptr,
+                                                      const int32_t* __restrict__ col,
+                                                      const float* __restrict__ dv,
+                                                      const float* __restrict__ lv,
+                                                      const float* __restrict__ scale,
+                                                      const int32_t* __restrict__ rslice,
+                                                      const int64_t* __restrict__ rptr,
+                                                      void* rci, int idx16, void* rdv,
+                                                      void* rlv, int32_t* plen) {
+  const int64_t row = (int64_t)blockIdx.x * kRowsPerWg + threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  if (row >= R) return;
+  const int sp = rslice[row];
+  const int64_t base = rptr[sp];
+  const int64_t a = row_ptr[row], n = row_ptr[row + 1] - a;
+  if (lane == 0) plen[sp] = (int32_t)n;
+  for (int64_t e = lane; e < n; e += kWave) {
+    const int64_t slot = base + e;
+    const int32_t c = col[a + e];
+    const float sc = scale ? scale[c] : 1.f;
+    if (idx16)
+      static_cast<uint16_t*>(rci)[slot] = (uint16_t)c;
+    else
+      static_cast<int32_t*>(rci)[slot] = c;
+    store_value(vtype, rdv, slot, dv[a + e], sc);
+    store_value(vtype, rlv, slot, lv[a + e], sc);
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_block_count(int64_t R, int64_t C, int rows_per_block,
                                                         const int64_t* __restrict__ row_ptr,
                                                         const int32_t* __restrict__ col,
@@ -412,6 +445,15 @@ void launch_pack_sell(int vtype, int64_t R, int lpr_log2, const int64_t* row_ptr
   if (R > 0)
     k_pack_sell<<<row_grid(R), kBlock, 0, s>>>(vtype, R, lpr_log2, row_ptr, col, dv, lv, scale,
                                                 rslice, sbase, sci, idx16, sdv, slv);
+}
+
+void launch_pack_rows(int vtype, int64_t R, const int64_t* row_ptr, const int32_t* col,
+                      const float* dv, const float* lv, const float* scale,
+                      const int32_t* rslice, const int64_t* rptr, void* rci, int idx16,
+                      void* rdv, void* rlv, int32_t* plen, hipStream_t s) {
+  if (R > 0)
+    k_pack_rows<<<row_grid(R), kBlock, 0, s>>>(vtype, R, row_ptr, col, dv, lv, scale, rslice,
+                                                rptr, rci, idx16, rdv, rlv, plen);
 }
 
 void launch_block_count(int64_t R, int64_t C, int rows_per_block, const int64_t* row_ptr,

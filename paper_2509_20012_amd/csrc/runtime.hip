@@ -143,9 +143,10 @@ struct Layout {
   size_t y, osbase, oswidth, osrow, osci, osdv, oslv, ogroups, pk_src, pk_dst, pk_len;
   size_t spart_a, spart_b, rpart, gpart, tpart, groups, row_items, tr_items, col_blocks;
   size_t bc, colcount, colmax, flags, rslice, rsum, goff, alist, spart, smask, sc_items,
-      ss_items, pkind, pf, okind, of, gcoef, coef_row, total;
+      ss_items, pkind, pf, okind, of, gcoef, coef_row, rptr, plen, rci, rdv, rlv, total;
   int64_t NP;                 // positions of the all-row view
   int64_t sell_slots, n_slices, csc_slots, obj_slots, max_rows, max_tr, n_groups, n_col_blocks;
+  int64_t row_slots;          // row-contiguous copy: every row padded to 4 slots
   int64_t obj_sell_slots, max_obj_slices, max_obj_groups, max_obj_srow;
   int64_t rows_per_block, nb;
 };
@@ -263,6 +264,12 @@ bool make_layout(int64_t R, int64_t C, int64_t nnz, int storage, int lpr_log2,
                                   : sizeof(uint64_t));
   L->sc_items = take(sizeof(ScItem) * kScatterMaxWGs);
   L->ss_items = take(sizeof(ScItem) * ((C + 63) / 64));
+  L->row_slots = nnz + 3 * R;
+  L->rptr = take(sizeof(int64_t) * (Pm + 1));
+  L->plen = take(sizeof(int32_t) * Pm);
+  L->rci = take((size_t)index_bytes(storage) * std::max<int64_t>(L->row_slots, 1));
+  L->rdv = take((size_t)vb * std::max<int64_t>(L->row_slots, 1));
+  L->rlv = take((size_t)vb * std::max<int64_t>(L->row_slots, 1));
   L->total = o;
   return true;
 }
@@ -313,6 +320,7 @@ struct fredopt_plan {
   std::vector<TrItem> tr, gtr;
   std::vector<int32_t> col_ts0, col_nch, gcol_ts0, gcol_nch;
   std::vector<int32_t> row_len;       // real row lengths
+  std::vector<int64_t> rptr;          // row-contiguous copy: first slot per position
   Sell osell;                         // objective-row view (host tables)
   std::vector<FwdGroup> ogroups;
   bool sched_obj = false;             // iterations use the objective-row view
@@ -761,6 +769,7 @@ void export_state(const DevState& d, fredopt_state* st) {
   st->n_active = d.n_active;
   st->projection_path = d.proj_scatter;
   st->reserved = 0;
+  st->active_entries = d.active_entries;
 }
 
 enum Kind {
@@ -971,6 +980,15 @@ fredopt_status ensure_graph(fredopt_plan* p, int r) {
   if (st != FREDOPT_OK) return st;
   p->graph_r = r;
   return FREDOPT_OK;
+}
+
+// Lanes per active row of the scatter: enough 4-entry quads for a mean row in one
+// step, from 4 to 64 (a wave takes 64 / lanes rows at once).
+int scatter_lanes_log2(int64_t R, int64_t nnz) {
+  const int64_t quads = R > 0 ? (nnz / R + 3) / 4 : 1;
+  int lg = 2;
+  while (lg < 6 && (int64_t(1) << lg) < quads) ++lg;
+  return lg;
 }
 
 // Default workgroups of the active-row scatter: one per 64k stored entries (each
@@ -1276,6 +1294,33 @@ static fredopt_status load_impl(const fredopt_matrices* m, void* workspace,
   launch_pack_sell(vt, R, S.lpr_log2, in_rp, in_col, in_dv, in_lv, scale, d_rslice, d_sbase,
                    sci, index16(m->storage) ? 1 : 0, ws + L.sdv, ws + L.slv, s);
 
+  // row-contiguous copy (active-row scatter), rows at their positions, each padded to
+  // a multiple of 4 slots
+  {
+    const int64_t NP = (int64_t)S.srow.size();
+    p->rptr.assign(NP + 1, 0);
+    for (int64_t sp = 0; sp < NP; ++sp) {
+      const int32_t row = S.srow[sp];
+      const int64_t len = row >= 0 ? h_rp[row + 1] - h_rp[row] : 0;
+      p->rptr[sp + 1] = p->rptr[sp] + ((len + 3) & ~int64_t(3));
+    }
+    if (p->rptr[NP] > L.row_slots)
+      return cleanup(fail(FREDOPT_E_WORKSPACE, "row copy exceeds the workspace bound"));
+    const size_t Pm1 = (size_t)std::max<int64_t>(L.NP, 1);
+    LCHK(hipMemsetAsync(ws + L.rptr, 0, sizeof(int64_t) * (Pm1 + 1), s));
+    LCHK(hipMemcpyAsync(ws + L.rptr, p->rptr.data(), sizeof(int64_t) * (NP + 1),
+                        hipMemcpyHostToDevice, s));
+    LCHK(hipMemsetAsync(ws + L.plen, 0, sizeof(int32_t) * Pm1, s));
+    const size_t rs = (size_t)std::max<int64_t>(p->rptr[NP], 1);
+    LCHK(hipMemsetAsync(ws + L.rci, 0, (size_t)index_bytes(m->storage) * rs, s));
+    LCHK(hipMemsetAsync(ws + L.rdv, 0, (size_t)vb * rs, s));
+    LCHK(hipMemsetAsync(ws + L.rlv, 0, (size_t)vb * rs, s));
+    launch_pack_rows(vt, R, in_rp, in_col, in_dv, in_lv, scale, d_rslice,
+                     reinterpret_cast<const int64_t*>(ws + L.rptr), ws + L.rci,
+                     index16(m->storage) ? 1 : 0, ws + L.rdv, ws + L.rlv,
+                     reinterpret_cast<int32_t*>(ws + L.plen), s);
+  }
+
   // CSC: zero (padding slots keep row 0, value 0), per-block counts, offsets, fill
   int64_t* d_cp = reinterpret_cast<int64_t*>(ws + L.cp);
   int32_t* ri = reinterpret_cast<int32_t*>(ws + L.ri);
@@ -1374,6 +1419,12 @@ static fredopt_status load_impl(const fredopt_matrices* m, void* workspace,
   h.smask = reinterpret_cast<uint64_t*>(ws + L.smask);
   h.n_scatter = p->n_scatter;
   h.scatter_global = p->scatter_global ? 1 : 0;
+  h.rptr = reinterpret_cast<const int64_t*>(ws + L.rptr);
+  h.plen = reinterpret_cast<const int32_t*>(ws + L.plen);
+  h.rci = ws + L.rci;
+  h.rdv = ws + L.rdv;
+  h.rlv = ws + L.rlv;
+  h.sc_lg2 = scatter_lanes_log2(R, nnz);
   h.scatter_max_rows = (int32_t)std::min<int64_t>(p->scatter_max_rows, INT32_MAX);
   h.st = p->d_state;
   p->d_sc = reinterpret_cast<ScItem*>(ws + L.sc_items);
@@ -1460,6 +1511,8 @@ fredopt_status fredopt_get_plan_info(const fredopt_plan* p, fredopt_plan_info* i
   info->scatter_max_rows = p->scatter_max_rows;
   info->obj_lanes_per_row = p->sched_obj ? 1 << p->hp.osell.lpr_log2 : 0;
   info->fwd_schedule = p->fwd_dynamic ? 1 : 2;
+  info->scatter_lanes = 1 << p->hp.sc_lg2;
+  info->row_copy_slots = p->rptr.empty() ? 0 : p->rptr.back();
   return FREDOPT_OK;
 }
 

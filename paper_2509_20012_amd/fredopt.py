@@ -62,7 +62,7 @@ class State(ct.Structure):
                 ("beta", ct.c_double), ("cost", ct.c_double), ("cost_perturbed", ct.c_double),
                 ("proximity", ct.c_double), ("grad_sq", ct.c_double), ("q", ct.c_double),
                 ("n_active", ct.c_int64), ("projection_path", ct.c_int32),
-                ("reserved", ct.c_int32)]
+                ("reserved", ct.c_int32), ("active_entries", ct.c_int64)]
 
     def as_dict(self) -> Dict[str, float]:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -79,7 +79,8 @@ class PlanInfo(ct.Structure):
                 ("fwd_grid", ct.c_int32), ("tr_chunk", ct.c_int32), ("lds_x", ct.c_int32),
                 ("schedule", ct.c_int32), ("scatter_wgs", ct.c_int32),
                 ("scatter_max_rows", ct.c_int64), ("obj_lanes_per_row", ct.c_int32),
-                ("fwd_schedule", ct.c_int32)]
+                ("fwd_schedule", ct.c_int32), ("scatter_lanes", ct.c_int32),
+                ("row_copy_slots", ct.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

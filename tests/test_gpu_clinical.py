@@ -1,0 +1,209 @@
+"""Oracle parity on the clinical-scale plan itself, in the launch shapes the
+benchmark times: 160 x 160 x 120 grid at 2 mm, three fields of 80 x 50 spots
+(12,000 beamlets), 457,793 voxel rows, 154,936,615 entries in each of D and L.
+
+What only this plan reaches: the all-row forward pass walks 3,577 groups on a
+persistent grid of 256 workgroups (several groups per workgroup, the scheduling
+counter re-armed between launches), the column-major passes stride over 43,637
+chunks, the objective-row view runs 16 lanes per row, and the active-row scatter
+runs 256 workgroups, so its share sums take every round (64 workgroups are also
+tested).
+
+Tiers as in test_gpu_parity: T1 (dose, LETd, cDL element-wise, 1e-5), T2 (one
+outer iteration normwise 1e-5 with the same integer step exponent), T3 (PTV D95
+and OAR mean LETd within 0.5 % after a solve).  The precision form of this plan
+(16-bit values with a per-beamlet FP32 scale) is held to 1e-3 against the oracle
+on the original values for dose, LETd and cDL.
+"""
+import numpy as np
+import pytest
+
+from oracle import Oracle, OracleParams
+from paper_2509_20012_amd import metrics
+from paper_2509_20012_amd import phantom as ph
+
+pytestmark = pytest.mark.gpu
+
+T1 = 1e-5
+T2 = 1e-5
+T3 = 5e-3
+T1_16 = 1e-3
+
+
+@pytest.fixture(scope="module")
+def fo():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    from paper_2509_20012_amd import fredopt
+    fredopt.lib()
+    return fredopt
+
+
+@pytest.fixture(scope="module")
+def clin():
+    print("generating the clinical plan", flush=True)
+    return ph.clinical()
+
+
+@pytest.fixture(scope="module")
+def orc(clin):
+    return Oracle(clin)
+
+
+@pytest.fixture(scope="module")
+def ref100(clin, orc):
+    """The oracle's 100 outer iterations from x0 (benchmark settings) and its plan
+    report."""
+    q = OracleParams()
+    xr, k, s, _ = orc.solve(clin.x0, 100, q)
+    d_ref, _, letd_ref, _ = orc.dose_let(xr)
+    return xr, k, s, metrics.plan_report(d_ref, letd_ref, clin.roi)
+
+
+@pytest.fixture(scope="module")
+def loaded(fo, clin):
+    plan, prob, x0 = fo.load_phantom(clin)
+    yield plan, prob, x0
+    plan.free()
+
+
+def _np(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def _max_rel(gpu, ref, mask):
+    return float(np.max(np.abs(gpu[mask] - ref[mask]) / np.abs(ref[mask])))
+
+
+def _oparams(q):
+    return OracleParams(lam=q.lam, alpha=q.alpha, eta=q.eta, reductions_n=q.reductions_n,
+                        normalization=q.normalization, line_search=1)
+
+
+def test_clinical_launch_shapes(fo, clin, loaded):
+    plan = loaded[0]
+    info = plan.info()
+    print("clinical plan", info, flush=True)
+    assert (clin.n_rows, clin.n_cols, clin.nnz) == (457793, 12000, 154936615)
+    assert info["n_slices"] > 8 * 2048 and info["fwd_grid"] == 256
+    assert info["tr_items"] > 8 * 4 * info["fwd_grid"]     # the chunk grid strides
+    assert info["scatter_wgs"] == 256
+    assert info["lanes_per_row"] == 4
+
+
+@pytest.mark.parametrize("which", ["x0", "random"])
+def test_clinical_dose_let(fo, clin, orc, loaded, which):
+    """T1 element-wise on every row of the plan."""
+    import torch
+    plan = loaded[0]
+    x = (clin.x0 if which == "x0" else
+         np.random.default_rng(5).uniform(0.0, 2.0, clin.n_cols)).astype(np.float32)
+    print(f"clinical dose_let at {which}", flush=True)
+    dose, letd, cdl = fo.dose_let(plan, torch.from_numpy(x).cuda(), clin.c)
+    torch.cuda.synchronize()
+    d_ref, _, letd_ref, cdl_ref = orc.dose_let(x)
+    m = d_ref > 0
+    dg, lg, cg = _np(dose), _np(letd), _np(cdl)
+    errs = (_max_rel(dg, d_ref, m), _max_rel(lg, letd_ref, m), _max_rel(cg, cdl_ref, m))
+    print(f"max rel err dose {errs[0]:.3g} LETd {errs[1]:.3g} cDL {errs[2]:.3g}", flush=True)
+    assert max(errs) <= T1
+    assert np.all(dg[~m] == 0.0) and np.all(lg[~m] == 0.0)
+
+
+# projection paths: column-major for every row, the active-row scatter with its
+# default 256 workgroups and with 64, and the plan's own choice
+PATHS = {"csc": (-1, -1), "scatter256": (256, 1 << 40), "scatter64": (64, 1 << 40),
+         "auto": (0, -1)}
+
+
+@pytest.mark.parametrize("path", list(PATHS))
+def test_clinical_superiorize_steps(fo, clin, orc, loaded, path):
+    """T2 and the exact step exponent over 4 outer iterations from x0."""
+    plan, prob, x0 = loaded
+    fo.set_scatter(plan, *PATHS[path])
+    q = fo.SolverParams()
+    st = fo.new_state()
+    x = x0.clone()
+    xr = clin.x0.astype(np.float64)
+    k, s = 0, -1
+    try:
+        for it in range(4):
+            print(f"clinical superiorize_step path={path} iteration {it}", flush=True)
+            fo.superiorize_step(plan, prob, q, st, x)
+            xr, k, s, inf = orc.sa_iteration(xr, k, s, _oparams(q))
+            err = np.linalg.norm(_np(x) - xr) / np.linalg.norm(xr)
+            print(f"  s {st.s}/{s} err {err:.3g} active {st.n_active} "
+                  f"path {st.projection_path}", flush=True)
+            assert (st.k, st.s) == (k, s)
+            assert err <= T2
+            assert st.cost == pytest.approx(inf["cost_before"], rel=1e-5)
+            assert st.grad_sq == pytest.approx(inf["grad_sq"], rel=1e-4)
+            assert st.proximity == pytest.approx(inf["proximity"], rel=1e-4)
+            if path.startswith("scatter"):
+                assert st.projection_path == 1
+            if path == "csc":
+                assert st.projection_path == 0
+    finally:
+        fo.set_scatter(plan, 0, -1)
+
+
+def test_clinical_solve_plan_quality(fo, clin, loaded, ref100):
+    """T3 after 100 superiorized iterations from x0 with the benchmark's settings."""
+    import torch
+    plan, prob, x0 = loaded
+    n = 100
+    q = fo.SolverParams(iter_max=n)
+    assert _oparams(q) == OracleParams()
+    st = fo.new_state()
+    x = x0.clone()
+    fo.solve(plan, prob, q, st, x)
+    print(f"clinical gpu solve done: k={st.k} s={st.s}", flush=True)
+    xr, k, s, rr = ref100
+    dose, letd, _ = fo.dose_let(plan, x, clin.c)
+    torch.cuda.synchronize()
+    rg = metrics.plan_report(_np(dose), _np(letd), clin.roi)
+    err_x = np.linalg.norm(_np(x) - xr) / np.linalg.norm(xr)
+    print(f"s {st.s}/{s}, x normwise {err_x:.3g}\ngpu {rg}\noracle {rr}", flush=True)
+    assert st.k == k == n
+    assert rg["PTV_D95"] == pytest.approx(rr["PTV_D95"], rel=T3)
+    for name in clin.roi:
+        if name.startswith("OAR"):
+            key = f"{name}_mean_LETd"
+            assert rg[key] == pytest.approx(rr[key], rel=T3), key
+
+
+def test_clinical_precision_form(fo, clin, orc, ref100):
+    """The precision form of the clinical plan: FP16 values with a per-beamlet FP32
+    scale (32-bit and 16-bit column indices) against the oracle on the original
+    values, element-wise, 1e-3; T3 after 100 iterations with 16-bit indices."""
+    import torch
+    x = np.random.default_rng(6).uniform(0.5, 1.5, clin.n_cols).astype(np.float32)
+    d_ref, _, letd_ref, cdl_ref = orc.dose_let(x)
+    m = d_ref > 0
+    for storage in (fo.F16, fo.F16_IDX16):
+        print(f"clinical precision form storage={storage}", flush=True)
+        plan, prob, x0 = fo.load_phantom(clin, storage=storage)
+        dose, letd, cdl = fo.dose_let(plan, torch.from_numpy(x).cuda(), clin.c)
+        torch.cuda.synchronize()
+        errs = (_max_rel(_np(dose), d_ref, m), _max_rel(_np(letd), letd_ref, m),
+                _max_rel(_np(cdl), cdl_ref, m))
+        print(f"  max rel err vs original values: dose {errs[0]:.3g} LETd {errs[1]:.3g} "
+              f"cDL {errs[2]:.3g}", flush=True)
+        assert max(errs) <= T1_16
+        if storage == fo.F16_IDX16:
+            q = fo.SolverParams(iter_max=100)
+            st = fo.new_state()
+            xs = x0.clone()
+            fo.solve(plan, prob, q, st, xs)
+            rr = ref100[3]
+            dg, lg, _ = fo.dose_let(plan, xs, clin.c)
+            torch.cuda.synchronize()
+            rg = metrics.plan_report(_np(dg), _np(lg), clin.roi)
+            print(f"  after 100 iterations: gpu {rg}\n  oracle {rr}", flush=True)
+            assert rg["PTV_D95"] == pytest.approx(rr["PTV_D95"], rel=T3)
+            for name in clin.roi:
+                if name.startswith("OAR"):
+                    key = f"{name}_mean_LETd"
+                    assert rg[key] == pytest.approx(rr[key], rel=T3), key
+        plan.free()
