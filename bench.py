@@ -37,6 +37,17 @@ KERNEL_SYMBOLS = {  # fredopt kernel id -> device symbol in profiler output (vt:
     "scatter": "fo::k_scatter<{vt}>", "scatter_sum": "fo::k_scatter_sum"}
 
 
+def dtype_of(storage: str) -> str:
+    """The arithmetic type of the path with the storage form it reads.  BF16 values
+    (8-bit mantissa) miss the 1e-3 tolerance of the reduced-precision form against
+    the original values; FP16 meets it."""
+    if storage == "f32":
+        return "f32"
+    if storage.startswith("bf16"):
+        return f"f32 (values stored {storage}; outside the 1e-3 tolerance of the 16-bit form)"
+    return f"f32 (values stored {storage})"
+
+
 def log(msg: str):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
@@ -94,26 +105,60 @@ def make_workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-def cpu_baseline(p, q, n_iters: int):
-    """The FP64 oracle, as it stands, on the host cores for n_iters outer iterations
-    (closed-form step search) of the same workload."""
-    from oracle import Oracle, OracleParams, num_threads
+def _oracle_run(o, p, prm, n_iters: int):
+    """n_iters outer iterations of the oracle from x0: seconds, the iterate and the
+    mean number of step sizes tried per iteration."""
+    x = p.x0.astype(np.float64)
+    k, s = 0, -1
+    trials = 0
+    t0 = time.perf_counter()
+    for _ in range(n_iters):
+        x, k, s, info = o.sa_iteration(x, k, s, prm)
+        trials += info["n_trials"]
+    return time.perf_counter() - t0, (x, k, s), trials / max(n_iters, 1)
+
+
+def cpu_baseline(p, q, n_iters: int, n_literal: int, n_single: int):
+    """The FP64 oracle, as it stands, on the host cores: n_iters outer iterations with
+    the closed-form step search on every thread (the reported value), then two
+    variants beside it: Fig. 3's literal backtracking search (each trial step
+    recomputes Eq. (2) with a full forward product) on every thread, and the
+    closed form on one thread.  Matrix passes per iteration count the forward
+    (D x, L x) and transposed (D^T u, L^T u) products over every row the oracle
+    makes: 1 for the starting cost, per perturbation 2 for the gradient plus 2
+    (closed form: direction product and new cost) or one per trial (literal), and 2
+    for the feasibility sweep."""
+    from oracle import Oracle, OracleParams, num_threads, set_threads
     t0 = time.perf_counter()
     o = Oracle(p)
     t_load = time.perf_counter() - t0
-    prm = OracleParams(lam=q.lam, alpha=q.alpha, eta=q.eta, reductions_n=q.reductions_n,
-                       normalization=q.normalization, line_search=1)
-    x = p.x0.astype(np.float64)
-    k, s = 0, -1
-    t0 = time.perf_counter()
-    for _ in range(n_iters):
-        x, k, s, _ = o.sa_iteration(x, k, s, prm)
-    dt = time.perf_counter() - t0
-    return {"value": n_iters / dt, "unit": "iters/s", "cores": num_threads(), "kind": "oracle",
-            "sample": f"{n_iters} outer iterations (reductions_n={q.reductions_n}, closed-form "
-                      f"step search) of the same workload from x0; oracle load "
-                      f"(FP64 promotion + CSC) {t_load:.1f} s not timed",
-            "seconds": dt}, (x, k, s)
+    cores = num_threads()
+    base = dict(lam=q.lam, alpha=q.alpha, eta=q.eta, reductions_n=q.reductions_n,
+                normalization=q.normalization)
+    r = q.reductions_n
+    dt, state, _ = _oracle_run(o, p, OracleParams(line_search=1, **base), n_iters)
+    variants = []
+    if n_literal > 0:
+        dl, _, trials = _oracle_run(o, p, OracleParams(line_search=0, **base), n_literal)
+        variants.append({"line_search": "literal (Fig. 3 backtracking)", "cores": cores,
+                         "iters_per_s": n_literal / dl, "sample": f"{n_literal} outer "
+                         f"iterations from x0", "trials_per_iteration": round(trials, 2),
+                         "matrix_passes_per_iteration": round(3 + r * 2 + trials, 2)})
+    if n_single > 0:
+        set_threads(1)
+        try:
+            ds, _, _ = _oracle_run(o, p, OracleParams(line_search=1, **base), n_single)
+        finally:
+            set_threads(cores)
+        variants.append({"line_search": "closed form", "cores": 1,
+                         "iters_per_s": n_single / ds,
+                         "sample": f"{n_single} outer iterations from x0",
+                         "matrix_passes_per_iteration": 3 + 4 * r})
+    return {"value": n_iters / dt, "unit": "iters/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n_iters} outer iterations (reductions_n={r}, closed-form step "
+                      f"search, {3 + 4 * r} matrix passes each) of the same workload from "
+                      f"x0; oracle load (FP64 promotion + CSC) {t_load:.1f} s not timed",
+            "variants": variants, "seconds": dt}, state
 
 
 def _timed(fn):
@@ -178,7 +223,7 @@ def bench_batch(args):
         "metric": METRIC, "value": round(rate, 2), "unit": "iters/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32" if storage == fredopt.F32 else f"f32 (values stored {args.storage})",
+        "dtype": dtype_of(args.storage),
         "data": "synthetic",
         "config": {"workload": desc, "plans": len(loaded), "nnz_total": nnz,
                    "storage": args.storage, "reductions_n": args.reductions,
@@ -242,6 +287,47 @@ def bench_serve(args):
     }
 
 
+def bench_small_plan(args, steps: int = 1000, warmup: int = 50):
+    """The 32^3 water plan (400 beamlets): small enough to stay in cache, so its rate
+    is set by launch and synchronisation latency.  Steady-state iterations/s after
+    warm-up, and its 100-iteration solve from x0."""
+    import torch
+    from paper_2509_20012_amd import fredopt, phantom as ph
+    p = ph.water32()
+    plan, prob, x0 = fredopt.load_phantom(p)
+    q = fredopt.SolverParams(reductions_n=args.reductions, iter_max=warmup)
+    x = x0.clone()
+    st = fredopt.new_state()
+    fredopt.solve(plan, prob, q, st, x)
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    q.iter_max = steps
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    fredopt.solve(plan, prob, q, st, x)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    n_full = int(p.meta.get("iterations", 100))
+    q.iter_max = n_full
+    xf = x0.clone()
+    sf = fredopt.new_state()
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    fredopt.solve(plan, prob, q, sf, xf)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_full = ev0.elapsed_time(ev1)
+    plan.free()
+    log(f"water32: {steps / ms * 1e3:.1f} it/s steady, {n_full} from x0 in {ms_full:.2f} ms")
+    return {"workload": f"water32: {p.name}, {p.n_rows} x {p.n_cols}, {p.nnz} entries",
+            "iters_per_s": round(steps / ms * 1e3, 1), "ms_per_step": round(ms / steps, 5),
+            "steps": steps, "warmup": warmup,
+            "full_solve": {"iterations": n_full, "ms": round(ms_full, 3),
+                           "iters_per_s": round(n_full / ms_full * 1e3, 1)}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -263,6 +349,15 @@ def main():
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=100)
+    ap.add_argument("--cpu-literal-iters", type=int, default=10,
+                    help="cpu baseline: iterations with the literal step search")
+    ap.add_argument("--cpu-single-iters", type=int, default=5,
+                    help="cpu baseline: iterations on one host thread")
+    ap.add_argument("--full-solve", type=int, default=None,
+                    help="iterations of the whole-trajectory solve from x0 (default: the "
+                         "workload's iteration count; 0 skips it)")
+    ap.add_argument("--no-config0", action="store_true",
+                    help="skip the 32^3 water plan's rate in the clinical line")
     ap.add_argument("--profile-iters", type=int, default=5)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (for PMC scaling)")
@@ -402,7 +497,7 @@ def main():
         "metric": METRIC, "value": round(its, 3), "unit": "iters/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32" if storage == fredopt.F32 else f"f32 (values stored {args.storage})",
+        "dtype": dtype_of(args.storage),
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {p.name}", "rows": R, "cols": C, "nnz": nnz,
                    "storage": args.storage, "reductions_n": args.reductions,
@@ -419,10 +514,35 @@ def main():
         "paper_context": "Table 2 stage (iv): 200 SA iterations in 2091 s / 1508 s "
                          "(0.096 / 0.133 it/s) on an NVIDIA P100, private patient matrices",
     }
+    # the whole trajectory: the workload's full iteration count from x0 (the timed
+    # window above samples iterations warmup+1 .. warmup+steps)
+    n_full = args.full_solve if args.full_solve is not None else int(p.meta.get("iterations", 0))
+    if n_full > 0:
+        qf = fredopt.SolverParams(reductions_n=args.reductions, iter_max=n_full)
+        xf = x0.clone()
+        sf = fredopt.new_state()
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        fredopt.solve(plan, prob, qf, sf, xf)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms_full = ev0.elapsed_time(ev1)
+        result["full_solve"] = {"iterations": n_full, "from": "x0", "ms": round(ms_full, 3),
+                                "iters_per_s": round(n_full / ms_full * 1e3, 2),
+                                "final": {"k": sf.k, "s": sf.s, "violated": sf.n_violated,
+                                          "active_rows": sf.n_active,
+                                          "projection_path": sf.projection_path}}
+        log(f"full solve: {n_full} iterations from x0 in {ms_full:.1f} ms "
+            f"({n_full / ms_full * 1e3:.1f} it/s)")
+    if args.workload == "clinical" and not args.no_config0:
+        result["config0"] = bench_small_plan(args)
     if not args.no_cpu_baseline:
-        log(f"cpu baseline: oracle, {args.cpu_iters} iterations")
-        cb, _ = cpu_baseline(p, q, args.cpu_iters)
-        log(f"cpu baseline {cb['value']:.4f} it/s on {cb['cores']} threads ({cb['seconds']:.1f} s)")
+        log(f"cpu baseline: oracle, {args.cpu_iters} iterations (+ {args.cpu_literal_iters} "
+            f"literal, {args.cpu_single_iters} on one thread)")
+        cb, _ = cpu_baseline(p, q, args.cpu_iters, args.cpu_literal_iters,
+                             args.cpu_single_iters)
+        log(f"cpu baseline {cb['value']:.4f} it/s on {cb['cores']} threads ({cb['seconds']:.1f} s); "
+            f"variants {cb['variants']}")
         cb.pop("seconds")
         result["cpu_baseline"] = cb
     print(json.dumps(result), flush=True)

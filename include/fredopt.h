@@ -39,7 +39,10 @@
  *  - Every call returns FREDOPT_OK or a negative status; on error nothing the
  *    caller owns has been modified and fredopt_last_error() describes the cause,
  *    except FREDOPT_E_NONFINITE raised by an iteration: x then holds the iterate
- *    reached when the non-finite value was detected.
+ *    reached when the non-finite value was detected.  The device checks for NaN or
+ *    Inf in every pass of every iteration; once it finds one, every later kernel of
+ *    the call skips the plan, so a long solve stops there and the returned state
+ *    (k, s) is the one at the detection.
  *  - Calls on one plan must not overlap; calls on distinct plans are independent.
  */
 #ifndef FREDOPT_H

@@ -87,6 +87,16 @@ int orc_num_threads(void) {
 #endif
 }
 
+/* Threads of the parallel loops that follow (n >= 1); used to time the oracle on one
+ * host core next to all of them. */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  if (n >= 1) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 /* ---------------------------------------------------------------- matrices ---- */
 
 /* Counting-sort transpose: within each column rows come out ascending. */

@@ -114,12 +114,18 @@ def _load():
                                   ct.c_int64, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_int64),
                                   P, ct.POINTER(_Info)]
         lib.orc_num_threads.restype = ct.c_int
+        lib.orc_set_threads.argtypes = [ct.c_int]
         _lib = lib
     return _lib
 
 
 def num_threads() -> int:
     return int(_load().orc_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops from now on (n >= 1)."""
+    _load().orc_set_threads(int(n))
 
 
 def _p(a: np.ndarray) -> int:

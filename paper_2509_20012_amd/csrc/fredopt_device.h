@@ -63,10 +63,13 @@ enum ColMode : int {
   kColProjMove = 3,  // x = max(0, x - beta g - scale sum)
   kColProjY = 4,     // x = y = max(0, y - scale sum)
   kColYMove = 5,     // y -= beta g (no sum)
-  kColYCopy = 6      // y = x (no sum)
+  kColYCopy = 6,     // y = x (no sum)
+  kColProjYMove = 7  // x = y = max(0, y - beta g - scale sum)
 };
 // which vector a forward pass multiplies
-enum VecSel : int { kVecX = 0, kVecY = 1, kVecG = 2 };
+// kVecYMove: y - beta g, the perturbed point after the pending step (staged in LDS
+// without writing y back)
+enum VecSel : int { kVecX = 0, kVecY = 1, kVecG = 2, kVecYMove = 3 };
 // plan-level finalisation
 enum FinMode : int {
   kFinDir0 = 0,        // first perturbation of an outer iteration: cost, reset, step

@@ -25,7 +25,8 @@ void launch_active_list(const DevPlan* plans, const FwdGroup* groups, int n_grou
 void launch_scatter(int vtype, const DevPlan* plans, const ScItem* items, int n_items,
                     size_t lds_bytes, hipStream_t s);
 hipError_t set_scatter_lds_limit(size_t bytes);
-// mode: the ColMode of the projection update (kColProj, kColProjMove, kColProjY)
+// mode: the ColMode of the projection update (kColProj, kColProjMove, kColProjY,
+// kColProjYMove)
 // items[i] = {plan, 64-column word}
 void launch_scatter_sum(int mode, const DevPlan* plans, const ScItem* items, int n_items,
                         hipStream_t s);

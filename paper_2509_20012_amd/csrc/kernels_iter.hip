@@ -276,6 +276,12 @@ __device__ __forceinline__ void residual_row(const DevPlan* P, int r, unsigned k
 
 __device__ __forceinline__ bool finite2(float a, float b) { return isfinite(a) && isfinite(b); }
 
+// A plan whose iteration produced a non-finite value is halted: every later kernel of
+// the call skips it (the flag is set by a finalisation kernel and cleared when the
+// host uploads a state), so x keeps the iterate reached when it was detected and a
+// long solve does no further work on it.
+__device__ __forceinline__ bool halted(const DevPlan* P) { return P->st->nonfinite != 0; }
+
 // Plan-level completion of a residual pass: proximity, weights, the projection
 // scale weight_scale / W, and the outer counter (Fig. 3: weights eta^k w).
 __device__ __forceinline__ void finalize_residuals(const DevPlan* P, const double* s) {
@@ -350,11 +356,14 @@ __device__ __forceinline__ constexpr unsigned fwd_slots() {
 
 // One slice of a sliced-ELL view: d = D v, l = L v for its rows, then the epilogue
 // of MODE.  SUB selects the objective-row view, whose direction pass only needs Q.
+// Without LDS staging the vector is read from global memory; gmv != null: the vector
+// is vec - beta gmv (the pending perturbation step, kVecYMove).
 template <int VT, int MODE, int SUB>
 __device__ __forceinline__ void forward_slice(const DevPlan* __restrict__ P, int s,
                                               const float* __restrict__ xs, bool use_lds,
-                                              const float* __restrict__ vec, int lane,
-                                              double* wpart) {
+                                              const float* __restrict__ vec,
+                                              const float* __restrict__ gmv, double beta,
+                                              int lane, double* wpart) {
   const SellView& V = SUB ? P->osell : P->sell;
   const int lg2 = uniform(V.lpr_log2);
   const int lpr = 1 << lg2;
@@ -396,16 +405,21 @@ __device__ __forceinline__ void forward_slice(const DevPlan* __restrict__ P, int
   } else {
     const FO_GLOBAL float* cs = gconst(P->cscale);
     const FO_GLOBAL float* gv = gconst(vec);
+    const FO_GLOBAL float* gg = gconst(gmv);
     const bool scaled = P->cscale != nullptr;
+    auto val = [&](int c) {
+      const float v = gmv ? (float)((double)gv[c] - beta * (double)gg[c]) : gv[c];
+      return scaled ? v * cs[c] : v;
+    };
     for (int t = 0; t < W; ++t) {
       const uint32_t e = (uint32_t)t * 256u + 4u * (uint32_t)lane;
       const v4i c4 = sell_idx4<VT>(ci, e);
       const v4f d4 = VLoad<VT>::q4(dv, e);
       const v4f l4 = VLoad<VT>::q4(lv, e);
-      const float x0 = scaled ? gv[c4.x] * cs[c4.x] : gv[c4.x];
-      const float x1 = scaled ? gv[c4.y] * cs[c4.y] : gv[c4.y];
-      const float x2 = scaled ? gv[c4.z] * cs[c4.z] : gv[c4.z];
-      const float x3 = scaled ? gv[c4.w] * cs[c4.w] : gv[c4.w];
+      const float x0 = val(c4.x);
+      const float x1 = val(c4.y);
+      const float x2 = val(c4.z);
+      const float x3 = val(c4.w);
       ad = fmaf(d4.x, x0, ad);
       ad = fmaf(d4.y, x1, ad);
       ad = fmaf(d4.z, x2, ad);
@@ -475,15 +489,22 @@ __device__ __forceinline__ void forward_slice(const DevPlan* __restrict__ P, int
 // round trips instead of one per kFwdBlock elements.
 constexpr int kStage = 16;
 
-template <bool SCALED>
+// MOVE: stages v - beta g, rounded to FP32 as the separate move would store it.
+template <bool SCALED, bool MOVE>
 __device__ __forceinline__ void stage_vector(const FO_GLOBAL float* v, const FO_GLOBAL float* cs,
-                                             int C, float* xs, int tid) {
+                                             const FO_GLOBAL float* g, double beta, int C,
+                                             float* xs, int tid) {
   for (int j0 = tid; j0 < C; j0 += kStage * kFwdBlock) {
     float t[kStage];
 #pragma unroll
     for (int u = 0; u < kStage; ++u) {
       const int j = j0 + u * kFwdBlock;
-      t[u] = j < C ? (SCALED ? v[j] * cs[j] : v[j]) : 0.f;
+      float a = 0.f;
+      if (j < C) {
+        a = MOVE ? (float)((double)v[j] - beta * (double)g[j]) : v[j];
+        if (SCALED) a *= cs[j];
+      }
+      t[u] = a;
     }
 #pragma unroll
     for (int u = 0; u < kStage; ++u) {
@@ -505,6 +526,8 @@ __global__ __launch_bounds__(kFwdBlock) void k_forward(const DevPlan* __restrict
   int cur = -1;
   bool use_lds = false;
   const float* vec = nullptr;
+  const float* gmv = nullptr;
+  double beta = 0.0;
   for (int it = 0;; ++it) {
     int gi;
     if (ctr) {  // dynamic: next group from a counter (taken only when this one is done,
@@ -530,23 +553,32 @@ __global__ __launch_bounds__(kFwdBlock) void k_forward(const DevPlan* __restrict
     }
     const FwdGroup G = groups[gi];
     const DevPlan* __restrict__ P = plans + G.plan;
+    if (MODE != kFwdDoseLet && halted(P)) continue;  // uniform over the workgroup
     if (G.plan != cur) {
-      vec = vsel == kVecG ? P->g : (vsel == kVecY ? P->y : P->x);
+      vec = vsel == kVecG ? P->g : (vsel == kVecX ? P->x : P->y);
+      const bool move = vsel == kVecYMove;
+      gmv = move ? P->g : nullptr;
+      beta = move ? P->st->beta : 0.0;
       use_lds = P->C <= (int64_t)lds_floats;
       if (use_lds) {
         const FO_GLOBAL float* gv = gconst(vec);
         const FO_GLOBAL float* cs = gconst(P->cscale);
+        const FO_GLOBAL float* gg = gconst(gmv);
         const int C = (int)P->C;
-        if (P->cscale)
-          stage_vector<true>(gv, cs, C, xs, tid);
-        else
-          stage_vector<false>(gv, cs, C, xs, tid);
+        if (P->cscale) {
+          if (move) stage_vector<true, true>(gv, cs, gg, beta, C, xs, tid);
+          else stage_vector<true, false>(gv, cs, gg, beta, C, xs, tid);
+        } else {
+          if (move) stage_vector<false, true>(gv, cs, gg, beta, C, xs, tid);
+          else stage_vector<false, false>(gv, cs, gg, beta, C, xs, tid);
+        }
       }
       __syncthreads();
       cur = G.plan;
     }
     if (wave < G.n)
-      forward_slice<VT, MODE, SUB>(P, G.slice0 + wave, xs, use_lds, vec, lane, wpart[wave]);
+      forward_slice<VT, MODE, SUB>(P, G.slice0 + wave, xs, use_lds, vec, gmv, beta, lane,
+                                   wpart[wave]);
     __syncthreads();
     if constexpr (MODE != kFwdDoseLet) {
       // the group's partial: its slices' partials in wave order
@@ -567,6 +599,7 @@ __global__ __launch_bounds__(kBlock) void k_rows(const DevPlan* __restrict__ pla
   __shared__ double sh4[kBlock / kWave];
   const RowItem w = items[blockIdx.x];
   const DevPlan* __restrict__ P = plans + w.plan;
+  if (halted(P)) return;
   const int tid = threadIdx.x;
   const double beta = P->st->beta;
   double acc[kNPart];
@@ -620,14 +653,15 @@ template <int VT, int TAG>
 __global__ __launch_bounds__(kBlock) void k_tr_chunks(const DevPlan* __restrict__ plans,
                                                       const TrItem* __restrict__ items,
                                                       int n_items, int nb8, int single) {
-  if (TAG == 1 && single && plans[0].st->proj_scatter) return;
+  if (single && (halted(plans) || (TAG == 1 && plans[0].st->proj_scatter))) return;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   for (int vb = blockIdx.x; vb < nb8 * 8; vb += gridDim.x) {
     const int lb = (vb & 7) * nb8 + (vb >> 3);
     const int it = lb * (kBlock / kWave) + wave;
     if (it >= n_items) continue;
     const TrItem w = items[uniform(it)];
-    if (TAG == 1 && !single && plans[w.plan].st->proj_scatter) continue;
+    if (!single && (halted(plans + w.plan) || (TAG == 1 && plans[w.plan].st->proj_scatter)))
+      continue;
     tr_chunk<VT, TAG>(plans, w, lane);
   }
 }
@@ -699,6 +733,7 @@ __global__ __launch_bounds__(kFwdBlock) void k_active_list(const DevPlan* __rest
   __shared__ int wsum[kFwdWaves];
   const FwdGroup G = groups[blockIdx.x];
   const DevPlan* __restrict__ P = plans + G.plan;
+  if (halted(P)) return;
   const int rpw_log2 = 6 - P->lpr_log2;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   const int n = G.n << rpw_log2;
@@ -760,7 +795,7 @@ __global__ __launch_bounds__(kScatterBlock) void k_scatter(const DevPlan* __rest
   const ScItem item = items[blockIdx.x];
   const DevPlan* __restrict__ P = plans + item.plan;
   const int wg = item.idx;
-  if (!P->st->proj_scatter) return;
+  if (halted(P) || !P->st->proj_scatter) return;
   const int C = (int)P->C;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   // column sums in LDS, or (plans too wide for LDS) in global memory, where the
@@ -828,13 +863,17 @@ __global__ __launch_bounds__(kScatterBlock) void k_scatter(const DevPlan* __rest
 // point, by MODE.
 template <int MODE>
 __device__ __forceinline__ void project_column(const DevPlan* __restrict__ P, int j, float t) {
+  constexpr bool fromy = MODE == kColProjY || MODE == kColProjYMove;
   if (P->cscale) t *= gconst(P->cscale)[j];
-  double y = MODE == kColProjY ? gconst(P->y)[j] : gconst(P->x)[j];
+  double y = fromy ? gconst(P->y)[j] : gconst(P->x)[j];
   if constexpr (MODE == kColProjMove) y -= P->st->beta * (double)gconst(P->g)[j];
+  // the perturbed point y - beta g, rounded to FP32 as the residual pass staged it
+  if constexpr (MODE == kColProjYMove)
+    y = (double)(float)(y - P->st->beta * (double)gconst(P->g)[j]);
   const double xn = y - P->st->scale * (double)t;
   const float xf = xn > 0.0 ? (float)xn : 0.f;
   gmut(P->x)[j] = xf;
-  if constexpr (MODE == kColProjY) gmut(P->y)[j] = xf;
+  if constexpr (fromy) gmut(P->y)[j] = xf;
 }
 
 // The sweep's update of 64 columns: on the active-row path, the sum of the scatter
@@ -847,6 +886,7 @@ __global__ __launch_bounds__(kScatterBlock) void k_scatter_sum(const DevPlan* __
   __shared__ int64_t part[kScatterBlock / kWave][kWave];
   const ScItem item = items[blockIdx.x];
   const DevPlan* __restrict__ P = plans + item.plan;
+  if (halted(P)) return;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   const int C = (int)P->C, nwords = (C + kWave - 1) / kWave;
   const int j = item.idx * kWave + lane;
@@ -899,6 +939,7 @@ __global__ __launch_bounds__(kBlock) void k_tcol(const DevPlan* __restrict__ pla
   __shared__ double sh4[kBlock / kWave];
   const ColBlock cb = blocks[blockIdx.x];
   const DevPlan* __restrict__ P = plans + cb.plan;
+  if (MODE != kColYCopy && halted(P)) return;
   const int j = cb.c0 + threadIdx.x;
   constexpr bool grad = MODE == kColGrad || MODE == kColGradMove;
   double cv = 0.0;
@@ -988,6 +1029,7 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(const DevPlan* __restric
   __shared__ double sh4[kFinWaves];
   __shared__ double shs[kFinWaves][kNPart];
   const DevPlan* __restrict__ P = plans + blockIdx.x;
+  if (halted(P)) return;
   const int ng = SUB ? P->osell.n_groups : P->sell.n_groups;
   double a[kNPart];
   if constexpr (MODE == kFinDir0 || MODE == kFinDir) {
@@ -1162,7 +1204,9 @@ void launch_scatter(int vtype, const DevPlan* plans, const ScItem* items, int n_
 void launch_scatter_sum(int mode, const DevPlan* plans, const ScItem* items, int n_items,
                         hipStream_t s) {
   if (n_items <= 0) return;
-  if (mode == kColProjY)
+  if (mode == kColProjYMove)
+    k_scatter_sum<kColProjYMove><<<n_items, kScatterBlock, 0, s>>>(plans, items);
+  else if (mode == kColProjY)
     k_scatter_sum<kColProjY><<<n_items, kScatterBlock, 0, s>>>(plans, items);
   else if (mode == kColProjMove)
     k_scatter_sum<kColProjMove><<<n_items, kScatterBlock, 0, s>>>(plans, items);

@@ -790,7 +790,9 @@ struct Launch {
 // taken once, at the perturbed point y, and feeds the constraint residuals.
 // Without it: the all-row forward products at x and along g, d and l moved by the
 // accepted step.  The caller sets y = x before the first iteration; the
-// projection writes x and y.
+// projection writes x and y.  fold (every plan stages its vector in LDS): the last
+// perturbation's move y = y - beta g is not stored; the residual pass stages
+// y - beta g and the projection update recomputes it.
 // The sweep's transposed product and update.  The device picks the path per plan
 // and iteration (proj_scatter): the kernels of the other path return at once.  The
 // last launch updates every column: from the scatter shares, or from the chunk
@@ -802,7 +804,7 @@ void add_projection(std::vector<Launch>* seq, int col_mode) {
   seq->push_back({FREDOPT_KERNEL_SCATTER_SUM, kKindScatterSum, col_mode});
 }
 
-std::vector<Launch> iteration_sequence(int r, bool obj) {
+std::vector<Launch> iteration_sequence(int r, bool obj, bool fold) {
   std::vector<Launch> seq;
   if (r == 0) {
     seq.push_back({FREDOPT_KERNEL_FWD_RESID, kKindFwd, kFwdResid, 0, kVecX});
@@ -817,11 +819,11 @@ std::vector<Launch> iteration_sequence(int r, bool obj) {
       seq.push_back({FREDOPT_KERNEL_COL, kKindCol, kColGrad});
       seq.push_back({FREDOPT_KERNEL_FWD_DIR, kKindFwd, kFwdDir, 1, kVecG});
       seq.push_back({FREDOPT_KERNEL_FINALIZE, kKindFin, t == 0 ? kFinDir0 : kFinDir, 1});
-      seq.push_back({FREDOPT_KERNEL_COL, kKindCol, kColYMove});
+      if (!(fold && t + 1 == r)) seq.push_back({FREDOPT_KERNEL_COL, kKindCol, kColYMove});
     }
-    seq.push_back({FREDOPT_KERNEL_FWD_RESID, kKindFwd, kFwdResid, 0, kVecY});
+    seq.push_back({FREDOPT_KERNEL_FWD_RESID, kKindFwd, kFwdResid, 0, fold ? kVecYMove : kVecY});
     seq.push_back({FREDOPT_KERNEL_FINALIZE, kKindFin, kFinResidFwd});
-    add_projection(&seq, kColProjY);
+    add_projection(&seq, fold ? kColProjYMove : kColProjY);
     return seq;
   }
   seq.push_back({FREDOPT_KERNEL_FWD_OBJ, kKindFwd, kFwdObj, 0, kVecX});
@@ -942,9 +944,15 @@ void enqueue(const Exec& e, const Launch& l, hipStream_t s) {
 
 void enqueue(fredopt_plan* p, const Launch& l, hipStream_t s) { enqueue(exec_of(p), l, s); }
 
+// The iteration for an exec: the last move folded when every plan stages its vector
+// in LDS.
+std::vector<Launch> sequence_of(const Exec& e, int r, bool obj) {
+  return iteration_sequence(r, obj, e.lds_floats > 0);
+}
+
 fredopt_status enqueue_iteration(fredopt_plan* p, int r, hipStream_t s) {
   const Exec e = exec_of(p);
-  for (const Launch& l : iteration_sequence(r, p->sched_obj)) enqueue(e, l, s);
+  for (const Launch& l : sequence_of(e, r, p->sched_obj)) enqueue(e, l, s);
   HIPCHK(hipGetLastError());
   return FREDOPT_OK;
 }
@@ -954,7 +962,7 @@ fredopt_status capture_iteration(const Exec& e, int r, bool obj, hipStream_t cap
                                  hipGraphExec_t* graph) {
   hipGraph_t g = nullptr;
   HIPCHK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
-  for (const Launch& l : iteration_sequence(r, obj)) enqueue(e, l, cap);
+  for (const Launch& l : sequence_of(e, r, obj)) enqueue(e, l, cap);
   const hipError_t le = hipGetLastError();
   const hipError_t ce = hipStreamEndCapture(cap, &g);
   if (le != hipSuccess || ce != hipSuccess) {
@@ -1619,7 +1627,7 @@ fredopt_status fredopt_profile_kernels(fredopt_plan* p, const fredopt_problem* p
   if ((st = upload_table(p, s)) != FREDOPT_OK) return st;
   if ((st = upload_state(p, stt, s)) != FREDOPT_OK) return st;
   enqueue(p, Launch{FREDOPT_KERNEL_COL, kKindCol, kColYCopy}, s);
-  const std::vector<Launch> seq = iteration_sequence(q->reductions_n, p->sched_obj);
+  const std::vector<Launch> seq = sequence_of(exec_of(p), q->reductions_n, p->sched_obj);
   const size_t n = seq.size() * (size_t)n_iters;
   std::vector<hipEvent_t> ev(2 * n, nullptr);
   for (auto& e : ev) HIPCHK(hipEventCreate(&e));
@@ -2059,7 +2067,7 @@ fredopt_status fredopt_batch_solve(fredopt_batch* b, const fredopt_params* q,
       hipGraph_t g = nullptr;
       HIPCHK(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
       for (const SubBatch& sb : b->subs)
-        for (const Launch& l : iteration_sequence(r, sb.obj)) enqueue(sb.ex, l, b->cap);
+        for (const Launch& l : sequence_of(sb.ex, r, sb.obj)) enqueue(sb.ex, l, b->cap);
       const hipError_t le = hipGetLastError();
       const hipError_t ce = hipStreamEndCapture(b->cap, &g);
       if (le != hipSuccess || ce != hipSuccess) {

@@ -446,6 +446,49 @@ def test_empty_plans(fo, case):
         assert (k, s) == (4, -1) and np.array_equal(xr, p.x0.astype(np.float64))
 
 
+def test_nonfinite_halts_the_solve(fo):
+    """An iterate that overflows FP32 mid-solve (raw weights, lambda = 2, large
+    priorities: the sweep overshoots and grows until d = D x is infinite) sets the
+    device's non-finite flag; every later kernel of the call skips the plan, so a
+    300-iteration solve stops where the step-by-step run first reports the error,
+    with the same state and the same x."""
+    import torch
+    p = ph.tiny_problem(300, 30, 0.15, seed=21)
+    p.w_feas[:] = 50.0
+    q = _params(fo, lam=2.0, normalization=2, eta=1.0, iter_max=300)
+    print("non-finite halt: step by step", flush=True)
+    plan, prob, x0 = fo.load_phantom(p)
+    st1 = fo.new_state()
+    x1 = x0.clone()
+    for it in range(300):
+        try:
+            fo.superiorize_step(plan, prob, q, st1, x1)
+        except fo.FredoptError as e:
+            assert e.name == "E_NONFINITE"
+            break
+    else:
+        pytest.fail("the iterate did not overflow")
+    assert 10 < it < 299, it
+    print(f"non-finite halt: detected in outer iteration {it}; solve", flush=True)
+    st2 = fo.new_state()
+    x2 = x0.clone()
+    with pytest.raises(fo.FredoptError) as e:
+        fo.solve(plan, prob, q, st2, x2)
+    assert e.value.name == "E_NONFINITE"
+    torch.cuda.synchronize()
+    assert (st2.k, st2.s) == (st1.k, st1.s)
+    assert np.array_equal(_np(x2), _np(x1), equal_nan=True)
+    # a NaN in the input is caught by the first pass and nothing moves
+    x3 = x0.clone()
+    x3[5] = float("nan")
+    st3 = fo.new_state()
+    with pytest.raises(fo.FredoptError):
+        fo.solve(plan, prob, q, st3, x3)
+    assert st3.k == 0
+    xs = _np(x3)
+    assert np.isnan(xs[5]) and np.array_equal(np.delete(xs, 5), np.delete(_np(x0), 5))
+
+
 def test_load_errors(fo):
     import torch
     p = ph.tiny_problem(10, 4, 0.5, seed=3)
