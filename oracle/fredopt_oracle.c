@@ -18,7 +18,8 @@
  *   CDL_HI   a = c L_i,           <= cdl_hi_i
  *   LETD_HI  a = L_i - T_i D_i,   <= 0            (LETd_i <= T_i, linearised)
  * Objective terms (Eq. 2): OBJ_DOSE rows w_obj (Dhat - d)^2, OBJ_CDL rows
- * w_obj (cDLhat - c l)^2.
+ * w_obj (cDLhat - c l)^2 as printed, or, with the one-sided reading of the OAR
+ * term, w_obj (cDLhat - c l)^2 only where c l > cDLhat (0 below the target).
  *
  * Parity is pinned by the CPU tests (dense brute force, closed forms, invariants);
  * nothing here is compared against itself.
@@ -62,6 +63,7 @@ typedef struct {
   const double *dose_lo, *dose_hi, *cdl_lo, *cdl_hi, *letd_max;
   const double *w_feas, *w_obj, *dose_target, *cdl_target;
   double c;
+  int32_t objective;     /* 0: Eq. (2) as printed, 1: OAR term one-sided (above cDLhat) */
 } orc_problem;
 
 typedef struct {
@@ -69,6 +71,7 @@ typedef struct {
   int32_t reductions_n;
   int32_t normalization; /* 0: convex over all constraints, 1: convex over violated, 2: raw */
   int32_t line_search;   /* 0: literal cost comparison, 1: exact quadratic identity */
+  int32_t unit_direction; /* 0: perturb along grad chi^2 as printed, 1: grad / ||grad|| */
 } orc_params;
 
 typedef struct {
@@ -189,8 +192,12 @@ void orc_dose_let(const orc_mat *m, const double *x, double c, double *d, double
 
 /* ---------------------------------------------------------------- objective --- */
 
+/* Whether the OAR term of row i counts at residual f = cDLhat - c l: always as Eq. (2)
+ * is printed; only above the target (f < 0) in the one-sided reading. */
+static int oar_term_on(const orc_problem *p, double f) { return p->objective == 0 || f < 0.0; }
+
 /* Eq. (2): sum over PTV rows of w (Dhat - d)^2 plus over OAR rows of
- * w (cDLhat - c l)^2. */
+ * w (cDLhat - c l)^2 (one-sided reading: only rows with c l > cDLhat). */
 static double cost_from_dl(const orc_mat *m, const orc_problem *p, const double *d,
                            const double *l) {
   double s = 0.0;
@@ -202,7 +209,7 @@ static double cost_from_dl(const orc_mat *m, const orc_problem *p, const double 
     }
     if (k & K_OBJ_CDL) {
       double f = p->cdl_target[i] - p->c * l[i];
-      s += p->w_obj[i] * f * f;
+      if (oar_term_on(p, f)) s += p->w_obj[i] * f * f;
     }
   }
   return s;
@@ -217,7 +224,9 @@ double orc_cost(const orc_mat *m, const orc_problem *p, const double *x) {
   return s;
 }
 
-/* Gradient of Eq. (2): -2 D^T[w (Dhat - d)]_PTV - 2 c L^T[w (cDLhat - c l)]_OAR. */
+/* Gradient of Eq. (2): -2 D^T[w (Dhat - d)]_PTV - 2 c L^T[w (cDLhat - c l)]_OAR; in the
+ * one-sided reading the OAR rows below their target contribute nothing (the squared
+ * hinge is differentiable, with derivative 0 at the target). */
 void orc_gradient(const orc_mat *m, const orc_problem *p, const double *x, double *g) {
   int64_t R = m->R;
   double *d = (double *)malloc((size_t)(R ? R : 1) * sizeof(double));
@@ -228,7 +237,10 @@ void orc_gradient(const orc_mat *m, const orc_problem *p, const double *x, doubl
   for (int64_t i = 0; i < R; ++i) {
     unsigned k = p->kind[i];
     if (k & K_OBJ_DOSE) ud[i] = -2.0 * p->w_obj[i] * (p->dose_target[i] - d[i]);
-    if (k & K_OBJ_CDL) ul[i] = -2.0 * p->c * p->w_obj[i] * (p->cdl_target[i] - p->c * l[i]);
+    if (k & K_OBJ_CDL) {
+      double f = p->cdl_target[i] - p->c * l[i];
+      if (oar_term_on(p, f)) ul[i] = -2.0 * p->c * p->w_obj[i] * f;
+    }
   }
   orc_transposed(m, ud, ul, g);
   free(d); free(l); free(ud); free(ul);
@@ -432,10 +444,14 @@ void orc_ams_sequential(const orc_mat *m, const orc_problem *p, double lambda,
  *     g = grad chi^2(y); stop perturbing if g = 0
  *     s = s + 1, beta = alpha^s, until chi^2(y - beta g) < chi^2(y); y = y - beta g
  *   x = AMS(y) with weights eta^k w, k = k + 1
- * line_search 0 evaluates chi^2 with full products for every trial (literal);
- * line_search 1 uses chi^2(y - beta g) - chi^2(y) = -beta ||g||^2 + beta^2 Q with
- * Q = sum_PTV w (Dg)^2 + sum_OAR w c^2 (Lg)^2, so a trial is accepted iff
- * beta Q < ||g||^2.  The AMS step is the simultaneous form. */
+ * The perturbation direction v is g as printed, or g / ||g|| (unit_direction, the
+ * normalised reading).  line_search 0 evaluates chi^2 with full products for every
+ * trial (literal); line_search 1 uses chi^2(y - beta v) - chi^2(y) =
+ * -beta <g, v> + beta^2 Q(v) with Q(v) = sum_PTV w (Dv)^2 + sum_OAR w c^2 (Lv)^2, so a
+ * trial is accepted iff beta Q(v) < <g, v>.  That identity needs the OAR term as
+ * printed; with the one-sided reading chi^2 is only piecewise quadratic along v and
+ * the literal comparison is used whatever line_search says.  The AMS step is the
+ * simultaneous form. */
 void orc_sa_iteration(const orc_mat *m, const orc_problem *p, const orc_params *q,
                       int64_t *k_io, int64_t *s_io, double *x, orc_iter_info *info) {
   int64_t R = m->R, C = m->C;
@@ -455,8 +471,16 @@ void orc_sa_iteration(const orc_mat *m, const orc_problem *p, const orc_params *
     for (int64_t j = 0; j < C; ++j) G += g[j] * g[j];
     info->grad_sq = G;
     if (!(G > 0.0)) break;
+    /* v (stored in g) and the slope <grad chi^2, v> */
+    double slope = G;
+    if (q->unit_direction) {
+      double nrm = sqrt(G);
+      for (int64_t j = 0; j < C; ++j) g[j] = g[j] / nrm;
+      slope = nrm;
+    }
+    const int closed = q->line_search == 1 && p->objective == 0;
     double Q = 0.0;
-    if (q->line_search == 1) {
+    if (closed) {
       orc_forward(m, g, dg, lg);
       for (int64_t i = 0; i < R; ++i) {
         if (p->kind[i] & K_OBJ_DOSE) Q += p->w_obj[i] * dg[i] * dg[i];
@@ -471,8 +495,8 @@ void orc_sa_iteration(const orc_mat *m, const orc_problem *p, const orc_params *
       double beta = pow(q->alpha, (double)s);
       info->n_trials++;
       if (beta < BETA_FLOOR) { info->capped = 1; break; }
-      if (q->line_search == 1) {
-        if (beta * Q < G) { accepted = 1; info->beta_last = beta; }
+      if (closed) {
+        if (beta * Q < slope) { accepted = 1; info->beta_last = beta; }
       } else {
         for (int64_t j = 0; j < C; ++j) yn[j] = y[j] - beta * g[j];
         double cn = orc_cost(m, p, yn);
@@ -483,7 +507,7 @@ void orc_sa_iteration(const orc_mat *m, const orc_problem *p, const orc_params *
     if (!accepted) { s = s_start; break; }
     for (int64_t j = 0; j < C; ++j) y[j] = y[j] - info->beta_last * g[j];
     info->n_accepted++;
-    if (q->line_search == 1) cost_y = orc_cost(m, p, y);
+    if (closed) cost_y = orc_cost(m, p, y);
   }
   info->cost_after_perturb = cost_y;
   double ws = pow(q->eta, (double)k);

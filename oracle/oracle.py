@@ -50,13 +50,13 @@ class _Problem(ct.Structure):
                 ("cdl_lo", ct.c_void_p), ("cdl_hi", ct.c_void_p), ("letd_max", ct.c_void_p),
                 ("w_feas", ct.c_void_p), ("w_obj", ct.c_void_p),
                 ("dose_target", ct.c_void_p), ("cdl_target", ct.c_void_p),
-                ("c", ct.c_double)]
+                ("c", ct.c_double), ("objective", ct.c_int32)]
 
 
 class _Params(ct.Structure):
     _fields_ = [("lambda_", ct.c_double), ("alpha", ct.c_double), ("eta", ct.c_double),
                 ("reductions_n", ct.c_int32), ("normalization", ct.c_int32),
-                ("line_search", ct.c_int32)]
+                ("line_search", ct.c_int32), ("unit_direction", ct.c_int32)]
 
 
 class _Info(ct.Structure):
@@ -75,6 +75,7 @@ class OracleParams:
     reductions_n: int = 1
     normalization: int = 0     # 0 convex over all, 1 convex over violated, 2 raw
     line_search: int = 1       # 0 literal (Fig. 3), 1 exact quadratic identity
+    unit_direction: int = 0    # 0 perturb along the gradient, 1 along gradient / norm
 
 
 _lib = None
@@ -139,10 +140,13 @@ def _f64(a) -> np.ndarray:
 class Oracle:
     """FP64 oracle bound to one pair of influence matrices and one problem.
 
-    ``values`` may override D and L (e.g. dequantised reduced-precision values)."""
+    ``values`` may override D and L (e.g. dequantised reduced-precision values).
+    ``objective``: 0 Eq. (2) as printed, 1 the OAR term one-sided (counted only where
+    cDL exceeds its target)."""
 
     def __init__(self, ph, d_val: Optional[np.ndarray] = None,
-                 l_val: Optional[np.ndarray] = None, problem: Optional[Dict] = None):
+                 l_val: Optional[np.ndarray] = None, problem: Optional[Dict] = None,
+                 objective: int = 0):
         lib = _load()
         self.R, self.C = int(ph.n_rows), int(ph.n_cols)
         self._row_ptr = np.ascontiguousarray(ph.row_ptr, dtype=np.int64)
@@ -160,7 +164,8 @@ class Oracle:
         for k in ("dose_lo", "dose_hi", "cdl_lo", "cdl_hi", "letd_max", "w_feas", "w_obj",
                   "dose_target", "cdl_target"):
             self._prob_arrays[k] = _f64(pa[k])
-        self._prob = _Problem(**{k: _p(v) for k, v in self._prob_arrays.items()}, c=self.c)
+        self._prob = _Problem(**{k: _p(v) for k, v in self._prob_arrays.items()}, c=self.c,
+                              objective=int(objective))
 
     def __del__(self):
         try:
@@ -238,7 +243,8 @@ class Oracle:
     @staticmethod
     def _params(q: OracleParams) -> _Params:
         return _Params(lambda_=q.lam, alpha=q.alpha, eta=q.eta, reductions_n=q.reductions_n,
-                       normalization=q.normalization, line_search=q.line_search)
+                       normalization=q.normalization, line_search=q.line_search,
+                       unit_direction=q.unit_direction)
 
     def sa_iteration(self, x, k: int, s: int, q: OracleParams):
         x = _f64(x).copy()

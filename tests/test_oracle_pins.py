@@ -436,3 +436,113 @@ def test_metrics_helpers():
     assert metrics.d_percent(np.array([7.0]), 0.95) == 7.0
     assert metrics.mean_letd(np.array([1.0, 0.0, 2.0]), np.array([2.0, 9.0, 4.0])) == 3.0
     assert ph.percentile_nearest_rank(np.arange(1, 11), 0.7) == 7.0
+
+
+# --- the one-sided OAR term (reading Q15 of Eq. 2) and the unit perturbation
+# direction (reading Q11 of Fig. 3) ----------------------------------------------
+
+def test_one_sided_objective_hand_worked():
+    """2 rows x 2 beamlets, worked by hand from Eq. (2).  D = diag(1, 2),
+    L = diag(1, 3), c = 0.5, x = (1, 1): d = (1, 2), l = (1, 3), c l_1 = 1.5.
+    Row 0 is PTV (target 2, weight 1): (2 - 1)^2 = 1, gradient -2 (2 - 1) D_0 = (-2, 0).
+    Row 1 is OAR (weight 2).  Target 1: c l_1 is above it, f = 1 - 1.5 = -0.5 counts in
+    both readings: 2 * 0.25 = 0.5, gradient -2 c w f L_1 = -2 * 0.5 * 2 * (-0.5) * (0, 3)
+    = (0, 3).  Target 2: c l_1 is below it, f = 0.5: as printed 0.5 and (0, -3); one-sided
+    0 and (0, 0)."""
+    D = np.array([[1.0, 0.0], [0.0, 2.0]])
+    L = np.array([[1.0, 0.0], [0.0, 3.0]])
+    x = np.array([1.0, 1.0])
+    for cdl_t, two, one, g_two, g_one in (
+            (1.0, 1.5, 1.5, (-2.0, 3.0), (-2.0, 3.0)),
+            (2.0, 1.5, 1.0, (-2.0, -3.0), (-2.0, 0.0))):
+        p = from_dense(D, L, c=0.5, kind=[ph.OBJ_DOSE, ph.OBJ_CDL], w_obj=[1.0, 2.0],
+                       dose_target=[2.0, 0.0], cdl_target=[0.0, cdl_t])
+        o2, o1 = Oracle(p, objective=0), Oracle(p, objective=1)
+        assert o2.cost(x) == two and o1.cost(x) == one
+        np.testing.assert_array_equal(o2.gradient(x), g_two)
+        np.testing.assert_array_equal(o1.gradient(x), g_one)
+
+
+@pytest.mark.parametrize("seed", [61, 62, 63])
+def test_one_sided_cost_and_gradient_dense(seed):
+    """Against dense brute force with the OAR hinge, at points where some OAR rows
+    are above their target and some below; gradient against central differences."""
+    p = ph.tiny_problem(64, 12, 0.3, seed=seed)
+    D, L = dense(p)
+    w = p.w_obj.astype(np.float64)
+    ptv = (p.kind & ph.OBJ_DOSE) > 0
+    oar = (p.kind & ph.OBJ_CDL) > 0
+    x = _x(12, seed)
+    d, l = D @ x, L @ x
+    # OAR targets at the median of c l: about half the rows above, half below
+    p.cdl_target[oar] = np.float32(np.median(p.c * l[oar]))
+    o = Oracle(p, objective=1)
+    f = p.cdl_target - p.c * l
+    above = oar & (f < 0)
+    assert above.any() and (oar & (f > 0)).any()
+    chi = np.sum(w[ptv] * (p.dose_target[ptv] - d[ptv]) ** 2) + np.sum(w[above] * f[above] ** 2)
+    assert o.cost(x) == pytest.approx(chi, rel=1e-13)
+    g = o.gradient(x)
+    h = 1e-6
+    for j in range(12):
+        e = np.zeros(12)
+        e[j] = h
+        fd = (o.cost(x + e) - o.cost(x - e)) / (2 * h)
+        assert g[j] == pytest.approx(fd, rel=1e-6, abs=1e-9)
+    # every OAR row above its target: the one-sided cost is the printed one
+    p_all = ph.tiny_problem(64, 12, 0.3, seed=seed)
+    p_all.cdl_target[:] = -1.0
+    assert Oracle(p_all, objective=1).cost(x) == Oracle(p_all, objective=0).cost(x)
+
+
+def _objective_only(seed, R=48, C=12):
+    p = ph.tiny_problem(R, C, 0.3, seed=seed)
+    p.kind = (p.kind & (ph.OBJ_DOSE | ph.OBJ_CDL)).astype(p.kind.dtype)
+    return p
+
+
+@pytest.mark.parametrize("seed", [71, 72])
+def test_unit_direction_moves_by_beta(seed):
+    """With the perturbation along g / ||g|| and no constraint rows (the sweep is then
+    the identity on a non-negative point), one outer iteration moves x by exactly the
+    accepted beta in Euclidean norm; literal and closed-form searches pick the same s."""
+    p = _objective_only(seed)
+    o = Oracle(p)
+    x = p.x0.astype(np.float64) + 5.0
+    k, s = 0, -1
+    for _ in range(4):
+        xa, ka, sa, ia = o.sa_iteration(x, k, s, OracleParams(reductions_n=1, line_search=0,
+                                                               unit_direction=1, alpha=0.9))
+        xb, kb, sb, ib = o.sa_iteration(x, k, s, OracleParams(reductions_n=1, line_search=1,
+                                                               unit_direction=1, alpha=0.9))
+        assert (ka, sa) == (kb, sb) and ib["n_accepted"] == 1
+        assert np.all(xb > 0)
+        assert np.linalg.norm(xb - x) == pytest.approx(ib["beta_last"], rel=1e-12)
+        g = o.gradient(x)
+        np.testing.assert_allclose(xb, x - ib["beta_last"] * g / np.linalg.norm(g),
+                                   rtol=1e-13, atol=1e-15)
+        x, k, s = xb, kb, sb
+
+
+@pytest.mark.parametrize("unit", [0, 1])
+@pytest.mark.parametrize("seed", [81, 82])
+def test_one_sided_step_is_the_first_decrease(seed, unit):
+    """Fig. 3's search with the one-sided objective: the accepted s is the first
+    exponent above the previous one whose step strictly lowers the cost, checked by
+    evaluating the (dense-pinned) cost at every exponent in between."""
+    p = _objective_only(seed, R=64)
+    o = Oracle(p, objective=1)
+    x = p.x0.astype(np.float64) + 1.0
+    k, s = 0, -1
+    for _ in range(5):
+        g = o.gradient(x)
+        v = g / np.linalg.norm(g) if unit else g
+        c0 = o.cost(x)
+        xn, kn, sn, info = o.sa_iteration(x, k, s, OracleParams(reductions_n=1, alpha=0.8,
+                                                                 unit_direction=unit))
+        assert info["n_accepted"] == 1 and sn > s
+        for t in range(s + 1, sn):
+            assert o.cost(x - 0.8 ** t * v) >= c0
+        assert o.cost(x - 0.8 ** sn * v) < c0
+        assert info["cost_after_perturb"] < info["cost_before"]
+        x, k, s = xn, kn, sn
