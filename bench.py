@@ -130,11 +130,13 @@ def cpu_baseline(p, q, n_iters: int, n_literal: int, n_single: int):
     for the feasibility sweep."""
     from oracle import Oracle, OracleParams, num_threads, set_threads
     t0 = time.perf_counter()
-    o = Oracle(p)
+    o = Oracle(p, objective=q.objective)
     t_load = time.perf_counter() - t0
     cores = num_threads()
+    # (with the one-sided objective the oracle's closed form falls back to the literal
+    # comparison, as the identity it rests on does not hold)
     base = dict(lam=q.lam, alpha=q.alpha, eta=q.eta, reductions_n=q.reductions_n,
-                normalization=q.normalization)
+                normalization=q.normalization, unit_direction=q.unit_direction)
     r = q.reductions_n
     dt, state, _ = _oracle_run(o, p, OracleParams(line_search=1, **base), n_iters)
     variants = []
@@ -342,6 +344,10 @@ def main():
                     help="matrix values in FP32, FP16 or BF16 (per-beamlet FP32 scale); the "
                          "i16 forms also keep column indices in 16 bits")
     ap.add_argument("--reductions", type=int, default=1)
+    ap.add_argument("--objective", type=int, default=0, choices=[0, 1],
+                    help="0 Eq. (2) as printed, 1 the OAR term one-sided (device step search)")
+    ap.add_argument("--unit-direction", type=int, default=0, choices=[0, 1],
+                    help="1 perturbs along the normalised gradient")
     ap.add_argument("--reserve", type=int, default=None,
                     help="gradient reserve of each plan in %% of its CSC (batch and serve "
                          "workloads: 100, so that every plan has the objective-row view; "
@@ -402,7 +408,8 @@ def main():
         log(f"autotuned: lanes {info['lanes_per_row']} chunk {info['tr_chunk']}")
     info = plan.info()
 
-    q = fredopt.SolverParams(reductions_n=args.reductions, iter_max=args.warmup)
+    q = fredopt.SolverParams(reductions_n=args.reductions, iter_max=args.warmup,
+                             objective=args.objective, unit_direction=args.unit_direction)
     x = x0.clone()
     st = fredopt.new_state()
     if args.warmup:
@@ -501,7 +508,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {p.name}", "rows": R, "cols": C, "nnz": nnz,
                    "storage": args.storage, "reductions_n": args.reductions,
-                   "normalization": "convex_all", "lanes_per_row": info["lanes_per_row"],
+                   "normalization": "convex_all",
+                   "objective": "one-sided OAR" if args.objective else "Eq. (2) as printed",
+                   "unit_direction": args.unit_direction,
+                   "lanes_per_row": info["lanes_per_row"],
                    "tr_chunk": info["tr_chunk"]},
         "hbm_gbps_iteration": round(b_iter * its / 1e9, 1),
         "hbm_frac_iteration": round(b_iter * its / 1e9 / HBM_PEAK_GBPS, 4),
@@ -518,7 +528,8 @@ def main():
     # window above samples iterations warmup+1 .. warmup+steps)
     n_full = args.full_solve if args.full_solve is not None else int(p.meta.get("iterations", 0))
     if n_full > 0:
-        qf = fredopt.SolverParams(reductions_n=args.reductions, iter_max=n_full)
+        qf = fredopt.SolverParams(reductions_n=args.reductions, iter_max=n_full,
+                                  objective=args.objective, unit_direction=args.unit_direction)
         xf = x0.clone()
         sf = fredopt.new_state()
         torch.cuda.synchronize()

@@ -130,16 +130,30 @@ typedef struct {
   double c; /* um/keV, > 0; 0.04 in the paper (Section 2.4) */
 } fredopt_problem;
 
+/* Objective of the perturbations (Eq. 2).  PRINTED: the OAR term
+ * w_obj (cdl_target - c l)^2 as the equation prints it (two-sided: it also pulls cDL
+ * up towards its target).  ONE_SIDED: the OAR term counts only where
+ * c l > cdl_target, so it only pushes cDL down; the cost is then piecewise quadratic
+ * along a perturbation and the step search evaluates it on the device for a window
+ * of candidate exponents per pass (Fig. 3's trials in order) instead of the closed
+ * form.  The PTV term is two-sided in both. */
+#define FREDOPT_OBJECTIVE_PRINTED 0
+#define FREDOPT_OBJECTIVE_ONE_SIDED 1
+
 /* Parameters of Figs. 2-3: relaxation lambda in (0, 2] (Fig. 2 caption), step base
  * alpha in (0, 1) and weight decay eta in (0, 1] (text after Fig. 3; eta = 1 is
  * accepted for testing), reductions_n >= 0 perturbations per outer iteration
- * (0 = feasibility seeking only), iter_max outer iterations for fredopt_solve. */
+ * (0 = feasibility seeking only), iter_max outer iterations for fredopt_solve.
+ * unit_direction 0 perturbs along grad chi^2 as Fig. 3 prints it, 1 along
+ * grad chi^2 / ||grad chi^2|| (the step then moves the point by exactly beta). */
 typedef struct {
   double lambda, alpha, eta;
   int32_t reductions_n;
   int32_t iter_max;
-  int32_t normalization; /* FREDOPT_NORM_* */
-  int32_t reserved;      /* must be 0 */
+  int32_t normalization;  /* FREDOPT_NORM_* */
+  int32_t objective;      /* FREDOPT_OBJECTIVE_* */
+  int32_t unit_direction; /* 0 or 1 */
+  int32_t reserved;       /* must be 0 */
 } fredopt_params;
 
 /* Solver state of Fig. 3: outer counter k (weights eta^k w) and the global step
@@ -148,7 +162,8 @@ typedef struct {
 typedef struct {
   int64_t k, s;
   int64_t n_violated;      /* violated constraints at the AMS input point       */
-  double beta;             /* last accepted step (0 if none)                    */
+  double beta;             /* last accepted step alpha^s (0 if none); the point moves
+                              by beta times the direction (g, or g / ||g||)      */
   double cost;             /* Eq. (2) at the start of the last outer iteration  */
   double cost_perturbed;   /* Eq. (2) at the perturbed point fed to AMS         */
   double proximity;        /* 1/2 sum (w_i / W_all) v_i^2 / ||a_i||^2 at that point */
@@ -277,7 +292,8 @@ fredopt_status fredopt_get_plan_info(const fredopt_plan *p, fredopt_plan_info *i
 #define FREDOPT_KERNEL_ACTIVE_LIST 8 /* list of rows with a projection coefficient  */
 #define FREDOPT_KERNEL_SCATTER 9   /* transposed product over those rows only       */
 #define FREDOPT_KERNEL_SCATTER_SUM 10 /* its per-workgroup sums; projection update  */
-#define FREDOPT_NUM_KERNELS 11
+#define FREDOPT_KERNEL_LINE_SEARCH 11 /* step search of the one-sided objective   */
+#define FREDOPT_NUM_KERNELS 12
 
 /* Runs n_iters outer iterations (as fredopt_superiorize_step would) launching each
  * kernel separately with HIP events around it on `stream`, and writes the mean

@@ -44,6 +44,7 @@ enum : unsigned {
   kDoseLo = 0x01u, kDoseHi = 0x02u, kCdlLo = 0x04u, kCdlHi = 0x08u, kLetdHi = 0x10u,
   kObjDose = 0x20u, kObjCdl = 0x40u, kConstraintBits = 0x1Fu
 };
+constexpr int kSearchWindow = 16;      // candidate exponents per pass of the step search
 
 // stored value type of a plan's matrices; kF16I / kBF16I also keep the column
 // indices of the sliced-ELL copy in 16 bits (the column-major copy keeps int32 rows)
@@ -83,11 +84,14 @@ struct DevParams {
   double lambda, alpha, eta, c;
   double ws_fixed;           // >= 0: weight scale used instead of eta^k
   int32_t normalization, reductions_n;
+  int32_t objective;         // 0: Eq. (2) as printed, 1: one-sided OAR term
+  int32_t unit_dir;          // 1: perturb along g / ||g||
 };
 
 struct DevState {
   int64_t k, s, n_violated, n_degenerate;
   double beta, cost, cost_y, proximity, G, Q, w_all, w_viol, scale, ws;
+  double step;                // multiplier of g in the moves: beta, or beta / ||g||
   int32_t pstop, capped, nonfinite, pad;
   int32_t n_active;           // rows with a non-zero projection coefficient
   int32_t proj_scatter;       // 1: the projection uses the active-row scatter
@@ -175,6 +179,12 @@ struct DevPlan {
   float* lg;
   float2* coef;               // per-position coefficients (dose part, LET part)
   float* g;
+  // d, l at y and D g, L g of the objective-row view's rows (its positions), for the
+  // step search of the one-sided objective
+  float* od;
+  float* ol;
+  float* odg;
+  float* olg;
   float* out_dose;
   float* out_letd;
   float* out_cdl;

@@ -168,6 +168,12 @@ __device__ __forceinline__ ObjArrays obj_arrays(const DevPlan* P) {
   else return ObjArrays{P->kind, P->wo, P->dt, P->ct, P->gcoef};
 }
 
+// Whether the OAR term of Eq. (2) counts at residual f = cDLhat - c l: always as
+// printed; only above the target (f < 0) with the one-sided objective.
+__device__ __forceinline__ bool oar_on(const DevPlan* P, double f) {
+  return P->prm.objective == 0 || f < 0.0;
+}
+
 // Eq. (2) terms of the row with data at position r (kinds k) at (d, l): adds the
 // value to *chi and stores the gradient coefficients (-2 w (Dhat - d),
 // -2 c w (cDLhat - c l)) at index rc (the row).
@@ -183,8 +189,10 @@ __device__ __forceinline__ void objective_row(const DevPlan* P, const ObjArrays&
     }
     if (k & kObjCdl) {
       const double f = (double)gconst(A.ct)[r] - c * (double)l;
-      *chi += w * f * f;
-      uL = -2.0 * c * w * f;
+      if (oar_on(P, f)) {
+        *chi += w * f * f;
+        uL = -2.0 * c * w * f;
+      }
     }
   }
   ((FO_GLOBAL v2f*)(A.coef))[rc] = v2f{(float)uD, (float)uL};
@@ -201,7 +209,7 @@ __device__ __forceinline__ double objective_value(const DevPlan* P, int r, unsig
     }
     if (k & kObjCdl) {
       const double f = (double)gconst(P->ct)[r] - c * (double)l;
-      s += w * f * f;
+      if (oar_on(P, f)) s += w * f * f;
     }
   }
   return s;
@@ -302,11 +310,14 @@ __device__ __forceinline__ void finalize_residuals(const DevPlan* P, const doubl
   if (P->prm.ws_fixed < 0.0) st->k += 1;
 }
 
-// Step decision of Fig. 3 on the device.  Along g the cost is quadratic:
-// chi^2(y - beta g) - chi^2(y) = -beta G + beta^2 Q, so a trial beta = alpha^s
-// strictly lowers it iff beta Q < G.  s is the smallest integer above the previous
-// s with that property (the inner loop of Fig. 3 tries s+1, s+2, ...).  A search
-// that would need alpha^s < 1e-300 skips the perturbation and leaves s unchanged.
+// Step decision of Fig. 3 on the device.  Along the direction v (g, or g / ||g||
+// with unit_dir) the cost is quadratic: chi^2(y - beta v) - chi^2(y) =
+// -beta slope + beta^2 Qv with slope = <g, v> (G = ||g||^2, or sqrt(G)) and Qv = Q(v)
+// (Q, or Q / G), so a trial beta = alpha^s strictly lowers it iff beta Qv < slope.  s is
+// the smallest integer above the previous s with that property (the inner loop of
+// Fig. 3 tries s+1, s+2, ...).  A search that would need alpha^s < 1e-300 skips the
+// perturbation and leaves s unchanged.  The moves take step = beta times the factor
+// that turns g into v.
 __device__ __forceinline__ void decide_step(const DevPlan* P, double G, double Q) {
   DevState* st = P->st;
   st->G = G;
@@ -314,18 +325,23 @@ __device__ __forceinline__ void decide_step(const DevPlan* P, double G, double Q
   if (!isfinite(G) || !isfinite(Q)) st->nonfinite = 1;
   if (st->pstop || !(G > 0.0) || !isfinite(G) || !isfinite(Q)) {
     st->beta = 0.0;
+    st->step = 0.0;
     st->pstop = 1;
     return;
   }
+  const bool unit = P->prm.unit_dir != 0;
+  const double nrm = sqrt(G);
+  const double slope = unit ? nrm : G, Qv = unit ? Q / G : Q;
   const double a = P->prm.alpha;
   const int64_t s0 = st->s;
-  auto ok = [&](int64_t s) { return pow(a, (double)s) * Q < G; };
+  auto ok = [&](int64_t s) { return pow(a, (double)s) * Qv < slope; };
   int64_t s = s0 + 1;
   if (!ok(s)) {
-    // here Q > 0: a^s Q < G  <=>  s > log(G / Q) / log(a)
-    const double est = log(G / Q) / log(a);
+    // here Qv > 0: a^s Qv < slope  <=>  s > log(slope / Qv) / log(a)
+    const double est = log(slope / Qv) / log(a);
     if (!(est < 1e6)) {
       st->beta = 0.0;
+      st->step = 0.0;
       st->pstop = 1;
       st->capped = 1;
       return;
@@ -339,12 +355,26 @@ __device__ __forceinline__ void decide_step(const DevPlan* P, double G, double Q
   const double beta = pow(a, (double)s);
   if (beta < kBetaFloor) {
     st->beta = 0.0;
+    st->step = 0.0;
     st->pstop = 1;
     st->capped = 1;
     return;
   }
   st->s = s;
   st->beta = beta;
+  st->step = unit ? beta / nrm : beta;
+}
+
+// The same inputs when the one-sided objective leaves the decision to the search
+// kernel: records G and Q and stops the perturbations if there is no descent.
+__device__ __forceinline__ void prepare_search(const DevPlan* P, double G, double Q) {
+  DevState* st = P->st;
+  st->G = G;
+  st->Q = Q;
+  st->beta = 0.0;
+  st->step = 0.0;
+  if (!isfinite(G) || !isfinite(Q)) st->nonfinite = 1;
+  if (st->pstop || !(G > 0.0) || !isfinite(G) || !isfinite(Q)) st->pstop = 1;
 }
 
 // -------------------------------------------------------------- forward pass ---
@@ -450,6 +480,9 @@ __device__ __forceinline__ void forward_slice(const DevPlan* __restrict__ P, int
       if constexpr (!SUB) {  // the all-row pass keeps d and l for the moves
         gmut(P->d)[sp] = ad;
         gmut(P->l)[sp] = al;
+      } else {               // the objective-row view keeps them for the step search
+        gmut(P->od)[sp] = ad;
+        gmut(P->ol)[sp] = al;
       }
       if (crow >= 0) objective_row(P, A, sp, crow, kind, ad, al, &acc[0]);
       if (!finite2(ad, al)) acc[5] += 1.0;
@@ -457,6 +490,9 @@ __device__ __forceinline__ void forward_slice(const DevPlan* __restrict__ P, int
       if constexpr (!SUB) {
         gmut(P->dg)[sp] = ad;
         gmut(P->lg)[sp] = al;
+      } else {
+        gmut(P->odg)[sp] = ad;
+        gmut(P->olg)[sp] = al;
       }
       if (kind & (kObjDose | kObjCdl)) {
         const double wo = gconst(A.wo)[sp], c = P->prm.c;
@@ -558,7 +594,7 @@ __global__ __launch_bounds__(kFwdBlock) void k_forward(const DevPlan* __restrict
       vec = vsel == kVecG ? P->g : (vsel == kVecX ? P->x : P->y);
       const bool move = vsel == kVecYMove;
       gmv = move ? P->g : nullptr;
-      beta = move ? P->st->beta : 0.0;
+      beta = move ? P->st->step : 0.0;
       use_lds = P->C <= (int64_t)lds_floats;
       if (use_lds) {
         const FO_GLOBAL float* gv = gconst(vec);
@@ -601,7 +637,7 @@ __global__ __launch_bounds__(kBlock) void k_rows(const DevPlan* __restrict__ pla
   const DevPlan* __restrict__ P = plans + w.plan;
   if (halted(P)) return;
   const int tid = threadIdx.x;
-  const double beta = P->st->beta;
+  const double beta = P->st->step;  // the accepted move along g
   double acc[kNPart];
 #pragma unroll
   for (int k = 0; k < kNPart; ++k) acc[k] = 0.0;
@@ -866,10 +902,10 @@ __device__ __forceinline__ void project_column(const DevPlan* __restrict__ P, in
   constexpr bool fromy = MODE == kColProjY || MODE == kColProjYMove;
   if (P->cscale) t *= gconst(P->cscale)[j];
   double y = fromy ? gconst(P->y)[j] : gconst(P->x)[j];
-  if constexpr (MODE == kColProjMove) y -= P->st->beta * (double)gconst(P->g)[j];
+  if constexpr (MODE == kColProjMove) y -= P->st->step * (double)gconst(P->g)[j];
   // the perturbed point y - beta g, rounded to FP32 as the residual pass staged it
   if constexpr (MODE == kColProjYMove)
-    y = (double)(float)(y - P->st->beta * (double)gconst(P->g)[j]);
+    y = (double)(float)(y - P->st->step * (double)gconst(P->g)[j]);
   const double xn = y - P->st->scale * (double)t;
   const float xf = xn > 0.0 ? (float)xn : 0.f;
   gmut(P->x)[j] = xf;
@@ -947,7 +983,7 @@ __global__ __launch_bounds__(kBlock) void k_tcol(const DevPlan* __restrict__ pla
     if constexpr (MODE == kColYCopy) {
       gmut(P->y)[j] = gconst(P->x)[j];
     } else if constexpr (MODE == kColYMove) {
-      const double b = P->st->beta;
+      const double b = P->st->step;
       gmut(P->y)[j] = (float)((double)gconst(P->y)[j] - b * (double)gconst(P->g)[j]);
     } else if (grad || !P->st->proj_scatter) {  // else the scatter sum updated x
       float t = 0.f;
@@ -957,7 +993,7 @@ __global__ __launch_bounds__(kBlock) void k_tcol(const DevPlan* __restrict__ pla
       if constexpr (grad) {
         if (P->cscale) t *= gconst(P->cscale)[j];
         if constexpr (MODE == kColGradMove) {
-          const double b = P->st->beta;
+          const double b = P->st->step;
           gmut(P->x)[j] = (float)((double)gconst(P->x)[j] - b * (double)gconst(P->g)[j]);
         }
         gmut(P->g)[j] = t;
@@ -1047,10 +1083,14 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(const DevPlan* __restric
         st->pstop = 0;
         st->capped = 0;
         st->beta = 0.0;
+        st->step = 0.0;
         if (a[5] > 0.0) st->nonfinite = 1;
       }
       if (b[5] > 0.0) st->nonfinite = 1;
-      decide_step(P, G, b[0]);
+      if (P->prm.objective == 0)
+        decide_step(P, G, b[0]);
+      else
+        prepare_search(P, G, b[0]);
     }
   } else if constexpr (MODE == kFinMoveObj) {
     sum_slots(P->rpart, P->n_row_items, a, 0x21u, shs);
@@ -1096,6 +1136,112 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(const DevPlan* __restric
       P->st->proj_scatter = scatter ? 1 : 0;
       P->st->fx_scale = B > 0.0 ? 0x1p61 / B : 1.0;
     }
+  }
+}
+
+// Step search of Fig. 3 for the one-sided objective.  Along v the cost is only
+// piecewise quadratic (an OAR term switches on or off where c l crosses its target),
+// so the closed form does not apply: each pass evaluates
+// chi^2(y - beta v) - chi^2(y) in FP64 for kSearchWindow candidate exponents
+// s0 + 1, s0 + 2, ... from the d, l, D g, L g the view's passes stored, and the first
+// candidate that strictly lowers the cost is taken (Fig. 3's trials, in order); the
+// next window follows while none does and alpha^s >= 1e-300.  The row terms are summed
+// in a fixed order (thread strides, wave sums, waves in order).  One workgroup per
+// plan; SUB: the objective-row view.
+template <int SUB>
+__global__ __launch_bounds__(kFinBlock) void k_linesearch(const DevPlan* __restrict__ plans) {
+  __shared__ double sh[kFinWaves][kSearchWindow];
+  __shared__ double sbeta[kSearchWindow];
+  __shared__ int s_pick;
+  const DevPlan* __restrict__ P = plans + blockIdx.x;
+  if (halted(P)) return;
+  DevState* st = P->st;
+  if (st->pstop) return;  // no descent direction this outer iteration
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+  const double vs = P->prm.unit_dir ? 1.0 / sqrt(st->G) : 1.0;  // v = vs g
+  const double c = P->prm.c, a = P->prm.alpha;
+  const SellView& V = SUB ? P->osell : P->sell;
+  const int n = V.n_slices << (6 - V.lpr_log2);
+  const FO_GLOBAL uint16_t* kind = gconst(SUB ? P->okind : P->kind);
+  const FO_GLOBAL float* wo = gconst(SUB ? P->owo : P->wo);
+  const FO_GLOBAL float* dt = gconst(SUB ? P->odt : P->dt);
+  const FO_GLOBAL float* ct = gconst(SUB ? P->oct : P->ct);
+  const FO_GLOBAL float* dd = gconst(SUB ? P->od : P->d);
+  const FO_GLOBAL float* ll = gconst(SUB ? P->ol : P->l);
+  const FO_GLOBAL float* dg = gconst(SUB ? P->odg : P->dg);
+  const FO_GLOBAL float* lg = gconst(SUB ? P->olg : P->lg);
+  const int64_t s0 = st->s;
+  for (int64_t base = s0 + 1;; base += kSearchWindow) {
+    if (tid < kSearchWindow) sbeta[tid] = pow(a, (double)(base + tid));
+    __syncthreads();
+    double bk[kSearchWindow], acc[kSearchWindow];
+#pragma unroll
+    for (int j = 0; j < kSearchWindow; ++j) {
+      bk[j] = sbeta[j];
+      acc[j] = 0.0;
+    }
+    for (int i = tid; i < n; i += kFinBlock) {
+      const unsigned k = kind[i];
+      if (!(k & (kObjDose | kObjCdl))) continue;
+      const double w = wo[i];
+      if (k & kObjDose) {  // w (e0 + beta Dv)^2 - w e0^2, e0 = Dhat - d
+        const double e0 = (double)dt[i] - (double)dd[i], dv = (double)dg[i] * vs;
+#pragma unroll
+        for (int j = 0; j < kSearchWindow; ++j) acc[j] += w * (bk[j] * dv) * (2.0 * e0 + bk[j] * dv);
+      }
+      if (k & kObjCdl) {   // w min(0, f0 + beta c Lv)^2 - w min(0, f0)^2
+        const double f0 = (double)ct[i] - c * (double)ll[i], lv = c * (double)lg[i] * vs;
+        const double t0 = f0 < 0.0 ? f0 * f0 : 0.0;
+#pragma unroll
+        for (int j = 0; j < kSearchWindow; ++j) {
+          const double fb = f0 + bk[j] * lv;
+          acc[j] += w * ((fb < 0.0 ? fb * fb : 0.0) - t0);
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kSearchWindow; ++j) acc[j] = wave_sum(acc[j]);
+    if (lane == 0) {
+#pragma unroll
+      for (int j = 0; j < kSearchWindow; ++j) sh[wave][j] = acc[j];
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int pick = -1;  // -1: none in this window, -2: beta below the floor first
+      for (int j = 0; j < kSearchWindow && pick == -1; ++j) {
+        if (bk[j] < kBetaFloor) {
+          pick = -2;
+          break;
+        }
+        double dchi = 0.0;
+        for (int v = 0; v < kFinWaves; ++v) dchi += sh[v][j];
+        if (!isfinite(dchi)) {
+          st->nonfinite = 1;
+          pick = -2;
+        } else if (dchi < 0.0) {
+          pick = j;
+        }
+      }
+      s_pick = pick;
+    }
+    __syncthreads();
+    const int pick = s_pick;
+    if (pick != -1) {
+      if (tid == 0) {
+        if (pick >= 0) {
+          st->s = base + pick;
+          st->beta = bk[pick];
+          st->step = bk[pick] * vs;
+        } else {  // s unchanged, no perturbation (as a search that finds no step)
+          st->beta = 0.0;
+          st->step = 0.0;
+          st->pstop = 1;
+          st->capped = 1;
+        }
+      }
+      return;
+    }
+    __syncthreads();  // sbeta and sh are rewritten by the next window
   }
 }
 
@@ -1237,6 +1383,14 @@ void launch_tcol(int mode, const DevPlan* plans, const ColBlock* blocks, int n_b
     case kColYMove: k_tcol<kColYMove><<<n_blocks, kBlock, 0, s>>>(plans, blocks); break;
     default: k_tcol<kColYCopy><<<n_blocks, kBlock, 0, s>>>(plans, blocks); break;
   }
+}
+
+void launch_linesearch(int sub, const DevPlan* plans, int n_plans, hipStream_t s) {
+  if (n_plans <= 0) return;
+  if (sub)
+    k_linesearch<1><<<n_plans, kFinBlock, 0, s>>>(plans);
+  else
+    k_linesearch<0><<<n_plans, kFinBlock, 0, s>>>(plans);
 }
 
 void launch_finalize(int mode, int sub, const DevPlan* plans, int n_plans, hipStream_t s) {

@@ -143,7 +143,7 @@ struct Layout {
   size_t y, osbase, oswidth, osrow, osci, osdv, oslv, ogroups, pk_src, pk_dst, pk_len;
   size_t spart_a, spart_b, rpart, gpart, tpart, groups, row_items, tr_items, col_blocks;
   size_t bc, colcount, colmax, flags, rslice, rsum, goff, alist, spart, smask, sc_items,
-      ss_items, pkind, pf, okind, of, gcoef, coef_row, rptr, plen, rci, rdv, rlv, total;
+      ss_items, pkind, pf, okind, of, ovec, gcoef, coef_row, rptr, plen, rci, rdv, rlv, total;
   int64_t NP;                 // positions of the all-row view
   int64_t sell_slots, n_slices, csc_slots, obj_slots, max_rows, max_tr, n_groups, n_col_blocks;
   int64_t row_slots;          // row-contiguous copy: every row padded to 4 slots
@@ -238,6 +238,7 @@ bool make_layout(int64_t R, int64_t C, int64_t nnz, int storage, int lpr_log2,
   L->pf = take(sizeof(float) * 9 * Pm);          // dlo dhi clo chi tmax wf wo dt ct
   L->okind = take(sizeof(uint16_t) * Om);
   L->of = take(sizeof(float) * 3 * Om);          // wo dt ct of the objective-row view
+  L->ovec = take(sizeof(float) * 4 * Om);        // its d, l, D g, L g (step search)
   L->gcoef = take(sizeof(float2) * Rm);          // gradient coefficients by row
   L->coef_row = take(sizeof(float2) * Rm);       // projection coefficients by row
   L->g = take(sizeof(float) * C);
@@ -469,6 +470,10 @@ fredopt_status check_params(const fredopt_params* q, bool need_iter) {
   if (need_iter && q->iter_max < 0) return fail(FREDOPT_E_ARG, "iter_max must be >= 0");
   if (q->normalization < 0 || q->normalization > 2)
     return fail(FREDOPT_E_ARG, "unknown normalization %d", q->normalization);
+  if (q->objective != FREDOPT_OBJECTIVE_PRINTED && q->objective != FREDOPT_OBJECTIVE_ONE_SIDED)
+    return fail(FREDOPT_E_ARG, "unknown objective %d", q->objective);
+  if (q->unit_direction != 0 && q->unit_direction != 1)
+    return fail(FREDOPT_E_ARG, "unit_direction must be 0 or 1, got %d", q->unit_direction);
   if (q->reserved != 0) return fail(FREDOPT_E_ARG, "reserved field must be 0");
   return FREDOPT_OK;
 }
@@ -496,6 +501,8 @@ void set_problem(fredopt_plan* p, const fredopt_problem* pr, const fredopt_param
   h.prm.ws_fixed = ws_fixed;
   h.prm.normalization = q->normalization;
   h.prm.reductions_n = q->reductions_n;
+  h.prm.objective = q->objective;
+  h.prm.unit_dir = q->unit_direction;
   h.x = x;
   h.out_dose = h.out_letd = h.out_cdl = nullptr;
 }
@@ -773,7 +780,8 @@ void export_state(const DevState& d, fredopt_state* st) {
 }
 
 enum Kind {
-  kKindFwd, kKindRows, kKindChunks, kKindCol, kKindFin, kKindList, kKindScatter, kKindScatterSum
+  kKindFwd, kKindRows, kKindChunks, kKindCol, kKindFin, kKindList, kKindScatter, kKindScatterSum,
+  kKindSearch
 };
 
 struct Launch {
@@ -804,7 +812,7 @@ void add_projection(std::vector<Launch>* seq, int col_mode) {
   seq->push_back({FREDOPT_KERNEL_SCATTER_SUM, kKindScatterSum, col_mode});
 }
 
-std::vector<Launch> iteration_sequence(int r, bool obj, bool fold) {
+std::vector<Launch> iteration_sequence(int r, bool obj, bool fold, bool onesided) {
   std::vector<Launch> seq;
   if (r == 0) {
     seq.push_back({FREDOPT_KERNEL_FWD_RESID, kKindFwd, kFwdResid, 0, kVecX});
@@ -819,6 +827,7 @@ std::vector<Launch> iteration_sequence(int r, bool obj, bool fold) {
       seq.push_back({FREDOPT_KERNEL_COL, kKindCol, kColGrad});
       seq.push_back({FREDOPT_KERNEL_FWD_DIR, kKindFwd, kFwdDir, 1, kVecG});
       seq.push_back({FREDOPT_KERNEL_FINALIZE, kKindFin, t == 0 ? kFinDir0 : kFinDir, 1});
+      if (onesided) seq.push_back({FREDOPT_KERNEL_LINE_SEARCH, kKindSearch, 0, 1});
       if (!(fold && t + 1 == r)) seq.push_back({FREDOPT_KERNEL_COL, kKindCol, kColYMove});
     }
     seq.push_back({FREDOPT_KERNEL_FWD_RESID, kKindFwd, kFwdResid, 0, fold ? kVecYMove : kVecY});
@@ -833,6 +842,7 @@ std::vector<Launch> iteration_sequence(int r, bool obj, bool fold) {
     seq.push_back({FREDOPT_KERNEL_COL, kKindCol, t == 0 ? kColGrad : kColGradMove});
     seq.push_back({FREDOPT_KERNEL_FWD_DIR, kKindFwd, kFwdDir, 0, kVecG});
     seq.push_back({FREDOPT_KERNEL_FINALIZE, kKindFin, t == 0 ? kFinDir0 : kFinDir, 0});
+    if (onesided) seq.push_back({FREDOPT_KERNEL_LINE_SEARCH, kKindSearch, 0, 0});
     seq.push_back({FREDOPT_KERNEL_ROWS, kKindRows, last ? kRowsMoveResid : kRowsMoveObj});
     seq.push_back({FREDOPT_KERNEL_FINALIZE, kKindFin, last ? kFinResidRows : kFinMoveObj});
   }
@@ -936,6 +946,9 @@ void enqueue(const Exec& e, const Launch& l, hipStream_t s) {
     case kKindScatterSum:
       if (e.n_ss > 0) launch_scatter_sum(l.mode, e.table, e.ss, e.n_ss, s);
       break;
+    case kKindSearch:
+      launch_linesearch(l.sub, e.table, e.n_plans, s);
+      break;
     default:
       launch_finalize(l.mode, l.sub, e.table, e.n_plans, s);
       break;
@@ -945,24 +958,29 @@ void enqueue(const Exec& e, const Launch& l, hipStream_t s) {
 void enqueue(fredopt_plan* p, const Launch& l, hipStream_t s) { enqueue(exec_of(p), l, s); }
 
 // The iteration for an exec: the last move folded when every plan stages its vector
-// in LDS.
-std::vector<Launch> sequence_of(const Exec& e, int r, bool obj) {
-  return iteration_sequence(r, obj, e.lds_floats > 0);
+// in LDS; the step search kernel with the one-sided objective.
+std::vector<Launch> sequence_of(const Exec& e, int r, bool obj, bool onesided) {
+  return iteration_sequence(r, obj, e.lds_floats > 0, onesided);
 }
+
+// Graphs are captured per (reductions_n, objective): the one-sided objective adds
+// the step search to the sequence.
+int graph_key(int r, int objective) { return 2 * r + (objective ? 1 : 0); }
 
 fredopt_status enqueue_iteration(fredopt_plan* p, int r, hipStream_t s) {
   const Exec e = exec_of(p);
-  for (const Launch& l : sequence_of(e, r, p->sched_obj)) enqueue(e, l, s);
+  for (const Launch& l : sequence_of(e, r, p->sched_obj, p->hp.prm.objective != 0))
+    enqueue(e, l, s);
   HIPCHK(hipGetLastError());
   return FREDOPT_OK;
 }
 
 // One outer iteration captured on `cap` (a stream of its own) into *graph.
-fredopt_status capture_iteration(const Exec& e, int r, bool obj, hipStream_t cap,
+fredopt_status capture_iteration(const Exec& e, int r, bool obj, bool onesided, hipStream_t cap,
                                  hipGraphExec_t* graph) {
   hipGraph_t g = nullptr;
   HIPCHK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
-  for (const Launch& l : sequence_of(e, r, obj)) enqueue(e, l, cap);
+  for (const Launch& l : sequence_of(e, r, obj, onesided)) enqueue(e, l, cap);
   const hipError_t le = hipGetLastError();
   const hipError_t ce = hipStreamEndCapture(cap, &g);
   if (le != hipSuccess || ce != hipSuccess) {
@@ -980,13 +998,15 @@ fredopt_status capture_iteration(const Exec& e, int r, bool obj, hipStream_t cap
 }
 
 fredopt_status ensure_graph(fredopt_plan* p, int r) {
-  if (p->graph && p->graph_r == r) return FREDOPT_OK;
+  const int key = graph_key(r, p->hp.prm.objective);
+  if (p->graph && p->graph_r == key) return FREDOPT_OK;
   drop_graph(p);
   // a plan loaded without allocation gets its capture stream here
   if (!p->cap) HIPCHK(hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking));
-  const fredopt_status st = capture_iteration(exec_of(p), r, p->sched_obj, p->cap, &p->graph);
+  const fredopt_status st = capture_iteration(exec_of(p), r, p->sched_obj,
+                                              p->hp.prm.objective != 0, p->cap, &p->graph);
   if (st != FREDOPT_OK) return st;
-  p->graph_r = r;
+  p->graph_r = key;
   return FREDOPT_OK;
 }
 
@@ -1411,6 +1431,11 @@ static fredopt_status load_impl(const fredopt_matrices* m, void* workspace,
     h.owo = of;
     h.odt = of + Om;
     h.oct = of + 2 * Om;
+    float* ov = reinterpret_cast<float*>(ws + L.ovec);
+    h.od = ov;
+    h.ol = ov + Om;
+    h.odg = ov + 2 * Om;
+    h.olg = ov + 3 * Om;
     h.gcoef = reinterpret_cast<float2*>(ws + L.gcoef);
     h.coef_row = reinterpret_cast<float2*>(ws + L.coef_row);
   }
@@ -1627,7 +1652,8 @@ fredopt_status fredopt_profile_kernels(fredopt_plan* p, const fredopt_problem* p
   if ((st = upload_table(p, s)) != FREDOPT_OK) return st;
   if ((st = upload_state(p, stt, s)) != FREDOPT_OK) return st;
   enqueue(p, Launch{FREDOPT_KERNEL_COL, kKindCol, kColYCopy}, s);
-  const std::vector<Launch> seq = sequence_of(exec_of(p), q->reductions_n, p->sched_obj);
+  const std::vector<Launch> seq =
+      sequence_of(exec_of(p), q->reductions_n, p->sched_obj, q->objective != 0);
   const size_t n = seq.size() * (size_t)n_iters;
   std::vector<hipEvent_t> ev(2 * n, nullptr);
   for (auto& e : ev) HIPCHK(hipEventCreate(&e));
@@ -2062,12 +2088,14 @@ fredopt_status fredopt_batch_solve(fredopt_batch* b, const fredopt_params* q,
     for (const SubBatch& sb : b->subs)
       enqueue(sb.ex, Launch{FREDOPT_KERNEL_COL, kKindCol, kColYCopy}, s);
     const int r = q->reductions_n;
-    if (!(b->graph && b->graph_r == r)) {
+    const int key = graph_key(r, q->objective);
+    if (!(b->graph && b->graph_r == key)) {
       drop_batch_graph(b);
       hipGraph_t g = nullptr;
       HIPCHK(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
       for (const SubBatch& sb : b->subs)
-        for (const Launch& l : sequence_of(sb.ex, r, sb.obj)) enqueue(sb.ex, l, b->cap);
+        for (const Launch& l : sequence_of(sb.ex, r, sb.obj, q->objective != 0))
+          enqueue(sb.ex, l, b->cap);
       const hipError_t le = hipGetLastError();
       const hipError_t ce = hipStreamEndCapture(b->cap, &g);
       if (le != hipSuccess || ce != hipSuccess) {
@@ -2081,7 +2109,7 @@ fredopt_status fredopt_batch_solve(fredopt_batch* b, const fredopt_params* q,
         b->graph = nullptr;
         return fail(FREDOPT_E_DEVICE, "graph instantiate failed: %s", hipGetErrorString(ie));
       }
-      b->graph_r = r;
+      b->graph_r = key;
     }
     for (int32_t i = 0; i < n_iters; ++i) HIPCHK(hipGraphLaunch(b->graph, s));
   }

@@ -21,8 +21,9 @@ F32, F16, BF16, F16_IDX16, BF16_IDX16 = 0, 1, 2, 3, 4
 STORAGE = {"f32": F32, "fp32": F32, "f16": F16, "fp16": F16, "bf16": BF16,
            "f16i16": F16_IDX16, "bf16i16": BF16_IDX16}
 NORM_CONVEX_ALL, NORM_CONVEX_VIOLATED, NORM_RAW = 0, 1, 2
+OBJECTIVE_PRINTED, OBJECTIVE_ONE_SIDED = 0, 1
 KERNEL_NAMES = ("fwd_obj", "tr_grad", "fwd_dir", "rows", "tr_proj", "fwd_resid", "col",
-                "finalize", "active_list", "scatter", "scatter_sum")
+                "finalize", "active_list", "scatter", "scatter_sum", "line_search")
 
 STATUS = {0: "OK", -1: "E_ARG", -2: "E_SHAPE", -3: "E_INDEX", -4: "E_NONFINITE",
           -5: "E_WORKSPACE", -6: "E_DEVICE", -7: "E_STATE", -8: "E_NOT_IMPLEMENTED"}
@@ -54,7 +55,8 @@ class Problem(ct.Structure):
 class Params(ct.Structure):
     _fields_ = [("lambda_", ct.c_double), ("alpha", ct.c_double), ("eta", ct.c_double),
                 ("reductions_n", ct.c_int32), ("iter_max", ct.c_int32),
-                ("normalization", ct.c_int32), ("reserved", ct.c_int32)]
+                ("normalization", ct.c_int32), ("objective", ct.c_int32),
+                ("unit_direction", ct.c_int32), ("reserved", ct.c_int32)]
 
 
 class State(ct.Structure):
@@ -214,11 +216,14 @@ class SolverParams:
     reductions_n: int = 1
     iter_max: int = 100
     normalization: int = NORM_CONVEX_ALL
+    objective: int = OBJECTIVE_PRINTED
+    unit_direction: int = 0
 
     def struct(self) -> Params:
         return Params(lambda_=self.lam, alpha=self.alpha, eta=self.eta,
                       reductions_n=self.reductions_n, iter_max=self.iter_max,
-                      normalization=self.normalization, reserved=0)
+                      normalization=self.normalization, objective=self.objective,
+                      unit_direction=self.unit_direction, reserved=0)
 
 
 class DeviceProblem:

@@ -104,7 +104,8 @@ def test_load_rejects_bad_workspace_before_device_work():
 
 @pytest.mark.parametrize("field,value", [("lam", 0.0), ("lam", 2.5), ("alpha", 1.0),
                                          ("eta", 0.0), ("normalization", 5),
-                                         ("reductions_n", -1)])
+                                         ("reductions_n", -1), ("objective", 2),
+                                         ("unit_direction", 2)])
 def test_param_ranges_documented(field, value):
     """Parameter ranges from Fig. 2's caption and the text after Fig. 3 are the ones
     the binding forwards; the library checks them (exercised on the GPU)."""
