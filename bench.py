@@ -34,7 +34,8 @@ KERNEL_SYMBOLS = {  # fredopt kernel id -> device symbol in profiler output (vt:
     "fwd_resid": "fo::k_forward<{vt}, 3, 0>", "tr_grad": "fo::k_tr_chunks<{vt}, 0>",
     "tr_proj": "fo::k_tr_chunks<{vt}, 1>", "rows": "fo::k_rows<1>", "col": "fo::k_tcol",
     "finalize": "fo::k_finalize", "active_list": "fo::k_active_list",
-    "scatter": "fo::k_scatter<{vt}>", "scatter_sum": "fo::k_scatter_sum"}
+    "scatter": "fo::k_scatter<{vt}>", "scatter_sum": "fo::k_scatter_sum",
+    "line_search": "fo::k_linesearch<{sub}>"}
 
 
 def dtype_of(storage: str) -> str:
@@ -89,6 +90,8 @@ def algorithmic_bytes(kernel: str, R: int, C: int, nnz: int, vb: int, n_tr_items
         return n_tr_items * 4 + C * 16
     if kernel == "rows":        # d, l, Dg, Lg in; d, l, coef out; problem data in
         return R * (16 + 8 + 8 + 2 + 20 + 4 + 24 + 12)
+    if kernel == "line_search":  # one window: kind, weight, targets, d, l, D g, L g per row
+        return (n_obj_rows if obj_entries else R) * (2 + 12 + 16)
     if kernel in ("finalize", "active_list", "scatter", "scatter_sum"):
         return 0  # scalars; the active-row work depends on the iterate (not priced)
     raise KeyError(kernel)
@@ -344,6 +347,9 @@ def main():
                     help="matrix values in FP32, FP16 or BF16 (per-beamlet FP32 scale); the "
                          "i16 forms also keep column indices in 16 bits")
     ap.add_argument("--reductions", type=int, default=1)
+    ap.add_argument("--problem", default="full", choices=["full", "dose_only"],
+                    help="full: dose and LETd terms; dose_only: the paper's dose-only arm "
+                         "(dose bounds and the PTV dose objective only)")
     ap.add_argument("--objective", type=int, default=0, choices=[0, 1],
                     help="0 Eq. (2) as printed, 1 the OAR term one-sided (device step search)")
     ap.add_argument("--unit-direction", type=int, default=0, choices=[0, 1],
@@ -394,6 +400,8 @@ def main():
     log(f"generating workload {args.workload}")
     t0 = time.perf_counter()
     p = make_workload(args.workload)
+    if args.problem == "dose_only":
+        p = p.dose_only()
     log(f"workload {p.summary()} in {time.perf_counter() - t0:.1f} s")
 
     storage = fredopt.STORAGE[args.storage]
@@ -508,7 +516,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {p.name}", "rows": R, "cols": C, "nnz": nnz,
                    "storage": args.storage, "reductions_n": args.reductions,
-                   "normalization": "convex_all",
+                   "problem": args.problem, "normalization": "convex_all",
                    "objective": "one-sided OAR" if args.objective else "Eq. (2) as printed",
                    "unit_direction": args.unit_direction,
                    "lanes_per_row": info["lanes_per_row"],

@@ -82,6 +82,15 @@ class Phantom:
     def problem_arrays(self) -> Dict[str, np.ndarray]:
         return {k: getattr(self, k) for k in PROBLEM_FIELDS}
 
+    def dose_only(self) -> "Phantom":
+        """The same plan with the paper's "dose only" problem (Section 2.5, the dose
+        arms of Table 2): dose bounds and the PTV dose objective kept, every cDL and
+        LETd constraint and the OAR cDL objective dropped.  The matrices are shared."""
+        keep = np.uint16(DOSE_LO | DOSE_HI | OBJ_DOSE)
+        return dataclasses.replace(self, name=f"{self.name}_dose_only",
+                                   kind=(self.kind & keep).astype(np.uint16),
+                                   meta={**self.meta, "problem": "dose only"})
+
     def summary(self) -> Dict[str, object]:
         return {"name": self.name, "rows": self.n_rows, "cols": self.n_cols,
                 "nnz": self.nnz, **{k: v for k, v in self.meta.items()

@@ -207,3 +207,25 @@ def test_clinical_precision_form(fo, clin, orc, ref100):
                     key = f"{name}_mean_LETd"
                     assert rg[key] == pytest.approx(rr[key], rel=T3), key
         plan.free()
+
+
+def test_clinical_dose_only_steps(fo, clin, loaded):
+    """The dose-only problem on the clinical plan (the same loaded matrices with a
+    problem of dose bounds and the PTV dose objective only): T2 and the exact step
+    exponent over 3 outer iterations from x0, with and without perturbations."""
+    plan, _, x0 = loaded
+    p = clin.dose_only()
+    prob = fo.DeviceProblem(p.problem_arrays(), p.c)
+    o = Oracle(p)
+    for r in (1, 0):
+        q = fo.SolverParams(reductions_n=r)
+        st = fo.new_state()
+        x = x0.clone()
+        xr = p.x0.astype(np.float64)
+        k, s = 0, -1
+        for it in range(3):
+            print(f"clinical dose-only r={r} iteration {it}", flush=True)
+            fo.superiorize_step(plan, prob, q, st, x)
+            xr, k, s, _ = o.sa_iteration(xr, k, s, _oparams(q))
+            assert (st.k, st.s) == (k, s)
+            assert np.linalg.norm(_np(x) - xr) <= T2 * np.linalg.norm(xr)

@@ -259,6 +259,40 @@ def test_solve_water32_plan_quality(fo, w32):
     print("normwise x error", np.linalg.norm(xg - xr) / np.linalg.norm(xr), flush=True)
 
 
+@pytest.mark.parametrize("r", [0, 1])
+def test_dose_only_problem_water32(fo, w32, r):
+    """The paper's dose-only arm (dose bounds and the PTV dose objective, no cDL or
+    LETd terms): three outer iterations at T2 with the same step exponent, then D95
+    within T3 after 100 iterations (r = 0: the feasibility sweep alone)."""
+    import torch
+    p = w32.dose_only()
+    print(f"dose-only water32 r={r}", flush=True)
+    plan, prob, x0 = fo.load_phantom(p)
+    q = _params(fo, reductions_n=r)
+    o = Oracle(p)
+    st = fo.new_state()
+    x = x0.clone()
+    xr = p.x0.astype(np.float64)
+    k, s = 0, -1
+    for it in range(3):
+        fo.superiorize_step(plan, prob, q, st, x)
+        xr, k, s, _ = o.sa_iteration(xr, k, s, _oparams(q))
+        assert (st.k, st.s) == (k, s)
+        assert np.linalg.norm(_np(x) - xr) <= T2 * np.linalg.norm(xr)
+    q.iter_max = 100
+    st = fo.new_state()
+    x = x0.clone()
+    fo.solve(plan, prob, q, st, x)
+    xr, _, _, _ = o.solve(p.x0, 100, _oparams(q))
+    dose, letd, _ = fo.dose_let(plan, x, p.c)
+    torch.cuda.synchronize()
+    d_ref, _, letd_ref, _ = o.dose_let(xr)
+    rg = metrics.plan_report(_np(dose), _np(letd), p.roi)
+    rr = metrics.plan_report(d_ref, letd_ref, p.roi)
+    print("gpu", rg, "\noracle", rr, flush=True)
+    assert rg["PTV_D95"] == pytest.approx(rr["PTV_D95"], rel=T3)
+
+
 @pytest.mark.parametrize("path", ["csc", "scatter"])
 def test_solve_deterministic_and_resumable(fo, w32, path):
     print(f"determinism water32 path={path}", flush=True)
