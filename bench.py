@@ -240,6 +240,57 @@ def bench_batch(args):
     }
 
 
+def bench_robust(args):
+    """Robustness evaluation: one fluence under the nominal plan and its 8 scenario
+    recalculations (+-2 mm shifts along each axis, ranges x (1 -+ 3.5 %)), dose, LETd
+    and cDL per scenario plus per-voxel bands, in one launch.  The plan is the largest
+    of the batched workload (110k voxels, 3,694 beamlets)."""
+    import torch
+    from paper_2509_20012_amd import fredopt, phantom as ph
+    t0 = time.perf_counter()
+    sd, r, c = max(ph.batch_sizes(48, seed=3), key=lambda t: t[1] * t[2])
+    scen = ph.robustness_scenarios(sd, r, c)
+    nnz = sum(p.nnz for p in scen)
+    R = scen[0].n_rows
+    log(f"{len(scen)} scenarios of {R} voxels x {scen[0].n_cols} beamlets, {nnz} entries "
+        f"in {time.perf_counter() - t0:.1f} s")
+    storage = fredopt.STORAGE[args.storage]
+    plans = [fredopt.load_matrices(p.row_ptr, p.col_idx, p.d_val, p.l_val, p.n_cols, storage)
+             for p in scen]
+    x = torch.from_numpy(np.random.default_rng(1).uniform(0.5, 1.5, scen[0].n_cols)
+                         .astype(np.float32)).cuda()
+    for _ in range(max(1, args.warmup)):
+        fredopt.scenario_dose_let(plans, x, scen[0].c)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        fredopt.scenario_dose_let(plans, x, scen[0].c)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    rate = args.steps / dt
+    vb = 4 if storage == fredopt.F32 else 2
+    ib = 2 if storage in (fredopt.F16_IDX16, fredopt.BF16_IDX16) else 4
+    # per evaluation: every scenario's entries once, x per scenario, three outputs per
+    # scenario row, and the four bands (filled, updated, decoded)
+    alg = nnz * (ib + 2 * vb) + len(scen) * (4 * scen[0].n_cols + 12 * R) + 4 * 4 * R * 3
+    log(f"robustness evaluation: {rate:.1f} evaluations/s ({dt / args.steps * 1e3:.3f} ms "
+        f"each, host call included), {alg * rate / 1e9:.0f} GB/s of algorithmic bytes")
+    for pl in plans:
+        pl.free()
+    return {
+        "metric": METRIC, "value": round(rate, 2), "unit": "evaluations/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(dt / args.steps * 1e3, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": dtype_of(args.storage),
+        "data": "synthetic",
+        "config": {"workload": f"robust9: {scen[0].name} and 8 scenarios, {R} voxels, "
+                               f"{nnz} entries in all", "storage": args.storage},
+        "value_meaning": "robustness evaluations per second (9 scenarios: dose, LETd, cDL "
+                         "and per-voxel bands), host call and synchronisation included",
+        "hbm_gbps": round(alg * rate / 1e9, 1), "alg_bytes_per_evaluation": alg,
+    }
+
+
 def bench_serve(args):
     """Poisson stream of re-optimisation requests (4/s), sizes as the batched plans
     plus 10 % at clinical scale, 200-1,000 iterations each, memory budget 200 GB;
@@ -341,8 +392,9 @@ def main():
     ap.add_argument("--workload", default="clinical",
                     help="clinical (160x160x120 grid, 12k beamlets), water32 (32^3, 400 "
                          "beamlets), clinical_x<scale>, batch48 (48 plans in batched "
-                         "launches), scenarios48 (6 plans x 8 robustness scenarios) or "
-                         "serve (request stream, continuous batching)")
+                         "launches), scenarios48 (6 plans x 8 robustness scenarios), "
+                         "robust9 (robustness evaluation of one fluence under 9 "
+                         "scenarios) or serve (request stream, continuous batching)")
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16", "f16i16", "bf16i16"],
                     help="matrix values in FP32, FP16 or BF16 (per-beamlet FP32 scale); the "
                          "i16 forms also keep column indices in 16 bits")
@@ -393,8 +445,13 @@ def main():
         raise SystemExit("bench.py needs a HIP device")
     torch.cuda.set_device(0)
     fredopt.lib()
-    if args.workload in ("batch48", "scenarios48", "serve"):
-        res = bench_serve(args) if args.workload == "serve" else bench_batch(args)
+    if args.workload in ("batch48", "scenarios48", "serve", "robust9"):
+        if args.workload == "serve":
+            res = bench_serve(args)
+        elif args.workload == "robust9":
+            res = bench_robust(args)
+        else:
+            res = bench_batch(args)
         print(json.dumps(res), flush=True)
         return
     log(f"generating workload {args.workload}")

@@ -252,6 +252,31 @@ fredopt_status fredopt_solve(fredopt_plan *p, const fredopt_problem *pr,
                              const fredopt_params *q, fredopt_state *st, float *x_inout,
                              void *stream);
 
+/* ---- robustness evaluation ---------------------------------------------------- */
+
+/* Device workspace of fredopt_scenario_dose_let for these n plans (0 for invalid
+ * input). */
+size_t fredopt_scenario_workspace_bytes(fredopt_plan *const *plans, int32_t n);
+
+/* The robustness evaluation of Section 2.5 (the final plan recomputed under setup
+ * and range scenarios; Figs. 4-5 show the spread): dose, LETd and cDL of one device
+ * fluence x[n_cols] under n scenario plans, in one launch over all their rows, and
+ * per-voxel bands over the scenarios.  plans[i] holds scenario i's matrices; every
+ * plan must have the same n_rows (row r is the same voxel in every scenario), n_cols
+ * (column j the same beamlet), storage and device, else FREDOPT_E_SHAPE / E_ARG.
+ * Outputs are device arrays, any of them NULL: dose, letd, cdl of n * n_rows floats,
+ * scenario-major (scenario i's row r at i * n_rows + r); dose_min, dose_max,
+ * letd_min, letd_max of n_rows floats (each pair both or neither): the smallest and
+ * largest value over the scenarios, exact (no rounding: the values are compared,
+ * in any order).  LETd is 0 where a scenario gives the voxel no dose.  `workspace`:
+ * 256-byte aligned device memory of fredopt_scenario_workspace_bytes(plans, n)
+ * bytes, used only during the call.  Synchronises `stream`. */
+fredopt_status fredopt_scenario_dose_let(fredopt_plan *const *plans, int32_t n,
+                                         const float *x, double c, float *dose, float *letd,
+                                         float *cdl, float *dose_min, float *dose_max,
+                                         float *letd_min, float *letd_max, void *workspace,
+                                         size_t workspace_bytes, void *stream);
+
 /* Thread-local description of the last failing call on this thread. */
 const char *fredopt_last_error(void);
 

@@ -188,6 +188,9 @@ struct DevPlan {
   float* out_dose;
   float* out_letd;
   float* out_cdl;
+  // per-voxel bands of a robustness evaluation (dose min, dose max, LETd min, LETd
+  // max), order-preserving encoded floats; null outside such an evaluation
+  uint32_t* band[4];
   // reductions
   double* spart_a;            // [groups * kNPart] objective / residual passes
   double* spart_b;            // [groups * kNPart] direction pass

@@ -18,6 +18,8 @@ void launch_tr_chunks(int vtype, int tag, const DevPlan* plans, const TrItem* it
 void launch_tcol(int mode, const DevPlan* plans, const ColBlock* blocks, int n_blocks,
                  hipStream_t s);
 void launch_finalize(int mode, int sub, const DevPlan* plans, int n_plans, hipStream_t s);
+// band arrays of a robustness evaluation: fill (finish 0) or decode (finish 1)
+void launch_band(int finish, int64_t n, uint32_t* lo, uint32_t* hi, hipStream_t s);
 // step search of the one-sided objective, one workgroup per plan (sub: objective view)
 void launch_linesearch(int sub, const DevPlan* plans, int n_plans, hipStream_t s);
 hipError_t set_forward_lds_limit(int vtype, size_t bytes);

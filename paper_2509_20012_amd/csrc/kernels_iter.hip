@@ -379,6 +379,17 @@ __device__ __forceinline__ void prepare_search(const DevPlan* P, double G, doubl
 
 // -------------------------------------------------------------- forward pass ---
 
+// Order-preserving map of a float's bits to an unsigned integer (negative values
+// below positive ones, -inf lowest, +inf highest), so integer atomic min / max keep
+// per-voxel bands over scenarios regardless of the order the scenarios arrive in.
+__host__ __device__ __forceinline__ uint32_t band_enc(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__host__ __device__ __forceinline__ float band_dec(uint32_t e) {
+  return __uint_as_float((e & 0x80000000u) ? (e & 0x7FFFFFFFu) : ~e);
+}
+
 template <int MODE>
 __device__ __forceinline__ constexpr unsigned fwd_slots() {
   return MODE == kFwdResid ? 0x3FFu : 0x21u;
@@ -472,9 +483,18 @@ __device__ __forceinline__ void forward_slice(const DevPlan* __restrict__ P, int
       // outputs in the caller's row order
       const int row = gconst(V.srow)[sp];
       if (row >= 0) {
+        const float letd = ad > 0.f ? al / ad : 0.f;
         if (P->out_dose) gmut(P->out_dose)[row] = ad;
-        if (P->out_letd) gmut(P->out_letd)[row] = ad > 0.f ? al / ad : 0.f;
+        if (P->out_letd) gmut(P->out_letd)[row] = letd;
         if (P->out_cdl) gmut(P->out_cdl)[row] = (float)(P->prm.c * (double)al);
+        if (P->band[0]) {  // robustness evaluation: the scenario joins the voxel's bands
+          atomicMin(P->band[0] + row, band_enc(ad));
+          atomicMax(P->band[1] + row, band_enc(ad));
+        }
+        if (P->band[2]) {
+          atomicMin(P->band[2] + row, band_enc(letd));
+          atomicMax(P->band[3] + row, band_enc(letd));
+        }
       }
     } else if constexpr (MODE == kFwdObj) {
       if constexpr (!SUB) {  // the all-row pass keeps d and l for the moves
@@ -1245,6 +1265,25 @@ __global__ __launch_bounds__(kFinBlock) void k_linesearch(const DevPlan* __restr
   }
 }
 
+// Band arrays before a robustness evaluation (min = encoded +inf, max = encoded
+// -inf; a fill kernel, not a memset, so the sequence can be captured in a graph) and
+// after it (decoded in place to floats).
+__global__ __launch_bounds__(kBlock) void k_band_fill(int64_t n, uint32_t* lo, uint32_t* hi) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) {
+    lo[i] = band_enc(__uint_as_float(0x7F800000u));
+    hi[i] = band_enc(__uint_as_float(0xFF800000u));
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_band_finish(int64_t n, uint32_t* lo, uint32_t* hi) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) {
+    lo[i] = __float_as_uint(band_dec(lo[i]));
+    hi[i] = __float_as_uint(band_dec(hi[i]));
+  }
+}
+
 // ---------------------------------------------------------------- launchers ----
 
 template <int VT, int SUB>
@@ -1383,6 +1422,15 @@ void launch_tcol(int mode, const DevPlan* plans, const ColBlock* blocks, int n_b
     case kColYMove: k_tcol<kColYMove><<<n_blocks, kBlock, 0, s>>>(plans, blocks); break;
     default: k_tcol<kColYCopy><<<n_blocks, kBlock, 0, s>>>(plans, blocks); break;
   }
+}
+
+void launch_band(int finish, int64_t n, uint32_t* lo, uint32_t* hi, hipStream_t s) {
+  if (n <= 0 || !lo) return;
+  const unsigned grid = (unsigned)((n + kBlock - 1) / kBlock);
+  if (finish)
+    k_band_finish<<<grid, kBlock, 0, s>>>(n, lo, hi);
+  else
+    k_band_fill<<<grid, kBlock, 0, s>>>(n, lo, hi);
 }
 
 void launch_linesearch(int sub, const DevPlan* plans, int n_plans, hipStream_t s) {

@@ -2125,4 +2125,103 @@ fredopt_status fredopt_batch_solve(fredopt_batch* b, const fredopt_params* q,
   return FREDOPT_OK;
 }
 
+// ------------------------------------------------------ robustness evaluation ----
+
+size_t fredopt_scenario_workspace_bytes(fredopt_plan* const* plans, int32_t n) {
+  if (!plans || n < 1) return 0;
+  size_t groups = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    if (!plans[i]) return 0;
+    groups += plans[i]->groups.size();
+  }
+  return align_up(sizeof(uint32_t) * kCounters) + align_up(sizeof(DevPlan) * (size_t)n) +
+         align_up(sizeof(FwdGroup) * std::max<size_t>(groups, 1));
+}
+
+fredopt_status fredopt_scenario_dose_let(fredopt_plan* const* plans, int32_t n, const float* x,
+                                         double c, float* dose, float* letd, float* cdl,
+                                         float* dose_min, float* dose_max, float* letd_min,
+                                         float* letd_max, void* workspace,
+                                         size_t workspace_bytes, void* stream) {
+  if (!plans || n < 1 || !x) return fail(FREDOPT_E_ARG, "plans (n >= 1) and x must be non-NULL");
+  if (!(c > 0.0) || !std::isfinite(c)) return fail(FREDOPT_E_ARG, "c must be positive and finite");
+  if ((dose_min == nullptr) != (dose_max == nullptr) ||
+      (letd_min == nullptr) != (letd_max == nullptr))
+    return fail(FREDOPT_E_ARG, "band arrays come in pairs (min and max)");
+  for (int32_t i = 0; i < n; ++i) {
+    if (!plans[i]) return fail(FREDOPT_E_ARG, "plan %d is NULL", i);
+    const fredopt_plan* p = plans[i];
+    if (p->R != plans[0]->R || p->C != plans[0]->C)
+      return fail(FREDOPT_E_SHAPE, "scenario %d is %lld x %lld, scenario 0 %lld x %lld: every "
+                  "scenario must have the nominal plan's voxels and beamlets", i,
+                  (long long)p->R, (long long)p->C, (long long)plans[0]->R,
+                  (long long)plans[0]->C);
+    if (p->storage != plans[0]->storage || p->device != plans[0]->device)
+      return fail(FREDOPT_E_ARG, "scenario %d has another storage or device than scenario 0", i);
+  }
+  const size_t need = fredopt_scenario_workspace_bytes(plans, n);
+  if (!workspace || (reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0 ||
+      workspace_bytes < need)
+    return fail(FREDOPT_E_WORKSPACE, "workspace must be 256-byte aligned and hold %zu bytes",
+                need);
+  const fredopt_plan* p0 = plans[0];
+  const int64_t R = p0->R;
+  DeviceGuard guard(p0->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // the scenarios' descriptors and the concatenation of their work lists
+  std::vector<DevPlan> table((size_t)n);
+  std::vector<FwdGroup> groups;
+  int lds = p0->lds_floats;
+  for (int32_t i = 0; i < n; ++i) {
+    DevPlan h = plans[i]->hp;
+    h.x = const_cast<float*>(x);
+    h.prm.c = c;
+    h.out_dose = dose ? dose + (int64_t)i * R : nullptr;
+    h.out_letd = letd ? letd + (int64_t)i * R : nullptr;
+    h.out_cdl = cdl ? cdl + (int64_t)i * R : nullptr;
+    h.band[0] = reinterpret_cast<uint32_t*>(dose_min);
+    h.band[1] = reinterpret_cast<uint32_t*>(dose_max);
+    h.band[2] = reinterpret_cast<uint32_t*>(letd_min);
+    h.band[3] = reinterpret_cast<uint32_t*>(letd_max);
+    table[(size_t)i] = h;
+    append(&groups, plans[i]->groups, i);
+    lds = std::min(lds, plans[i]->lds_floats);
+  }
+  char* ws = static_cast<char*>(workspace);
+  uint32_t* ctr = reinterpret_cast<uint32_t*>(ws);
+  DevPlan* d_table = reinterpret_cast<DevPlan*>(ws + align_up(sizeof(uint32_t) * kCounters));
+  FwdGroup* d_groups = reinterpret_cast<FwdGroup*>(reinterpret_cast<char*>(d_table) +
+                                                   align_up(sizeof(DevPlan) * (size_t)n));
+  HIPCHK(hipMemsetAsync(ctr, 0, sizeof(uint32_t) * kCounters, s));
+  HIPCHK(hipMemcpyAsync(d_table, table.data(), sizeof(DevPlan) * table.size(),
+                        hipMemcpyHostToDevice, s));
+  if (!groups.empty())
+    HIPCHK(hipMemcpyAsync(d_groups, groups.data(), sizeof(FwdGroup) * groups.size(),
+                          hipMemcpyHostToDevice, s));
+  launch_band(0, R, reinterpret_cast<uint32_t*>(dose_min), reinterpret_cast<uint32_t*>(dose_max),
+              s);
+  launch_band(0, R, reinterpret_cast<uint32_t*>(letd_min), reinterpret_cast<uint32_t*>(letd_max),
+              s);
+  Exec e;
+  e.storage = p0->storage;
+  e.n_cu = p0->n_cu;
+  e.wgs_per_cu = p0->wgs_per_cu;
+  e.lds_floats = lds;
+  e.n_plans = n;
+  e.fwd_dynamic = true;
+  e.table = d_table;
+  e.groups = d_groups;
+  e.n_groups = (int)groups.size();
+  e.ctr = ctr;
+  if (e.n_groups > 0 && (dose || letd || cdl || dose_min || letd_min))
+    enqueue(e, Launch{0, kKindFwd, kFwdDoseLet, 0, kVecX}, s);
+  launch_band(1, R, reinterpret_cast<uint32_t*>(dose_min), reinterpret_cast<uint32_t*>(dose_max),
+              s);
+  launch_band(1, R, reinterpret_cast<uint32_t*>(letd_min), reinterpret_cast<uint32_t*>(letd_max),
+              s);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));  // the host tables above are read until here
+  return FREDOPT_OK;
+}
+
 }  // extern "C"

@@ -94,7 +94,8 @@ EXPORTED = ("fredopt_workspace_bytes", "fredopt_workspace_bytes_csr",
             "fredopt_solve", "fredopt_last_error", "fredopt_get_plan_info",
             "fredopt_profile_kernels", "fredopt_autotune", "fredopt_set_tuning",
             "fredopt_set_scatter", "fredopt_batch_workspace_bytes", "fredopt_batch_create",
-            "fredopt_batch_solve", "fredopt_batch_free")
+            "fredopt_batch_solve", "fredopt_batch_free", "fredopt_scenario_workspace_bytes",
+            "fredopt_scenario_dose_let")
 
 _lib = None
 
@@ -140,6 +141,11 @@ def lib():
         L.fredopt_batch_solve.argtypes = [P, ct.POINTER(Params), ct.POINTER(State),
                                           ct.POINTER(ct.c_void_p), ct.c_int32, P]
         L.fredopt_batch_free.argtypes = [P]
+        L.fredopt_scenario_workspace_bytes.argtypes = [ct.POINTER(ct.c_void_p), ct.c_int32]
+        L.fredopt_scenario_workspace_bytes.restype = ct.c_size_t
+        L.fredopt_scenario_dose_let.argtypes = [ct.POINTER(ct.c_void_p), ct.c_int32, P,
+                                                ct.c_double, P, P, P, P, P, P, P, P,
+                                                ct.c_size_t, P]
         for name in EXPORTED:
             if name not in ("fredopt_workspace_bytes", "fredopt_workspace_bytes_csr",
                             "fredopt_last_error", "fredopt_batch_workspace_bytes"):
@@ -332,6 +338,35 @@ def dose_let(plan: Plan, x, c: float = 0.04, stream=None, want=("dose", "letd", 
                                   _ptr(outs["dose"]),
                                   _ptr(outs["letd"]), _ptr(outs["cdl"]), _stream(stream)))
     return outs["dose"], outs["letd"], outs["cdl"]
+
+
+def scenario_dose_let(plans, x, c: float = 0.04, stream=None,
+                      want=("dose", "letd", "cdl"), bands: bool = True):
+    """Robustness evaluation of one fluence x under n scenario plans (same voxels and
+    beamlets): a dict with the per-scenario "dose", "letd", "cdl" device tensors of
+    shape (n, n_rows) named in want, and, with bands, the per-voxel "dose_min",
+    "dose_max", "letd_min", "letd_max" over the scenarios."""
+    torch = _torch()
+    n = len(plans)
+    if n < 1:
+        raise FredoptError(-1, "at least one scenario plan")
+    R, C = plans[0].n_rows, plans[0].n_cols
+    hp = (ct.c_void_p * n)(*[p.handle for p in plans])
+    nbytes = int(lib().fredopt_scenario_workspace_bytes(hp, n))
+    if nbytes == 0:
+        raise FredoptError(-1, "scenario workspace size: a plan is invalid")
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=x.device)
+    out = {k: torch.empty((n, R), dtype=torch.float32, device=x.device)
+           for k in ("dose", "letd", "cdl") if k in want}
+    if bands:
+        for k in ("dose_min", "dose_max", "letd_min", "letd_max"):
+            out[k] = torch.empty(R, dtype=torch.float32, device=x.device)
+    _check(lib().fredopt_scenario_dose_let(
+        hp, n, _dev(x, C, "x"), float(c), _ptr(out.get("dose")), _ptr(out.get("letd")),
+        _ptr(out.get("cdl")), _ptr(out.get("dose_min")), _ptr(out.get("dose_max")),
+        _ptr(out.get("letd_min")), _ptr(out.get("letd_max")), _ptr(ws), nbytes,
+        _stream(stream)))
+    return out
 
 
 def project_sweep(plan: Plan, problem: DeviceProblem, params: SolverParams, x,

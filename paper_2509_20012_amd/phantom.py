@@ -340,14 +340,20 @@ def _voxel_centres(shape, h_mm, vox_ids):
 
 
 def _finish(name, shape, h_mm, kept, row_ptr, col, d_raw, let, C, masks, bounds, seed,
-            extra_meta=None) -> Phantom:
-    """Normalise dose, build L = D * LET and the per-row problem."""
+            extra_meta=None, dose_scale: Optional[float] = None) -> Phantom:
+    """Normalise dose, build L = D * LET and the per-row problem.  dose_scale: the
+    factor that turns raw depth-dose into Gy per unit fluence, given for a robustness
+    scenario (the nominal plan's), else chosen so that the mean PTV dose at unit
+    fluence is 2 Gy."""
     R = kept.size
     ptv = masks["PTV"]
     d_raw64 = d_raw.astype(np.float64)
     rid = np.repeat(np.arange(R), np.diff(row_ptr))
     rs = np.bincount(rid, weights=d_raw64, minlength=R)
-    A = 2.0 / float(np.mean(rs[ptv])) if ptv.any() else 1.0
+    if dose_scale is not None:
+        A = float(dose_scale)
+    else:
+        A = 2.0 / float(np.mean(rs[ptv])) if ptv.any() else 1.0
     d = (d_raw64 * A).astype(np.float32)
     l = (d.astype(np.float64) * let.astype(np.float64)).astype(np.float32)
     # row sums at unit fluence of the stored FP32 values: place the OAR cDL target
@@ -452,7 +458,8 @@ def clinical(seed: int = 1, progress: Optional[Callable[[str], None]] = None,
 
 
 def small_plan(seed: int, n_rows_target: int, n_cols_target: int, range_scale: float = 1.0,
-               shift_mm: Sequence[float] = (0.0, 0.0, 0.0), tag: str = "") -> Phantom:
+               shift_mm: Sequence[float] = (0.0, 0.0, 0.0), tag: str = "",
+               dose_scale: Optional[float] = None) -> Phantom:
     """One plan of the batched workload: a cubic water grid holding about
     n_rows_target voxels (all kept), two opposed fields with n_cols_target/2 spots
     each, the density of the 32^3 water phantom (sigma 1.5 voxels, 3 mm voxels, ranges
@@ -488,7 +495,8 @@ def small_plan(seed: int, n_rows_target: int, n_cols_target: int, range_scale: f
               "oar_letd_max": 2.0}
     return _finish(f"plan_s{seed}_{n}cube_C{C}{tag}", shape, h, kept, row_ptr, col, d_raw, let,
                    C, masks, bounds, seed, {"iterations": 100, "range_scale": float(range_scale),
-                                            "shift_mm": [float(v) for v in shift_mm]})
+                                            "shift_mm": [float(v) for v in shift_mm]},
+                   dose_scale=dose_scale)
 
 
 # range errors and setup shifts of the robustness scenarios (8 per base plan)
@@ -506,6 +514,29 @@ def scenario_plans(n_base: int = 6, seed: int = 3) -> List[Phantom]:
     for sd, r, c in batch_sizes(n_base, seed):
         for k, (rs, sh) in enumerate(SCENARIOS):
             out.append(small_plan(sd, r, c, range_scale=rs, shift_mm=sh, tag=f"_sc{k}"))
+    return out
+
+
+def robustness_scenarios(seed: int, n_rows_target: int, n_cols_target: int,
+                         shift_mm: float = 2.0, range_error: float = 0.035) -> List[Phantom]:
+    """The nominal plan and the recalculations of its robustness evaluation (Section
+    2.5: +-2 mm setup shifts along each axis and +-3.5 % density, 9 in all): beamlet
+    ranges scaled by 1 -+ range_error (denser water stops the beam earlier) and the
+    beams shifted against the patient.  Every scenario keeps the nominal plan's voxel
+    rows (all voxels of the same grid), beamlets and dose scale, so row i is the same
+    voxel and column j the same beamlet throughout."""
+    nominal = small_plan(seed, n_rows_target, n_cols_target, tag="_nominal")
+    A = float(nominal.meta["dose_scale"])
+    out = [nominal]
+    for k, rs in enumerate((1.0 - range_error, 1.0 + range_error)):
+        out.append(small_plan(seed, n_rows_target, n_cols_target, range_scale=rs,
+                              tag=f"_range{k}", dose_scale=A))
+    for axis in range(3):
+        for sign in (1.0, -1.0):
+            sh = [0.0, 0.0, 0.0]
+            sh[axis] = sign * shift_mm
+            out.append(small_plan(seed, n_rows_target, n_cols_target, shift_mm=sh,
+                                  tag=f"_shift{axis}{'p' if sign > 0 else 'm'}", dose_scale=A))
     return out
 
 
