@@ -277,6 +277,31 @@ fredopt_status fredopt_scenario_dose_let(fredopt_plan *const *plans, int32_t n,
                                          float *letd_min, float *letd_max, void *workspace,
                                          size_t workspace_bytes, void *stream);
 
+/* ---- evaluation: volume histograms and quantiles ---------------------------------- */
+
+/* Cumulative volume histogram of one region of interest (the DVH, LVH or cDLVH of
+ * Figs. 4-5 and Section 2.5): with `values` a device array of n_rows floats (dose,
+ * LETd or cDL per voxel row) and `rows` a device array of the region's n row indices,
+ * cum[b] (device, n_bins + 1 uint32) = the number of the region's rows whose value is
+ * at least b * vmax / n_bins, for b = 0..n_bins (the bin of a value v >= 0 is
+ * floor(v * n_bins / vmax) in FP64, values >= vmax fall in bin n_bins; negative and
+ * NaN values count in no bin).  Exact integer counts.  1 <= n_bins <= 32768, vmax > 0.
+ * Rows outside [0, n_rows) are skipped.  Asynchronous on `stream`. */
+fredopt_status fredopt_volume_histogram(const float *values, int64_t n_rows,
+                                        const int32_t *rows, int64_t n, double vmax,
+                                        int32_t n_bins, uint32_t *cum, void *stream);
+
+/* Nearest-rank quantiles of one region's values, exactly as a sort would give them:
+ * out[k] (device, n_q floats) = the value at 1-based rank max(1, ceil(q[k] n)) of the
+ * region's values in ascending order, for host q[k] in (0, 1], 1 <= n_q <= 16.  D95
+ * of a PTV is q = 0.05 of its doses (the dose the hottest 95 % receive at least), D98
+ * q = 0.02; the cDL30 of an OAR that sets its percentile constraint from a forward
+ * calculation (Section 2.4.1) is q = 0.70 of its cDL.  An empty region gives 0.
+ * Rows as for fredopt_volume_histogram.  Asynchronous on `stream`. */
+fredopt_status fredopt_roi_quantiles(const float *values, int64_t n_rows, const int32_t *rows,
+                                     int64_t n, const double *q, int32_t n_q, float *out,
+                                     void *stream);
+
 /* Thread-local description of the last failing call on this thread. */
 const char *fredopt_last_error(void);
 

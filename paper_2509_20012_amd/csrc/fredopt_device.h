@@ -45,6 +45,8 @@ enum : unsigned {
   kObjDose = 0x20u, kObjCdl = 0x40u, kConstraintBits = 0x1Fu
 };
 constexpr int kSearchWindow = 16;      // candidate exponents per pass of the step search
+constexpr int kMaxQuantiles = 16;      // ranks per quantile call
+constexpr int kMaxHistBins = 32768;    // bins of a volume histogram (LDS counts)
 
 // stored value type of a plan's matrices; kF16I / kBF16I also keep the column
 // indices of the sliced-ELL copy in 16 bits (the column-major copy keeps int32 rows)

@@ -35,6 +35,16 @@ hipError_t set_scatter_lds_limit(size_t bytes);
 void launch_scatter_sum(int mode, const DevPlan* plans, const ScItem* items, int n_items,
                         hipStream_t s);
 
+// evaluation kernels (kernels_eval.hip)
+// cum[b], b = 0..n_bins: rows of the list with value >= b vmax / n_bins (last bin: >= vmax)
+void launch_volume_histogram(const float* values, int64_t n_rows, const int32_t* rows,
+                             int64_t n, double vmax, int n_bins, uint32_t* cum, int n_cu,
+                             hipStream_t s);
+hipError_t set_histogram_lds_limit(size_t bytes);
+// out[k]: the value at 1-based rank ranks[k] of the list's values in ascending order
+void launch_quantiles(const float* values, int64_t n_rows, const int32_t* rows, int64_t n,
+                      const int64_t* ranks, int n_q, float* out, hipStream_t s);
+
 // load kernels (kernels_load.hip)
 // flags bits: 1 column index out of range, 2 columns not strictly increasing,
 //             4 non-finite or negative value

@@ -2224,4 +2224,52 @@ fredopt_status fredopt_scenario_dose_let(fredopt_plan* const* plans, int32_t n, 
   return FREDOPT_OK;
 }
 
+// ---------------------------------------------------------------- evaluation ----
+
+fredopt_status fredopt_volume_histogram(const float* values, int64_t n_rows, const int32_t* rows,
+                                        int64_t n, double vmax, int32_t n_bins, uint32_t* cum,
+                                        void* stream) {
+  if (!cum || (n > 0 && (!values || !rows)))
+    return fail(FREDOPT_E_ARG, "values, rows and cum must be non-NULL");
+  if (n_rows < 0 || n < 0) return fail(FREDOPT_E_SHAPE, "n_rows and n must be >= 0");
+  if (!(vmax > 0.0) || !std::isfinite(vmax)) return fail(FREDOPT_E_ARG, "vmax must be positive");
+  if (n_bins < 1 || n_bins > kMaxHistBins)
+    return fail(FREDOPT_E_ARG, "n_bins must lie in [1, %d], got %d", kMaxHistBins, n_bins);
+  int dev = 0, ncu = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  HIPCHK(set_histogram_lds_limit(sizeof(uint32_t) * (kMaxHistBins + 1)));
+  launch_volume_histogram(values, n_rows, rows, n, vmax, n_bins, cum, ncu,
+                          static_cast<hipStream_t>(stream));
+  HIPCHK(hipGetLastError());
+  return FREDOPT_OK;
+}
+
+fredopt_status fredopt_roi_quantiles(const float* values, int64_t n_rows, const int32_t* rows,
+                                     int64_t n, const double* q, int32_t n_q, float* out,
+                                     void* stream) {
+  if (!q || !out || (n > 0 && (!values || !rows)))
+    return fail(FREDOPT_E_ARG, "values, rows, q and out must be non-NULL");
+  if (n_rows < 0 || n < 0) return fail(FREDOPT_E_SHAPE, "n_rows and n must be >= 0");
+  if (n_q < 1 || n_q > kMaxQuantiles)
+    return fail(FREDOPT_E_ARG, "n_q must lie in [1, %d], got %d", kMaxQuantiles, n_q);
+  for (int32_t k = 0; k < n_q; ++k)
+    if (!(q[k] > 0.0 && q[k] <= 1.0)) return fail(FREDOPT_E_ARG, "q[%d] must lie in (0, 1]", k);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (n == 0) {  // an empty region: every quantile is 0
+    HIPCHK(hipMemsetAsync(out, 0, sizeof(float) * (size_t)n_q, s));
+    return FREDOPT_OK;
+  }
+  int64_t ranks[kMaxQuantiles];
+  for (int32_t k = 0; k < n_q; ++k) {
+    // nearest rank: ceil(q n), at least 1 (a guard of 1e-12 keeps q n = 95.0000000001
+    // from rounding up a representation error)
+    int64_t r = (int64_t)std::ceil(q[k] * (double)n - 1e-12);
+    ranks[k] = std::min<int64_t>(std::max<int64_t>(r, 1), n);
+  }
+  launch_quantiles(values, n_rows, rows, n, ranks, n_q, out, s);
+  HIPCHK(hipGetLastError());
+  return FREDOPT_OK;
+}
+
 }  // extern "C"

@@ -95,7 +95,7 @@ EXPORTED = ("fredopt_workspace_bytes", "fredopt_workspace_bytes_csr",
             "fredopt_profile_kernels", "fredopt_autotune", "fredopt_set_tuning",
             "fredopt_set_scatter", "fredopt_batch_workspace_bytes", "fredopt_batch_create",
             "fredopt_batch_solve", "fredopt_batch_free", "fredopt_scenario_workspace_bytes",
-            "fredopt_scenario_dose_let")
+            "fredopt_scenario_dose_let", "fredopt_volume_histogram", "fredopt_roi_quantiles")
 
 _lib = None
 
@@ -141,6 +141,10 @@ def lib():
         L.fredopt_batch_solve.argtypes = [P, ct.POINTER(Params), ct.POINTER(State),
                                           ct.POINTER(ct.c_void_p), ct.c_int32, P]
         L.fredopt_batch_free.argtypes = [P]
+        L.fredopt_volume_histogram.argtypes = [P, ct.c_int64, P, ct.c_int64, ct.c_double,
+                                               ct.c_int32, P, P]
+        L.fredopt_roi_quantiles.argtypes = [P, ct.c_int64, P, ct.c_int64,
+                                            ct.POINTER(ct.c_double), ct.c_int32, P, P]
         L.fredopt_scenario_workspace_bytes.argtypes = [ct.POINTER(ct.c_void_p), ct.c_int32]
         L.fredopt_scenario_workspace_bytes.restype = ct.c_size_t
         L.fredopt_scenario_dose_let.argtypes = [ct.POINTER(ct.c_void_p), ct.c_int32, P,
@@ -367,6 +371,51 @@ def scenario_dose_let(plans, x, c: float = 0.04, stream=None,
         _ptr(out.get("letd_min")), _ptr(out.get("letd_max")), _ptr(ws), nbytes,
         _stream(stream)))
     return out
+
+
+def _roi_rows(rows, n_rows: int, device):
+    """A region's row indices as a device int32 tensor, checked against n_rows."""
+    torch = _torch()
+    if isinstance(rows, torch.Tensor):
+        rows = rows.detach().cpu().numpy()
+    r = np.ascontiguousarray(rows, np.int64)
+    if r.size and (r.min() < 0 or r.max() >= n_rows):
+        raise FredoptError(-3, f"region rows must lie in [0, {n_rows})")
+    return torch.from_numpy(r.astype(np.int32)).to(device)
+
+
+def volume_histogram(values, rows, vmax: float, n_bins: int, stream=None):
+    """Cumulative volume histogram of a region (DVH / LVH / cDLVH): a device uint32
+    tensor cum[0..n_bins], cum[b] = rows with value >= b vmax / n_bins."""
+    torch = _torch()
+    n_rows = int(values.numel())
+    rt = _roi_rows(rows, n_rows, values.device)
+    cum = torch.empty(n_bins + 1, dtype=torch.int32, device=values.device)
+    _check(lib().fredopt_volume_histogram(_dev(values, n_rows, "values"), n_rows, _ptr(rt),
+                                          int(rt.numel()), float(vmax), int(n_bins), _ptr(cum),
+                                          _stream(stream)))
+    return cum
+
+
+def roi_quantiles(values, rows, qs, stream=None):
+    """Nearest-rank quantiles (value at rank ceil(q n)) of a region's values: a device
+    float tensor, one entry per q (D95: q = 0.05 of dose, cDL30: q = 0.70 of cDL)."""
+    torch = _torch()
+    n_rows = int(values.numel())
+    rt = _roi_rows(rows, n_rows, values.device)
+    qa = (ct.c_double * len(qs))(*[float(q) for q in qs])
+    out = torch.empty(len(qs), dtype=torch.float32, device=values.device)
+    _check(lib().fredopt_roi_quantiles(_dev(values, n_rows, "values"), n_rows, _ptr(rt),
+                                       int(rt.numel()), qa, len(qs), _ptr(out),
+                                       _stream(stream)))
+    return out
+
+
+def percentile_target(plan: Plan, x, rows, c: float = 0.04, q: float = 0.70) -> float:
+    """A percentile constraint from a forward calculation (Section 2.4.1): the cDL of
+    fluence x over a region, and its nearest-rank q quantile (cDL30 for q = 0.70)."""
+    _, _, cdl = dose_let(plan, x, c, want=("cdl",))
+    return float(roi_quantiles(cdl, rows, [q])[0].item())
 
 
 def project_sweep(plan: Plan, problem: DeviceProblem, params: SolverParams, x,
