@@ -368,6 +368,64 @@ double orc_ams_simultaneous(const orc_mat *m, const orc_problem *p, double lambd
   return wall > 0.0 ? 0.5 * prox / wall : 0.0;
 }
 
+/* Block-sequential form of the sweep (Fig. 2 processes one constraint after the
+ * other on the current x; the text calls for projections in parallel, and the
+ * simultaneous form above takes them all at one x).  Rows are cut into consecutive
+ * blocks of block_rows rows; the blocks are taken in ascending order, each as a
+ * simultaneous relaxed projection of its own rows' constraints at the current x,
+ * with the weights normalised over that block only (convex over its enabled pairs,
+ * over its violated pairs, or raw).  x >= 0 is imposed once, after the last block,
+ * as Fig. 2 clamps at the end.  One block of R rows is the simultaneous sweep;
+ * blocks of one row with one constraint each and raw weights are the sequential
+ * sweep of Fig. 2. */
+void orc_ams_blocks(const orc_mat *m, const orc_problem *p, double lambda, double weight_scale,
+                    int normalization, int64_t block_rows, const double *y, double *x_out) {
+  int64_t R = m->R, C = m->C;
+  double *x = (double *)malloc((size_t)(C ? C : 1) * sizeof(double));
+  double *d = (double *)malloc((size_t)(R ? R : 1) * sizeof(double));
+  double *l = (double *)malloc((size_t)(R ? R : 1) * sizeof(double));
+  double *cd = (double *)malloc((size_t)(R ? R : 1) * sizeof(double));
+  double *cl = (double *)malloc((size_t)(R ? R : 1) * sizeof(double));
+  double *t = (double *)malloc((size_t)(C ? C : 1) * sizeof(double));
+  memcpy(x, y, (size_t)C * sizeof(double));
+  if (block_rows < 1) block_rows = 1;
+  for (int64_t b0 = 0; b0 < R; b0 += block_rows) {
+    int64_t b1 = b0 + block_rows < R ? b0 + block_rows : R;
+    orc_forward(m, x, d, l);
+    double wall = 0.0, wviol = 0.0;
+    for (int64_t i = b0; i < b1; ++i)
+      for (int q = 0; q < 5; ++q) {
+        unsigned kb = KIND_ORDER[q];
+        if (!(p->kind[i] & kb)) continue;
+        wall += p->w_feas[i];
+        if (violation(p, i, kb, d[i], l[i]) != 0.0) {
+          double scale, n2 = normal_sq(m, p, i, kb, &scale);
+          if (n2 > DEGENERATE_REL * scale) wviol += p->w_feas[i];
+        }
+      }
+    double W = normalization == 0 ? wall : (normalization == 1 ? wviol : 1.0);
+    memset(cd, 0, (size_t)R * sizeof(double));
+    memset(cl, 0, (size_t)R * sizeof(double));
+    for (int64_t i = b0; i < b1; ++i)
+      for (int q = 0; q < 5; ++q) {
+        unsigned kb = KIND_ORDER[q];
+        if (!(p->kind[i] & kb)) continue;
+        double vi = violation(p, i, kb, d[i], l[i]);
+        if (vi == 0.0) continue;
+        double scale, n2 = normal_sq(m, p, i, kb, &scale);
+        if (!(n2 > DEGENERATE_REL * scale)) continue;
+        double kappa = lambda * (weight_scale * p->w_feas[i] / W) * vi / n2;
+        if (kb == K_DOSE_HI || kb == K_DOSE_LO) cd[i] += kappa;
+        else if (kb == K_CDL_HI || kb == K_CDL_LO) cl[i] += p->c * kappa;
+        else { cl[i] += kappa; cd[i] -= p->letd_max[i] * kappa; }
+      }
+    orc_transposed(m, cd, cl, t);
+    for (int64_t j = 0; j < C; ++j) x[j] = x[j] - t[j];
+  }
+  for (int64_t j = 0; j < C; ++j) x_out[j] = x[j] > 0.0 ? x[j] : 0.0;
+  free(x); free(d); free(l); free(cd); free(cl); free(t);
+}
+
 /* Row dot product <a, x> for one (row, kind). */
 static double row_dot(const orc_mat *m, const orc_problem *p, int64_t i, unsigned kind,
                       const double *x) {

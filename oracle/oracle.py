@@ -105,6 +105,8 @@ def _load():
                                              ct.c_double, ct.c_double, ct.c_int, P, P,
                                              ct.POINTER(ct.c_int64)]
         lib.orc_ams_simultaneous.restype = ct.c_double
+        lib.orc_ams_blocks.argtypes = [ct.POINTER(_Mat), ct.POINTER(_Problem), ct.c_double,
+                                       ct.c_double, ct.c_int, ct.c_int64, P, P]
         lib.orc_ams_sequential.argtypes = [ct.POINTER(_Mat), ct.POINTER(_Problem),
                                            ct.c_double, ct.c_double, P, ct.c_int64, P,
                                            ct.c_int64, P]
@@ -229,6 +231,16 @@ class Oracle:
                                             lam, weight_scale, normalization, _p(y), _p(out),
                                             ct.byref(nv))
         return out, float(prox), int(nv.value)
+
+    def ams_blocks(self, y, block_rows: int, lam: float = 1.0, weight_scale: float = 1.0,
+                   normalization: int = 0) -> np.ndarray:
+        """Block-sequential sweep: consecutive blocks of block_rows rows in ascending
+        order, each a simultaneous projection at the current point; clamp at the end."""
+        y = _f64(y)
+        out = np.empty(self.C)
+        _load().orc_ams_blocks(ct.byref(self._mat), ct.byref(self._prob), lam, weight_scale,
+                               normalization, int(block_rows), _p(y), _p(out))
+        return out
 
     def ams_sequential(self, x, dose_order: Sequence[int], cdl_order: Sequence[int],
                        lam: float = 1.0, weight_scale: float = 1.0) -> np.ndarray:

@@ -546,3 +546,66 @@ def test_one_sided_step_is_the_first_decrease(seed, unit):
         assert o.cost(x - 0.8 ** sn * v) < c0
         assert info["cost_after_perturb"] < info["cost_before"]
         x, k, s = xn, kn, sn
+
+
+# --- block-sequential sweeps (Fig. 2's order over blocks of rows) ------------------
+
+@pytest.mark.parametrize("norm", [0, 1, 2])
+def test_one_block_is_the_simultaneous_sweep(norm):
+    p = ph.tiny_problem(48, 12, 0.3, seed=91)
+    o = Oracle(p)
+    x = _x(12, 91)
+    xs, _, _ = o.ams_simultaneous(x, lam=1.3, weight_scale=0.8, normalization=norm)
+    for block in (48, 1000):
+        xb = o.ams_blocks(x, block, lam=1.3, weight_scale=0.8, normalization=norm)
+        np.testing.assert_array_equal(xb, xs)
+
+
+def test_blocks_of_one_row_are_the_sequential_sweep():
+    """Rows of one dose constraint each, on overlapping beamlets, raw weights and
+    lambda = 1: blocks of one row project onto one half-space after the other, which
+    is Fig. 2's sequential sweep (its dose block, voxels in ascending order).  The
+    sweep with every row in one block differs (the rows interact)."""
+    rng = np.random.default_rng(93)
+    R, C = 8, 5
+    D = rng.uniform(0.2, 1.0, (R, C)).astype(np.float32)
+    L = (D * 3.0).astype(np.float32)
+    x = rng.uniform(0.5, 1.5, C)
+    d0 = D.astype(np.float64) @ x
+    kind = [ph.DOSE_HI if i % 2 == 0 else ph.DOSE_LO for i in range(R)]
+    dose_hi = [0.8 * d0[i] if i % 2 == 0 else 0.0 for i in range(R)]
+    dose_lo = [1.2 * d0[i] if i % 2 == 1 else 0.0 for i in range(R)]
+    p = from_dense(D, L, kind=kind, dose_hi=dose_hi, dose_lo=dose_lo, w_feas=np.ones(R))
+    o = Oracle(p)
+    xq = o.ams_sequential(x, range(R), [], lam=1.0, weight_scale=1.0)
+    x1 = o.ams_blocks(x, 1, lam=1.0, weight_scale=1.0, normalization=2)
+    np.testing.assert_allclose(x1, xq, rtol=1e-13, atol=1e-15)
+    xall = o.ams_blocks(x, R, lam=1.0, weight_scale=1.0, normalization=2)
+    assert np.max(np.abs(xall - xq)) > 1e-3
+
+
+def test_block_sweep_fixed_point_and_blocks():
+    """A feasible non-negative point is fixed for every block size; two blocks equal
+    two simultaneous sweeps of the halves' sub-problems taken one after the other."""
+    p = ph.tiny_problem(40, 10, 0.3, seed=95)
+    o = Oracle(p)
+    D, L = dense(p)
+    x = _x(10, 95)
+    for block in (1, 7, 20, 40):
+        pa = ph.tiny_problem(40, 10, 0.3, seed=95)
+        pa.kind[:] = 0  # no constraints: every point is feasible
+        np.testing.assert_array_equal(Oracle(pa).ams_blocks(x, block), x)
+    # two blocks of 20 rows: the first half's sweep, then the second half's, each with
+    # weights normalised over its own half, the clamp at the end only
+    half = [ph.tiny_problem(40, 10, 0.3, seed=95), ph.tiny_problem(40, 10, 0.3, seed=95)]
+    half[0].kind[20:] = 0
+    half[1].kind[:20] = 0
+    y = x.copy()
+    for h in half:
+        oh = Oracle(h)
+        # the half sweep without its clamp: raw move of the simultaneous form
+        t = oh.ams_simultaneous(y, lam=1.2, weight_scale=0.9, normalization=0)[0]
+        assert np.all(t > 0)   # no clamp in play at this point
+        y = t
+    xb = o.ams_blocks(x, 20, lam=1.2, weight_scale=0.9, normalization=0)
+    np.testing.assert_allclose(xb, y, rtol=1e-13, atol=1e-15)
