@@ -291,6 +291,56 @@ def bench_robust(args):
     }
 
 
+def bench_sweeps(args):
+    """Feasibility seeking alone, simultaneous against block-sequential: sweeps from x0
+    with weights w_i (no decay), the proximity of every iterate and the time per
+    sweep.  One sweep streams every row once in every form; the blocks add launches."""
+    import torch
+    from paper_2509_20012_amd import fredopt
+    wl = args.sweep_plan
+    p = make_workload(wl)
+    plan, prob, x0 = fredopt.load_phantom(p)
+    q = fredopt.SolverParams()
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    forms = {"simultaneous": None}
+    for b in (8192, 65536):
+        if b < p.n_rows:
+            forms[f"blocks of {b} rows"] = b
+    out = {}
+    for name, block in forms.items():
+        x = x0.clone()
+        prox = [fredopt.project_sweep(plan, prob, q, x.clone())]
+        ms = 0.0
+        for _ in range(args.steps):
+            torch.cuda.synchronize()
+            ev0.record(stream)
+            if block is None:
+                fredopt.project_sweep(plan, prob, q, x)
+            else:
+                fredopt.project_sweep_blocks(plan, prob, q, x, block)
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            ms += ev0.elapsed_time(ev1)
+            prox.append(fredopt.project_sweep(plan, prob, q, x.clone()))
+        out[name] = {"ms_per_sweep": round(ms / args.steps, 4),
+                     "proximity": [float(f"{v:.6g}") for v in prox]}
+        log(f"{name}: {ms / args.steps:.3f} ms per sweep, proximity {prox[0]:.4g} -> "
+            f"{prox[-1]:.4g}")
+    sim = out["simultaneous"]
+    return {
+        "metric": METRIC, "value": round(1e3 / sim["ms_per_sweep"], 2), "unit": "sweeps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": 0, "ms_per_step": sim["ms_per_sweep"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"sweeps: {p.name}, {p.n_rows} x {p.n_cols}, {p.nnz} entries",
+                   "weights": "w_i, no decay, convex over all constraints, lambda 1"},
+        "value_meaning": "simultaneous feasibility sweeps per second (each host-synchronised)",
+        "forms": out,
+    }
+
+
 def bench_serve(args):
     """Poisson stream of re-optimisation requests (4/s), sizes as the batched plans
     plus 10 % at clinical scale, 200-1,000 iterations each, memory budget 200 GB;
@@ -394,7 +444,9 @@ def main():
                          "beamlets), clinical_x<scale>, batch48 (48 plans in batched "
                          "launches), scenarios48 (6 plans x 8 robustness scenarios), "
                          "robust9 (robustness evaluation of one fluence under 9 "
-                         "scenarios) or serve (request stream, continuous batching)")
+                         "scenarios), sweeps (simultaneous against block-sequential "
+                         "feasibility sweeps) or serve (request stream, continuous "
+                         "batching)")
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16", "f16i16", "bf16i16"],
                     help="matrix values in FP32, FP16 or BF16 (per-beamlet FP32 scale); the "
                          "i16 forms also keep column indices in 16 bits")
@@ -425,6 +477,8 @@ def main():
     ap.add_argument("--profile-iters", type=int, default=5)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (for PMC scaling)")
+    ap.add_argument("--sweep-plan", default="clinical",
+                    help="sweeps: the plan (clinical or water32)")
     ap.add_argument("--requests", type=int, default=120, help="serve: trace length")
     ap.add_argument("--quantum", type=int, default=50, help="serve: iterations per round")
     ap.add_argument("--rate", type=float, default=4.0, help="serve: requests per second")
@@ -445,9 +499,11 @@ def main():
         raise SystemExit("bench.py needs a HIP device")
     torch.cuda.set_device(0)
     fredopt.lib()
-    if args.workload in ("batch48", "scenarios48", "serve", "robust9"):
+    if args.workload in ("batch48", "scenarios48", "serve", "robust9", "sweeps"):
         if args.workload == "serve":
             res = bench_serve(args)
+        elif args.workload == "sweeps":
+            res = bench_sweeps(args)
         elif args.workload == "robust9":
             res = bench_robust(args)
         else:

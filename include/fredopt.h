@@ -252,6 +252,20 @@ fredopt_status fredopt_solve(fredopt_plan *p, const fredopt_problem *pr,
                              const fredopt_params *q, fredopt_state *st, float *x_inout,
                              void *stream);
 
+/* Block-sequential sweep (Fig. 2 takes the constraints one after another on the
+ * current fluence; this takes them in consecutive blocks of block_rows rows, in
+ * ascending row order): each block is a simultaneous relaxed projection of its own
+ * rows' constraints at the current x, with weights weight_scale * w_i / W normalised
+ * over that block (q->normalization), and x >= 0 is imposed once after the last
+ * block, as Fig. 2 does.  block_rows >= n_rows is the simultaneous sweep of
+ * fredopt_project_sweep; otherwise it must be a multiple of 8192 (the layout keeps
+ * such blocks of rows contiguous).  Uses the active-row projection for every block.
+ * In place on the device fluence x_inout[n_cols].  Synchronises `stream`. */
+fredopt_status fredopt_project_sweep_blocks(fredopt_plan *p, const fredopt_problem *pr,
+                                            const fredopt_params *q, double weight_scale,
+                                            int64_t block_rows, float *x_inout,
+                                            void *stream);
+
 /* ---- robustness evaluation ---------------------------------------------------- */
 
 /* Device workspace of fredopt_scenario_dose_let for these n plans (0 for invalid

@@ -67,7 +67,9 @@ enum ColMode : int {
   kColProjY = 4,     // x = y = max(0, y - scale sum)
   kColYMove = 5,     // y -= beta g (no sum)
   kColYCopy = 6,     // y = x (no sum)
-  kColProjYMove = 7  // x = y = max(0, y - beta g - scale sum)
+  kColProjYMove = 7, // x = y = max(0, y - beta g - scale sum)
+  kColProjNoClamp = 8,  // x = x - scale sum (a block of a block-sequential sweep)
+  kColClamp = 9      // x = max(0, x) (the end of a block-sequential sweep)
 };
 // which vector a forward pass multiplies
 // kVecYMove: y - beta g, the perturbed point after the pending step (staged in LDS

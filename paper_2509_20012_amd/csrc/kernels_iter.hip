@@ -927,6 +927,10 @@ __device__ __forceinline__ void project_column(const DevPlan* __restrict__ P, in
   if constexpr (MODE == kColProjYMove)
     y = (double)(float)(y - P->st->step * (double)gconst(P->g)[j]);
   const double xn = y - P->st->scale * (double)t;
+  if constexpr (MODE == kColProjNoClamp) {  // the clamp waits for the sweep's end
+    gmut(P->x)[j] = (float)xn;
+    return;
+  }
   const float xf = xn > 0.0 ? (float)xn : 0.f;
   gmut(P->x)[j] = xf;
   if constexpr (fromy) gmut(P->y)[j] = xf;
@@ -1002,6 +1006,9 @@ __global__ __launch_bounds__(kBlock) void k_tcol(const DevPlan* __restrict__ pla
   if (j < cb.c1) {
     if constexpr (MODE == kColYCopy) {
       gmut(P->y)[j] = gconst(P->x)[j];
+    } else if constexpr (MODE == kColClamp) {
+      const float v = gconst(P->x)[j];
+      gmut(P->x)[j] = v > 0.f ? v : 0.f;
     } else if constexpr (MODE == kColYMove) {
       const double b = P->st->step;
       gmut(P->y)[j] = (float)((double)gconst(P->y)[j] - b * (double)gconst(P->g)[j]);
@@ -1389,7 +1396,9 @@ void launch_scatter(int vtype, const DevPlan* plans, const ScItem* items, int n_
 void launch_scatter_sum(int mode, const DevPlan* plans, const ScItem* items, int n_items,
                         hipStream_t s) {
   if (n_items <= 0) return;
-  if (mode == kColProjYMove)
+  if (mode == kColProjNoClamp)
+    k_scatter_sum<kColProjNoClamp><<<n_items, kScatterBlock, 0, s>>>(plans, items);
+  else if (mode == kColProjYMove)
     k_scatter_sum<kColProjYMove><<<n_items, kScatterBlock, 0, s>>>(plans, items);
   else if (mode == kColProjY)
     k_scatter_sum<kColProjY><<<n_items, kScatterBlock, 0, s>>>(plans, items);
@@ -1420,6 +1429,7 @@ void launch_tcol(int mode, const DevPlan* plans, const ColBlock* blocks, int n_b
     case kColProjMove: k_tcol<kColProjMove><<<n_blocks, kBlock, 0, s>>>(plans, blocks); break;
     case kColProjY: k_tcol<kColProjY><<<n_blocks, kBlock, 0, s>>>(plans, blocks); break;
     case kColYMove: k_tcol<kColYMove><<<n_blocks, kBlock, 0, s>>>(plans, blocks); break;
+    case kColClamp: k_tcol<kColClamp><<<n_blocks, kBlock, 0, s>>>(plans, blocks); break;
     default: k_tcol<kColYCopy><<<n_blocks, kBlock, 0, s>>>(plans, blocks); break;
   }
 }

@@ -143,10 +143,12 @@ struct Layout {
   size_t y, osbase, oswidth, osrow, osci, osdv, oslv, ogroups, pk_src, pk_dst, pk_len;
   size_t spart_a, spart_b, rpart, gpart, tpart, groups, row_items, tr_items, col_blocks;
   size_t bc, colcount, colmax, flags, rslice, rsum, goff, alist, spart, smask, sc_items,
-      ss_items, pkind, pf, okind, of, ovec, gcoef, coef_row, rptr, plen, rci, rdv, rlv, total;
+      ss_items, pkind, pf, okind, of, ovec, gcoef, coef_row, rptr, plen, rci, rdv, rlv, btable,
+      bgroups, total;
   int64_t NP;                 // positions of the all-row view
   int64_t sell_slots, n_slices, csc_slots, obj_slots, max_rows, max_tr, n_groups, n_col_blocks;
   int64_t row_slots;          // row-contiguous copy: every row padded to 4 slots
+  int64_t max_blocks;         // blocks of a block-sequential sweep (one per sort window)
   int64_t obj_sell_slots, max_obj_slices, max_obj_groups, max_obj_srow;
   int64_t rows_per_block, nb;
 };
@@ -271,6 +273,9 @@ bool make_layout(int64_t R, int64_t C, int64_t nnz, int storage, int lpr_log2,
   L->rci = take((size_t)index_bytes(storage) * std::max<int64_t>(L->row_slots, 1));
   L->rdv = take((size_t)vb * std::max<int64_t>(L->row_slots, 1));
   L->rlv = take((size_t)vb * std::max<int64_t>(L->row_slots, 1));
+  L->max_blocks = R / kSortWindow + 2;
+  L->btable = take(sizeof(DevPlan) * L->max_blocks);
+  L->bgroups = take(sizeof(FwdGroup) * (L->n_groups + L->max_blocks));
   L->total = o;
   return true;
 }
@@ -322,6 +327,8 @@ struct fredopt_plan {
   std::vector<int32_t> col_ts0, col_nch, gcol_ts0, gcol_nch;
   std::vector<int32_t> row_len;       // real row lengths
   std::vector<int64_t> rptr;          // row-contiguous copy: first slot per position
+  int64_t blk_rows = 0;               // block-sequential sweep: rows per block (cached lists)
+  std::vector<int32_t> blk_g0, blk_ng;  // its blocks' first group and group count
   Sell osell;                         // objective-row view (host tables)
   std::vector<FwdGroup> ogroups;
   bool sched_obj = false;             // iterations use the objective-row view
@@ -2269,6 +2276,92 @@ fredopt_status fredopt_roi_quantiles(const float* values, int64_t n_rows, const 
   }
   launch_quantiles(values, n_rows, rows, n, ranks, n_q, out, s);
   HIPCHK(hipGetLastError());
+  return FREDOPT_OK;
+}
+
+// ----------------------------------------------------- block-sequential sweep ----
+
+fredopt_status fredopt_project_sweep_blocks(fredopt_plan* p, const fredopt_problem* pr,
+                                            const fredopt_params* q, double weight_scale,
+                                            int64_t block_rows, float* x_inout, void* stream) {
+  if (!p || !x_inout) return fail(FREDOPT_E_ARG, "plan and x must be non-NULL");
+  fredopt_status st = check_problem_ptrs(pr, p->R);
+  if (st != FREDOPT_OK) return st;
+  if ((st = check_params(q, false)) != FREDOPT_OK) return st;
+  if (!(weight_scale > 0.0) || !std::isfinite(weight_scale))
+    return fail(FREDOPT_E_ARG, "weight_scale must be positive and finite");
+  if (block_rows < 1 || (block_rows < p->R && block_rows % kSortWindow != 0))
+    return fail(FREDOPT_E_ARG, "block_rows must be a multiple of %lld rows (or cover every "
+                "row), got %lld", (long long)kSortWindow, (long long)block_rows);
+  if (p->n_scatter <= 0)
+    return fail(FREDOPT_E_STATE, "block sweeps use the active-row projection, which is off "
+                "for this plan (fredopt_set_scatter)");
+  DeviceGuard guard(p->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if ((st = bind_problem(p, pr, false, s)) != FREDOPT_OK) return st;
+  set_problem(p, pr, q, weight_scale, x_inout);
+  if ((st = upload_table(p, s)) != FREDOPT_OK) return st;
+  fredopt_state zero{};
+  zero.s = -1;
+  if ((st = upload_state(p, &zero, s)) != FREDOPT_OK) return st;
+  const Layout& L = p->L;
+  const int64_t R = p->R;
+  const int64_t rows_b = std::min<int64_t>(block_rows, std::max<int64_t>(R, 1));
+  // blocks of whole sort windows: their rows own a contiguous range of slices
+  const int rpw = kWave >> p->sell.lpr_log2;
+  std::vector<FwdGroup> bg;
+  if (p->blk_rows != rows_b) {
+    p->blk_g0.clear();
+    p->blk_ng.clear();
+    int64_t slice = 0;
+    for (int64_t r0 = 0; r0 < R; r0 += rows_b) {
+      const int64_t r1 = std::min(R, r0 + rows_b);
+      int64_t n_sl = 0;  // slices of the windows [r0, r1): each window's own count
+      for (int64_t w0 = r0; w0 < r1; w0 += kSortWindow)
+        n_sl += (std::min(r1, w0 + kSortWindow) - w0 + rpw - 1) / rpw;
+      p->blk_g0.push_back((int32_t)bg.size());
+      int32_t slot = 0;
+      for (int64_t s0 = slice; s0 < slice + n_sl; s0 += kFwdWaves)
+        bg.push_back(FwdGroup{0, (int32_t)s0, (int32_t)std::min<int64_t>(kFwdWaves, slice + n_sl - s0),
+                              slot++});
+      p->blk_ng.push_back(slot);
+      slice += n_sl;
+    }
+    if (slice != p->sell.n_slices || (int64_t)p->blk_g0.size() > L.max_blocks ||
+        (int64_t)bg.size() > L.n_groups + L.max_blocks)
+      return fail(FREDOPT_E_STATE, "block layout does not match the plan's slices");
+    HIPCHK(hipMemcpyAsync(p->ws + L.bgroups, bg.data(), sizeof(FwdGroup) * bg.size(),
+                          hipMemcpyHostToDevice, s));
+    p->blk_rows = rows_b;
+  }
+  const int nb = (int)p->blk_g0.size();
+  // one descriptor per block: the plan's, with the block's group count (its partial
+  // slots) and the active-row projection for every active count
+  std::vector<DevPlan> tb((size_t)std::max(nb, 1), p->hp);
+  for (int b = 0; b < nb; ++b) {
+    tb[b].sell.n_groups = p->blk_ng[b];
+    tb[b].scatter_max_rows = INT32_MAX;
+  }
+  DevPlan* d_tb = at<DevPlan>(p, L.btable);
+  HIPCHK(hipMemcpyAsync(d_tb, tb.data(), sizeof(DevPlan) * (size_t)nb, hipMemcpyHostToDevice, s));
+  const FwdGroup* d_bg = at<FwdGroup>(p, L.bgroups);
+  for (int b = 0; b < nb; ++b) {
+    if (p->blk_ng[b] == 0) continue;
+    Exec e = exec_of(p);
+    e.table = d_tb + b;
+    e.groups = d_bg + p->blk_g0[b];
+    e.n_groups = p->blk_ng[b];
+    enqueue(e, Launch{FREDOPT_KERNEL_FWD_RESID, kKindFwd, kFwdResid, 0, kVecX}, s);
+    enqueue(e, Launch{FREDOPT_KERNEL_FINALIZE, kKindFin, kFinResidFwd}, s);
+    enqueue(e, Launch{FREDOPT_KERNEL_ACTIVE_LIST, kKindList, 0}, s);
+    enqueue(e, Launch{FREDOPT_KERNEL_SCATTER, kKindScatter, 0}, s);
+    enqueue(e, Launch{FREDOPT_KERNEL_SCATTER_SUM, kKindScatterSum, kColProjNoClamp}, s);
+  }
+  enqueue(p, Launch{FREDOPT_KERNEL_COL, kKindCol, kColClamp}, s);
+  HIPCHK(hipGetLastError());
+  DevState d;
+  if ((st = download_state(p, &d, s)) != FREDOPT_OK) return st;  // synchronises
+  if (d.nonfinite) return fail(FREDOPT_E_NONFINITE, "non-finite value during the sweep");
   return FREDOPT_OK;
 }
 

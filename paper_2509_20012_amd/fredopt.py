@@ -95,7 +95,8 @@ EXPORTED = ("fredopt_workspace_bytes", "fredopt_workspace_bytes_csr",
             "fredopt_profile_kernels", "fredopt_autotune", "fredopt_set_tuning",
             "fredopt_set_scatter", "fredopt_batch_workspace_bytes", "fredopt_batch_create",
             "fredopt_batch_solve", "fredopt_batch_free", "fredopt_scenario_workspace_bytes",
-            "fredopt_scenario_dose_let", "fredopt_volume_histogram", "fredopt_roi_quantiles")
+            "fredopt_scenario_dose_let", "fredopt_volume_histogram", "fredopt_roi_quantiles",
+            "fredopt_project_sweep_blocks")
 
 _lib = None
 
@@ -141,6 +142,8 @@ def lib():
         L.fredopt_batch_solve.argtypes = [P, ct.POINTER(Params), ct.POINTER(State),
                                           ct.POINTER(ct.c_void_p), ct.c_int32, P]
         L.fredopt_batch_free.argtypes = [P]
+        L.fredopt_project_sweep_blocks.argtypes = [P, ct.POINTER(Problem), ct.POINTER(Params),
+                                                   ct.c_double, ct.c_int64, P, P]
         L.fredopt_volume_histogram.argtypes = [P, ct.c_int64, P, ct.c_int64, ct.c_double,
                                                ct.c_int32, P, P]
         L.fredopt_roi_quantiles.argtypes = [P, ct.c_int64, P, ct.c_int64,
@@ -416,6 +419,16 @@ def percentile_target(plan: Plan, x, rows, c: float = 0.04, q: float = 0.70) -> 
     fluence x over a region, and its nearest-rank q quantile (cDL30 for q = 0.70)."""
     _, _, cdl = dose_let(plan, x, c, want=("cdl",))
     return float(roi_quantiles(cdl, rows, [q])[0].item())
+
+
+def project_sweep_blocks(plan: Plan, problem: DeviceProblem, params: SolverParams, x,
+                         block_rows: int, weight_scale: float = 1.0, stream=None):
+    """One block-sequential sweep in place on x (blocks of block_rows rows, a multiple
+    of 8192, or every row)."""
+    pr, q = problem.struct(plan.n_rows), params.struct()
+    _check(lib().fredopt_project_sweep_blocks(plan.handle, ct.byref(pr), ct.byref(q),
+                                              float(weight_scale), int(block_rows),
+                                              _dev(x, plan.n_cols, "x"), _stream(stream)))
 
 
 def project_sweep(plan: Plan, problem: DeviceProblem, params: SolverParams, x,

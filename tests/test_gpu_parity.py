@@ -631,3 +631,47 @@ def test_set_scatter_arguments(fo):
     for bad in [(-2, -1), (257, -1), (0, -2)]:
         with pytest.raises(fo.FredoptError):
             fo.set_scatter(plan, *bad)
+
+
+@pytest.mark.parametrize("norm", [0, 1, 2])
+@pytest.mark.parametrize("block", [8192, 16384, 32768])
+def test_block_sequential_sweep_water32(fo, w32, block, norm):
+    """Block-sequential sweeps (4, 2 and 1 blocks of the 32,768 rows) against the
+    oracle's, three in a row at T2; one block equals the simultaneous sweep on the
+    active-row path bit for bit."""
+    import torch
+    print(f"block sweep water32 block={block} norm={norm}", flush=True)
+    plan, prob, x0 = fo.load_phantom(w32)
+    q = _params(fo, lam=1.2, normalization=norm)
+    o = Oracle(w32)
+    x = x0.clone()
+    xr = w32.x0.astype(np.float64)
+    for it in range(3):
+        fo.project_sweep_blocks(plan, prob, q, x, block, weight_scale=0.9)
+        xr = o.ams_blocks(xr, block, lam=1.2, weight_scale=0.9, normalization=norm)
+        assert np.linalg.norm(_np(x) - xr) <= T2 * np.linalg.norm(xr), it
+    if block == 32768:
+        _set_path(fo, plan, "scatter")
+        xa, xb = x0.clone(), x0.clone()
+        fo.project_sweep(plan, prob, q, xa, weight_scale=0.9)
+        fo.project_sweep_blocks(plan, prob, q, xb, block, weight_scale=0.9)
+        torch.cuda.synchronize()
+        assert np.array_equal(_np(xa), _np(xb))
+
+
+def test_block_sequential_sweep_ragged(fo):
+    """20,000 random rows (windows of 8,192, 8,192 and 3,616 rows; lanes per row 1 and
+    4), against the oracle; a block size that is not a multiple of 8,192 is refused."""
+    p = ph.tiny_problem(20000, 300, 0.01, seed=97)
+    o = Oracle(p)
+    for lpr in (1, 4):
+        print(f"block sweep ragged lpr={lpr}", flush=True)
+        plan, prob, x0 = fo.load_phantom(p, lanes_per_row=lpr)
+        q = _params(fo, lam=1.0, normalization=0)
+        x = x0.clone()
+        fo.project_sweep_blocks(plan, prob, q, x, 8192)
+        xr = o.ams_blocks(p.x0, 8192, lam=1.0, weight_scale=1.0, normalization=0)
+        assert np.linalg.norm(_np(x) - xr) <= T2 * np.linalg.norm(xr)
+        with pytest.raises(fo.FredoptError) as e:
+            fo.project_sweep_blocks(plan, prob, q, x, 5000)
+        assert e.value.name == "E_ARG"
