@@ -375,6 +375,32 @@ def bench_serve(args):
     lat_b = [r.latency for r in base]
     log(f"one at a time: p50 {serve.percentile(lat_b, 50):.3f} s, p99 "
         f"{serve.percentile(lat_b, 99):.3f} s, {iters / wall_b:.1f} plan-iterations/s")
+
+    def breakdown(rs):
+        """Latency percentiles per request class, and the mean wait for admission,
+        load time and time from load to result."""
+        out = {}
+        for name, sel in (("clinical", lambda r: r.phantom is big),
+                          ("small", lambda r: r.phantom is not big)):
+            sub = [r for r in rs if sel(r)]
+            if not sub:
+                continue
+            lt = [r.latency for r in sub]
+            out[name] = {
+                "requests": len(sub),
+                "latency_p50_s": round(serve.percentile(lt, 50), 4),
+                "latency_p99_s": round(serve.percentile(lt, 99), 4),
+                "latency_max_s": round(max(lt), 4),
+                "mean_admit_wait_s": round(float(np.mean([r.admitted - r.arrival for r in sub])), 4),
+                "mean_load_s": round(float(np.mean([r.loaded - r.admitted for r in sub])), 4),
+                "mean_solve_s": round(float(np.mean([r.finished - r.loaded for r in sub])), 4),
+            }
+        return out
+
+    by_b, by_o = breakdown(done), breakdown(base)
+    for name in by_b:
+        log(f"  {name}: batching {by_b[name]}")
+        log(f"  {name}: one at a time {by_o[name]}")
     return {
         "metric": METRIC, "value": round(iters / wall, 2), "unit": "iters/s", "n_gpus": 1,
         "steps": iters, "warmup": 0, "ms_per_step": round(wall / iters * 1e3, 5),
@@ -386,9 +412,11 @@ def bench_serve(args):
         "value_meaning": "plan-iterations per second over the whole trace (wall clock)",
         "latency_p50_s": round(serve.percentile(lat, 50), 4),
         "latency_p99_s": round(serve.percentile(lat, 99), 4),
+        "by_class": by_b,
         "one_at_a_time": {"latency_p50_s": round(serve.percentile(lat_b, 50), 4),
                           "latency_p99_s": round(serve.percentile(lat_b, 99), 4),
-                          "iters_per_s": round(iters / wall_b, 2)},
+                          "iters_per_s": round(iters / wall_b, 2),
+                          "by_class": by_o},
         "peak_resident_plans": srv.peak_active, "batches_built": srv.batches_built,
     }
 

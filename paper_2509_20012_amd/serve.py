@@ -5,8 +5,11 @@ time) are admitted while the device memory they need fits a budget; admitted pla
 stay resident and are iterated together by batched launches (fredopt_batch_*):
 continuous batching, where the batch is rebuilt whenever a request joins or
 leaves, between quanta of outer iterations.  A lane with a single active request
-runs the plain single-plan solve instead (no batch to build).  A request's latency runs from its
-arrival to its result (the fluence) being on the host, and includes the load.
+runs the plain single-plan solve instead (no batch to build).  Loads run on a
+loader thread per lane, on a stream of their own: the lane keeps iterating its
+resident plans while the next plan's matrices are copied and laid out, and a
+request joins the batch when its load has completed.  A request's latency runs from
+its arrival to its result (the fluence) being on the host, and includes the load.
 
 Every batched iteration of a plan equals its single-plan iteration bit for bit,
 and quanta resume exactly, so a request's result does not depend on what else was
@@ -18,6 +21,8 @@ served, each request solved alone with the plain single-plan call.
 from __future__ import annotations
 
 import dataclasses
+import queue as _queue
+import threading
 import time
 from typing import Callable, List, Optional
 
@@ -33,6 +38,7 @@ class Request:
     iters: int
     arrival: float             # seconds after the start of the trace
     admitted: Optional[float] = None
+    loaded: Optional[float] = None     # load complete (matrices resident)
     finished: Optional[float] = None
     x: Optional[np.ndarray] = None
     k: int = 0
@@ -59,6 +65,55 @@ class _Active:
         self.state = fredopt.new_state()
         self.left = req.iters
         self.bytes = plan_bytes(req.phantom, storage, reserve)
+        self.loaded: Optional[float] = None
+
+
+class _Loader:
+    """Loads admitted requests in order on a host thread with its own stream.  A load
+    is handed over only after its stream has drained, so the lane's stream sees
+    complete matrices without any cross-stream event.  An exception in a load is
+    handed over in place of the request and raised by the lane."""
+
+    def __init__(self, storage: int, reserve: int, now: Callable[[], float]):
+        self.storage, self.reserve, self.now = storage, reserve, now
+        self.inbox: _queue.Queue = _queue.Queue()
+        self.ready: _queue.Queue = _queue.Queue()
+        self.thread = threading.Thread(target=self._run, daemon=True)
+        self.thread.start()
+
+    def _run(self):
+        import torch
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            while True:
+                req = self.inbox.get()
+                if req is None:
+                    return
+                try:
+                    a = _Active(req, self.storage, self.reserve)
+                    stream.synchronize()
+                    a.loaded = self.now()
+                    self.ready.put(a)
+                except BaseException as e:  # raised by the lane that asked for it
+                    self.ready.put(e)
+
+    def submit(self, req: Request):
+        self.inbox.put(req)
+
+    def take(self, timeout: Optional[float]):
+        """The next finished load, or None when none finishes within timeout
+        (0: do not wait)."""
+        try:
+            got = self.ready.get(block=timeout != 0, timeout=timeout or None)
+        except _queue.Empty:
+            return None
+        if isinstance(got, BaseException):
+            raise got
+        return got
+
+    def close(self):
+        self.inbox.put(None)
+        self.thread.join()
 
 
 class Server:
@@ -88,7 +143,6 @@ class Server:
         self.peak_bytes = 0
 
     def run(self, requests: List[Request]) -> List[Request]:
-        import threading
         queue = sorted(requests, key=lambda r: (r.arrival, r.rid))
         for r in queue:
             if plan_bytes(r.phantom, self.storage, self.reserve) > self.budget:
@@ -124,13 +178,22 @@ class Server:
         return sorted(done, key=lambda r: r.rid)
 
     def _lane(self, queue, lock, state, done, now):
+        loader = _Loader(self.storage, self.reserve, now)
+        try:
+            self._lane_loop(queue, lock, state, done, now, loader)
+        finally:
+            loader.close()
+
+    def _lane_loop(self, queue, lock, state, done, now, loader):
         import torch
         params = dataclasses.replace(self.params)
         active: List[_Active] = []
         batch = None
         qi = 0
-        while qi < len(queue) or active:
-            changed = False
+        loading = 0     # admitted requests whose load has not been handed over yet
+        while qi < len(queue) or active or loading:
+            # admission: arrival order, while the shared budget allows; the memory
+            # is counted from the moment the load starts
             while qi < len(queue) and queue[qi].arrival <= now():
                 need = plan_bytes(queue[qi].phantom, self.storage, self.reserve)
                 with lock:
@@ -143,11 +206,28 @@ class Server:
                 req = queue[qi]
                 qi += 1
                 req.admitted = now()
-                active.append(_Active(req, self.storage, self.reserve))
-                changed = True
+                loader.submit(req)
+                loading += 1
+            # completed loads join; with nothing resident, wait for one (or for the
+            # next arrival)
+            changed = False
+            wait = 0.0
             if not active:
-                wait = queue[qi].arrival - now() if qi < len(queue) else 0.0
-                time.sleep(wait if wait > 0 else 0.001)  # next arrival, or budget freed
+                nxt = queue[qi].arrival - now() if qi < len(queue) else 0.05
+                wait = min(max(nxt, 0.0005), 0.05) if loading else None
+            if wait is None:  # nothing resident or loading: sleep to the next arrival
+                nxt = queue[qi].arrival - now() if qi < len(queue) else 0.0
+                time.sleep(nxt if nxt > 0 else 0.001)  # next arrival, or budget freed
+                continue
+            while loading:
+                a = loader.take(wait)
+                if a is None:
+                    break
+                active.append(a)
+                loading -= 1
+                changed = True
+                wait = 0.0
+            if not active:
                 continue
             n = min(self.quantum, min(a.left for a in active))
             if len(active) == 1:
@@ -178,13 +258,16 @@ class Server:
                     req.x = a.x.cpu().numpy()
                     req.k, req.s = a.state.k, a.state.s
                     req.finished = now()
+                    req.loaded = a.loaded
+                # every launch that reads the finished plans has completed before
+                # their memory goes back to the allocator
+                torch.cuda.current_stream().synchronize()
                 if batch is not None:
                     batch.free()
                     batch = None
                 active = [a for a in active if a.left > 0]
                 for a in finished:
                     a.plan.free()
-                torch.cuda.current_stream().synchronize()
                 with lock:
                     for a in finished:
                         done.append(a.req)
@@ -202,6 +285,7 @@ def serve_one_at_a_time(requests: List[Request], params: fredopt.SolverParams,
                         log: Optional[Callable[[str], None]] = None,
                         gradient_reserve_pct: int = 0) -> List[Request]:
     """First come, first served; each request solved alone by fredopt_solve."""
+    import torch
     queue = sorted(requests, key=lambda r: (r.arrival, r.rid))
     t0 = time.perf_counter()
     now = lambda: time.perf_counter() - t0  # noqa: E731
@@ -212,6 +296,8 @@ def serve_one_at_a_time(requests: List[Request], params: fredopt.SolverParams,
         req.admitted = now()
         plan, prob, x = fredopt.load_phantom(req.phantom, storage=storage,
                                              gradient_reserve_pct=gradient_reserve_pct)
+        torch.cuda.current_stream().synchronize()
+        req.loaded = now()
         st = fredopt.new_state()
         params.iter_max = req.iters
         fredopt.solve(plan, prob, params, st, x)

@@ -35,9 +35,10 @@ def test_served_results_equal_alone(fo):
            ph.tiny_problem(1000, 130, 0.05, seed=5), ph.small_plan(3003, 9000, 400),
            ph.tiny_problem(64, 16, 0.3, seed=6, empty_rows=[0, 5, 63], empty_cols=[3, 15]),
            ph.small_plan(3004, 5000, 220)]
-    iters = [7, 12, 5, 20, 9, 3]
-    # the three small requests (one lane) arrive together: they form a batch, leave
-    # it at different times and the longest finishes alone; the water plans (the
+    iters = [160, 12, 120, 20, 140, 3]
+    # the three small requests (one lane) arrive together; the first to finish its
+    # load starts alone, the others join it as their loads complete (a batch), they
+    # leave at different times and the longest finishes alone; the water plans (the
     # other lane) queue on the budget
     arrivals = [0.0, 0.0, 0.0, 0.0, 0.0, 0.05]
     reqs = [serve.Request(i, p, n, t) for i, (p, n, t) in enumerate(zip(phs, iters, arrivals))]
@@ -56,7 +57,7 @@ def test_served_results_equal_alone(fo):
         x_ref, ks = _alone(fo, r.phantom, fo.SolverParams(alpha=0.9), r.iters)
         assert (r.k, r.s) == ks, r.rid
         assert np.array_equal(r.x, x_ref), r.rid
-        assert r.finished >= r.admitted >= r.arrival
+        assert r.finished >= r.loaded >= r.admitted >= r.arrival
 
 
 def test_one_at_a_time_baseline_runs(fo):
