@@ -28,6 +28,7 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef float v2f __attribute__((ext_vector_type(2)));
 typedef unsigned v2u __attribute__((ext_vector_type(2)));
+typedef double v2d __attribute__((ext_vector_type(2)));
 
 constexpr int kWave = 64;              // CDNA wavefront width
 constexpr int kFwdBlock = 512;         // forward kernel: 8 waves, one slice each

@@ -1038,51 +1038,68 @@ __global__ __launch_bounds__(kBlock) void k_tcol(const DevPlan* __restrict__ pla
 
 // ------------------------------------------------------------ finalisation ----
 
-constexpr int kFinBlock = 512;   // finalisation: one workgroup of 8 waves per plan
+// finalisation: one workgroup of 10 waves per plan; 640 threads is a multiple of the
+// slot count and of the wave, which the coalesced slot sums below rely on
+constexpr int kFinBlock = 640;
 constexpr int kFinWaves = kFinBlock / kWave;
+constexpr int kFinUnroll = 8;      // loads in flight per thread in the slot sums
+constexpr int kCountCap = 16384;   // groups whose active-row counts are kept in LDS
+static_assert(kFinBlock % kNPart == 0 && kFinBlock % kWave == 0, "slot sums");
 
-// Slot-wise sums of n partial slots over the finalisation workgroup: thread t sums
-// the contiguous segment [t per, (t + 1) per) in index order, then wave sums and the
-// waves in order (one pair of barriers for all slots).  Every thread gets the result.
 __device__ __forceinline__ int seg_len(int n) { return (n + kFinBlock - 1) / kFinBlock; }
 
+struct FinShared {
+  double red[2][kFinBlock];  // per-thread sums of its two slots
+  double slot[kNPart];       // the slot sums
+};
+
+// Slot-wise sums of n partial slots of kNPart doubles (kNPart even), read as one flat
+// array of 16-byte pairs: thread t reads pairs t, t + kFinBlock, ... (consecutive
+// threads read consecutive pairs, so a wave's load covers whole lines; every round
+// issues kFinUnroll loads per thread, predicated at the end), and the two doubles of
+// each of its pairs always belong to slots 2t mod kNPart and 2t + 1 mod kNPart.  A
+// slot's thread sums are then added in thread order.  The order is fixed, so the sums
+// do not depend on timing.  With cnt, slot 7 (the groups' active-row counts, integers)
+// is also kept in LDS by group.  Slots not in `used` read as 0.  Every thread gets the
+// result.
 __device__ __forceinline__ void sum_slots(const double* part_, int n, double* out,
-                                          unsigned used, double (*sh)[kNPart],
-                                          double* own = nullptr) {
-  const FO_GLOBAL double* part = gconst(part_);
-  double s[kNPart];
+                                          unsigned used, FinShared* sh, int* cnt = nullptr) {
+  static_assert(kNPart % 2 == 0 && kNPart == 10, "pairs of slots; slot 7 is the odd one of 6, 7");
+  const FO_GLOBAL v2d* part = (const FO_GLOBAL v2d*)gconst(part_);
+  const int t = threadIdx.x;
+  const int pairs = n * (kNPart / 2);
+  const bool keep = cnt != nullptr && (2 * t) % kNPart == 6;
+  double a0 = 0.0, a1 = 0.0;
+  for (int f = t; f < pairs; f += kFinBlock * kFinUnroll) {
+    v2d v[kFinUnroll];
 #pragma unroll
-  for (int k = 0; k < kNPart; ++k) s[k] = 0.0;
-  const int per = seg_len(n), i0 = threadIdx.x * per, i1 = min(n, i0 + per);
-#pragma unroll 4
-  for (int i = i0; i < i1; ++i) {
-    const FO_GLOBAL double* p = part + (int64_t)i * kNPart;
+    for (int u = 0; u < kFinUnroll; ++u) {
+      const int i = f + kFinBlock * u;
+      v[u] = i < pairs ? part[i] : v2d{0.0, 0.0};
+    }
 #pragma unroll
-    for (int k = 0; k < kNPart; ++k)
-      if (used & (1u << k)) s[k] += p[k];
+    for (int u = 0; u < kFinUnroll; ++u) {
+      a0 += v[u].x;
+      a1 += v[u].y;
+      const int i = f + kFinBlock * u;
+      if (keep && i < pairs) cnt[(2 * i + 1) / kNPart] = (int)v[u].y;
+    }
   }
-  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-  if (own) {  // the thread's own segment sums
-#pragma unroll
-    for (int k = 0; k < kNPart; ++k) own[k] = s[k];
-  }
-#pragma unroll
-  for (int k = 0; k < kNPart; ++k)
-    if (used & (1u << k)) s[k] = wave_sum(s[k]);
+  sh->red[0][t] = a0;
+  sh->red[1][t] = a1;
   __syncthreads();
-  if (lane == 0) {
-#pragma unroll
-    for (int k = 0; k < kNPart; ++k)
-      if (used & (1u << k)) sh[wave][k] = s[k];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < kNPart; ++k) {
+  if (t < kNPart) {
+    // slot t: the threads c + 5 m with 2c = t rounded down to even, first or second
+    // double of their pairs
+    const int c = t / 2, h = t & 1;
     double r = 0.0;
-    if (used & (1u << k))
-      for (int w = 0; w < kFinWaves; ++w) r += sh[w][k];
-    out[k] = r;
+    if (used & (1u << t))
+      for (int m = 0; m < kFinBlock / (kNPart / 2); ++m) r += sh->red[h][c + (kNPart / 2) * m];
+    sh->slot[t] = r;
   }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kNPart; ++k) out[k] = sh->slot[k];
   __syncthreads();
 }
 
@@ -1090,18 +1107,18 @@ __device__ __forceinline__ void sum_slots(const double* part_, int n, double* ou
 template <int MODE, int SUB>
 __global__ __launch_bounds__(kFinBlock) void k_finalize(const DevPlan* __restrict__ plans) {
   __shared__ double sh4[kFinWaves];
-  __shared__ double shs[kFinWaves][kNPart];
+  __shared__ FinShared shs;
   const DevPlan* __restrict__ P = plans + blockIdx.x;
   if (halted(P)) return;
   const int ng = SUB ? P->osell.n_groups : P->sell.n_groups;
   double a[kNPart];
   if constexpr (MODE == kFinDir0 || MODE == kFinDir) {
     double b[kNPart];
-    sum_slots(P->spart_b, ng, b, 0x21u, shs);
+    sum_slots(P->spart_b, ng, b, 0x21u, &shs);
     double g = 0.0;
     for (int i = threadIdx.x; i < P->n_col_blocks; i += kFinBlock) g += gconst(P->gpart)[i];
     const double G = block_sum<kFinWaves>(g, sh4);
-    if constexpr (MODE == kFinDir0) sum_slots(P->spart_a, ng, a, 0x21u, shs);
+    if constexpr (MODE == kFinDir0) sum_slots(P->spart_a, ng, a, 0x21u, &shs);
     if (threadIdx.x == 0) {
       DevState* st = P->st;
       if constexpr (MODE == kFinDir0) {
@@ -1120,13 +1137,13 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(const DevPlan* __restric
         prepare_search(P, G, b[0]);
     }
   } else if constexpr (MODE == kFinMoveObj) {
-    sum_slots(P->rpart, P->n_row_items, a, 0x21u, shs);
+    sum_slots(P->rpart, P->n_row_items, a, 0x21u, &shs);
     if (threadIdx.x == 0) {
       P->st->cost_y = a[0];
       if (a[5] > 0.0) P->st->nonfinite = 1;
     }
   } else if constexpr (MODE == kFinResidRows) {
-    sum_slots(P->rpart, P->n_row_items, a, 0x3FFu, shs);
+    sum_slots(P->rpart, P->n_row_items, a, 0x3FFu, &shs);
     if (threadIdx.x == 0) {
       finalize_residuals(P, a);
       P->st->n_active = (int)a[7];
@@ -1134,8 +1151,12 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(const DevPlan* __restric
       P->st->proj_scatter = 0;
     }
   } else {
-    double own[kNPart];
-    sum_slots(P->spart_a, P->sell.n_groups, a, 0x3FFu, shs, own);
+    // the groups' active-row counts stay in LDS for the list offsets (plans of up to
+    // kCountCap groups; larger ones read them again from the partials)
+    __shared__ int cnt[kCountCap];
+    const int n = P->sell.n_groups;
+    const bool lds_cnt = n <= kCountCap;
+    sum_slots(P->spart_a, n, a, 0x3FFu, &shs, lds_cnt ? cnt : nullptr);
     const int A = (int)a[7];
     // contributions are rounded to multiples of 1 / fx_scale; with every column
     // total bounded by a[8], 2^61 / a[8] keeps all sums far inside int64
@@ -1147,13 +1168,18 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(const DevPlan* __restric
       // the segment totals
       __shared__ int sc[kFinWaves];
       const FO_GLOBAL double* part = gconst(P->spart_a);
-      const int n = P->sell.n_groups, per = seg_len(n);
+      const int per = seg_len(n);
       const int i0 = threadIdx.x * per, i1 = min(n, i0 + per);
+      auto count = [&](int i) {
+        return lds_cnt ? cnt[i] : (int)part[(int64_t)i * kNPart + 7];
+      };
+      int own = 0;
+      for (int i = i0; i < i1; ++i) own += count(i);
       int total;
-      int off = block_scan<kFinWaves>((int)own[7], sc, &total);
+      int off = block_scan<kFinWaves>(own, sc, &total);
       for (int i = i0; i < i1; ++i) {
         gmut(P->goff)[i] = off;
-        off += (int)part[(int64_t)i * kNPart + 7];
+        off += count(i);
       }
     }
     if (threadIdx.x == 0) {
