@@ -372,6 +372,62 @@ void build_groups(int64_t n_slices, std::vector<FwdGroup>* groups) {
                                (int32_t)groups->size()});
 }
 
+// Groups of the objective-row view: consecutive slices, at most kFwdWaves of them, a
+// group closed before it would exceed `target` steps (a slice's weight is its steps,
+// the quads each of its lanes streams).  The view's passes run their groups all at
+// once, one per workgroup slot, and last as long as the heaviest group; with groups of
+// 8 slices the heaviest holds 1.5x the mean on the clinical plan.  target is the
+// smallest weight that leaves at most `slots` groups, but not below the mean weight of
+// 8-slice groups (small views are not cut into groups of single slices).
+int64_t count_groups(const std::vector<int32_t>& w, int64_t target) {
+  int64_t n = 0, cur = 0, in = 0;
+  for (int32_t x : w) {
+    if (in > 0 && (in == kFwdWaves || cur + x > target)) {
+      ++n;
+      cur = 0;
+      in = 0;
+    }
+    cur += x;
+    ++in;
+  }
+  return n + (in > 0 ? 1 : 0);
+}
+
+void build_groups_balanced(const std::vector<int32_t>& w, int64_t slots,
+                           std::vector<FwdGroup>* groups) {
+  groups->clear();
+  const int64_t n = (int64_t)w.size();
+  if (n == 0) return;
+  int64_t tot = 0, wmax = 0;
+  for (int32_t x : w) {
+    tot += x;
+    wmax = std::max<int64_t>(wmax, x);
+  }
+  const int64_t n8 = (n + kFwdWaves - 1) / kFwdWaves;
+  int64_t lo = std::max<int64_t>(wmax, 1), hi = std::max(tot, lo);  // count(hi) = n8
+  if (n8 <= slots) {
+    while (lo < hi) {  // smallest target with at most `slots` groups
+      const int64_t mid = lo + (hi - lo) / 2;
+      if (count_groups(w, mid) <= slots) hi = mid;
+      else lo = mid + 1;
+    }
+  }
+  const int64_t target = std::max(hi, (tot + n8 - 1) / n8);
+  int32_t s0 = 0, in = 0;
+  int64_t cur = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    if (in > 0 && (in == kFwdWaves || cur + w[i] > target)) {
+      groups->push_back(FwdGroup{0, s0, in, (int32_t)groups->size()});
+      s0 = (int32_t)i;
+      in = 0;
+      cur = 0;
+    }
+    cur += w[i];
+    ++in;
+  }
+  groups->push_back(FwdGroup{0, s0, in, (int32_t)groups->size()});
+}
+
 // Ranges of positions of the all-row view (per-row data are in position order).
 void build_row_items(fredopt_plan* p) {
   p->rows.clear();
@@ -643,7 +699,9 @@ fredopt_status prepare_objective_view(fredopt_plan* p, const fredopt_problem* pr
     if (fits()) break;
     if (olg == p->sell.lpr_log2) return FREDOPT_OK;  // the all-row view serves instead
   }
-  build_groups(O.n_slices, &p->ogroups);
+  build_groups_balanced(O.width, std::min<int64_t>((int64_t)p->n_cu * kObjWgsPerCu,
+                                                  L.max_obj_groups),
+                        &p->ogroups);
   if ((int64_t)p->ogroups.size() > L.max_obj_groups) return FREDOPT_OK;
   std::vector<int32_t> src(n), len(n);
   for (int64_t i = 0; i < n; ++i) {
