@@ -23,7 +23,7 @@ void launch_band(int finish, int64_t n, uint32_t* lo, uint32_t* hi, hipStream_t 
 // step search of the one-sided objective, one workgroup per plan (sub: objective view)
 void launch_linesearch(int sub, const DevPlan* plans, int n_plans, hipStream_t s);
 hipError_t set_forward_lds_limit(int vtype, size_t bytes);
-void launch_active_list(const DevPlan* plans, const FwdGroup* groups, int n_groups,
+void launch_active_list(const DevPlan* plans, const FwdGroup* groups, int n_groups, int block,
                         hipStream_t s);
 // one workgroup per item: items[i] = {plan, share}; lds_bytes = 8 x the widest plan's C
 void launch_scatter(int vtype, const DevPlan* plans, const ScItem* items, int n_items,

@@ -782,7 +782,9 @@ __device__ __forceinline__ void tr_chunk(const DevPlan* __restrict__ plans, cons
 
 // The rows with a non-zero projection coefficient, group by group in slice order
 // (list offsets from the residual finalisation), with what the scatter needs; when
-// the sweep takes the column-major path instead, the coefficients in row order.
+// the sweep takes the column-major path instead, the coefficients in row order.  One
+// workgroup per group, one thread per row position: the launch's block is the most
+// rows a group of any of its plans holds (8 slices of 64 / lanes-per-row rows).
 __global__ __launch_bounds__(kFwdBlock) void k_active_list(const DevPlan* __restrict__ plans,
                                                            const FwdGroup* __restrict__ groups,
                                                            int n_groups) {
@@ -1399,9 +1401,9 @@ void launch_tr_chunks(int vtype, int tag, const DevPlan* plans, const TrItem* it
     launch_tr_tag<1>(vtype, plans, items, n_items, grid, nb8, single, s);
 }
 
-void launch_active_list(const DevPlan* plans, const FwdGroup* groups, int n_groups,
+void launch_active_list(const DevPlan* plans, const FwdGroup* groups, int n_groups, int block,
                         hipStream_t s) {
-  if (n_groups > 0) k_active_list<<<n_groups, kFwdBlock, 0, s>>>(plans, groups, n_groups);
+  if (n_groups > 0) k_active_list<<<n_groups, block, 0, s>>>(plans, groups, n_groups);
 }
 
 void launch_scatter(int vtype, const DevPlan* plans, const ScItem* items, int n_items,

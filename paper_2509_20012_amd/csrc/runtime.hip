@@ -921,6 +921,7 @@ std::vector<Launch> iteration_sequence(int r, bool obj, bool fold, bool onesided
 // of a batch of plans (every work item names its plan).
 struct Exec {
   int storage = 0, n_cu = 256, wgs_per_cu = 2, lds_floats = 0, n_plans = 1;
+  int list_block = kFwdBlock;  // threads of the list kernel: the most rows of a group
   bool fwd_dynamic = true;
   DevPlan* table = nullptr;
   const FwdGroup* groups = nullptr;
@@ -943,12 +944,16 @@ struct Exec {
   size_t sc_lds = 0;           // LDS bytes of a scatter workgroup (widest plan)
 };
 
+// Rows a group of the all-row view holds: kFwdWaves slices of 64 / lanes-per-row.
+int group_rows(const fredopt_plan* p) { return kFwdWaves << (6 - p->sell.lpr_log2); }
+
 Exec exec_of(const fredopt_plan* p) {
   Exec e;
   e.storage = p->storage;
   e.n_cu = p->n_cu;
   e.wgs_per_cu = p->wgs_per_cu;
   e.lds_floats = p->lds_floats;
+  e.list_block = group_rows(p);
   e.fwd_dynamic = p->fwd_dynamic;
   e.table = p->d_table;
   e.groups = p->d_groups;
@@ -1003,7 +1008,7 @@ void enqueue(const Exec& e, const Launch& l, hipStream_t s) {
       launch_tcol(l.mode, e.table, e.cblocks, e.n_cblocks, s);
       break;
     case kKindList:  // active-row list, or the coefficients by row for the CSC path
-      launch_active_list(e.table, e.groups, e.n_groups, s);
+      launch_active_list(e.table, e.groups, e.n_groups, e.list_block, s);
       break;
     case kKindScatter:
       launch_scatter(e.storage, e.table, e.sc, e.n_sc, e.sc_lds, s);
@@ -2038,7 +2043,7 @@ fredopt_status fredopt_batch_create(fredopt_plan* const* plans, int32_t n,
     std::vector<TrItem> tr, gtr;
     std::vector<ColBlock> cblocks;
     std::vector<ScItem> sc, ss;
-    int lds = 0, wgs = 4;
+    int lds = 0, wgs = 4, list_block = kWave;
     size_t sc_lds = 0;
     bool all_lds = true;
     for (size_t j = 0; j < sb.idx.size(); ++j) {
@@ -2062,6 +2067,7 @@ fredopt_status fredopt_batch_create(fredopt_plan* const* plans, int32_t n,
       if (nsc > 0 && !p->scatter_global) sc_lds = std::max(sc_lds, (size_t)p->C * sizeof(int64_t));
       lds = std::max(lds, p->lds_floats);
       all_lds = all_lds && p->lds_floats > 0;
+      list_block = std::max(list_block, group_rows(p));
       wgs = std::min(wgs, p->wgs_per_cu);
     }
     Exec& e = sb.ex;
@@ -2069,6 +2075,7 @@ fredopt_status fredopt_batch_create(fredopt_plan* const* plans, int32_t n,
     e.n_cu = plans[0]->n_cu;
     e.wgs_per_cu = std::max(1, wgs);
     e.lds_floats = all_lds ? lds : 0;
+    e.list_block = list_block;
     e.n_plans = (int)sb.idx.size();
     e.fwd_dynamic = true;
     e.table = b->d_table + base;
