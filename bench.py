@@ -34,7 +34,7 @@ KERNEL_SYMBOLS = {  # fredopt kernel id -> device symbol in profiler output (vt:
     "fwd_resid": "fo::k_forward<{vt}, 3, 0>", "tr_grad": "fo::k_tr_chunks<{vt}, 0>",
     "tr_proj": "fo::k_tr_chunks<{vt}, 1>", "rows": "fo::k_rows<1>", "col": "fo::k_tcol",
     "finalize": "fo::k_finalize", "active_list": "fo::k_active_list",
-    "scatter": "fo::k_scatter<{vt}>", "scatter_sum": "fo::k_scatter_sum",
+    "scatter": "fo::k_project<{vt}, ...>", "scatter_sum": "fo::k_scatter_sum",
     "line_search": "fo::k_linesearch<{sub}>"}
 
 
@@ -606,10 +606,14 @@ def main():
                                n_obj_rows, info["obj_entries"], ib)
         if name == "tr_proj" and scatter_path:
             ab = 0  # its workgroups see the active-row path and return at once
-        if name == "scatter" and scatter_path:
-            # the active rows' stored entries (counted on the device by the residual
-            # pass that listed them) and their 32-byte list records
-            ab = int(sp.active_entries * (ib + 2 * vb) + 32 * sp.n_active)
+        if name == "scatter":
+            # one launch takes the path the device chose: the active rows' stored
+            # entries (counted on the device by the residual pass that listed them)
+            # and their 32-byte list records, or the column-major pass
+            ab = (int(sp.active_entries * (ib + 2 * vb) + 32 * sp.n_active) if scatter_path
+                  else algorithmic_bytes("tr_proj", R, C, nnz, vb, info["tr_items"],
+                                         info["grad_entries"], n_obj_rows,
+                                         info["obj_entries"], ib))
         per_kernel[name] = {"ms": ms, "launches_per_iter": cnt / args.profile_iters,
                             "alg_bytes": ab, "gbps": ab / (ms * 1e-3) / 1e9 if ms > 0 else 0.0}
     dom = max((k for k in per_kernel if per_kernel[k]["alg_bytes"] > 0),

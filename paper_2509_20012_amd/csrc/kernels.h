@@ -29,6 +29,12 @@ void launch_active_list(const DevPlan* plans, const FwdGroup* groups, int n_grou
 void launch_scatter(int vtype, const DevPlan* plans, const ScItem* items, int n_items,
                     size_t lds_bytes, hipStream_t s);
 hipError_t set_scatter_lds_limit(size_t bytes);
+// The sweep's transposed product by the path each plan's device state chose: the
+// active-row scatter shares and the column-major chunk walk in one launch (grid: the
+// larger of n_sc and the walk's, which max_grid caps in workgroups of kScatterBlock).
+void launch_project(int vtype, const DevPlan* plans, const ScItem* sc, int n_sc, size_t lds_bytes,
+                    const TrItem* tr, int n_tr, int max_grid, int single, hipStream_t s);
+hipError_t set_project_lds_limit(size_t bytes);
 // mode: the ColMode of the projection update (kColProj, kColProjMove, kColProjY,
 // kColProjYMove)
 // items[i] = {plan, 64-column word}

@@ -705,21 +705,28 @@ __device__ __forceinline__ void tr_chunk(const DevPlan* __restrict__ plans, cons
 // (vb mod 8) nb8 + vb / 8, so each workgroup stays on one XCD's contiguous share of
 // columns.  single: every item belongs to plans[0] (its projection path is checked
 // once).
-template <int VT, int TAG>
-__global__ __launch_bounds__(kBlock) void k_tr_chunks(const DevPlan* __restrict__ plans,
-                                                      const TrItem* __restrict__ items,
-                                                      int n_items, int nb8, int single) {
+template <int VT, int TAG, int B>
+__device__ __forceinline__ void chunk_walk(const DevPlan* __restrict__ plans,
+                                           const TrItem* __restrict__ items, int n_items, int nb8,
+                                           int single) {
   if (single && (halted(plans) || (TAG == 1 && plans[0].st->proj_scatter))) return;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   for (int vb = blockIdx.x; vb < nb8 * 8; vb += gridDim.x) {
     const int lb = (vb & 7) * nb8 + (vb >> 3);
-    const int it = lb * (kBlock / kWave) + wave;
+    const int it = lb * (B / kWave) + wave;
     if (it >= n_items) continue;
     const TrItem w = items[uniform(it)];
     if (!single && (halted(plans + w.plan) || (TAG == 1 && plans[w.plan].st->proj_scatter)))
       continue;
     tr_chunk<VT, TAG>(plans, w, lane);
   }
+}
+
+template <int VT, int TAG>
+__global__ __launch_bounds__(kBlock) void k_tr_chunks(const DevPlan* __restrict__ plans,
+                                                      const TrItem* __restrict__ items,
+                                                      int n_items, int nb8, int single) {
+  chunk_walk<VT, TAG, kBlock>(plans, items, n_items, nb8, single);
 }
 
 template <int VT, int TAG>
@@ -847,10 +854,8 @@ __device__ __forceinline__ void fx_add_global(unsigned long long* acc, int col, 
 // bit.  Workgroup w takes a contiguous share of the list; the column kernel adds
 // the shares.
 template <int VT>
-__global__ __launch_bounds__(kScatterBlock) void k_scatter(const DevPlan* __restrict__ plans,
-                                                          const ScItem* __restrict__ items) {
-  extern __shared__ unsigned long long facc[];
-  const ScItem item = items[blockIdx.x];
+__device__ __forceinline__ void scatter_share(const DevPlan* __restrict__ plans, const ScItem item,
+                                              unsigned long long* facc) {
   const DevPlan* __restrict__ P = plans + item.plan;
   const int wg = item.idx;
   if (halted(P) || !P->st->proj_scatter) return;
@@ -914,6 +919,28 @@ __global__ __launch_bounds__(kScatterBlock) void k_scatter(const DevPlan* __rest
     if (v != 0) out[j] = v;
     if (lane == 0) msk[w] = m;
   }
+}
+
+template <int VT>
+__global__ __launch_bounds__(kScatterBlock) void k_scatter(const DevPlan* __restrict__ plans,
+                                                          const ScItem* __restrict__ items) {
+  extern __shared__ unsigned long long facc[];
+  scatter_share<VT>(plans, items[blockIdx.x], facc);
+}
+
+// The sweep's transposed product by either path in one launch: the device chose the
+// path of each plan (proj_scatter), and a kernel whose workgroups only return still
+// costs a launch.  Workgroup b takes scatter share b (plans on the active-row path),
+// then its part of the persistent walk over the column-major chunks (plans on the
+// column-major path); VT is the row copy's storage, VC the column copy's.
+template <int VT, int VC>
+__global__ __launch_bounds__(kScatterBlock) void k_project(const DevPlan* __restrict__ plans,
+                                                          const ScItem* __restrict__ sc, int n_sc,
+                                                          const TrItem* __restrict__ tr, int n_tr,
+                                                          int nb8, int single) {
+  extern __shared__ unsigned long long facc[];
+  if ((int)blockIdx.x < n_sc) scatter_share<VT>(plans, sc[blockIdx.x], facc);
+  if (n_tr > 0) chunk_walk<VC, 1, kScatterBlock>(plans, tr, n_tr, nb8, single);
 }
 
 // The projection update of column j (Fig. 2, last loop) from the transposed sum t
@@ -1419,6 +1446,45 @@ void launch_scatter(int vtype, const DevPlan* plans, const ScItem* items, int n_
     k_scatter<kBF16><<<n_items, kScatterBlock, lds_bytes, s>>>(plans, items);
   else
     k_scatter<kF32><<<n_items, kScatterBlock, lds_bytes, s>>>(plans, items);
+}
+
+void launch_project(int vtype, const DevPlan* plans, const ScItem* sc, int n_sc, size_t lds_bytes,
+                    const TrItem* tr, int n_tr, int max_grid, int single, hipStream_t s) {
+  // the chunk walk's virtual blocks of kScatterBlock / kWave items, grouped by 8
+  constexpr int per = kScatterBlock / kWave;
+  const int nb8 = n_tr > 0 ? ((n_tr + per - 1) / per + 7) / 8 : 0;
+  const int walk = n_tr > 0 ? std::min(nb8 * 8, std::max(8, max_grid / 8 * 8)) : 0;
+  const int grid = std::max(n_sc, walk);
+  if (grid <= 0) return;
+  switch (vtype) {
+    case kF16I:
+      k_project<kF16I, kF16><<<grid, kScatterBlock, lds_bytes, s>>>(plans, sc, n_sc, tr, n_tr, nb8, single);
+      break;
+    case kBF16I:
+      k_project<kBF16I, kBF16><<<grid, kScatterBlock, lds_bytes, s>>>(plans, sc, n_sc, tr, n_tr, nb8, single);
+      break;
+    case kF16:
+      k_project<kF16, kF16><<<grid, kScatterBlock, lds_bytes, s>>>(plans, sc, n_sc, tr, n_tr, nb8, single);
+      break;
+    case kBF16:
+      k_project<kBF16, kBF16><<<grid, kScatterBlock, lds_bytes, s>>>(plans, sc, n_sc, tr, n_tr, nb8, single);
+      break;
+    default:
+      k_project<kF32, kF32><<<grid, kScatterBlock, lds_bytes, s>>>(plans, sc, n_sc, tr, n_tr, nb8, single);
+      break;
+  }
+}
+
+hipError_t set_project_lds_limit(size_t bytes) {
+  hipError_t e = hipSuccess;
+  for (const void* f : {(const void*)k_project<kF32, kF32>, (const void*)k_project<kF16, kF16>,
+                        (const void*)k_project<kBF16, kBF16>, (const void*)k_project<kF16I, kF16>,
+                        (const void*)k_project<kBF16I, kBF16>}) {
+    const hipError_t r =
+        hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (r != hipSuccess) e = r;
+  }
+  return e;
 }
 
 void launch_scatter_sum(int mode, const DevPlan* plans, const ScItem* items, int n_items,

@@ -51,6 +51,8 @@ constexpr int64_t kTrChunkDefault = 4096;
 constexpr int64_t kGradChunk = 512;
 constexpr int64_t kBlockCountCap = int64_t(1) << 24;
 constexpr int kTrWgsPerCu = 8;            // persistent grid of the column-major passes
+constexpr size_t kProjectTwoPerCuLds = 72 * 1024;  // LDS sums that let two projection
+                                                   // workgroups share a CU
 constexpr int kObjWgsPerCu = 2;           // forward passes over the objective-row view
 constexpr size_t kScatterLdsMax = 159744; // its LDS accumulator: C 64-bit sums
 
@@ -846,7 +848,7 @@ void export_state(const DevState& d, fredopt_state* st) {
 
 enum Kind {
   kKindFwd, kKindRows, kKindChunks, kKindCol, kKindFin, kKindList, kKindScatter, kKindScatterSum,
-  kKindSearch
+  kKindSearch, kKindProject
 };
 
 struct Launch {
@@ -867,13 +869,12 @@ struct Launch {
 // perturbation's move y = y - beta g is not stored; the residual pass stages
 // y - beta g and the projection update recomputes it.
 // The sweep's transposed product and update.  The device picks the path per plan
-// and iteration (proj_scatter): the kernels of the other path return at once.  The
-// last launch updates every column: from the scatter shares, or from the chunk
-// partials of the column-major path.
+// and iteration (proj_scatter); one launch runs the transposed product by the path
+// each plan took.  The last launch updates every column: from the scatter shares, or
+// from the chunk partials of the column-major path.
 void add_projection(std::vector<Launch>* seq, int col_mode) {
   seq->push_back({FREDOPT_KERNEL_ACTIVE_LIST, kKindList, 0});
-  seq->push_back({FREDOPT_KERNEL_SCATTER, kKindScatter, 0});
-  seq->push_back({FREDOPT_KERNEL_TR_PROJ, kKindChunks, 1});
+  seq->push_back({FREDOPT_KERNEL_SCATTER, kKindProject, 0});  // either path, one launch
   seq->push_back({FREDOPT_KERNEL_SCATTER_SUM, kKindScatterSum, col_mode});
 }
 
@@ -1013,6 +1014,14 @@ void enqueue(const Exec& e, const Launch& l, hipStream_t s) {
     case kKindScatter:
       launch_scatter(e.storage, e.table, e.sc, e.n_sc, e.sc_lds, s);
       break;
+    case kKindProject: {
+      // the chunk walk's workgroups per CU: two unless the scatter's LDS sums leave
+      // room for one (the same waves per CU as the separate chunk kernel when two fit)
+      const int per_cu = e.sc_lds <= kProjectTwoPerCuLds ? 2 : 1;
+      launch_project(e.storage, e.table, e.sc, e.n_sc, e.sc_lds, e.tr, e.n_tr, e.n_cu * per_cu,
+                     e.n_plans == 1, s);
+      break;
+    }
     case kKindScatterSum:
       if (e.n_ss > 0) launch_scatter_sum(l.mode, e.table, e.ss, e.n_ss, s);
       break;
@@ -1116,6 +1125,7 @@ fredopt_status device_limits(fredopt_plan* p) {
   for (int vt = FREDOPT_F32; vt <= FREDOPT_BF16_IDX16; ++vt)
     HIPCHK(set_forward_lds_limit(vt, dyn_max));
   HIPCHK(set_scatter_lds_limit(dyn_max));
+  HIPCHK(set_project_lds_limit(dyn_max));
   const size_t need = (size_t)p->C * sizeof(float);
   if (need <= dyn_max) {
     p->lds_floats = (int)p->C;
