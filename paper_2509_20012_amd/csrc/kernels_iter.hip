@@ -1086,20 +1086,25 @@ struct FinShared {
 // array of 16-byte pairs: thread t reads pairs t, t + kFinBlock, ... (consecutive
 // threads read consecutive pairs, so a wave's load covers whole lines; every round
 // issues kFinUnroll loads per thread, predicated at the end), and the two doubles of
-// each of its pairs always belong to slots 2t mod kNPart and 2t + 1 mod kNPart.  A
-// slot's thread sums are then added in thread order.  The order is fixed, so the sums
-// do not depend on timing.  With cnt, slot 7 (the groups' active-row counts, integers)
-// is also kept in LDS by group.  Slots not in `used` read as 0.  Every thread gets the
-// result.
-__device__ __forceinline__ void sum_slots(const double* part_, int n, double* out,
-                                          unsigned used, FinShared* sh, int* cnt = nullptr) {
+// each of its pairs always belong to slots 2t mod kNPart and 2t + 1 mod kNPart.  The
+// slots' thread sums are then added in a fixed tree, so the sums do not depend on
+// timing.  With cnt, slot 7 (the groups' active-row counts, integers) is also kept in
+// LDS by group.  Slots not in `used` read as 0, and threads whose two slots are both
+// unused read nothing.  Every thread gets the result.
+//
+// The thread's two slot sums (loads and additions; no barrier, so the loads of
+// several calls can be in flight together).
+__device__ __forceinline__ void thread_slot_sums(const double* part_, int n, unsigned used,
+                                                 int* cnt, double* s0, double* s1) {
   static_assert(kNPart % 2 == 0 && kNPart == 10, "pairs of slots; slot 7 is the odd one of 6, 7");
   const FO_GLOBAL v2d* part = (const FO_GLOBAL v2d*)gconst(part_);
   const int t = threadIdx.x;
   const int pairs = n * (kNPart / 2);
   const bool keep = cnt != nullptr && (2 * t) % kNPart == 6;
+  // threads whose pair holds no slot in `used` (or slot 7 for cnt) read nothing
+  const bool need = ((used >> ((2 * t) % kNPart)) & 3u) != 0 || keep;
   double a0 = 0.0, a1 = 0.0;
-  for (int f = t; f < pairs; f += kFinBlock * kFinUnroll) {
+  for (int f = need ? t : pairs; f < pairs; f += kFinBlock * kFinUnroll) {
     v2d v[kFinUnroll];
 #pragma unroll
     for (int u = 0; u < kFinUnroll; ++u) {
@@ -1114,22 +1119,41 @@ __device__ __forceinline__ void sum_slots(const double* part_, int n, double* ou
       if (keep && i < pairs) cnt[(2 * i + 1) / kNPart] = (int)v[u].y;
     }
   }
-  sh->red[0][t] = a0;
-  sh->red[1][t] = a1;
+  *s0 = a0;
+  *s1 = a1;
+}
+
+// The slot sums from every thread's two sums: wave k sums slot k.  Its thread sums
+// are those of threads c + 5 m (2c = k rounded down to even; the first or second
+// double of their pairs), m = 0 .. 127; lane l adds m = l and m = l + 64, then a fixed
+// shuffle tree.
+__device__ __forceinline__ void reduce_slots(double s0, double s1, unsigned used, FinShared* sh,
+                                             double* out) {
+  static_assert(kFinWaves == kNPart && kFinBlock / (kNPart / 2) == 2 * kWave, "slot waves");
+  const int t = threadIdx.x;
+  sh->red[0][t] = s0;
+  sh->red[1][t] = s1;
   __syncthreads();
-  if (t < kNPart) {
-    // slot t: the threads c + 5 m with 2c = t rounded down to even, first or second
-    // double of their pairs
-    const int c = t / 2, h = t & 1;
+  {
+    const int k = t / kWave, l = t & (kWave - 1);
+    const int c = k / 2, h = k & 1;
     double r = 0.0;
-    if (used & (1u << t))
-      for (int m = 0; m < kFinBlock / (kNPart / 2); ++m) r += sh->red[h][c + (kNPart / 2) * m];
-    sh->slot[t] = r;
+    if (used & (1u << k))
+      r = sh->red[h][c + (kNPart / 2) * l] + sh->red[h][c + (kNPart / 2) * (l + kWave)];
+    r = wave_sum(r);
+    if (l == 0) sh->slot[k] = r;
   }
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < kNPart; ++k) out[k] = sh->slot[k];
   __syncthreads();
+}
+
+__device__ __forceinline__ void sum_slots(const double* part_, int n, double* out,
+                                          unsigned used, FinShared* sh, int* cnt = nullptr) {
+  double s0, s1;
+  thread_slot_sums(part_, n, used, cnt, &s0, &s1);
+  reduce_slots(s0, s1, used, sh, out);
 }
 
 // SUB: the objective and direction partials come from the objective-row view.
@@ -1142,12 +1166,15 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(const DevPlan* __restric
   const int ng = SUB ? P->osell.n_groups : P->sell.n_groups;
   double a[kNPart];
   if constexpr (MODE == kFinDir0 || MODE == kFinDir) {
-    double b[kNPart];
-    sum_slots(P->spart_b, ng, b, 0x21u, &shs);
+    // the three inputs' loads first, all in flight together, then the reductions
+    double b[kNPart], b0, b1, a0 = 0.0, a1 = 0.0;
+    thread_slot_sums(P->spart_b, ng, 0x21u, nullptr, &b0, &b1);
+    if constexpr (MODE == kFinDir0) thread_slot_sums(P->spart_a, ng, 0x21u, nullptr, &a0, &a1);
     double g = 0.0;
     for (int i = threadIdx.x; i < P->n_col_blocks; i += kFinBlock) g += gconst(P->gpart)[i];
+    reduce_slots(b0, b1, 0x21u, &shs, b);
     const double G = block_sum<kFinWaves>(g, sh4);
-    if constexpr (MODE == kFinDir0) sum_slots(P->spart_a, ng, a, 0x21u, &shs);
+    if constexpr (MODE == kFinDir0) reduce_slots(a0, a1, 0x21u, &shs, a);
     if (threadIdx.x == 0) {
       DevState* st = P->st;
       if constexpr (MODE == kFinDir0) {
