@@ -945,17 +945,35 @@ __global__ __launch_bounds__(kScatterBlock) void k_project(const DevPlan* __rest
 
 // The projection update of column j (Fig. 2, last loop) from the transposed sum t
 // in stored units: x = max(0, y - scale t), with y = x, x - beta g or the perturbed
-// point, by MODE.
+// point, by MODE.  The column's inputs are loaded apart from the update, so that a
+// caller can have them in flight while it forms t.
+struct ColIn {
+  float cs;      // the column's scale of stored values (1 if none)
+  double y;      // the point the update starts from
+  double scale;  // the sweep's weight scale
+};
+
 template <int MODE>
-__device__ __forceinline__ void project_column(const DevPlan* __restrict__ P, int j, float t) {
+__device__ __forceinline__ ColIn load_column(const DevPlan* __restrict__ P, int j) {
   constexpr bool fromy = MODE == kColProjY || MODE == kColProjYMove;
-  if (P->cscale) t *= gconst(P->cscale)[j];
+  ColIn in;
+  in.cs = P->cscale ? gconst(P->cscale)[j] : 1.f;
   double y = fromy ? gconst(P->y)[j] : gconst(P->x)[j];
   if constexpr (MODE == kColProjMove) y -= P->st->step * (double)gconst(P->g)[j];
   // the perturbed point y - beta g, rounded to FP32 as the residual pass staged it
   if constexpr (MODE == kColProjYMove)
     y = (double)(float)(y - P->st->step * (double)gconst(P->g)[j]);
-  const double xn = y - P->st->scale * (double)t;
+  in.y = y;
+  in.scale = P->st->scale;
+  return in;
+}
+
+template <int MODE>
+__device__ __forceinline__ void apply_column(const DevPlan* __restrict__ P, int j, float t,
+                                             const ColIn& in) {
+  constexpr bool fromy = MODE == kColProjY || MODE == kColProjYMove;
+  if (P->cscale) t *= in.cs;
+  const double xn = in.y - in.scale * (double)t;
   if constexpr (MODE == kColProjNoClamp) {  // the clamp waits for the sweep's end
     gmut(P->x)[j] = (float)xn;
     return;
@@ -963,6 +981,11 @@ __device__ __forceinline__ void project_column(const DevPlan* __restrict__ P, in
   const float xf = xn > 0.0 ? (float)xn : 0.f;
   gmut(P->x)[j] = xf;
   if constexpr (fromy) gmut(P->y)[j] = xf;
+}
+
+template <int MODE>
+__device__ __forceinline__ void project_column(const DevPlan* __restrict__ P, int j, float t) {
+  apply_column<MODE>(P, j, t, load_column<MODE>(P, j));
 }
 
 // The sweep's update of 64 columns: on the active-row path, the sum of the scatter
@@ -999,6 +1022,9 @@ __global__ __launch_bounds__(kScatterBlock) void k_scatter_sum(const DevPlan* __
     }
     return;
   }
+  // the column's own inputs go out with the masks
+  ColIn in{1.f, 0.0, 0.0};
+  if (wave == 0 && j < C) in = load_column<MODE>(P, j);
   const FO_GLOBAL int64_t* sp = gconst(P->spart) + j;
   const FO_GLOBAL uint64_t* mk = gconst(P->smask) + item.idx;
   // all masks first, then the shares they mark: two dependent rounds of loads
@@ -1018,7 +1044,7 @@ __global__ __launch_bounds__(kScatterBlock) void k_scatter_sum(const DevPlan* __
   __syncthreads();
   if (wave == 0) {
     for (int v = 1; v < kScatterBlock / kWave; ++v) S += part[v][lane];
-    if (j < C) project_column<MODE>(P, j, (float)((double)S / P->st->fx_scale));
+    if (j < C) apply_column<MODE>(P, j, (float)((double)S / P->st->fx_scale), in);
   }
 }
 
