@@ -142,6 +142,8 @@ struct DevPlan {
   int64_t NP;                 // positions of the all-row view (slices * rpw)
   int32_t vtype, lpr_log2;    // lanes per row (log2) of the all-row view
   int32_t n_row_items, n_col_blocks;
+  int32_t search_cap;        // step-search partial sums the direction partial area holds
+  int32_t search_pad;
   SellView sell;              // every row
   SellView osell;             // rows with objective terms (per problem), for Eq. (2)
   // CSC copy, columns padded to 4 slots, rows ascending in a column (projection)

@@ -21,6 +21,8 @@ void launch_finalize(int mode, int sub, const DevPlan* plans, int n_plans, hipSt
 // band arrays of a robustness evaluation: fill (finish 0) or decode (finish 1)
 void launch_band(int finish, int64_t n, uint32_t* lo, uint32_t* hi, hipStream_t s);
 // step search of the one-sided objective, one workgroup per plan (sub: objective view)
+// The one-sided step search's first window summed by many workgroups per plan.
+void launch_search_part(int sub, const DevPlan* plans, int n_plans, hipStream_t s);
 void launch_linesearch(int sub, const DevPlan* plans, int n_plans, hipStream_t s);
 hipError_t set_forward_lds_limit(int vtype, size_t bytes);
 void launch_active_list(const DevPlan* plans, const FwdGroup* groups, int n_groups, int block,

@@ -1276,13 +1276,91 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(const DevPlan* __restric
 
 // Step search of Fig. 3 for the one-sided objective.  Along v the cost is only
 // piecewise quadratic (an OAR term switches on or off where c l crosses its target),
-// so the closed form does not apply: each pass evaluates
+// so the closed form does not apply: each window evaluates
 // chi^2(y - beta v) - chi^2(y) in FP64 for kSearchWindow candidate exponents
 // s0 + 1, s0 + 2, ... from the d, l, D g, L g the view's passes stored, and the first
 // candidate that strictly lowers the cost is taken (Fig. 3's trials, in order); the
-// next window follows while none does and alpha^s >= 1e-300.  The row terms are summed
-// in a fixed order (thread strides, wave sums, waves in order).  One workgroup per
-// plan; SUB: the objective-row view.
+// next window follows while none does and alpha^s >= 1e-300.  The first window is
+// summed by k_search_part over many workgroups (its per-workgroup sums added here in
+// workgroup order); later windows, rarely needed, by this kernel's single workgroup.
+// SUB: the objective-row view.
+constexpr int kSearchBlocks = 64;  // workgroups per plan of the first window
+
+// Workgroups of k_search_part for a view of n positions: what the plan's partial area
+// holds, at least kBlock positions each.
+__device__ __forceinline__ int search_blocks(const DevPlan* P, int n) {
+  return max(1, min(min(kSearchBlocks, P->search_cap), (n + kBlock - 1) / kBlock));
+}
+
+// The row's terms of chi^2(y - beta_j v) - chi^2(y) for the window's candidates.
+template <int SUB>
+__device__ __forceinline__ void search_row(const DevPlan* __restrict__ P, int i, double vs,
+                                           const double* bk, double* acc) {
+  const FO_GLOBAL uint16_t* kind = gconst(SUB ? P->okind : P->kind);
+  const unsigned k = kind[i];
+  if (!(k & (kObjDose | kObjCdl))) return;
+  const double c = P->prm.c;
+  const double w = gconst(SUB ? P->owo : P->wo)[i];
+  if (k & kObjDose) {  // w (e0 + beta Dv)^2 - w e0^2, e0 = Dhat - d
+    const double e0 = (double)gconst(SUB ? P->odt : P->dt)[i] - (double)gconst(SUB ? P->od : P->d)[i];
+    const double dv = (double)gconst(SUB ? P->odg : P->dg)[i] * vs;
+#pragma unroll
+    for (int j = 0; j < kSearchWindow; ++j) acc[j] += w * (bk[j] * dv) * (2.0 * e0 + bk[j] * dv);
+  }
+  if (k & kObjCdl) {   // w min(0, f0 + beta c Lv)^2 - w min(0, f0)^2
+    const double f0 = (double)gconst(SUB ? P->oct : P->ct)[i] -
+                      c * (double)gconst(SUB ? P->ol : P->l)[i];
+    const double lv = c * (double)gconst(SUB ? P->olg : P->lg)[i] * vs;
+    const double t0 = f0 < 0.0 ? f0 * f0 : 0.0;
+#pragma unroll
+    for (int j = 0; j < kSearchWindow; ++j) {
+      const double fb = f0 + bk[j] * lv;
+      acc[j] += w * ((fb < 0.0 ? fb * fb : 0.0) - t0);
+    }
+  }
+}
+
+// The first window's sums over a share of the rows: workgroup b of plan blockIdx.y
+// takes positions b kBlock + t, stepping by the plan's workgroups times kBlock, and
+// writes its kSearchWindow sums (waves in order) to the plan's partial area.
+template <int SUB>
+__global__ __launch_bounds__(kBlock) void k_search_part(const DevPlan* __restrict__ plans) {
+  __shared__ double sh[kBlock / kWave][kSearchWindow];
+  __shared__ double sbeta[kSearchWindow];
+  const DevPlan* __restrict__ P = plans + blockIdx.y;
+  if (halted(P)) return;
+  const DevState* st = P->st;
+  if (st->pstop) return;
+  const SellView& V = SUB ? P->osell : P->sell;
+  const int n = V.n_slices << (6 - V.lpr_log2);
+  const int nb = search_blocks(P, n);
+  if ((int)blockIdx.x >= nb) return;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+  const double vs = P->prm.unit_dir ? 1.0 / sqrt(st->G) : 1.0;  // v = vs g
+  const int64_t base = st->s + 1;
+  if (tid < kSearchWindow) sbeta[tid] = pow(P->prm.alpha, (double)(base + tid));
+  __syncthreads();
+  double bk[kSearchWindow], acc[kSearchWindow];
+#pragma unroll
+  for (int j = 0; j < kSearchWindow; ++j) {
+    bk[j] = sbeta[j];
+    acc[j] = 0.0;
+  }
+  for (int i = blockIdx.x * kBlock + tid; i < n; i += nb * kBlock) search_row<SUB>(P, i, vs, bk, acc);
+#pragma unroll
+  for (int j = 0; j < kSearchWindow; ++j) acc[j] = wave_sum(acc[j]);
+  if (lane == 0) {
+#pragma unroll
+    for (int j = 0; j < kSearchWindow; ++j) sh[wave][j] = acc[j];
+  }
+  __syncthreads();
+  if (tid < kSearchWindow) {
+    double r = 0.0;
+    for (int v = 0; v < kBlock / kWave; ++v) r += sh[v][tid];
+    gmut(P->spart_b)[(int64_t)blockIdx.x * kSearchWindow + tid] = r;
+  }
+}
+
 template <int SUB>
 __global__ __launch_bounds__(kFinBlock) void k_linesearch(const DevPlan* __restrict__ plans) {
   __shared__ double sh[kFinWaves][kSearchWindow];
@@ -1294,51 +1372,36 @@ __global__ __launch_bounds__(kFinBlock) void k_linesearch(const DevPlan* __restr
   if (st->pstop) return;  // no descent direction this outer iteration
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   const double vs = P->prm.unit_dir ? 1.0 / sqrt(st->G) : 1.0;  // v = vs g
-  const double c = P->prm.c, a = P->prm.alpha;
+  const double a = P->prm.alpha;
   const SellView& V = SUB ? P->osell : P->sell;
   const int n = V.n_slices << (6 - V.lpr_log2);
-  const FO_GLOBAL uint16_t* kind = gconst(SUB ? P->okind : P->kind);
-  const FO_GLOBAL float* wo = gconst(SUB ? P->owo : P->wo);
-  const FO_GLOBAL float* dt = gconst(SUB ? P->odt : P->dt);
-  const FO_GLOBAL float* ct = gconst(SUB ? P->oct : P->ct);
-  const FO_GLOBAL float* dd = gconst(SUB ? P->od : P->d);
-  const FO_GLOBAL float* ll = gconst(SUB ? P->ol : P->l);
-  const FO_GLOBAL float* dg = gconst(SUB ? P->odg : P->dg);
-  const FO_GLOBAL float* lg = gconst(SUB ? P->olg : P->lg);
   const int64_t s0 = st->s;
   for (int64_t base = s0 + 1;; base += kSearchWindow) {
     if (tid < kSearchWindow) sbeta[tid] = pow(a, (double)(base + tid));
     __syncthreads();
-    double bk[kSearchWindow], acc[kSearchWindow];
+    double bk[kSearchWindow];
 #pragma unroll
-    for (int j = 0; j < kSearchWindow; ++j) {
-      bk[j] = sbeta[j];
-      acc[j] = 0.0;
-    }
-    for (int i = tid; i < n; i += kFinBlock) {
-      const unsigned k = kind[i];
-      if (!(k & (kObjDose | kObjCdl))) continue;
-      const double w = wo[i];
-      if (k & kObjDose) {  // w (e0 + beta Dv)^2 - w e0^2, e0 = Dhat - d
-        const double e0 = (double)dt[i] - (double)dd[i], dv = (double)dg[i] * vs;
-#pragma unroll
-        for (int j = 0; j < kSearchWindow; ++j) acc[j] += w * (bk[j] * dv) * (2.0 * e0 + bk[j] * dv);
+    for (int j = 0; j < kSearchWindow; ++j) bk[j] = sbeta[j];
+    if (base == s0 + 1) {
+      // the first window: k_search_part's per-workgroup sums, in workgroup order
+      const int nb = search_blocks(P, n);
+      if (tid < kSearchWindow) {
+        double r = 0.0;
+        for (int b = 0; b < nb; ++b) r += gconst(P->spart_b)[(int64_t)b * kSearchWindow + tid];
+        sh[0][tid] = r;
+        for (int v = 1; v < kFinWaves; ++v) sh[v][tid] = 0.0;
       }
-      if (k & kObjCdl) {   // w min(0, f0 + beta c Lv)^2 - w min(0, f0)^2
-        const double f0 = (double)ct[i] - c * (double)ll[i], lv = c * (double)lg[i] * vs;
-        const double t0 = f0 < 0.0 ? f0 * f0 : 0.0;
+    } else {
+      double acc[kSearchWindow];
 #pragma unroll
-        for (int j = 0; j < kSearchWindow; ++j) {
-          const double fb = f0 + bk[j] * lv;
-          acc[j] += w * ((fb < 0.0 ? fb * fb : 0.0) - t0);
-        }
+      for (int j = 0; j < kSearchWindow; ++j) acc[j] = 0.0;
+      for (int i = tid; i < n; i += kFinBlock) search_row<SUB>(P, i, vs, bk, acc);
+#pragma unroll
+      for (int j = 0; j < kSearchWindow; ++j) acc[j] = wave_sum(acc[j]);
+      if (lane == 0) {
+#pragma unroll
+        for (int j = 0; j < kSearchWindow; ++j) sh[wave][j] = acc[j];
       }
-    }
-#pragma unroll
-    for (int j = 0; j < kSearchWindow; ++j) acc[j] = wave_sum(acc[j]);
-    if (lane == 0) {
-#pragma unroll
-      for (int j = 0; j < kSearchWindow; ++j) sh[wave][j] = acc[j];
     }
     __syncthreads();
     if (tid == 0) {
@@ -1588,6 +1651,15 @@ void launch_band(int finish, int64_t n, uint32_t* lo, uint32_t* hi, hipStream_t 
     k_band_finish<<<grid, kBlock, 0, s>>>(n, lo, hi);
   else
     k_band_fill<<<grid, kBlock, 0, s>>>(n, lo, hi);
+}
+
+void launch_search_part(int sub, const DevPlan* plans, int n_plans, hipStream_t s) {
+  if (n_plans <= 0) return;
+  const dim3 grid(kSearchBlocks, n_plans);
+  if (sub)
+    k_search_part<1><<<grid, kBlock, 0, s>>>(plans);
+  else
+    k_search_part<0><<<grid, kBlock, 0, s>>>(plans);
 }
 
 void launch_linesearch(int sub, const DevPlan* plans, int n_plans, hipStream_t s) {

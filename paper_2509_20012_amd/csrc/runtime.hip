@@ -848,7 +848,7 @@ void export_state(const DevState& d, fredopt_state* st) {
 
 enum Kind {
   kKindFwd, kKindRows, kKindChunks, kKindCol, kKindFin, kKindList, kKindScatter, kKindScatterSum,
-  kKindSearch, kKindProject
+  kKindSearch, kKindProject, kKindSearchPart
 };
 
 struct Launch {
@@ -893,7 +893,10 @@ std::vector<Launch> iteration_sequence(int r, bool obj, bool fold, bool onesided
       seq.push_back({FREDOPT_KERNEL_COL, kKindCol, kColGrad});
       seq.push_back({FREDOPT_KERNEL_FWD_DIR, kKindFwd, kFwdDir, 1, kVecG});
       seq.push_back({FREDOPT_KERNEL_FINALIZE, kKindFin, t == 0 ? kFinDir0 : kFinDir, 1});
-      if (onesided) seq.push_back({FREDOPT_KERNEL_LINE_SEARCH, kKindSearch, 0, 1});
+      if (onesided) {
+        seq.push_back({FREDOPT_KERNEL_LINE_SEARCH, kKindSearchPart, 0, 1});
+        seq.push_back({FREDOPT_KERNEL_LINE_SEARCH, kKindSearch, 0, 1});
+      }
       if (!(fold && t + 1 == r)) seq.push_back({FREDOPT_KERNEL_COL, kKindCol, kColYMove});
     }
     seq.push_back({FREDOPT_KERNEL_FWD_RESID, kKindFwd, kFwdResid, 0, fold ? kVecYMove : kVecY});
@@ -908,7 +911,10 @@ std::vector<Launch> iteration_sequence(int r, bool obj, bool fold, bool onesided
     seq.push_back({FREDOPT_KERNEL_COL, kKindCol, t == 0 ? kColGrad : kColGradMove});
     seq.push_back({FREDOPT_KERNEL_FWD_DIR, kKindFwd, kFwdDir, 0, kVecG});
     seq.push_back({FREDOPT_KERNEL_FINALIZE, kKindFin, t == 0 ? kFinDir0 : kFinDir, 0});
-    if (onesided) seq.push_back({FREDOPT_KERNEL_LINE_SEARCH, kKindSearch, 0, 0});
+    if (onesided) {
+      seq.push_back({FREDOPT_KERNEL_LINE_SEARCH, kKindSearchPart, 0, 0});
+      seq.push_back({FREDOPT_KERNEL_LINE_SEARCH, kKindSearch, 0, 0});
+    }
     seq.push_back({FREDOPT_KERNEL_ROWS, kKindRows, last ? kRowsMoveResid : kRowsMoveObj});
     seq.push_back({FREDOPT_KERNEL_FINALIZE, kKindFin, last ? kFinResidRows : kFinMoveObj});
   }
@@ -1024,6 +1030,9 @@ void enqueue(const Exec& e, const Launch& l, hipStream_t s) {
     }
     case kKindScatterSum:
       if (e.n_ss > 0) launch_scatter_sum(l.mode, e.table, e.ss, e.n_ss, s);
+      break;
+    case kKindSearchPart:
+      launch_search_part(l.sub, e.table, e.n_plans, s);
       break;
     case kKindSearch:
       launch_linesearch(l.sub, e.table, e.n_plans, s);
@@ -1522,6 +1531,10 @@ static fredopt_status load_impl(const fredopt_matrices* m, void* workspace,
   h.g = reinterpret_cast<float*>(ws + L.g);
   h.spart_a = reinterpret_cast<double*>(ws + L.spart_a);
   h.spart_b = reinterpret_cast<double*>(ws + L.spart_b);
+  // the step search's first-window sums (kSearchWindow doubles per workgroup) reuse it
+  h.search_cap = (int32_t)std::min<int64_t>(
+      (int64_t)kNPart * std::max(L.n_groups, L.max_obj_groups) / kSearchWindow, 1 << 30);
+  h.search_pad = 0;
   h.rpart = reinterpret_cast<double*>(ws + L.rpart);
   h.gpart = reinterpret_cast<double*>(ws + L.gpart);
   h.tpart = reinterpret_cast<float*>(ws + L.tpart);
