@@ -81,6 +81,46 @@ def test_batch_equals_alone_bitwise(fo, r, reserve):
     batch.free()
 
 
+def test_batch_mixed_projection_paths(fo):
+    """One launch serves both projection paths: in the same batched iteration one plan
+    takes the active-row scatter (allowed for any number of active rows), one the
+    column-major walk (scatter off) and one whichever its device state picks.  Each
+    plan's iterates equal its run alone with the same setting, bit for bit."""
+    print("batch with mixed projection paths", flush=True)
+    phs = [ph.small_plan(3001, 5000, 200), ph.tiny_problem(1000, 130, 0.05, seed=5),
+           ph.tiny_problem(300, 30, 0.15, seed=21)]
+    settings = [("scatter", lambda pl: fo.set_scatter(pl, 0, pl.n_rows)),
+                ("column-major", lambda pl: fo.set_scatter(pl, -1)),
+                ("device", lambda pl: None)]
+    q = fo.SolverParams(alpha=0.9, reductions_n=1)
+    iters = 5
+    ref = []
+    for p, (_, setup) in zip(phs, settings):
+        plan, prob, x0 = fo.load_phantom(p, gradient_reserve_pct=100)
+        setup(plan)
+        x = x0.clone()
+        st = fo.new_state()
+        q.iter_max = iters
+        fo.solve(plan, prob, q, st, x)
+        ref.append((_np(x), (st.k, st.s), st.projection_path))
+        plan.free()
+    loaded = [fo.load_phantom(p, gradient_reserve_pct=100) for p in phs]
+    for (pl, _, _), (_, setup) in zip(loaded, settings):
+        setup(pl)
+    states = [fo.new_state() for _ in phs]
+    xs = [x0.clone() for _, _, x0 in loaded]
+    batch = fo.Batch([pl for pl, _, _ in loaded], [pr for _, pr, _ in loaded])
+    batch.solve(q, states, xs, iters)
+    assert ref[0][2] == 1 and ref[1][2] == 0  # the two forced paths were taken
+    for i, (p, (name, _)) in enumerate(zip(phs, settings)):
+        assert states[i].projection_path == ref[i][2], name
+        assert (states[i].k, states[i].s) == ref[i][1], name
+        assert np.array_equal(_np(xs[i]), ref[i][0]), name
+    batch.free()
+    for pl, _, _ in loaded:
+        pl.free()
+
+
 def test_batch_independent_of_workspace_contents(fo):
     """Plans whose workspaces start as NaN bytes give, in a batch, the iterates of
     the same plans alone (every plan with the objective-row view, r = 1)."""
