@@ -359,7 +359,7 @@ def bench_serve(args):
     log(f"{n_req} requests over {arrivals[-1]:.1f} s ({args.rate:g}/s), {n_big} at clinical scale")
     q = fredopt.SolverParams(reductions_n=args.reductions)
     srv = serve.Server(200 * 10**9, q, quantum=args.quantum, log=log,
-                       gradient_reserve_pct=args.reserve)
+                       gradient_reserve_pct=args.reserve, plan_cache=args.plan_cache)
     t0 = time.perf_counter()
     done = srv.run([dataclasses.replace(r) for r in reqs])
     wall = time.perf_counter() - t0
@@ -370,7 +370,8 @@ def bench_serve(args):
         f"{srv.batches_built} batches, peak {srv.peak_active} resident")
     t0 = time.perf_counter()
     base = serve.serve_one_at_a_time([dataclasses.replace(r) for r in reqs], q, log=log,
-                                     gradient_reserve_pct=args.reserve)
+                                     gradient_reserve_pct=args.reserve,
+                                     plan_cache=args.plan_cache)
     wall_b = time.perf_counter() - t0
     lat_b = [r.latency for r in base]
     log(f"one at a time: p50 {serve.percentile(lat_b, 50):.3f} s, p99 "
@@ -408,7 +409,8 @@ def bench_serve(args):
         "data": "synthetic",
         "config": {"workload": f"serve: {n_req} Poisson requests at {args.rate:g}/s, {n_big} at "
                                f"clinical scale, 200-1000 iterations, 200 GB budget",
-                   "quantum": args.quantum, "reductions_n": args.reductions},
+                   "quantum": args.quantum, "reductions_n": args.reductions,
+                   "plan_cache": args.plan_cache},
         "value_meaning": "plan-iterations per second over the whole trace (wall clock)",
         "latency_p50_s": round(serve.percentile(lat, 50), 4),
         "latency_p99_s": round(serve.percentile(lat, 99), 4),
@@ -418,6 +420,7 @@ def bench_serve(args):
                           "iters_per_s": round(iters / wall_b, 2),
                           "by_class": by_o},
         "peak_resident_plans": srv.peak_active, "batches_built": srv.batches_built,
+        "plan_cache_hits": srv.cache_hits,
     }
 
 
@@ -510,6 +513,9 @@ def main():
     ap.add_argument("--requests", type=int, default=120, help="serve: trace length")
     ap.add_argument("--quantum", type=int, default=50, help="serve: iterations per round")
     ap.add_argument("--rate", type=float, default=4.0, help="serve: requests per second")
+    ap.add_argument("--plan-cache", action="store_true",
+                    help="serve: plans stay resident between requests of the same plan "
+                         "(both forms)")
     ap.add_argument("--serve-small-only", action="store_true",
                     help="serve: no clinical-scale requests")
     args = ap.parse_args()

@@ -11,6 +11,11 @@ resident plans while the next plan's matrices are copied and laid out, and a
 request joins the batch when its load has completed.  A request's latency runs from
 its arrival to its result (the fluence) being on the host, and includes the load.
 
+With plan_cache, a finished request's plan stays resident (its bytes still counted
+in the budget) for the next request of the same plan, a re-optimisation of the same
+patient's matrices: that request starts without a load, and idle plans are freed,
+least recently used first, when an admission needs their room.
+
 Every batched iteration of a plan equals its single-plan iteration bit for bit,
 and quanta resume exactly, so a request's result does not depend on what else was
 served with it.
@@ -20,6 +25,7 @@ served, each request solved alone with the plain single-plan call.
 """
 from __future__ import annotations
 
+import collections
 import dataclasses
 import queue as _queue
 import threading
@@ -58,14 +64,84 @@ def plan_bytes(ph, storage: int = fredopt.F32, gradient_reserve_pct: int = 0) ->
 
 
 class _Active:
-    def __init__(self, req: Request, storage: int, reserve: int):
+    def __init__(self, req: Request, storage: int, reserve: int, keep_x0: bool = False):
         self.req = req
         self.plan, self.prob, self.x = fredopt.load_phantom(req.phantom, storage=storage,
                                                             gradient_reserve_pct=reserve)
+        # the starting fluence, kept for the next request of the plan when plans stay
+        self.x0 = self.x.clone() if keep_x0 else None
         self.state = fredopt.new_state()
         self.left = req.iters
         self.bytes = plan_bytes(req.phantom, storage, reserve)
         self.loaded: Optional[float] = None
+
+    @classmethod
+    def reuse(cls, req: Request, kept: "_Kept", at: float) -> "_Active":
+        """A request served by a resident plan: no load, a fresh state and x0."""
+        a = cls.__new__(cls)
+        a.req = req
+        a.plan, a.prob, a.x0, a.bytes = kept.plan, kept.prob, kept.x0, kept.bytes
+        a.x = kept.x0.clone()
+        a.state = fredopt.new_state()
+        a.left = req.iters
+        a.loaded = at
+        return a
+
+
+@dataclasses.dataclass
+class _Kept:
+    plan: object
+    prob: object
+    x0: object
+    bytes: int
+    phantom: object   # keeps the key's object alive while the plan stays
+
+
+class _Resident:
+    """Plans kept on the device after their request finished, by phantom (one
+    patient's matrices and problem), for the next request of the same plan.  Idle
+    plans only: a plan in use by a request is not here.  The caller holds the
+    serving lock around every call."""
+
+    def __init__(self):
+        self.idle: "collections.OrderedDict[int, List[_Kept]]" = collections.OrderedDict()
+        self.hits = 0
+        self.evictions = 0
+
+    def take(self, phantom) -> Optional[_Kept]:
+        got = self.idle.get(id(phantom))
+        if not got:
+            return None
+        k = got.pop()
+        if not got:
+            del self.idle[id(phantom)]
+        self.hits += 1
+        return k
+
+    def put(self, a: _Active):
+        self.idle.setdefault(id(a.req.phantom), []).append(
+            _Kept(a.plan, a.prob, a.x0, a.bytes, a.req.phantom))
+        self.idle.move_to_end(id(a.req.phantom))
+
+    def evict(self, counted: bool = True) -> int:
+        """Frees the least recently kept idle plan; its bytes (0 if none is idle)."""
+        if not self.idle:
+            return 0
+        key, lst = next(iter(self.idle.items()))
+        k = lst.pop(0)
+        if not lst:
+            del self.idle[key]
+        k.plan.free()
+        if counted:
+            self.evictions += 1
+        return k.bytes
+
+    def clear(self) -> int:
+        """Frees every kept plan (not counted as evictions); their bytes."""
+        freed = 0
+        while self.idle:
+            freed += self.evict(counted=False)
+        return freed
 
 
 class _Loader:
@@ -74,8 +150,9 @@ class _Loader:
     complete matrices without any cross-stream event.  An exception in a load is
     handed over in place of the request and raised by the lane."""
 
-    def __init__(self, storage: int, reserve: int, now: Callable[[], float]):
-        self.storage, self.reserve, self.now = storage, reserve, now
+    def __init__(self, storage: int, reserve: int, now: Callable[[], float],
+                 keep_x0: bool = False):
+        self.storage, self.reserve, self.now, self.keep_x0 = storage, reserve, now, keep_x0
         self.inbox: _queue.Queue = _queue.Queue()
         self.ready: _queue.Queue = _queue.Queue()
         self.thread = threading.Thread(target=self._run, daemon=True)
@@ -90,7 +167,7 @@ class _Loader:
                 if req is None:
                     return
                 try:
-                    a = _Active(req, self.storage, self.reserve)
+                    a = _Active(req, self.storage, self.reserve, self.keep_x0)
                     stream.synchronize()
                     a.loaded = self.now()
                     self.ready.put(a)
@@ -127,9 +204,12 @@ class Server:
 
     def __init__(self, budget_bytes: int, params: fredopt.SolverParams, quantum: int = 50,
                  storage: int = fredopt.F32, big_nnz: int = 20_000_000,
-                 log: Optional[Callable[[str], None]] = None, gradient_reserve_pct: int = 0):
+                 log: Optional[Callable[[str], None]] = None, gradient_reserve_pct: int = 0,
+                 plan_cache: bool = False):
         fredopt.lib()
         self.reserve = int(gradient_reserve_pct)   # per plan, % of its CSC (0 default)
+        self.plan_cache = bool(plan_cache)
+        self.resident = _Resident()
         self.budget = int(budget_bytes)
         self.params = params
         self.quantum = int(quantum)
@@ -141,6 +221,10 @@ class Server:
         self.solo_quanta = 0        # quanta run by a lane's single active request
         self.peak_active = 0
         self.peak_bytes = 0
+
+    @property
+    def cache_hits(self) -> int:
+        return self.resident.hits
 
     def run(self, requests: List[Request]) -> List[Request]:
         queue = sorted(requests, key=lambda r: (r.arrival, r.rid))
@@ -173,12 +257,13 @@ class Server:
             t.start()
         for t in threads:
             t.join()
+        state["used"] -= self.resident.clear()   # resident plans end with the run
         if errors:
             raise errors[0]
         return sorted(done, key=lambda r: r.rid)
 
     def _lane(self, queue, lock, state, done, now):
-        loader = _Loader(self.storage, self.reserve, now)
+        loader = _Loader(self.storage, self.reserve, now, keep_x0=self.plan_cache)
         try:
             self._lane_loop(queue, lock, state, done, now, loader)
         finally:
@@ -192,25 +277,38 @@ class Server:
         qi = 0
         loading = 0     # admitted requests whose load has not been handed over yet
         while qi < len(queue) or active or loading:
+            changed = False
             # admission: arrival order, while the shared budget allows; the memory
-            # is counted from the moment the load starts
+            # is counted from the moment the load starts.  A request whose plan is
+            # resident and idle takes it and joins at once; otherwise idle resident
+            # plans make room, least recently used first
             while qi < len(queue) and queue[qi].arrival <= now():
-                need = plan_bytes(queue[qi].phantom, self.storage, self.reserve)
+                req = queue[qi]
+                need = plan_bytes(req.phantom, self.storage, self.reserve)
                 with lock:
-                    if state["used"] + need > self.budget:
-                        break
-                    state["used"] += need
+                    kept = self.resident.take(req.phantom) if self.plan_cache else None
+                    if kept is None:
+                        while state["used"] + need > self.budget:
+                            freed = self.resident.evict()
+                            if freed == 0:
+                                break
+                            state["used"] -= freed
+                        if state["used"] + need > self.budget:
+                            break
+                        state["used"] += need
                     state["active"] += 1
                     self.peak_bytes = max(self.peak_bytes, state["used"])
                     self.peak_active = max(self.peak_active, state["active"])
-                req = queue[qi]
                 qi += 1
                 req.admitted = now()
-                loader.submit(req)
-                loading += 1
+                if kept is not None:
+                    active.append(_Active.reuse(req, kept, req.admitted))
+                    changed = True
+                else:
+                    loader.submit(req)
+                    loading += 1
             # completed loads join; with nothing resident, wait for one (or for the
             # next arrival)
-            changed = False
             wait = 0.0
             if not active:
                 nxt = queue[qi].arrival - now() if qi < len(queue) else 0.05
@@ -266,12 +364,16 @@ class Server:
                     batch.free()
                     batch = None
                 active = [a for a in active if a.left > 0]
-                for a in finished:
-                    a.plan.free()
+                if not self.plan_cache:
+                    for a in finished:
+                        a.plan.free()
                 with lock:
                     for a in finished:
                         done.append(a.req)
-                        state["used"] -= a.bytes
+                        if self.plan_cache:
+                            self.resident.put(a)   # its bytes stay counted
+                        else:
+                            state["used"] -= a.bytes
                         state["active"] -= 1
                         if len(done) % self.progress_every == 0:
                             self.log(f"served {len(done)} requests")
@@ -283,10 +385,13 @@ class Server:
 def serve_one_at_a_time(requests: List[Request], params: fredopt.SolverParams,
                         storage: int = fredopt.F32,
                         log: Optional[Callable[[str], None]] = None,
-                        gradient_reserve_pct: int = 0) -> List[Request]:
-    """First come, first served; each request solved alone by fredopt_solve."""
+                        gradient_reserve_pct: int = 0,
+                        plan_cache: bool = False) -> List[Request]:
+    """First come, first served; each request solved alone by fredopt_solve.  With
+    plan_cache, plans stay resident between requests of the same plan (no budget)."""
     import torch
     queue = sorted(requests, key=lambda r: (r.arrival, r.rid))
+    kept = {}
     t0 = time.perf_counter()
     now = lambda: time.perf_counter() - t0  # noqa: E731
     for i, req in enumerate(queue):
@@ -294,8 +399,14 @@ def serve_one_at_a_time(requests: List[Request], params: fredopt.SolverParams,
         if wait > 0:
             time.sleep(wait)
         req.admitted = now()
-        plan, prob, x = fredopt.load_phantom(req.phantom, storage=storage,
-                                             gradient_reserve_pct=gradient_reserve_pct)
+        if plan_cache and id(req.phantom) in kept:
+            plan, prob, x0, _ = kept[id(req.phantom)]
+            x = x0.clone()
+        else:
+            plan, prob, x = fredopt.load_phantom(req.phantom, storage=storage,
+                                                 gradient_reserve_pct=gradient_reserve_pct)
+            if plan_cache:
+                kept[id(req.phantom)] = (plan, prob, x.clone(), req.phantom)
         torch.cuda.current_stream().synchronize()
         req.loaded = now()
         st = fredopt.new_state()
@@ -304,9 +415,12 @@ def serve_one_at_a_time(requests: List[Request], params: fredopt.SolverParams,
         req.x = x.cpu().numpy()
         req.k, req.s = st.k, st.s
         req.finished = now()
-        plan.free()
+        if not plan_cache:
+            plan.free()
         if log and (i + 1) % 100 == 0:
             log(f"served {i + 1} requests one at a time")
+    for plan, _, _, _ in kept.values():
+        plan.free()
     return queue
 
 

@@ -67,3 +67,39 @@ def test_one_at_a_time_baseline_runs(fo):
     done = serve.serve_one_at_a_time(reqs, fo.SolverParams())
     assert all(r.k == 5 for r in done)
     assert serve.percentile([r.latency for r in done], 50) > 0
+
+
+def test_plan_cache_reuses_and_evicts(fo):
+    """With plan_cache, a later request of a finished plan takes its resident matrices
+    (no load); an admission that needs room frees idle plans, least recently used
+    first; every result equals the request served alone, bit for bit, and the budget
+    holds throughout."""
+    from paper_2509_20012_amd import serve
+    A = ph.tiny_problem(300, 30, 0.15, seed=21)
+    B = ph.tiny_problem(1000, 130, 0.05, seed=5)
+    C = ph.tiny_problem(800, 90, 0.08, seed=8)
+    size = {id(p): serve.plan_bytes(p) for p in (A, B, C)}
+    assert size[id(C)] <= size[id(B)]
+    # room for A and B: C's admission evicts the idle B (A was used after it); B's
+    # return evicts the idle C; both later A requests find A resident
+    seq = [(A, 0.0, 6), (B, 0.0, 9), (A, 0.3, 7), (C, 0.6, 5), (A, 0.9, 8), (B, 1.2, 4)]
+    reqs = [serve.Request(i, p, n, t) for i, (p, t, n) in enumerate(seq)]
+    budget = size[id(A)] + size[id(B)] + 1
+    srv = serve.Server(budget, fo.SolverParams(alpha=0.9), quantum=4, plan_cache=True)
+    done = srv.run(reqs)
+    print(f"cache hits {srv.cache_hits}, evictions {srv.resident.evictions}, peak bytes "
+          f"{srv.peak_bytes} of {budget}", flush=True)
+    assert len(done) == len(reqs)
+    assert srv.peak_bytes <= budget
+    assert srv.cache_hits == 2 and srv.resident.evictions == 2
+    for r in done:
+        x_ref, ks = _alone(fo, r.phantom, fo.SolverParams(alpha=0.9), r.iters)
+        assert (r.k, r.s) == ks, r.rid
+        assert np.array_equal(r.x, x_ref), r.rid
+        assert r.finished >= r.loaded >= r.admitted >= r.arrival
+    # the one-at-a-time form with resident plans gives the same results
+    base = serve.serve_one_at_a_time([serve.Request(i, p, n, t) for i, (p, t, n) in
+                                      enumerate(seq)], fo.SolverParams(alpha=0.9),
+                                     plan_cache=True)
+    for r, b in zip(done, base):
+        assert np.array_equal(r.x, b.x) and (r.k, r.s) == (b.k, b.s)
