@@ -100,8 +100,10 @@ class _Kept:
 class _Resident:
     """Plans kept on the device after their request finished, by phantom (one
     patient's matrices and problem), for the next request of the same plan.  Idle
-    plans only: a plan in use by a request is not here.  The caller holds the
-    serving lock around every call."""
+    plans only: a plan in use by a request is not here.  Phantoms are ordered by
+    their latest use (a plan kept or taken); eviction frees the oldest kept plan of
+    the least recently used phantom.  The caller holds the serving lock around every
+    call."""
 
     def __init__(self):
         self.idle: "collections.OrderedDict[int, List[_Kept]]" = collections.OrderedDict()
@@ -113,7 +115,9 @@ class _Resident:
         if not got:
             return None
         k = got.pop()
-        if not got:
+        if got:
+            self.idle.move_to_end(id(phantom))   # a use: the phantom is the newest
+        else:
             del self.idle[id(phantom)]
         self.hits += 1
         return k

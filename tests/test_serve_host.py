@@ -49,3 +49,40 @@ def test_scenarios_shift_and_range():
     # longer ranges deposit dose deeper: more entries, same beamlets
     assert lr.n_cols == base.n_cols and lr.nnz > base.nnz
     assert len(ph.scenario_plans(1)) == 8
+
+
+class _FakePlan:
+    def __init__(self, name, log):
+        self.name, self.log = name, log
+
+    def free(self):
+        self.log.append(self.name)
+
+
+def test_resident_plans_lru_order():
+    """Idle resident plans: take() hands back the newest kept plan of the phantom and
+    counts a hit; phantoms are ordered by their latest use (kept or taken), and
+    evict() frees the oldest plan of the least recently used phantom and returns its
+    bytes; clear() frees the rest without counting them as evictions."""
+    freed = []
+    res = serve._Resident()
+
+    class _A:  # what put() reads of a finished request
+        def __init__(self, phantom, name, nbytes):
+            self.req = serve.Request(0, phantom, 1, 0.0)
+            self.plan, self.prob, self.x0, self.bytes = _FakePlan(name, freed), None, None, nbytes
+
+    pa, pb, pc = object(), object(), object()
+    res.put(_A(pa, "a1", 10))
+    res.put(_A(pb, "b1", 20))
+    res.put(_A(pa, "a2", 11))        # order by latest use: b, a
+    assert res.take(pc) is None and res.hits == 0
+    k = res.take(pa)                 # the newest plan of a; a stays the newest phantom
+    assert k is not None and k.bytes == 11 and res.hits == 1
+    res.put(_A(pc, "c1", 5))         # order: b, a, c
+    assert res.evict() == 20 and freed == ["b1"]
+    assert res.evict() == 10 and freed == ["b1", "a1"]
+    assert res.take(pa) is None      # a has no idle plan left
+    assert res.evictions == 2
+    assert res.clear() == 5 and res.evictions == 2 and freed == ["b1", "a1", "c1"]
+    assert res.evict() == 0
