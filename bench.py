@@ -38,6 +38,22 @@ KERNEL_SYMBOLS = {  # fredopt kernel id -> device symbol in profiler output (vt:
     "line_search": "fo::k_linesearch<{sub}>"}
 
 
+def device_info() -> dict:
+    """The GPU the line was measured on, as the runtime reports it (the roofline's
+    peak is the published 8 TB/s of HBM3E, not a measured figure)."""
+    import torch
+    pr = torch.cuda.get_device_properties(0)
+    info = {"name": pr.name, "compute_units": pr.multi_processor_count,
+            "memory_gib": round(pr.total_memory / 2**30, 1)}
+    arch = getattr(pr, "gcnArchName", None)
+    if arch:
+        info["arch"] = arch
+    lds = getattr(pr, "shared_memory_per_multiprocessor", None)
+    if lds:
+        info["lds_kib_per_cu"] = round(lds / 1024)
+    return info
+
+
 def dtype_of(storage: str) -> str:
     """The arithmetic type of the path with the storage form it reads.  BF16 values
     (8-bit mantissa) miss the 1e-3 tolerance of the reduced-precision form against
@@ -542,6 +558,7 @@ def main():
             res = bench_robust(args)
         else:
             res = bench_batch(args)
+        res["device"] = device_info()
         print(json.dumps(res), flush=True)
         return
     log(f"generating workload {args.workload}")
@@ -715,6 +732,7 @@ def main():
             f"variants {cb['variants']}")
         cb.pop("seconds")
         result["cpu_baseline"] = cb
+    result["device"] = device_info()
     print(json.dumps(result), flush=True)
 
 
