@@ -877,9 +877,21 @@ __device__ __forceinline__ void scatter_share(const DevPlan* __restrict__ plans,
   const int grp = lane >> lg2, gl = lane & (G - 1);
   const double fs = P->st->fx_scale;
   const ActRow* list = P->alist;
-  for (int i = i0 + wave * rg + grp; i < i1; i += (kScatterBlock / kWave) * rg) {
-    const v4i a0 = ((const FO_GLOBAL v4i*)(list + i))[0];
-    const v4i a1 = ((const FO_GLOBAL v4i*)(list + i))[1];
+  // the next row's record is loaded while this row's entries stream, and a row's
+  // quads go out two steps at a time before their additions
+  const int stride = (kScatterBlock / kWave) * rg;
+  int i = i0 + wave * rg + grp;
+  v4i n0 = v4i{0, 0, 0, 0}, n1 = n0;
+  if (i < i1) {
+    n0 = ((const FO_GLOBAL v4i*)(list + i))[0];
+    n1 = ((const FO_GLOBAL v4i*)(list + i))[1];
+  }
+  for (; i < i1; i += stride) {
+    const v4i a0 = n0, a1 = n1;
+    if (i + stride < i1) {
+      n0 = ((const FO_GLOBAL v4i*)(list + i + stride))[0];
+      n1 = ((const FO_GLOBAL v4i*)(list + i + stride))[1];
+    }
     const int64_t off = (int64_t)(((uint64_t)(uint32_t)a0.y << 32) | (uint32_t)a0.x);
     const int nq = a0.z;
     const double cd = __int_as_float(a1.x), cl = __int_as_float(a1.y);
@@ -887,22 +899,36 @@ __device__ __forceinline__ void scatter_share(const DevPlan* __restrict__ plans,
     const FO_GLOBAL void* ci = sell_idx_ptr<VT>(P->rci, off);
     const FO_GLOBAL void* dv = value_ptr<VT>(P->rdv, off);
     const FO_GLOBAL void* lv = value_ptr<VT>(P->rlv, off);
-    for (int q = gl; q < nq; q += G) {
-      const uint32_t e = (uint32_t)q * 4u;
-      const v4i c4 = sell_idx4<VT>(ci, e);
-      const v4f d4 = VLoad<VT>::q4(dv, e);
-      const v4f l4 = VLoad<VT>::q4(lv, e);
-      // padding slots hold the value 0 and add nothing
-      if (glob) {
-        fx_add_global(acc, c4.x, cd * d4.x + cl * l4.x, fs);
-        fx_add_global(acc, c4.y, cd * d4.y + cl * l4.y, fs);
-        fx_add_global(acc, c4.z, cd * d4.z + cl * l4.z, fs);
-        fx_add_global(acc, c4.w, cd * d4.w + cl * l4.w, fs);
-      } else {
-        fx_add(facc, c4.x, cd * d4.x + cl * l4.x, fs);
-        fx_add(facc, c4.y, cd * d4.y + cl * l4.y, fs);
-        fx_add(facc, c4.z, cd * d4.z + cl * l4.z, fs);
-        fx_add(facc, c4.w, cd * d4.w + cl * l4.w, fs);
+    for (int q0 = gl; q0 < nq; q0 += 2 * G) {
+      v4i c4[2];
+      v4f d4[2], l4[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int q = q0 + u * G;
+        c4[u] = v4i{0, 0, 0, 0};
+        d4[u] = v4f{0.f, 0.f, 0.f, 0.f};
+        l4[u] = d4[u];
+        if (q < nq) {
+          const uint32_t e = (uint32_t)q * 4u;
+          c4[u] = sell_idx4<VT>(ci, e);
+          d4[u] = VLoad<VT>::q4(dv, e);
+          l4[u] = VLoad<VT>::q4(lv, e);
+        }
+      }
+      // padding slots (and the second step past the row's end) hold 0 and add nothing
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        if (glob) {
+          fx_add_global(acc, c4[u].x, cd * d4[u].x + cl * l4[u].x, fs);
+          fx_add_global(acc, c4[u].y, cd * d4[u].y + cl * l4[u].y, fs);
+          fx_add_global(acc, c4[u].z, cd * d4[u].z + cl * l4[u].z, fs);
+          fx_add_global(acc, c4[u].w, cd * d4[u].w + cl * l4[u].w, fs);
+        } else {
+          fx_add(facc, c4[u].x, cd * d4[u].x + cl * l4[u].x, fs);
+          fx_add(facc, c4[u].y, cd * d4[u].y + cl * l4[u].y, fs);
+          fx_add(facc, c4[u].z, cd * d4[u].z + cl * l4[u].z, fs);
+          fx_add(facc, c4[u].w, cd * d4[u].w + cl * l4[u].w, fs);
+        }
       }
     }
   }
