@@ -3,21 +3,33 @@
 //
 //  k_forward    d = D v and l = L v over a sliced-ELL copy (rows sorted by length
 //               inside windows, lpr lanes per row, 16-byte loads per lane and step,
-//               the vector staged in LDS), slices handed out to 512-thread groups by
-//               an atomic counter (scheduling only; every slice writes its own
-//               partial, so results do not depend on the schedule).  Epilogues:
-//               dose / LETd / cDL (Eq. 1), Eq. (2) value and gradient coefficients,
+//               the vector staged in LDS), groups of 8 slices per 512-thread
+//               workgroup, handed out by an atomic counter (all-row passes) or round
+//               robin (objective-row passes, whose groups are balanced by weight);
+//               scheduling only: every group writes its own partial, so results do
+//               not depend on the schedule.  Epilogues: dose / LETd / cDL (Eq. 1, with
+//               per-voxel scenario bands), Eq. (2) value and gradient coefficients,
 //               the direction products with Q, or the Fig. 2 residuals folded into
 //               projection coefficients.
 //  k_rows       moves d and l along the accepted perturbation and evaluates the
 //               constraint residuals (or the next gradient coefficients).
 //  k_tr_chunks  D^T cD + L^T cL over the CSC copy, one wavefront per fixed-size chunk
 //               of a column; chunk partials only (no floating-point atomics).
-//  k_tcol       per column: chunk partials summed in chunk order, then the gradient
-//               store or the projection update with the pending perturbation and
-//               the x >= 0 clamp (Fig. 2, last loop).
-//  k_finalize   one workgroup per plan: sums the partial slots in index order (FP64)
-//               and makes the plan-level decisions (step size of Fig. 3, weights).
+//  k_active_list  the rows with a non-zero projection coefficient, compacted in slice
+//               order (or, on the column-major path, the coefficients in row order).
+//  k_project    the sweep's transposed product by the path the device chose: the
+//               active-row scatter (64-bit fixed-point sums in LDS, order free) and
+//               the column-major chunk walk in one launch; k_scatter is the scatter
+//               alone (block-sequential sweeps).
+//  k_scatter_sum  per column: the scatter shares or the chunk partials, then the
+//               projection update and the x >= 0 clamp (Fig. 2, last loop).
+//  k_tcol       per column: gradient chunk sums, moves of y and x, the clamp.
+//  k_finalize   one workgroup per plan: sums the partial slots in a fixed order (FP64)
+//               and makes the plan-level decisions (step size of Fig. 3, weights,
+//               list offsets, projection path).
+//  k_search_part, k_linesearch  the one-sided objective's step search (Fig. 3's
+//               trials, a window of candidate exponents at a time).
+//  k_band_fill, k_band_finish  per-voxel min / max bands of a robustness evaluation.
 //
 // Partial slot layout (kNPart doubles):
 //   objective pass  [0] chi^2                         [5] non-finite rows
