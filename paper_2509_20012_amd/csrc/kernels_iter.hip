@@ -596,11 +596,12 @@ __global__ __launch_bounds__(kFwdBlock) void k_forward(const DevPlan* __restrict
   const float* vec = nullptr;
   const float* gmv = nullptr;
   double beta = 0.0;
+  int next = -1;  // thread 0: the next group, requested while this one finishes
   for (int it = 0;; ++it) {
     int gi;
     if (ctr) {  // dynamic: next group from a counter (taken only when this one is done,
                 // so the last groups go to whichever workgroups are free)
-      if (tid == 0) s_g = (int)atomicAdd(&ctr[0], 1u);
+      if (tid == 0) s_g = next >= 0 ? next : (int)atomicAdd(&ctr[0], 1u);
       __syncthreads();
       gi = s_g;
       if (gi >= n_groups) {
@@ -621,7 +622,10 @@ __global__ __launch_bounds__(kFwdBlock) void k_forward(const DevPlan* __restrict
     }
     const FwdGroup G = groups[gi];
     const DevPlan* __restrict__ P = plans + G.plan;
-    if (MODE != kFwdDoseLet && halted(P)) continue;  // uniform over the workgroup
+    if (MODE != kFwdDoseLet && halted(P)) {  // uniform over the workgroup
+      next = -1;
+      continue;
+    }
     if (G.plan != cur) {
       vec = vsel == kVecG ? P->g : (vsel == kVecX ? P->x : P->y);
       const bool move = vsel == kVecYMove;
@@ -647,6 +651,9 @@ __global__ __launch_bounds__(kFwdBlock) void k_forward(const DevPlan* __restrict
     if (wave < G.n)
       forward_slice<VT, MODE, SUB>(P, G.slice0 + wave, xs, use_lds, vec, gmv, beta, lane,
                                    wpart[wave]);
+    // the next group is requested once wave 0's slice is done, so that the counter's
+    // round trip overlaps the other waves' work instead of following the group
+    if (ctr && tid == 0) next = (int)atomicAdd(&ctr[0], 1u);
     __syncthreads();
     if constexpr (MODE != kFwdDoseLet) {
       // the group's partial: its slices' partials in wave order
