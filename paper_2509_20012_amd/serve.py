@@ -394,6 +394,7 @@ def serve_one_at_a_time(requests: List[Request], params: fredopt.SolverParams,
     """First come, first served; each request solved alone by fredopt_solve.  With
     plan_cache, plans stay resident between requests of the same plan (no budget)."""
     import torch
+    params = dataclasses.replace(params)   # iter_max is set per request on this copy
     queue = sorted(requests, key=lambda r: (r.arrival, r.rid))
     kept = {}
     t0 = time.perf_counter()

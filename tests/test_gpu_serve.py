@@ -64,8 +64,11 @@ def test_one_at_a_time_baseline_runs(fo):
     from paper_2509_20012_amd import serve
     reqs = [serve.Request(i, ph.tiny_problem(200, 24, 0.2, seed=40 + i), 5, 0.0)
             for i in range(3)]
-    done = serve.serve_one_at_a_time(reqs, fo.SolverParams())
+    params = fo.SolverParams()
+    iter_max = params.iter_max
+    done = serve.serve_one_at_a_time(reqs, params)
     assert all(r.k == 5 for r in done)
+    assert params.iter_max == iter_max   # the caller's parameters are left as they were
     assert serve.percentile([r.latency for r in done], 50) > 0
 
 
