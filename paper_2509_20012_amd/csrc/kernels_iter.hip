@@ -180,27 +180,58 @@ __device__ __forceinline__ ObjArrays obj_arrays(const DevPlan* P) {
   else return ObjArrays{P->kind, P->wo, P->dt, P->ct, P->gcoef};
 }
 
+// A row's epilogue inputs, read at the start of its slice so that their latency
+// overlaps the slice's matrix stream (read in the epilogue, each of the row's kinds
+// cost a dependent memory round trip with no matrix loads in flight).  Every array
+// holds a value at every position of its view; padding positions have kind 0 and
+// their values are never used.
+struct RowIn {
+  float wo = 0.f, dt = 0.f, ct = 0.f;                          // Eq. (2)
+  float wf = 0.f, dhi = 0.f, dlo = 0.f, chi = 0.f, clo = 0.f, tmax = 0.f;  // Fig. 2
+  double sdd = 0.0, sll = 0.0, sdl = 0.0;                      // row moments
+};
+
+__device__ __forceinline__ void load_obj_in(const ObjArrays& A, int r, RowIn* in) {
+  in->wo = gconst(A.wo)[r];
+  in->dt = gconst(A.dt)[r];
+  in->ct = gconst(A.ct)[r];
+}
+
+__device__ __forceinline__ void load_feas_in(const DevPlan* P, int r, RowIn* in) {
+  in->wf = gconst(P->wf)[r];
+  in->dhi = gconst(P->dhi)[r];
+  in->dlo = gconst(P->dlo)[r];
+  in->chi = gconst(P->chi)[r];
+  in->clo = gconst(P->clo)[r];
+  in->tmax = gconst(P->tmax)[r];
+  const FO_GLOBAL double* m = gconst(P->mom) + 3 * (int64_t)r;
+  in->sdd = m[0];
+  in->sll = m[1];
+  in->sdl = m[2];
+}
+
 // Whether the OAR term of Eq. (2) counts at residual f = cDLhat - c l: always as
 // printed; only above the target (f < 0) with the one-sided objective.
 __device__ __forceinline__ bool oar_on(const DevPlan* P, double f) {
   return P->prm.objective == 0 || f < 0.0;
 }
 
-// Eq. (2) terms of the row with data at position r (kinds k) at (d, l): adds the
-// value to *chi and stores the gradient coefficients (-2 w (Dhat - d),
-// -2 c w (cDLhat - c l)) at index rc (the row).
-__device__ __forceinline__ void objective_row(const DevPlan* P, const ObjArrays& A, int r, int rc,
-                                              unsigned k, float d, float l, double* chi) {
+// Eq. (2) terms of a row (kinds k, inputs in) at (d, l): adds the value to *chi and
+// stores the gradient coefficients (-2 w (Dhat - d), -2 c w (cDLhat - c l)) at index
+// rc (the row).
+__device__ __forceinline__ void objective_row(const DevPlan* P, const ObjArrays& A,
+                                              const RowIn& in, int rc, unsigned k, float d,
+                                              float l, double* chi) {
   double uD = 0.0, uL = 0.0;
   if (k & (kObjDose | kObjCdl)) {
-    const double w = gconst(A.wo)[r], c = P->prm.c;
+    const double w = in.wo, c = P->prm.c;
     if (k & kObjDose) {
-      const double e = (double)gconst(A.dt)[r] - (double)d;
+      const double e = (double)in.dt - (double)d;
       *chi += w * e * e;
       uD = -2.0 * w * e;
     }
     if (k & kObjCdl) {
-      const double f = (double)gconst(A.ct)[r] - c * (double)l;
+      const double f = (double)in.ct - c * (double)l;
       if (oar_on(P, f)) {
         *chi += w * f * f;
         uL = -2.0 * c * w * f;
@@ -210,17 +241,17 @@ __device__ __forceinline__ void objective_row(const DevPlan* P, const ObjArrays&
   ((FO_GLOBAL v2f*)(A.coef))[rc] = v2f{(float)uD, (float)uL};
 }
 
-__device__ __forceinline__ double objective_value(const DevPlan* P, int r, unsigned k, float d,
-                                                  float l) {
+__device__ __forceinline__ double objective_value(const DevPlan* P, const RowIn& in, unsigned k,
+                                                  float d, float l) {
   double s = 0.0;
   if (k & (kObjDose | kObjCdl)) {
-    const double w = gconst(P->wo)[r], c = P->prm.c;
+    const double w = in.wo, c = P->prm.c;
     if (k & kObjDose) {
-      const double e = (double)gconst(P->dt)[r] - (double)d;
+      const double e = (double)in.dt - (double)d;
       s += w * e * e;
     }
     if (k & kObjCdl) {
-      const double f = (double)gconst(P->ct)[r] - c * (double)l;
+      const double f = (double)in.ct - c * (double)l;
       if (oar_on(P, f)) s += w * f * f;
     }
   }
@@ -232,14 +263,13 @@ __device__ __forceinline__ double objective_value(const DevPlan* P, int r, unsig
 // folded into the (D, L) coefficient pair of the row.  ||a||^2 comes from the row
 // moments: ||D_i||^2, c^2 ||L_i||^2, ||L_i - T D_i||^2 = sum L^2 - 2T sum DL +
 // T^2 sum D^2.  Accumulates slots [0]..[4] of the residual layout.
-__device__ __forceinline__ void residual_row(const DevPlan* P, int r, unsigned k, float d,
-                                             float l, double* acc) {
+__device__ __forceinline__ void residual_row(const DevPlan* P, const RowIn& in, int r,
+                                             unsigned k, float d, float l, double* acc) {
   double kD = 0.0, kL = 0.0;
   if (k & kConstraintBits) {
-    const double w = gconst(P->wf)[r], lam = P->prm.lambda, c = P->prm.c;
+    const double w = in.wf, lam = P->prm.lambda, c = P->prm.c;
     const double dd = d, ll = l;
-    const FO_GLOBAL double* m = gconst(P->mom) + 3 * (int64_t)r;
-    const double sdd = m[0], sll = m[1], sdl = m[2];
+    const double sdd = in.sdd, sll = in.sll, sdl = in.sdl;
     auto take = [&](double v, double n2, double scale, int which, double T) {
       if (!(n2 > kDegenerateRel * scale)) {
         acc[4] += 1.0;
@@ -260,27 +290,27 @@ __device__ __forceinline__ void residual_row(const DevPlan* P, int r, unsigned k
     };
     if (k & kDoseHi) {
       acc[0] += w;
-      const double b = gconst(P->dhi)[r];
+      const double b = in.dhi;
       if (dd > b) take(dd - b, sdd, sdd, 0, 0.0);
     }
     if (k & kDoseLo) {
       acc[0] += w;
-      const double b = gconst(P->dlo)[r];
+      const double b = in.dlo;
       if (dd < b) take(dd - b, sdd, sdd, 0, 0.0);
     }
     if (k & kCdlHi) {
       acc[0] += w;
-      const double b = gconst(P->chi)[r], ax = c * ll;
+      const double b = in.chi, ax = c * ll;
       if (ax > b) take(ax - b, c * c * sll, c * c * sll, 1, 0.0);
     }
     if (k & kCdlLo) {
       acc[0] += w;
-      const double b = gconst(P->clo)[r], ax = c * ll;
+      const double b = in.clo, ax = c * ll;
       if (ax < b) take(ax - b, c * c * sll, c * c * sll, 1, 0.0);
     }
     if (k & kLetdHi) {
       acc[0] += w;
-      const double T = gconst(P->tmax)[r], ax = ll - T * dd;
+      const double T = in.tmax, ax = ll - T * dd;
       if (ax > 0.0) take(ax, sll - 2.0 * T * sdl + T * T * sdd, sll + T * T * sdd, 2, T);
     }
   }
@@ -432,6 +462,14 @@ __device__ __forceinline__ void forward_slice(const DevPlan* __restrict__ P, int
   // the gradient coefficients are stored by row (the column-major gradient gathers them)
   int crow = 0;
   if constexpr (MODE == kFwdObj) crow = gconst(V.srow)[sp];
+  // the epilogue's row inputs, requested before the matrix stream by every lane of
+  // the row (the same addresses; loaded by the owner lane alone, the values become
+  // a branch's results and the compiler converts them before the stream starts);
+  // the direction pass needs the objective weight only
+  RowIn in;
+  if constexpr (MODE == kFwdDir) in.wo = gconst(A.wo)[sp];
+  if constexpr (MODE == kFwdObj || MODE == kFwdResid) load_obj_in(A, sp, &in);
+  if constexpr (MODE == kFwdResid) load_feas_in(P, sp, &in);
   // slice-relative element offsets fit 32 bits; the slice bases are wave-uniform
 
   const FO_GLOBAL void* ci = sell_idx_ptr<VT>(V.sci, sb);
@@ -516,7 +554,7 @@ __device__ __forceinline__ void forward_slice(const DevPlan* __restrict__ P, int
         gmut(P->od)[sp] = ad;
         gmut(P->ol)[sp] = al;
       }
-      if (crow >= 0) objective_row(P, A, sp, crow, kind, ad, al, &acc[0]);
+      if (crow >= 0) objective_row(P, A, in, crow, kind, ad, al, &acc[0]);
       if (!finite2(ad, al)) acc[5] += 1.0;
     } else if constexpr (MODE == kFwdDir) {
       if constexpr (!SUB) {
@@ -527,7 +565,7 @@ __device__ __forceinline__ void forward_slice(const DevPlan* __restrict__ P, int
         gmut(P->olg)[sp] = al;
       }
       if (kind & (kObjDose | kObjCdl)) {
-        const double wo = gconst(A.wo)[sp], c = P->prm.c;
+        const double wo = in.wo, c = P->prm.c;
         if (kind & kObjDose) acc[0] += wo * (double)ad * (double)ad;
         if (kind & kObjCdl) acc[0] += wo * c * c * (double)al * (double)al;
       }
@@ -535,8 +573,8 @@ __device__ __forceinline__ void forward_slice(const DevPlan* __restrict__ P, int
     } else {
       gmut(P->d)[sp] = ad;
       gmut(P->l)[sp] = al;
-      residual_row(P, sp, kind, ad, al, acc);
-      acc[6] += objective_value(P, sp, kind, ad, al);
+      residual_row(P, in, sp, kind, ad, al, acc);
+      acc[6] += objective_value(P, in, kind, ad, al);
       if (!finite2(ad, al)) acc[5] += 1.0;
     }
   }
@@ -686,13 +724,17 @@ __global__ __launch_bounds__(kBlock) void k_rows(const DevPlan* __restrict__ pla
     const float l = (float)((double)gmut(P->l)[r] - beta * (double)gmut(P->lg)[r]);
     gmut(P->d)[r] = d;
     gmut(P->l)[r] = l;
+    const ObjArrays A = obj_arrays<0>(P);
+    RowIn in;
+    load_obj_in(A, r, &in);
     if constexpr (MODE == kRowsMoveObj) {
       const int row = gconst(P->sell.srow)[r];
-      if (row >= 0) objective_row(P, obj_arrays<0>(P), r, row, gconst(P->kind)[r], d, l, &acc[0]);
+      if (row >= 0) objective_row(P, A, in, row, gconst(P->kind)[r], d, l, &acc[0]);
     } else {
+      load_feas_in(P, r, &in);
       const unsigned kr = gconst(P->kind)[r];
-      residual_row(P, r, kr, d, l, acc);
-      acc[6] += objective_value(P, r, kr, d, l);
+      residual_row(P, in, r, kr, d, l, acc);
+      acc[6] += objective_value(P, in, kr, d, l);
     }
     if (!finite2(d, l)) acc[5] += 1.0;
   }
