@@ -591,31 +591,63 @@ __device__ __forceinline__ void forward_slice(const DevPlan* __restrict__ P, int
 }
 
 // Copies v (times the per-column scales when SCALED) into LDS.  Each thread has
-// kStage loads in flight before its first store, so the copy costs a few memory
-// round trips instead of one per kFwdBlock elements.
+// kStage loads (kStageMix elements of two or three arrays) in flight before its first
+// store, so the copy costs a few memory round trips instead of one per kFwdBlock
+// elements.
 constexpr int kStage = 16;
+constexpr int kStageMix = 8;  // elements per round when two or three arrays are read
+
+// One element of the staged vector: v, or v - beta g rounded to FP32 as the separate
+// move would store it (MOVE), times the column scale (SCALED).
+template <bool SCALED, bool MOVE>
+__device__ __forceinline__ float staged(float v, float g, float cs, double beta) {
+  float a = MOVE ? (float)((double)v - beta * (double)g) : v;
+  if (SCALED) a *= cs;
+  return a;
+}
 
 // MOVE: stages v - beta g, rounded to FP32 as the separate move would store it.
 template <bool SCALED, bool MOVE>
 __device__ __forceinline__ void stage_vector(const FO_GLOBAL float* v, const FO_GLOBAL float* cs,
                                              const FO_GLOBAL float* g, double beta, int C,
                                              float* xs, int tid) {
-  for (int j0 = tid; j0 < C; j0 += kStage * kFwdBlock) {
-    float t[kStage];
+  if (C <= kFwdBlock) {  // one element per thread
+    if (tid < C) xs[tid] = staged<SCALED, MOVE>(v[tid], MOVE ? g[tid] : 0.f,
+                                                 SCALED ? cs[tid] : 0.f, beta);
+    return;
+  }
+  if constexpr (!SCALED && !MOVE) {
+    // a plain copy: the loads are issued together and only the stores are tested
+    for (int j0 = tid; j0 < C; j0 += kStage * kFwdBlock) {
+      float t[kStage];
 #pragma unroll
-    for (int u = 0; u < kStage; ++u) {
-      const int j = j0 + u * kFwdBlock;
-      float a = 0.f;
-      if (j < C) {
-        a = MOVE ? (float)((double)v[j] - beta * (double)g[j]) : v[j];
-        if (SCALED) a *= cs[j];
+      for (int u = 0; u < kStage; ++u) {
+        const int j = j0 + u * kFwdBlock;
+        t[u] = j < C ? v[j] : 0.f;
       }
-      t[u] = a;
-    }
 #pragma unroll
-    for (int u = 0; u < kStage; ++u) {
-      const int j = j0 + u * kFwdBlock;
-      if (j < C) xs[j] = t[u];
+      for (int u = 0; u < kStage; ++u) {
+        const int j = j0 + u * kFwdBlock;
+        if (j < C) xs[j] = t[u];
+      }
+    }
+  } else {
+    for (int j0 = tid; j0 < C; j0 += kStageMix * kFwdBlock) {
+      // every load is issued before any value is used, and none sits behind a
+      // branch: indices past the end take element C - 1 and store its own value
+      // again.  With the arithmetic inside a bounds test, each element waited for its
+      // own loads
+      float tv[kStageMix], tg[kStageMix], ts[kStageMix];
+#pragma unroll
+      for (int u = 0; u < kStageMix; ++u) {
+        const int j = min(j0 + u * kFwdBlock, C - 1);
+        tv[u] = v[j];
+        tg[u] = MOVE ? g[j] : 0.f;
+        ts[u] = SCALED ? cs[j] : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < kStageMix; ++u)
+        xs[min(j0 + u * kFwdBlock, C - 1)] = staged<SCALED, MOVE>(tv[u], tg[u], ts[u], beta);
     }
   }
 }
