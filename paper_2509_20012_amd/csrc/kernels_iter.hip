@@ -1155,10 +1155,15 @@ __global__ __launch_bounds__(kScatterBlock) void k_scatter_sum(const DevPlan* __
     const int w = wave + i * kNW;
     m[i] = w < NW ? mk[(int64_t)w * nwords] : 0ull;
   }
+  // the marked shares' loads all go out before the first add (with the add inside
+  // the bit test, each share waited for its own load); a set bit implies j < C
+  int64_t v[kPer];
+#pragma unroll
+  for (int i = 0; i < kPer; ++i)
+    v[i] = ((m[i] >> lane) & 1ull) ? sp[(int64_t)(wave + i * kNW) * C] : int64_t(0);
   int64_t S = 0;
 #pragma unroll
-  for (int i = 0; i < kPer; ++i)  // a set bit implies j < C
-    if ((m[i] >> lane) & 1ull) S += sp[(int64_t)(wave + i * kNW) * C];
+  for (int i = 0; i < kPer; ++i) S += v[i];
   part[wave][lane] = S;
   __syncthreads();
   if (wave == 0) {
